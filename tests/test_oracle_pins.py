@@ -1,0 +1,269 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+None of these re-types the oracle's own arithmetic: the element matrix is
+computed by Gauss quadrature in the oracle and checked against the
+tensor-product closed form here; the assembled matrix against the stencil
+and counting formulas; the solver against dense LAPACK solves, the
+finite-element patch test, linearity, symmetry, the maximum principle and
+the separation-of-variables series.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def closed_form_element(hx, hy, hz):
+    """K_ab = (hy hz/hx) s_x m_y m_z + (hx hz/hy) m_x s_y m_z + (hx hy/hz) m_x m_y s_z,
+    with 1-D stiffness s = +1 (same node) / -1 and 1-D mass m = 1/3 / 1/6."""
+    K = np.zeros((8, 8))
+    for a, b in itertools.product(range(8), range(8)):
+        f = [(a >> d) & 1 == (b >> d) & 1 for d in range(3)]
+        s = [1.0 if e else -1.0 for e in f]
+        mm = [1 / 3 if e else 1 / 6 for e in f]
+        K[a, b] = (hy * hz / hx) * s[0] * mm[1] * mm[2] + (hx * hz / hy) * mm[0] * s[1] * mm[2] \
+            + (hx * hy / hz) * mm[0] * mm[1] * s[2]
+    return K
+
+
+# ---------------------------------------------------------------- element operator (Sec. 1)
+
+@pytest.mark.parametrize("h", [(1.0, 1.0, 1.0), (0.05, 0.05, 0.05), (0.1, 0.25, 1 / 3), (1 / 96, 1 / 16, 1 / 50)])
+def test_element_matrix_closed_form(h):
+    K = oracle.element_matrix(*h)
+    Kc = closed_form_element(*h)
+    assert np.allclose(K, Kc, rtol=0, atol=1e-15 * np.abs(Kc).max())
+    assert np.array_equal(K, K.T)
+    assert np.abs(K.sum(axis=1)).max() <= 1e-14 * np.abs(K).max()
+
+
+def test_element_matrix_cube_values():
+    h = 0.125
+    K = oracle.element_matrix(h, h, h)
+    for a, b in itertools.product(range(8), range(8)):
+        nd = bin(a ^ b).count("1")  # 0 same node, 1 edge, 2 face diagonal, 3 body diagonal
+        want = {0: h / 3, 1: 0.0, 2: -h / 12, 3: -h / 12}[nd]
+        assert abs(K[a, b] - want) <= 1e-16, (a, b)
+    ev = np.linalg.eigvalsh(K)
+    assert abs(ev[0]) < 1e-15 and ev[1] > 1e-3  # PSD, only constants in the null space
+
+
+# ---------------------------------------------------------------- structure (Fig 3.6) and formats (Sec. 3.1)
+
+def sizes(Nx, Ny, Nz):
+    nx, ny, nz = Nx + 1, Ny + 1, Nz + 1
+    return dict(m=nx * ny * nz, nnz=(3 * nx - 2) * (3 * ny - 2) * (3 * nz - 2),
+                nns=nx * (3 * ny - 2) * (3 * nz - 2))
+
+
+@pytest.mark.parametrize("N", [(1, 1, 1), (2, 3, 4), (3, 3, 3), (7, 5, 6), (20, 20, 20)])
+def test_counts(N):
+    s = sizes(*N)
+    assert oracle.num_rows(*N) == s["m"]
+    assert oracle.count_nnz(*N) == s["nnz"]
+    A = oracle.assemble(*N, apply_bc=False)
+    assert A.ptr[-1] == s["nnz"] and A.ptr[0] == 0 and np.all(np.diff(A.ptr) > 0)
+    for i in range(A.m):  # ascending, distinct, in range
+        c = A.col[A.ptr[i]:A.ptr[i + 1]]
+        assert np.all(np.diff(c) > 0) and c[0] >= 0 and c[-1] < A.m
+    jas, offs, bptr = oracle.bcrsvar(A)
+    assert bptr[-1] == len(jas) and offs[-1] == A.nnz  # ptr[m] = nns, offsets[nns] = nnz
+    lengths = np.diff(offs)
+    if N[0] >= 3:
+        # one segment per (dy, dz) line; length 3 inside in x, 2 on the x faces
+        assert len(jas) == s["nns"]
+        nx, ny, nz = N[0] + 1, N[1] + 1, N[2] + 1
+        assert np.sum(lengths == 2) == 2 * (3 * ny - 2) * (3 * nz - 2)
+        assert np.sum(lengths == 3) == (nx - 2) * (3 * ny - 2) * (3 * nz - 2)
+    bptr13, bcol13, bval13 = oracle.bcrs13(A)
+    if N[0] >= 2:
+        assert len(bcol13) == s["nns"]
+
+
+def test_golden_sizes():
+    """Sizes of the paper-problem meshes used throughout (tests/golden/sizes.json)."""
+    with open(os.path.join(GOLDEN, "sizes.json")) as f:
+        gold = json.load(f)
+    for key, row in gold["meshes"].items():
+        N = tuple(row["N"])
+        want = sizes(*N)
+        assert all(want[k] == row[k] for k in ("m", "nnz", "nns") if k in row)
+        if row["m"] < 3_000_000:
+            assert oracle.count_nnz(*N) == row["nnz"]
+
+
+def test_interior_stencil_and_symmetry():
+    N = 6
+    h = 1.0 / N
+    A = oracle.assemble(N, N, N, apply_bc=False)
+    D = A.dense()
+    assert np.array_equal(D, D.T)
+    assert np.abs(D.sum(axis=1)).max() <= 1e-14 * np.abs(np.diag(D)).max()
+    n = N + 1
+    for (ix, iy, iz) in [(3, 3, 3), (1, 2, 4), (5, 5, 1)]:
+        i = ix + n * (iy + n * iz)
+        for sx, sy, sz in itertools.product((-1, 0, 1), repeat=3):
+            j = (ix + sx) + n * ((iy + sy) + n * (iz + sz))
+            nz_ = abs(sx) + abs(sy) + abs(sz)
+            want = {0: 32, 1: 0, 2: -2, 3: -1}[nz_] * h / 12
+            assert abs(D[i, j] - want) <= 1e-15, (i, j)
+
+
+# ---------------------------------------------------------------- Dirichlet faces (Sec. 1)
+
+@pytest.mark.parametrize("N", [4, 9])
+def test_dirichlet_rhs_and_identity_rows(N):
+    h = 1.0 / N
+    A = oracle.assemble(N, N, N)
+    dirm, g = oracle.boundary(N, N, N)
+    n = N + 1
+    ix = np.arange(A.m) % n
+    free = ~dirm
+    # paper BCs: 1 on every node with x = 1 (edges included), 0 on the rest of the surface
+    assert np.all(g[dirm & (ix == N)] == 1.0) and np.all(g[dirm & (ix < N)] == 0.0)
+    assert np.allclose(A.b[free & (ix == N - 1)], h, rtol=0, atol=1e-15)
+    assert np.all(A.b[free & (ix < N - 1)] == 0.0)
+    D = A.dense()
+    assert np.array_equal(D, D.T)
+    for i in np.nonzero(dirm)[0]:
+        assert D[i, i] == 1.0 and np.count_nonzero(D[i]) == 1 and A.b[i] == g[i]
+    # rows whose whole neighbourhood is free keep a zero row sum
+    iy = (np.arange(A.m) // n) % n
+    iz = np.arange(A.m) // (n * n)
+    deep = (ix >= 2) & (ix <= N - 2) & (iy >= 2) & (iy <= N - 2) & (iz >= 2) & (iz <= N - 2)
+    assert np.abs(D[deep].sum(axis=1)).max() <= 1e-15
+
+
+# ---------------------------------------------------------------- SpMV (Figs 3.1-3.3)
+
+@pytest.mark.parametrize("N", [(1, 1, 1), (2, 2, 2), (3, 4, 2), (4, 4, 4), (2, 5, 3)])
+def test_spmv_formats_against_dense(N):
+    A = oracle.assemble(*N)
+    x = np.random.default_rng(1).uniform(-1, 1, A.m)
+    y = oracle.csr_spmv(A, x)
+    yd = A.dense() @ x
+    scale = np.abs(A.dense()) @ np.abs(x)
+    assert np.all(np.abs(y - yd) <= 1e-14 * scale + 1e-300)
+    fmt = oracle.bcrsvar(A)
+    assert np.array_equal(oracle.bcrsvar_spmv(A, fmt, x), y)
+    assert np.array_equal(oracle.bcrsvar_spmv(A, fmt, x, switch=True), y)
+    f13 = oracle.bcrs13(A)
+    y13 = oracle.bcrs13_spmv(A, f13, x)
+    # same columns, same order, padding adds +-0 products only
+    assert np.all(y13 == y)
+    # every stored entry lands in exactly one slot
+    bptr, bcol, bval = f13
+    assert np.count_nonzero(bval) == np.count_nonzero(A.val)
+    assert np.isclose(bval.sum(), A.val.sum(), rtol=0, atol=1e-12)
+
+
+# ---------------------------------------------------------------- CG (Sec. 1 CG module)
+
+@pytest.mark.parametrize("N", [(1, 1, 1), (2, 2, 2), (3, 2, 4), (4, 4, 4)])
+def test_cg_matches_dense_solve(N):
+    A = oracle.assemble(*N)
+    r = oracle.cg(A, tol=1e-14, max_iter=500)
+    assert r["status"] == oracle.OK
+    xs = np.linalg.solve(A.dense(), A.b)
+    assert np.linalg.norm(r["x"] - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert r["rel_res_true"] <= 1e-13
+
+
+def test_cg_history_and_stop_rule():
+    A = oracle.assemble(20, 20, 20)
+    r = oracle.cg(A, tol=1e-8, max_iter=200, history=True)
+    h = r["history"]
+    assert r["status"] == oracle.OK
+    assert h[0] == 1.0  # x0 = 0 so r0 = b
+    assert h[-1] <= 1e-8 and np.all(h[:-1] > 1e-8)
+    assert len(h) == r["iterations"] + 1
+    assert abs(r["rel_res_true"] - r["rel_res_rec"]) <= 1e-10
+    capped = oracle.cg(A, tol=1e-8, max_iter=10)
+    assert capped["status"] == oracle.NOT_CONVERGED and capped["iterations"] == 10
+    zero = oracle.cg(A, tol=1e-8, max_iter=0)
+    assert zero["iterations"] == 0 and np.all(zero["x"] == 0)
+
+
+@pytest.mark.parametrize("N", [(6, 6, 6), (5, 3, 7), (9, 4, 4)])
+def test_patch_test_affine_exact(N):
+    """Trilinear elements reproduce affine fields exactly (Galerkin is exact on the FE space)."""
+    Nx, Ny, Nz = N
+    m = oracle.num_rows(*N)
+    n = np.arange(m)
+    x = (n % (Nx + 1)) / Nx
+    y = ((n // (Nx + 1)) % (Ny + 1)) / Ny
+    z = (n // ((Nx + 1) * (Ny + 1))) / Nz
+    u = 0.3 + 0.7 * x - 0.2 * y + 0.45 * z
+    A = oracle.assemble(*N, node_g=u)
+    r = oracle.cg(A, tol=1e-13, max_iter=2000)
+    assert r["status"] == oracle.OK
+    assert np.abs(r["x"] - u).max() <= 1e-9
+
+
+def test_constant_and_superposition():
+    N = 8
+    c = 0.37
+    A = oracle.assemble(N, N, N, face_vals=[c] * 6)
+    r = oracle.cg(A, tol=1e-13, max_iter=1000)
+    assert np.abs(r["x"] - c).max() <= 1e-10
+    total = np.zeros(A.m)
+    for f in range(6):
+        fv = [0.0] * 6
+        fv[f] = 1.0
+        total += oracle.cg(oracle.assemble(N, N, N, face_vals=fv), tol=1e-13, max_iter=1000)["x"]
+    assert np.abs(total - 1.0).max() <= 1e-10
+
+
+def test_maximum_principle_and_symmetry():
+    N = 12
+    A = oracle.assemble(N, N, N)
+    u = oracle.cg(A, tol=1e-13, max_iter=1000)["x"].reshape(N + 1, N + 1, N + 1)  # [z, y, x]
+    assert u.min() >= -1e-12 and u.max() <= 1 + 1e-12
+    assert np.abs(u - u[:, ::-1, :]).max() <= 1e-10  # y -> 1 - y
+    assert np.abs(u - u[::-1, :, :]).max() <= 1e-10  # z -> 1 - z
+    assert np.abs(u - u.transpose(1, 0, 2)).max() <= 1e-10  # y <-> z
+    assert np.all(np.diff(u[N // 2, N // 2, :]) > 0)  # increases towards x = 1
+
+
+# ---------------------------------------------------------------- analytic solution (Sec. 1 verification)
+
+def test_series_identities():
+    # superposing the six single-face problems gives 1, and at the centre all six are equal
+    assert abs(oracle.analytic_u(0.5, 0.5, 0.5) - 1 / 6) <= 1e-13
+    assert oracle.analytic_u(0.0, 0.3, 0.6) == 0.0
+    assert abs(oracle.analytic_u(0.4, 0.0, 0.6)) <= 1e-15
+    assert abs(oracle.analytic_u(0.4, 0.2, 0.7) - oracle.analytic_u(0.4, 0.8, 0.3)) <= 1e-13
+    assert abs(oracle.analytic_u(0.4, 0.2, 0.7) - oracle.analytic_u(0.4, 0.7, 0.2)) <= 1e-13
+    # near the x = 1 face the series approaches the face value 1
+    assert abs(oracle.analytic_u(0.999, 0.5, 0.5) - 1.0) < 0.01
+
+
+def test_fe_converges_to_series():
+    errs = []
+    for N in (8, 16, 32):
+        A = oracle.assemble(N, N, N)
+        u = oracle.cg(A, tol=1e-12, max_iter=2000)["x"].reshape(N + 1, N + 1, N + 1)
+        e = 0.0
+        for a, b, c in itertools.product((N // 4, N // 2, 3 * N // 4), repeat=3):
+            e = max(e, abs(u[c, b, a] - oracle.analytic_u(a / N, b / N, c / N)))
+        errs.append(e)
+    assert errs[0] < 0.05
+    assert errs[1] < errs[0] / 3 and errs[2] < errs[1] / 3  # second order in h
+
+
+# ---------------------------------------------------------------- mixed precision extension
+
+def test_mixed_precision_reaches_fp64_accuracy():
+    N = 16
+    A = oracle.assemble(N, N, N)
+    ref = oracle.cg(A, tol=1e-13, max_iter=2000)["x"]
+    r = oracle.cg_mixed(A, tol=1e-10, inner_tol=1e-4)
+    assert r["status"] == oracle.OK and r["rel_res_true"] <= 1e-10
+    assert r["outer"] >= 2  # FP32 alone cannot reach 1e-10
+    assert np.linalg.norm(r["x"] - ref) <= 1e-8 * np.linalg.norm(ref)
