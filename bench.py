@@ -1,0 +1,168 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X: plain FP64 CG on the 256^3 MiniFE
+heat-conduction mesh (unit cube, u = 1 on x = 1, 0 on the other faces, zero
+source, x0 = 0) to ||r||/||b|| <= 1e-8 with the 1x3 BCRS SpMV.
+
+One step = one complete CG solve (every iteration: fused SpMV + p.q, r update
++ r.r, x/p update, all scalars on the device).  value = CG iterations per
+second over the K timed solves.  Printed as one JSON line, with
+  roofline      the fused SpMV + dot kernel (the dominant kernel of the
+                loop), its algorithmic bytes per launch over its mean
+                launch duration measured with HIP events on its stream;
+  cpu_baseline  the CPU oracle's CG on the same matrix, a bounded sample of
+                iterations on one host core.
+Progress goes to stderr.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def spmv_bytes(fmt, m, nnz, nb, fp=8):
+    """Algorithmic bytes of one SpMV: matrix streamed once, x read once, y
+    written once, int32 indices; for the fused dot p_i is the x entry already
+    read.  CRS: 12 nnz + 4 (m+1) + 16 m; 1x3 BCRS: 28 nb + 4 (m+1) + 16 m."""
+    if fmt == "csr":
+        return (fp + 4) * nnz + 4 * (m + 1) + 2 * fp * m
+    return (3 * fp + 4) * nb + 4 * (m + 1) + 2 * fp * m
+
+
+def time_spmv_dot(P, fmt, reps, torch):
+    """Mean duration of the fused SpMV + dot kernel from HIP event pairs
+    recorded around each launch on the library's stream."""
+    from paper_1505_08023_amd import inputs
+    x = torch.tensor(inputs.spmv_vector(P.m, seed=0), device=P.ctx.device)
+    q = torch.empty_like(x)
+    pq = torch.zeros(1, dtype=torch.float64, device=x.device)
+    pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+    P.spmv_dot(x, q, pq, fmt=fmt)  # warm-up
+    for ev in pairs:
+        P.spmv_dot(x, q, pq, fmt=fmt, events=ev)
+    P.ctx.stream.synchronize()
+    ms = [a.elapsed_time(b) for a, b in pairs]
+    return sum(ms) / len(ms), min(ms)
+
+
+def cpu_baseline(N, its=(2, 8)):
+    """Oracle CG on the host: iterations its[1]-its[0] timed as the
+    difference of two capped runs (assembly untimed)."""
+    import oracle
+    t = time.perf_counter()
+    A = oracle.assemble(N, N, N)
+    log(f"[bench] oracle assembly {N}^3: {time.perf_counter() - t:.1f} s")
+    times = []
+    for k in its:
+        t = time.perf_counter()
+        oracle.cg(A, tol=1e-8, max_iter=k)
+        times.append(time.perf_counter() - t)
+    dt = times[1] - times[0]
+    n = its[1] - its[0]
+    return dict(value=n / dt, unit="CG iter/s", cores=1, kind="oracle",
+                sample=f"{N}^3 FP64 CRS oracle CG, {n} iterations timed as cg(max_iter={its[1]}) minus "
+                       f"cg(max_iter={its[0]}) on one host core; assembly untimed")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=256, help="elements per axis")
+    ap.add_argument("--fmt", default="bcrs13", choices=["bcrs13", "csr"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--max-iter", type=int, default=20000)
+    ap.add_argument("--spmv-reps", type=int, default=20)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
+              "this build has no multi-GPU path", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1505_08023_amd.mfe import Context, Problem
+
+    N = args.n
+    ctx = Context(0)
+    t = time.perf_counter()
+    P = Problem.mesh(ctx, N, N, N, formats=("csr", "bcrs13"))
+    log(f"[bench] assembled {N}^3 on the GPU (m={P.m}, nnz={P.nnz}, 1x3 blocks={P.nblocks}) "
+        f"in {time.perf_counter() - t:.2f} s")
+    x = torch.zeros(P.m, dtype=torch.float64, device=ctx.device)
+
+    def solve():
+        with torch.cuda.stream(ctx.stream):
+            x.zero_()
+        return P.cg(x, tol=args.tol, max_iter=args.max_iter, fmt=args.fmt)[1]
+
+    for _ in range(args.warmup):
+        st = solve()
+        log(f"[bench] warm-up solve: {st['iterations']} its, {st['seconds']:.3f} s")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stats = [solve() for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    its = sum(s["iterations"] for s in stats)
+    log(f"[bench] {args.steps} timed solves: {its} its in {elapsed:.3f} s")
+
+    # dominant kernel: fused SpMV + dot, both formats
+    spmv = {}
+    for fmt in ("bcrs13", "csr"):
+        mean_ms, min_ms = time_spmv_dot(P, fmt, args.spmv_reps, torch)
+        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks)
+        spmv[fmt] = dict(mean_ms=mean_ms, min_ms=min_ms, bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
+                         frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        log(f"[bench] spmv_dot {fmt}: {mean_ms:.4f} ms, {spmv[fmt]['GBps']:.0f} GB/s")
+    dom = spmv[args.fmt]
+    vec_bytes = 64 * P.m
+    it_bytes = dom["bytes"] + vec_bytes
+
+    line = {
+        "metric": METRIC,
+        "value": its / elapsed,
+        "unit": "CG iter/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"minife_heat_{N}cubed_fp64_cg_{args.fmt}", "mesh": [N, N, N],
+                   "rows": P.m, "nnz": P.nnz, "blocks_1x3": P.nblocks, "format": args.fmt,
+                   "tol": args.tol, "x0": "zero", "step": "one CG solve to tol"},
+        "roofline": {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": f"k_spmv_{'b13' if args.fmt == 'bcrs13' else 'csr'}<double, dot>",
+                     "bytes_per_launch": dom["bytes"], "mean_launch_ms": dom["mean_ms"]},
+        "cg": {"iterations_per_solve": stats[-1]["iterations"], "time_to_tol_s": elapsed / args.steps,
+               "rel_res_true": stats[-1]["rel_res_true"], "status": stats[-1]["status"],
+               "bytes_per_iteration": it_bytes,
+               "effective_GBps": its / elapsed * it_bytes / 1e9},
+        "spmv": spmv,
+    }
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (bounded sample) ...")
+        line["cpu_baseline"] = cpu_baseline(N)
+        log(f"[bench] oracle {line['cpu_baseline']['value']:.3f} it/s")
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

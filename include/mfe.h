@@ -1,0 +1,179 @@
+/*
+ * mfe.h -- C ABI of the MI355X (gfx950) library for the MiniFE-style
+ * finite-element method of Wu, Yang, Xiang and Cheng, "The Research and
+ * Optimization of Parallel Finite Element Algorithm based on MiniFE".
+ *
+ * The library generates the Nx x Ny x Nz hexahedral box mesh of the unit
+ * cube, assembles the trilinear element equations of steady heat conduction
+ * with Dirichlet faces (Sec. 1: u = 1 on x = 1, u = 0 on the other faces by
+ * default), stores the matrix in CRS (Sec. 3.1, Fig 3.1) and in fixed 1x3
+ * BCRS (the segment format of Sec. 3.1, Figs 3.2/3.3, with the segment
+ * length fixed to 3 and zero padding), and solves it with unpreconditioned
+ * conjugate gradient (Sec. 1, CG module: MATVEC, DOT, WAXPY).
+ *
+ * Conventions for every entry point
+ *   - Return value: MFE_OK (0), MFE_NOT_CONVERGED (1, results valid, the
+ *     iteration cap was reached) or a negative error code.  No function
+ *     throws or aborts.  mfe_last_error() gives a message for the calling
+ *     thread's last failure.
+ *   - Pointers named *_dev are device pointers (HIP global memory of the
+ *     context's device); all other pointers are host pointers.  Vectors are
+ *     dense, contiguous, of length m (rows) unless stated otherwise.
+ *   - Caller-owned: every pointer argument.  Library-owned: the context and
+ *     problem objects and the matrix/format/workspace storage behind them,
+ *     released by the matching *_destroy call.
+ *   - Work is enqueued on the context's stream.  Calls that return results
+ *     on the host (stats, info, dot values) synchronise that stream first;
+ *     the others return without synchronising.
+ *   - Mesh numbering: node (ix, iy, iz), 0 <= ix <= Nx, ..., has id
+ *     ix + (Nx+1)*(iy + (Ny+1)*iz) (x fastest) and coordinates
+ *     (ix/Nx, iy/Ny, iz/Nz).  Matrix rows are nodes, all of them: Dirichlet
+ *     rows are identity rows and Dirichlet columns of free rows are zeroed
+ *     (symmetric elimination); structural zeros stay stored, so every row
+ *     holds its full in-range 27-point neighbourhood in ascending column
+ *     order, nnz = (3Nx+1)(3Ny+1)(3Nz+1).
+ */
+#ifndef MFE_H
+#define MFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define MFE_OK 0
+#define MFE_NOT_CONVERGED 1
+#define MFE_EINVAL (-1)        /* bad argument (null pointer, size, flag) */
+#define MFE_ENOMEM (-2)        /* device allocation failed */
+#define MFE_EHIP (-3)          /* a HIP runtime call failed */
+#define MFE_EBREAKDOWN (-4)    /* CG met p.Ap <= 0 or a non-finite value */
+#define MFE_EUNSUPPORTED (-5)  /* size beyond 32-bit indexing, or format/precision not built */
+
+/* matrix formats (bit flags) */
+#define MFE_CSR 1      /* compressed row storage, Sec. 3.1 */
+#define MFE_BCRS13 2   /* fixed 1x3 blocks, zero padded, 64-row slice-major layout */
+
+/* precisions (bit flags) */
+#define MFE_F64 1
+#define MFE_F32 2
+
+typedef struct mfe_ctx mfe_ctx;
+typedef struct mfe_problem mfe_problem;
+
+/* Optional device allocator.  alloc returns a device pointer aligned to at
+ * least 256 bytes, or NULL; free releases it.  With NULL callbacks the
+ * library uses hipMalloc / hipFree. */
+typedef void *(*mfe_alloc_fn)(size_t bytes, void *user);
+typedef void (*mfe_free_fn)(void *ptr, void *user);
+
+typedef struct mfe_cg_stats {
+    int32_t status;            /* MFE_OK, MFE_NOT_CONVERGED or MFE_EBREAKDOWN */
+    int32_t iterations;        /* SpMVs inside the CG loop (mixed: summed over inner solves) */
+    int32_t outer;             /* mixed precision: refinement steps; else 0 */
+    int32_t spmv_count;        /* all SpMVs issued, including residual evaluations */
+    double rel_res_recurrence; /* sqrt(r.r)/||b|| of the recurrence residual at exit */
+    double rel_res_true;       /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
+    double seconds;            /* host wall time of the call */
+} mfe_cg_stats;
+
+/* Message for the calling thread's last error ("" if none). */
+const char *mfe_last_error(void);
+
+/* ABI version, bumped on any change of these declarations. */
+int mfe_version(void);
+
+/* Create a context on HIP device `device`.  `stream` is a hipStream_t (NULL =
+ * the null stream) on which all work of this context is enqueued.  The
+ * allocator pair may be NULL.  *out receives the context. */
+int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn,
+                   void *alloc_user, mfe_ctx **out);
+/* Synchronises the stream and destroys the context together with every
+ * problem still attached to it (their handles become invalid). */
+int mfe_ctx_destroy(mfe_ctx *ctx);
+
+/* Problem statement and assembly (Sec. 1; Fig 3.6 structure, Fig 3.7
+ * element assembly).  Nx, Ny, Nz >= 1 elements per axis.  Boundary values:
+ * node_g_dev (device, length m, only boundary entries read) if non-NULL,
+ * else face_vals[6] = {x=0, x=1, y=0, y=1, z=0, z=1} if non-NULL, else the
+ * paper's {0, 1, 0, 0, 0, 0}.  A node on several faces takes the first face
+ * in the order x=1, x=0, y=1, y=0, z=1, z=0.  Zero source.
+ * `formats` (MFE_CSR | MFE_BCRS13) and `precisions` (MFE_F64 | MFE_F32)
+ * select which stored forms are built (CSR FP64 is always built: it is the
+ * assembly format).  Fails with MFE_EUNSUPPORTED when nnz >= 2^31. */
+int mfe_problem_create(mfe_ctx *ctx, int Nx, int Ny, int Nz, const double *face_vals,
+                       const double *node_g_dev, int formats, int precisions, mfe_problem **out);
+
+/* Generic CRS problem (Sec. 3.1): copies ptr_dev[m+1], col_dev[nnz] (ascending,
+ * distinct, in [0,m) per row), val_dev[nnz], b_dev[m] (b_dev may be NULL: b = 0).
+ * Rows may be empty.  Intended for symmetric positive definite A. */
+int mfe_problem_from_csr(mfe_ctx *ctx, int64_t m, const int32_t *ptr_dev, const int32_t *col_dev,
+                         const double *val_dev, const double *b_dev, int formats, int precisions,
+                         mfe_problem **out);
+
+/* Re-impose new Dirichlet data on a mesh problem without re-assembling:
+ * recomputes b (same rules as mfe_problem_create).  MFE_EINVAL for a problem
+ * made by mfe_problem_from_csr. */
+int mfe_problem_set_bc(mfe_problem *p, const double *face_vals, const double *node_g_dev);
+
+/* Sizes: rows, stored entries, 1x3 blocks (0 when BCRS13 was not built).
+ * Any output pointer may be NULL. */
+int mfe_problem_info(const mfe_problem *p, int64_t *m, int64_t *nnz, int64_t *nblocks);
+
+/* Copy the FP64 CRS matrix and b into caller device buffers
+ * (ptr_dev[m+1], col_dev[nnz], val_dev[nnz], b_dev[m]; any may be NULL). */
+int mfe_problem_export_csr(const mfe_problem *p, int32_t *ptr_dev, int32_t *col_dev,
+                           double *val_dev, double *b_dev);
+
+/* Copy the 1x3 BCRS as per-row block lists: bptr_dev[m+1] (first block of
+ * each row, bptr[m] = nblocks), bcol_dev[nblocks] (first column of each
+ * block), bval_dev[3*nblocks] (FP64).  Padding slots of the slice layout
+ * are dropped; blocks keep their per-row order. */
+int mfe_problem_export_bcrs13(const mfe_problem *p, int32_t *bptr_dev, int32_t *bcol_dev,
+                              double *bval_dev);
+
+int mfe_problem_destroy(mfe_problem *p);
+
+/* y = A x (Sec. 3.1 MATVEC; Fig 3.1 for MFE_CSR, the 1x3 segment loop of
+ * Figs 3.2/3.3 for MFE_BCRS13).  FP64 values and vectors, FP64 sums.
+ * x_dev and y_dev must not overlap. */
+int mfe_spmv(const mfe_problem *p, int format, const double *x_dev, double *y_dev);
+
+/* FP32 values and vectors, FP32 sums (needs MFE_F32 at create). */
+int mfe_spmv_f32(const mfe_problem *p, int format, const float *x_dev, float *y_dev);
+
+/* q = A p fused with the DOT that follows MATVEC in CG (Sec. 1 CG module;
+ * Sec. 3.1 on the dot product after SpMV): writes q_dev and the FP64 value
+ * p.q to *pq_dev (a device scalar), reduced in a fixed order.  FP64.  The
+ * kernel is the one each CG iteration runs; this entry point exists to use
+ * and time it on its own.  ev_before / ev_after (hipEvent_t, may be NULL)
+ * are recorded on the context's stream immediately before and after that
+ * kernel's launch.  Does not synchronise. */
+int mfe_spmv_dot(const mfe_problem *p, int format, const double *p_dev, double *q_dev, double *pq_dev,
+                 void *ev_before, void *ev_after);
+
+/* Dot product (Sec. 1, DOT) of two FP64 device vectors of length n >= 0
+ * (x_dev, y_dev may be NULL when n = 0),
+ * reduced in a fixed order (bitwise reproducible run to run).  The result is
+ * written to *out_host (the stream is synchronised). */
+int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, double *out_host);
+
+/* Unpreconditioned CG (Sec. 1 CG module) on A x = b in FP64, with the
+ * SpMV of `format` (MFE_CSR or MFE_BCRS13, which must have been built).
+ * x_dev holds x0 on entry and the solution on exit.  r0 = b - A x0; the loop
+ * stops when the recurrence residual satisfies ||r_k||_2 / ||b||_2 <= tol
+ * (k = number of SpMVs in the loop) or after max_iter iterations; b = 0
+ * gives x = 0.  tol >= 0, max_iter >= 0.  hist_dev (may be NULL) receives
+ * ||r_k||/||b|| for k = 0..iterations (room for max_iter+1 doubles).  stats
+ * may be NULL.  Returns MFE_OK, MFE_NOT_CONVERGED or MFE_EBREAKDOWN (x then
+ * holds the last iterate).  Calls on one problem must not overlap. */
+int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
+           double *hist_dev, mfe_cg_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MFE_H */

@@ -44,6 +44,9 @@ def lib():
         L.orc_assemble.restype = _c_int
         L.orc_assemble.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _c_int,
                                                   _i64p, _i32p, _f64p, _f64p]
+        L.orc_assemble_rows.restype = _c_int
+        L.orc_assemble_rows.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _c_i64, _i64p,
+                                                       _i32p, _f64p, _i32p, _f64p]
         L.orc_csr_spmv.restype = None
         L.orc_csr_spmv.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p]
         L.orc_bcrsvar_count.restype = _c_i64
@@ -142,6 +145,24 @@ def assemble(Nx, Ny, Nz, face_vals=None, node_g=None, apply_bc=True):
     if st != OK:
         raise ValueError(f"orc_assemble failed with status {st}")
     return CSR(ptr, col, val, b)
+
+
+def assemble_rows(Nx, Ny, Nz, rows, face_vals=None, node_g=None):
+    """Selected rows of the assembled system, built one at a time (same
+    arithmetic as assemble()).  Returns a list of (cols, vals) and b[rows]."""
+    rows = np.ascontiguousarray(rows, np.int64)
+    n = len(rows)
+    cols = np.zeros(27 * n, np.int32)
+    vals = np.zeros(27 * n, np.float64)
+    cnt = np.zeros(n, np.int32)
+    b = np.zeros(n, np.float64)
+    fv, fvp = _opt(face_vals, np.float64)
+    ng, ngp = _opt(node_g, np.float64)
+    st = lib().orc_assemble_rows(Nx, Ny, Nz, fvp, ngp, n, rows, cols, vals, cnt, b)
+    if st != OK:
+        raise ValueError(f"orc_assemble_rows failed with status {st}")
+    out = [(cols[27 * r:27 * r + cnt[r]].copy(), vals[27 * r:27 * r + cnt[r]].copy()) for r in range(n)]
+    return out, b
 
 
 def csr_spmv(A, x):

@@ -67,31 +67,40 @@ static int64_t node_id(int Nx, int Ny, int Nz, int ix, int iy, int iz)
     return (int64_t)ix + (int64_t)(Nx + 1) * ((int64_t)iy + (int64_t)(Ny + 1) * iz);
 }
 
-/* Boundary flag and value of every node.  face_vals = {x0,x1,y0,y1,z0,z1};
- * NULL means the paper's problem {0,1,0,0,0,0}.  When node_g is given, the
- * value of a boundary node is node_g[id] instead (face_vals then unused). */
-void orc_boundary(int Nx, int Ny, int Nz, const double *face_vals,
-                  const double *node_g, uint8_t *is_dir, double *g)
+/* Boundary value of node (ix,iy,iz): returns 1 and sets *g for a boundary
+ * node, 0 for an interior node.  face_vals = {x0,x1,y0,y1,z0,z1}; NULL means
+ * the paper's problem {0,1,0,0,0,0}.  When node_g is given, the value of a
+ * boundary node is node_g[id] instead (face_vals then unused). */
+static int boundary_of(int Nx, int Ny, int Nz, const double *face_vals, const double *node_g,
+                       int ix, int iy, int iz, double *g)
 {
     static const double paper_faces[6] = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
     const double *f = face_vals ? face_vals : paper_faces;
+    double v;
+    /* first face in the order x=1, x=0, y=1, y=0, z=1, z=0 */
+    if (ix == Nx) v = f[1];
+    else if (ix == 0) v = f[0];
+    else if (iy == Ny) v = f[3];
+    else if (iy == 0) v = f[2];
+    else if (iz == Nz) v = f[5];
+    else if (iz == 0) v = f[4];
+    else return 0;
+    if (node_g) v = node_g[node_id(Nx, Ny, Nz, ix, iy, iz)];
+    *g = v;
+    return 1;
+}
+
+/* Boundary flag and value of every node (g = 0 for interior nodes). */
+void orc_boundary(int Nx, int Ny, int Nz, const double *face_vals,
+                  const double *node_g, uint8_t *is_dir, double *g)
+{
     for (int iz = 0; iz <= Nz; ++iz)
         for (int iy = 0; iy <= Ny; ++iy)
             for (int ix = 0; ix <= Nx; ++ix) {
                 int64_t id = node_id(Nx, Ny, Nz, ix, iy, iz);
                 double v = 0.0;
-                int dir = 1;
-                /* first face in the order x=1, x=0, y=1, y=0, z=1, z=0 */
-                if (ix == Nx) v = f[1];
-                else if (ix == 0) v = f[0];
-                else if (iy == Ny) v = f[3];
-                else if (iy == 0) v = f[2];
-                else if (iz == Nz) v = f[5];
-                else if (iz == 0) v = f[4];
-                else dir = 0;
-                if (dir && node_g) v = node_g[id];
-                is_dir[id] = (uint8_t)dir;
-                g[id] = dir ? v : 0.0;
+                is_dir[id] = (uint8_t)boundary_of(Nx, Ny, Nz, face_vals, node_g, ix, iy, iz, &v);
+                g[id] = v;
             }
 }
 
@@ -230,6 +239,64 @@ int orc_assemble(int Nx, int Ny, int Nz, const double *face_vals, const double *
     }
     free(dir);
     free(g);
+    return ORC_OK;
+}
+
+/* Selected rows of the same assembled system, one at a time, for checks on
+ * meshes too large to assemble whole.  Row i is built exactly as in
+ * orc_assemble: element contributions in ascending element order, then the
+ * Dirichlet elimination of that row.  For rows[r], cols/vals[27*r ..] get the
+ * row's entries in ascending column order, counts[r] their number, b[r] the
+ * right-hand side. */
+int orc_assemble_rows(int Nx, int Ny, int Nz, const double *face_vals, const double *node_g,
+                      int64_t nrows, const int64_t *rows, int32_t *cols, double *vals,
+                      int32_t *counts, double *b)
+{
+    if (Nx < 1 || Ny < 1 || Nz < 1) return ORC_EINVAL;
+    const int64_t m = orc_num_rows(Nx, Ny, Nz);
+    double K[64];
+    orc_element_matrix(1.0 / Nx, 1.0 / Ny, 1.0 / Nz, K);
+    for (int64_t r = 0; r < nrows; ++r) {
+        int64_t i = rows[r];
+        if (i < 0 || i >= m) return ORC_EINVAL;
+        int ix = (int)(i % (Nx + 1)), iy = (int)((i / (Nx + 1)) % (Ny + 1));
+        int iz = (int)(i / ((int64_t)(Nx + 1) * (Ny + 1)));
+        int32_t *c = cols + 27 * r;
+        double *v = vals + 27 * r;
+        int n = 0;
+        for (int sz = -1; sz <= 1; ++sz)          /* structure: Fig 3.6 loop */
+            for (int sy = -1; sy <= 1; ++sy)
+                for (int sx = -1; sx <= 1; ++sx) {
+                    int64_t j = node_id(Nx, Ny, Nz, ix + sx, iy + sy, iz + sz);
+                    if (j >= 0) { c[n] = (int32_t)j; v[n] = 0.0; ++n; }
+                }
+        counts[r] = n;
+        for (int ez = iz - 1; ez <= iz; ++ez)     /* elements holding node i, ascending id */
+            for (int ey = iy - 1; ey <= iy; ++ey)
+                for (int ex = ix - 1; ex <= ix; ++ex) {
+                    if (ex < 0 || ex >= Nx || ey < 0 || ey >= Ny || ez < 0 || ez >= Nz) continue;
+                    int a = (ix - ex) + 2 * (iy - ey) + 4 * (iz - ez);
+                    for (int bb = 0; bb < 8; ++bb) {
+                        int64_t j = node_id(Nx, Ny, Nz, ex + (bb & 1), ey + ((bb >> 1) & 1), ez + ((bb >> 2) & 1));
+                        for (int k = 0; k < n; ++k)
+                            if (c[k] == j) { v[k] += K[a * 8 + bb]; break; }
+                    }
+                }
+        double gi, bi = 0.0;
+        if (boundary_of(Nx, Ny, Nz, face_vals, node_g, ix, iy, iz, &gi)) {
+            for (int k = 0; k < n; ++k) v[k] = (c[k] == i) ? 1.0 : 0.0;
+            bi = gi;
+        } else {
+            for (int k = 0; k < n; ++k) {
+                int64_t j = c[k];
+                int jx = (int)(j % (Nx + 1)), jy = (int)((j / (Nx + 1)) % (Ny + 1));
+                int jz = (int)(j / ((int64_t)(Nx + 1) * (Ny + 1)));
+                double gj;
+                if (boundary_of(Nx, Ny, Nz, face_vals, node_g, jx, jy, jz, &gj)) { bi -= v[k] * gj; v[k] = 0.0; }
+            }
+        }
+        b[r] = bi;
+    }
     return ORC_OK;
 }
 

@@ -1,0 +1,201 @@
+// Unpreconditioned CG driver (Sec. 1 CG module).
+//
+// The paper's CG loop is MATVEC, DOT with a global reduction, and WAXPY, each
+// iteration ending in a synchronisation of all processes for the dot
+// products.  Here one iteration is three kernels, all scalars stay in device
+// memory, and the host never waits per iteration:
+//   spmv_dot  : q = A p, p.q, alpha = rho / p.q          (last workgroup)
+//   update_r  : r -= alpha q, rho_new = r.r, stop test, beta (last workgroup)
+//   update_xp : x += alpha p, p = r + beta p
+// K iterations are captured once into a HIP graph and replayed.  The host
+// keeps one graph ahead and polls a pinned copy of the solver state after
+// each; once the state leaves "running" every kernel returns at entry, so
+// the speculative graph changes nothing.
+#include <chrono>
+#include <cmath>
+#include <vector>
+
+#include "common.hpp"
+
+struct mfe_graph_cache {
+    struct Entry {
+        int format;
+        bool f32;
+        const void *x;
+        int k;
+        hipGraphExec_t exec;
+    };
+    std::vector<Entry> entries;
+};
+
+namespace mfe {
+namespace {
+
+constexpr int kGraphIters = 16;  // CG iterations per captured graph
+
+int ensure_workspace(mfe_problem *P) {
+    mfe_ctx *ctx = P->ctx;
+    const size_t vb = (size_t)P->m * sizeof(double);
+    if (!P->r.ptr) MFE_TRY(dev_alloc(ctx, &P->r, vb));
+    if (!P->p.ptr) MFE_TRY(dev_alloc(ctx, &P->p, vb));
+    if (!P->q.ptr) MFE_TRY(dev_alloc(ctx, &P->q, vb));
+    if (!P->state.ptr) {
+        MFE_TRY(dev_alloc(ctx, &P->state, sizeof(CgState)));
+        MFE_HIP_TRY(hipMemsetAsync(P->state.ptr, 0, sizeof(CgState), ctx->stream));
+    }
+    if (!P->partials.ptr) MFE_TRY(dev_alloc(ctx, &P->partials, 2 * kMaxPartials * sizeof(double)));
+    if (!P->graphs) P->graphs = new mfe_graph_cache();
+    return MFE_OK;
+}
+
+// Capture k CG iterations on the context's private capture stream.
+int capture(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, int k,
+            hipGraphExec_t *out) {
+    hipStream_t cs = P->ctx->cap_stream;
+    CgState *st = (CgState *)P->state.ptr;
+    double *partials = (double *)P->partials.ptr;
+    MFE_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = MFE_OK;
+    for (int i = 0; i < k && rc == MFE_OK; ++i) {
+        SpmvArgs a{p, q, nullptr, nullptr, st, partials};
+        rc = launch_spmv(P, format, f32, kSpmvDot, a, cs);
+        if (rc == MFE_OK) rc = launch_update_r(P, f32, r, q, st, partials, cs);
+        if (rc == MFE_OK) rc = launch_update_xp(P, f32, x, p, r, st, cs);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != MFE_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (e != hipSuccess) {
+        set_error(std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
+        return MFE_EHIP;
+    }
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        set_error(std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e2));
+        return MFE_EHIP;
+    }
+    return MFE_OK;
+}
+
+int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, int k,
+              hipGraphExec_t *out) {
+    for (auto &e : P->graphs->entries)
+        if (e.format == format && e.f32 == f32 && e.x == x && e.k == k) {
+            *out = e.exec;
+            return MFE_OK;
+        }
+    hipGraphExec_t ex = nullptr;
+    MFE_TRY(capture(P, format, f32, x, r, p, q, k, &ex));
+    P->graphs->entries.push_back({format, f32, x, k, ex});
+    *out = ex;
+    return MFE_OK;
+}
+
+}  // namespace
+
+void release_graphs(mfe_problem *P) {
+    if (!P->graphs) return;
+    for (auto &e : P->graphs->entries) (void)hipGraphExecDestroy(e.exec);
+    delete P->graphs;
+    P->graphs = nullptr;
+}
+
+// Replay the iteration graph until the device state stops running.  On
+// return *fin holds the final state.
+int run_iterations(mfe_problem *P, hipGraphExec_t exec, int k, int max_iter, CgState *fin) {
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    CgState *pin = (CgState *)ctx->pinned;
+    const CgState *st = (const CgState *)P->state.ptr;
+    const long limit = (long)max_iter / k + 3;  // the device cap ends the loop well before this
+    long launched = 0;
+    int slot = 0;
+    MFE_HIP_TRY(hipGraphLaunch(exec, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipEventRecord(ctx->ev[0], s));
+    launched = 1;
+    for (;;) {
+        const int nxt = slot ^ 1;
+        const bool more = launched < limit;
+        if (more) {
+            MFE_HIP_TRY(hipGraphLaunch(exec, s));
+            MFE_HIP_TRY(hipMemcpyAsync(&pin[nxt], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            MFE_HIP_TRY(hipEventRecord(ctx->ev[nxt], s));
+            ++launched;
+        }
+        MFE_HIP_TRY(hipEventSynchronize(ctx->ev[slot]));
+        if (pin[slot].status != kRunning) {
+            if (more) MFE_HIP_TRY(hipEventSynchronize(ctx->ev[nxt]));
+            *fin = pin[slot];
+            return MFE_OK;
+        }
+        if (!more) {
+            set_error("CG state still running after the iteration cap");
+            return MFE_EHIP;
+        }
+        slot = nxt;
+    }
+}
+
+int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist,
+             mfe_cg_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    MFE_TRY(ensure_workspace(P));
+    CgState *st = (CgState *)P->state.ptr;
+    double *partials = (double *)P->partials.ptr;
+    CgState *pin = (CgState *)ctx->pinned;
+
+    // initial state
+    CgState h{};
+    h.tol = tol;
+    h.max_iter = max_iter;
+    h.hist = hist;
+    h.status = kRunning;
+    pin[2] = h;
+    MFE_HIP_TRY(hipMemcpyAsync(st, &pin[2], sizeof(CgState), hipMemcpyHostToDevice, s));
+    // r = b - A x0, p = r, rho, ||b||, start test
+    SpmvArgs a0{x, P->r.ptr, P->p.ptr, (const double *)P->b.ptr, st, partials};
+    MFE_TRY(launch_spmv(P, format, false, kSpmvResid, a0, s));
+    MFE_TRY(launch_zero_if(P->m, x, st, ctx->num_cu, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    CgState fin = pin[0];
+    int spmvs = 1;
+    if (fin.status == kRunning) {
+        const int k = kGraphIters < max_iter ? kGraphIters : max_iter;
+        hipGraphExec_t exec = nullptr;
+        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, k, &exec));
+        MFE_TRY(run_iterations(P, exec, k, max_iter, &fin));
+        spmvs += fin.iters + (fin.status == kBreakdown ? 1 : 0);
+    }
+    // true residual ||b - A x|| in FP64
+    SpmvArgs a1{x, nullptr, nullptr, (const double *)P->b.ptr, st, partials};
+    MFE_TRY(launch_spmv(P, format, false, kSpmvTrue, a1, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    ++spmvs;
+    const double rr_true = pin[0].rr_true;
+    const double bn = fin.bnorm;
+    int rc = MFE_OK;
+    if (fin.status == kCapped) rc = MFE_NOT_CONVERGED;
+    else if (fin.status == kBreakdown) rc = MFE_EBREAKDOWN;
+    if (stats) {
+        stats->status = rc;
+        stats->iterations = fin.iters;
+        stats->outer = 0;
+        stats->spmv_count = spmvs;
+        stats->rel_res_recurrence = bn > 0.0 ? std::sqrt(fin.rho) / bn : 0.0;
+        stats->rel_res_true = bn > 0.0 ? std::sqrt(rr_true) / bn : 0.0;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+    if (rc == MFE_EBREAKDOWN) set_error("CG breakdown: p.Ap <= 0 or not finite");
+    return rc;
+}
+
+}  // namespace mfe

@@ -1,0 +1,194 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mfe.h"
+
+namespace mfe {
+
+// ------------------------------------------------------------------ errors
+
+void set_error(const std::string &msg);
+void clear_error();
+
+#define MFE_HIP_TRY(expr)                                                         \
+    do {                                                                          \
+        hipError_t e_ = (expr);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::mfe::set_error(std::string(#expr " failed: ") + hipGetErrorString(e_)); \
+            return MFE_EHIP;                                                      \
+        }                                                                         \
+    } while (0)
+
+#define MFE_TRY(expr)            \
+    do {                         \
+        int s_ = (expr);         \
+        if (s_ != MFE_OK) return s_; \
+    } while (0)
+
+// ------------------------------------------------------------------ launch geometry
+
+constexpr int kBlock = 256;     // threads per workgroup for every streaming kernel
+constexpr int kSlice = 64;      // rows per slice of the 1x3 BCRS layout (one wavefront)
+constexpr int kNumXcd = 8;      // accelerator complex dies of an MI355X
+constexpr int kMaxPartials = 4096;  // per-workgroup partial sums one reduction may hold
+constexpr int kPinnedSlots = 4;     // pinned CgState slots per context
+
+// ------------------------------------------------------------------ device solver state
+
+enum CgStatus : int { kRunning = 0, kConverged = 1, kCapped = 2, kBreakdown = -4 };
+
+// One per solve (one per system in a batched solve).  Lives in device memory;
+// every scalar the CG recurrences need stays on the device.
+struct CgState {
+    double rho;       // r.r of the current residual
+    double alpha;     // rho / p.q of the current iteration
+    double beta;      // rho_new / rho
+    double bnorm;     // ||b||_2
+    double tol;       // relative tolerance on ||r||/||b||
+    double pq;        // last p.q
+    double rr_true;   // ||b - A x||^2 evaluated at exit
+    double scale;     // mixed precision: ||r|| of the outer residual
+    double *hist;     // optional: hist[k] = ||r_k||/||b||, k = 0..max_iter
+    double *dot_out;  // optional: the fused SpMV's p.q is also written here
+    int status;       // CgStatus
+    int iters;        // completed iterations
+    int max_iter;
+    int xpending;     // set when the x/p update of the current iteration is due
+    int zero_x;       // b = 0: the solution is x = 0
+    int pad_;
+    unsigned int counter[4];  // arrival counters of the last-workgroup reductions (0 when idle)
+};
+
+// ------------------------------------------------------------------ matrix views
+
+struct CsrView {
+    int64_t m;
+    const int32_t *ptr;
+    const int32_t *col;
+    const void *val;  // double or float
+};
+
+// 1x3 BCRS in 64-row slices.  Slice s owns slot rows slot_base[s] ..
+// slot_base[s+1]-1; in slot row k, lane l (row 64 s + l) has its block's
+// first column at jas[64 k + l] and its three values at val[(3 k + j) 64 + l].
+struct B13View {
+    int64_t m;
+    int64_t nslices;
+    const int32_t *slot_base;  // [nslices + 1]
+    const int32_t *jas;        // [64 * nslots]
+    const void *val;           // [3 * 64 * nslots], double or float
+};
+
+// ------------------------------------------------------------------ context / problem
+
+struct Buffer {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+}  // namespace mfe
+
+struct mfe_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;      // caller's stream: all work goes here
+    hipStream_t cap_stream = nullptr;  // private stream used only to capture graphs
+    mfe_alloc_fn alloc = nullptr;
+    mfe_free_fn free_fn = nullptr;
+    void *alloc_user = nullptr;
+    int num_cu = 256;
+    void *pinned = nullptr;  // pinned host slots (kPinnedSlots x CgState) for solver state
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    mfe::Buffer scratch;     // reduction partials for mfe_dot
+    mfe::Buffer dot_state;   // CgState used by mfe_dot
+    mfe::Buffer spmv_dot_state;  // CgState used by mfe_spmv_dot
+    std::vector<mfe_problem *> problems;  // live problems, destroyed with the context
+};
+
+namespace mfe {
+
+int dev_alloc(mfe_ctx *ctx, Buffer *b, size_t bytes);
+void dev_free(mfe_ctx *ctx, Buffer *b);
+
+}  // namespace mfe
+
+struct mfe_graph_cache;
+
+struct mfe_problem {
+    mfe_ctx *ctx = nullptr;
+    bool is_mesh = false;
+    int Nx = 0, Ny = 0, Nz = 0;
+    int64_t m = 0, nnz = 0, nblocks = 0, nslots = 0;
+    int formats = 0, precisions = 0;
+    // CRS (always FP64; FP32 values when MFE_F32)
+    mfe::Buffer ptr, col, val64, val32, b;
+    // 1x3 BCRS
+    mfe::Buffer slot_base, jas, bval64, bval32, rowblocks;
+    // CG workspace (allocated on first solve)
+    mfe::Buffer r, p, q, state, partials;
+    mfe::Buffer r32, p32, q32, d32, ax;  // mixed precision workspace
+    mfe_graph_cache *graphs = nullptr;
+};
+
+namespace mfe {
+
+// ------------------------------------------------------------------ kernel launchers (host)
+
+// assembly (assemble.hip)
+int launch_assemble(mfe_problem *P, const double *face_vals, const double *node_g, bool values_and_rhs,
+                    bool rhs_only);
+
+// formats (formats.hip)
+int build_bcrs13(mfe_problem *P);
+int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const int32_t *col);
+int cast_values_f32(mfe_problem *P);
+int export_bcrs13(const mfe_problem *P, int32_t *bptr, int32_t *bcol, double *bval);
+
+// SpMV modes
+enum SpmvMode : int {
+    kSpmvPlain = 0,   // y = A x
+    kSpmvDot = 1,     // y = A x, partial x.y, last workgroup: alpha = rho / (x.y)
+    kSpmvResid = 2,   // r = b - A x, p = r, partials r.r and b.b, last workgroup: CG start
+    kSpmvTrue = 3,    // partial ||b - A x||^2, last workgroup: state->rr_true
+};
+
+struct SpmvArgs {
+    const void *x;
+    void *y;         // y (plain/dot) or r (resid)
+    void *p_out;     // resid: p = r (may be null)
+    const double *b; // resid/true
+    CgState *st;
+    double *partials;
+};
+
+int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const SpmvArgs &a,
+                hipStream_t s);
+
+// CG driver (cg.hip)
+int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st);
+void release_graphs(mfe_problem *P);
+
+// vector kernels (vector.hip)
+int launch_update_r(const mfe_problem *P, bool f32, void *r, const void *q, CgState *st, double *partials,
+                    hipStream_t s);
+int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const void *r, CgState *st,
+                     hipStream_t s);
+int launch_state_reset(CgState *st, double *dot_out, hipStream_t s);
+int launch_zero_if(int64_t m, double *x, const CgState *st, int num_cu, hipStream_t s);
+int launch_dot(mfe_ctx *ctx, int64_t n, const double *x, const double *y, double *partials, CgState *st,
+               hipStream_t s);
+
+// Grid sizing shared by the launchers.  resident_per_cu: workgroups of
+// kBlock threads of `kernel` that fit on one CU (cached per kernel).
+// resident_grid: min(max_groups, kMaxPartials, ntiles rounded up to a multiple
+// of kNumXcd), itself a multiple of kNumXcd and at least kNumXcd.
+int resident_per_cu(const void *kernel);
+int resident_grid(long max_groups, long ntiles);
+
+}  // namespace mfe

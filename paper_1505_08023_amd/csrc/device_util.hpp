@@ -1,0 +1,96 @@
+// Device helpers: wavefront/workgroup reductions, the last-workgroup
+// arrival test, XCD-aware tile ranges and streaming loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.hpp"
+
+namespace mfe {
+
+// Sum over the 64 lanes of a wavefront by an xor butterfly: every lane ends
+// with the same value, combined in a fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+// Sum over the workgroup (kBlock threads).  Fixed order: lanes, then waves
+// 0..3 in sequence.  Valid in thread 0 only.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double red[kBlock / 64];
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) red[w] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int i = 0; i < kBlock / 64; ++i) s += red[i];
+    }
+    __syncthreads();
+    return s;
+}
+
+// Partials cross workgroups (and XCDs, whose L2s are not coherent with one
+// another), so they are written and read with device-scope atomics.
+__device__ __forceinline__ void put_partial(double *p, int i, double v) {
+    __hip_atomic_store(p + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ double get_partial(const double *p, int i) {
+    return __hip_atomic_load(const_cast<double *>(p) + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Called by every thread of every workgroup after thread 0 stored the
+// workgroup's partial(s).  Returns true in exactly one workgroup: the last to
+// arrive, which then sees every partial.  The counter is back at 0 on return
+// of the last workgroup, ready for the next kernel.
+__device__ __forceinline__ bool arrive_last(unsigned int *counter) {
+    __shared__ int last;
+    if (threadIdx.x == 0) {
+        __threadfence();
+        unsigned int prev =
+            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        last = (prev == gridDim.x - 1);
+        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+    if (last) __threadfence();
+    return last != 0;
+}
+
+// Fixed-order sum of n partials by one workgroup (result in thread 0).
+__device__ __forceinline__ double sum_partials(const double *p, int n) {
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += kBlock) s += get_partial(p, i);
+    return block_sum(s);
+}
+
+// Tile range of this workgroup.  Workgroups are dispatched to the 8 XCDs
+// round-robin (workgroup w runs on XCD w % 8), so XCD k takes the k-th
+// contiguous eighth of the tiles and its workgroups stride through it
+// together: each XCD's L2 then holds only the x entries near its own rows.
+// gridDim.x must be a multiple of kNumXcd.
+struct TileRange {
+    long t, end, step;
+};
+__device__ __forceinline__ TileRange xcd_tiles(long ntiles) {
+    const int xcd = blockIdx.x % kNumXcd;
+    const int lid = blockIdx.x / kNumXcd;
+    const int per = gridDim.x / kNumXcd;
+    TileRange r;
+    r.t = ntiles * xcd / kNumXcd + lid;
+    r.end = ntiles * (xcd + 1) / kNumXcd;
+    r.step = per;
+    return r;
+}
+
+// Matrix streams are read once per product: load them non-temporally so
+// they do not evict the x entries that the gathers reuse.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p) {
+    return __builtin_nontemporal_load(p);
+}
+
+}  // namespace mfe

@@ -1,0 +1,281 @@
+// CRS -> fixed 1x3 BCRS conversion (Sec. 3.1: the matrix is converted at the
+// start of CG; CRS stays the assembly format) and FP32 value copies.
+//
+// The paper's BCRS stores 1xn segments of variable length n with an offsets
+// array and unrolls the segment loop with a switch on n (Figs 3.2, 3.3).  On
+// a GPU the switch becomes divergence, so the segment length is fixed to 3
+// (the length of almost every segment of this matrix) and shorter segments
+// are zero padded: no offsets array, no branch.  Rows are grouped in slices
+// of 64 (one wavefront); inside a slice the k-th block of every row is stored
+// contiguously, so each block load of a wavefront is one coalesced access.
+#include "common.hpp"
+#include "device_util.hpp"
+
+namespace mfe {
+namespace {
+
+// Greedy 1x3 blocking of one CRS row: a block starts at the first stored
+// column not yet covered (moved back to m-3 near the end of the matrix) and
+// covers c, c+1, c+2.  Calls f(block, c, slot values) for every block.
+template <typename F>
+__device__ __forceinline__ int row_blocks(const int32_t *col, const double *val, int32_t lo, int32_t hi,
+                                          int64_t m, F f) {
+    int nb = 0;
+    int32_t k = lo;
+    while (k < hi) {
+        int64_t c = col[k];
+        if (c > m - 3) c = m - 3;
+        double v[3] = {0.0, 0.0, 0.0};
+        while (k < hi && col[k] <= c + 2) {
+            if (val) v[col[k] - c] = val[k];
+            ++k;
+        }
+        f(nb, (int32_t)c, v);
+        ++nb;
+    }
+    return nb;
+}
+
+// Blocks per row, and per slice the maximum over its 64 rows.
+__global__ __launch_bounds__(kBlock) void k_b13_count(int64_t m, const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      int32_t *__restrict__ rowblocks,
+                                                      int32_t *__restrict__ slice_n) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    int nb = 0;
+    if (i < m) {
+        nb = row_blocks(col, nullptr, ptr[i], ptr[i + 1], m, [](int, int32_t, const double *) {});
+        rowblocks[i] = nb;
+    }
+    int mx = nb;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
+    if ((threadIdx.x & 63) == 0 && (i >> 6) * 64 < m) slice_n[i >> 6] = mx;
+}
+
+// Exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total),
+// by a single workgroup of 1024 threads: each thread scans a contiguous
+// chunk, the chunk totals are scanned in LDS, then each chunk is written.
+// scale multiplies every count (e.g. rows per slice).
+__global__ __launch_bounds__(1024) void k_scan1(int64_t n, const int32_t *__restrict__ in,
+                                                int32_t *__restrict__ out, int scale,
+                                                int64_t *__restrict__ total) {
+    __shared__ int64_t sums[1024];
+    const int t = threadIdx.x;
+    const int64_t chunk = (n + 1023) / 1024;
+    const int64_t lo = min(n, t * chunk), hi = min(n, lo + chunk);
+    int64_t s = 0;
+    for (int64_t i = lo; i < hi; ++i) s += (int64_t)in[i] * scale;
+    sums[t] = s;
+    __syncthreads();
+    if (t == 0) {
+        int64_t acc = 0;
+        for (int j = 0; j < 1024; ++j) {
+            int64_t v = sums[j];
+            sums[j] = acc;
+            acc += v;
+        }
+        out[n] = (int32_t)acc;
+        *total = acc;
+    }
+    __syncthreads();
+    int64_t acc = sums[t];
+    for (int64_t i = lo; i < hi; ++i) {
+        out[i] = (int32_t)acc;
+        acc += (int64_t)in[i] * scale;
+    }
+}
+
+// Write every row's blocks into its slice; pad up to the slice's slot count
+// with zero blocks that point at the row's last block column (a valid index
+// whose x entries are already in cache).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_b13_fill(int64_t m, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const double *__restrict__ val,
+                                                     const int32_t *__restrict__ slot_base,
+                                                     int32_t *__restrict__ jas, T *__restrict__ bval) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = i >> 6;
+    const int lane = (int)(i & 63);
+    if (s * 64 >= m) return;
+    const int64_t k0 = slot_base[s], k1 = slot_base[s + 1];
+    int32_t last_c = 0;
+    int nb = 0;
+    if (i < m) {
+        nb = row_blocks(col, val, ptr[i], ptr[i + 1], m, [&](int blk, int32_t c, const double *v) {
+            const int64_t k = k0 + blk;
+            jas[k * 64 + lane] = c;
+            bval[(k * 3 + 0) * 64 + lane] = (T)v[0];
+            bval[(k * 3 + 1) * 64 + lane] = (T)v[1];
+            bval[(k * 3 + 2) * 64 + lane] = (T)v[2];
+            last_c = c;
+        });
+    }
+    for (int64_t k = k0 + nb; k < k1; ++k) {
+        jas[k * 64 + lane] = last_c;
+        bval[(k * 3 + 0) * 64 + lane] = (T)0;
+        bval[(k * 3 + 1) * 64 + lane] = (T)0;
+        bval[(k * 3 + 2) * 64 + lane] = (T)0;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t n, const double *__restrict__ in,
+                                                     float *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
+        out[i] = (float)in[i];
+}
+
+// Per-row block lists out of the slice layout (for inspection and tests).
+__global__ __launch_bounds__(kBlock) void k_b13_export(int64_t m, const int32_t *__restrict__ slot_base,
+                                                       const int32_t *__restrict__ rowblocks,
+                                                       const int32_t *__restrict__ bptr,
+                                                       const int32_t *__restrict__ jas,
+                                                       const double *__restrict__ bv,
+                                                       int32_t *__restrict__ bcol,
+                                                       double *__restrict__ bval) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int64_t s = i >> 6;
+    const int lane = (int)(i & 63);
+    const int64_t k0 = slot_base[s];
+    for (int blk = 0; blk < rowblocks[i]; ++blk) {
+        const int64_t k = k0 + blk, o = bptr[i] + blk;
+        if (bcol) bcol[o] = jas[k * 64 + lane];
+        if (bval)
+            for (int j = 0; j < 3; ++j) bval[3 * o + j] = bv[(k * 3 + j) * 64 + lane];
+    }
+}
+
+// Structure check of a caller-supplied CRS: ptr[0] = 0, ptr non-decreasing,
+// ptr[m] = nnz, columns strictly ascending within a row and inside [0, m).
+// Any violation sets *bad.
+__global__ __launch_bounds__(kBlock) void k_validate_csr(int64_t m, int64_t nnz, const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ col, int *bad) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int64_t lo = ptr[i], hi = ptr[i + 1];
+    bool ok = lo >= 0 && lo <= hi && hi <= nnz && (i != 0 || lo == 0) && (i != m - 1 || hi == nnz);
+    for (int64_t k = lo; ok && k < hi; ++k) {
+        const int32_t c = col[k];
+        ok = c >= 0 && c < m && (k == lo || c > col[k - 1]);
+    }
+    if (!ok) atomicOr(bad, 1);
+}
+
+}  // namespace
+
+int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const int32_t *col) {
+    Buffer bad;
+    MFE_TRY(dev_alloc(ctx, &bad, sizeof(int)));
+    MFE_HIP_TRY(hipMemsetAsync(bad.ptr, 0, sizeof(int), ctx->stream));
+    hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                       ctx->stream, m, nnz, ptr, col, (int *)bad.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    int h = 0;
+    MFE_HIP_TRY(hipMemcpyAsync(&h, bad.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    MFE_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    dev_free(ctx, &bad);
+    if (h) {
+        set_error("CRS structure invalid: ptr must rise from 0 to nnz and columns ascend inside [0, m)");
+        return MFE_EINVAL;
+    }
+    return MFE_OK;
+}
+
+int build_bcrs13(mfe_problem *P) {
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t m = P->m;
+    if (m < 3) {
+        set_error("1x3 BCRS needs at least 3 rows");
+        return MFE_EUNSUPPORTED;
+    }
+    const int64_t nslices = (m + 63) / 64;
+    Buffer slice_n, total;
+    MFE_TRY(dev_alloc(ctx, &P->rowblocks, (size_t)m * sizeof(int32_t)));
+    MFE_TRY(dev_alloc(ctx, &slice_n, (size_t)nslices * sizeof(int32_t)));
+    MFE_TRY(dev_alloc(ctx, &P->slot_base, (size_t)(nslices + 1) * sizeof(int32_t)));
+    MFE_TRY(dev_alloc(ctx, &total, 2 * sizeof(int64_t)));
+    const unsigned grid = (unsigned)((nslices * 64 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_b13_count, dim3(grid), dim3(kBlock), 0, s, m, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, (int32_t *)P->rowblocks.ptr, (int32_t *)slice_n.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    // slot rows per slice -> slot_base; the same counts x 1 give the total slot rows
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, nslices, (const int32_t *)slice_n.ptr,
+                       (int32_t *)P->slot_base.ptr, 1, (int64_t *)total.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    int64_t nslots = 0;
+    MFE_HIP_TRY(hipMemcpyAsync(&nslots, total.ptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    if (nslots * 64 * 3 >= ((int64_t)1 << 31)) {
+        dev_free(ctx, &slice_n);
+        dev_free(ctx, &total);
+        set_error("1x3 BCRS slot count exceeds 32-bit indexing");
+        return MFE_EUNSUPPORTED;
+    }
+    P->nslots = nslots;
+    MFE_TRY(dev_alloc(ctx, &P->jas, (size_t)nslots * 64 * sizeof(int32_t)));
+    MFE_TRY(dev_alloc(ctx, &P->bval64, (size_t)nslots * 64 * 3 * sizeof(double)));
+    hipLaunchKernelGGL(k_b13_fill<double>, dim3(grid), dim3(kBlock), 0, s, m, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, (const double *)P->val64.ptr,
+                       (const int32_t *)P->slot_base.ptr, (int32_t *)P->jas.ptr, (double *)P->bval64.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    // number of real (unpadded) blocks: scan of the per-row counts
+    Buffer bptr;
+    MFE_TRY(dev_alloc(ctx, &bptr, (size_t)(m + 1) * sizeof(int32_t)));
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, m, (const int32_t *)P->rowblocks.ptr,
+                       (int32_t *)bptr.ptr, 1, (int64_t *)total.ptr + 1);
+    MFE_HIP_TRY(hipGetLastError());
+    int64_t nb = 0;
+    MFE_HIP_TRY(hipMemcpyAsync(&nb, (int64_t *)total.ptr + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    P->nblocks = nb;
+    dev_free(ctx, &bptr);
+    dev_free(ctx, &slice_n);
+    dev_free(ctx, &total);
+    return MFE_OK;
+}
+
+int cast_values_f32(mfe_problem *P) {
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    MFE_TRY(dev_alloc(ctx, &P->val32, (size_t)P->nnz * sizeof(float)));
+    hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(kBlock), 0, s, P->nnz, (const double *)P->val64.ptr,
+                       (float *)P->val32.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    if (P->formats & MFE_BCRS13) {
+        const int64_t n = P->nslots * 64 * 3;
+        MFE_TRY(dev_alloc(ctx, &P->bval32, (size_t)n * sizeof(float)));
+        hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(kBlock), 0, s, n, (const double *)P->bval64.ptr,
+                           (float *)P->bval32.ptr);
+        MFE_HIP_TRY(hipGetLastError());
+    }
+    return MFE_OK;
+}
+
+int export_bcrs13(const mfe_problem *P, int32_t *bptr_out, int32_t *bcol, double *bval) {
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t m = P->m;
+    Buffer bptr, total;
+    MFE_TRY(dev_alloc(ctx, &bptr, (size_t)(m + 1) * sizeof(int32_t)));
+    MFE_TRY(dev_alloc(ctx, &total, sizeof(int64_t)));
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, m, (const int32_t *)P->rowblocks.ptr,
+                       (int32_t *)bptr.ptr, 1, (int64_t *)total.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_b13_export, dim3(grid), dim3(kBlock), 0, s, m, (const int32_t *)P->slot_base.ptr,
+                       (const int32_t *)P->rowblocks.ptr, (const int32_t *)bptr.ptr,
+                       (const int32_t *)P->jas.ptr, (const double *)P->bval64.ptr, bcol, bval);
+    MFE_HIP_TRY(hipGetLastError());
+    if (bptr_out)
+        MFE_HIP_TRY(hipMemcpyAsync(bptr_out, bptr.ptr, (size_t)(m + 1) * sizeof(int32_t),
+                                   hipMemcpyDeviceToDevice, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    dev_free(ctx, &bptr);
+    dev_free(ctx, &total);
+    return MFE_OK;
+}
+
+}  // namespace mfe

@@ -1,0 +1,240 @@
+// Sparse matrix-vector products (Sec. 3.1 MATVEC) with optional fused CG
+// epilogues (the DOT that follows MATVEC in CG, Sec. 3.1 discussion of
+// Fig 3.5, and the residual at CG start/exit).
+//
+//   CRS (Fig 3.1):  L lanes per row stream the row's (val, col) pairs
+//                   contiguously, gather x, and combine by an xor butterfly.
+//   1x3 BCRS:       one lane per row; per block one column index and three
+//                   values, all coalesced across the wavefront's 64 rows,
+//                   and three consecutive x entries (the implicit column
+//                   increment of Fig 3.2, unrolled as in Fig 3.3).
+//
+// Both kernels run a workgroup grid sized to stay resident and walk row tiles
+// in XCD-contiguous ranges, so each XCD's L2 holds the x entries of the mesh
+// planes its rows touch while the matrix streams past non-temporally.
+#include <type_traits>
+
+#include "common.hpp"
+#include "device_util.hpp"
+
+namespace mfe {
+namespace {
+
+template <typename T>
+struct Epi {
+    const T *__restrict__ x;
+    T *__restrict__ y;
+    T *__restrict__ pout;
+    const double *__restrict__ b;
+};
+
+// Per-row epilogue; accumulates the reduction terms in FP64.
+template <typename T, int MODE>
+__device__ __forceinline__ void finish_row(const Epi<T> &E, int64_t row, T sum, double &d1, double &d2) {
+    if (MODE == kSpmvPlain) {
+        E.y[row] = sum;
+    } else if (MODE == kSpmvDot) {
+        E.y[row] = sum;
+        d1 += (double)E.x[row] * (double)sum;
+    } else if (MODE == kSpmvResid) {
+        const double bi = E.b[row];
+        const double r = bi - (double)sum;
+        E.y[row] = (T)r;
+        if (E.pout) E.pout[row] = (T)r;
+        d1 += r * r;
+        d2 += bi * bi;
+    } else {  // kSpmvTrue
+        const double r = E.b[row] - (double)sum;
+        d1 += r * r;
+    }
+}
+
+// Workgroup partial(s), then the last workgroup finishes the reduction and
+// updates the solver scalars.
+template <int MODE>
+__device__ __forceinline__ void reduce_epilogue(double d1, double d2, CgState *st, double *partials) {
+    if (MODE == kSpmvPlain) return;
+    d1 = block_sum(d1);
+    if (MODE == kSpmvResid) d2 = block_sum(d2);
+    if (threadIdx.x == 0) {
+        put_partial(partials, blockIdx.x, d1);
+        if (MODE == kSpmvResid) put_partial(partials, kMaxPartials + blockIdx.x, d2);
+    }
+    if (!arrive_last(&st->counter[0])) return;
+    const double s1 = sum_partials(partials, gridDim.x);
+    double s2 = 0.0;
+    if (MODE == kSpmvResid) s2 = sum_partials(partials + kMaxPartials, gridDim.x);
+    if (threadIdx.x != 0) return;
+    if (MODE == kSpmvDot) {
+        st->pq = s1;
+        if (st->dot_out) *st->dot_out = s1;
+        if (!(s1 > 0.0) || !isfinite(s1)) st->status = kBreakdown;
+        else st->alpha = st->rho / s1;
+    } else if (MODE == kSpmvResid) {
+        const double bnorm = sqrt(s2);
+        st->bnorm = bnorm;
+        st->iters = 0;
+        st->xpending = 0;
+        if (bnorm == 0.0) {
+            st->rho = 0.0;
+            st->zero_x = 1;
+            st->status = kConverged;
+            if (st->hist) st->hist[0] = 0.0;
+        } else {
+            st->rho = s1;
+            const double res = sqrt(s1) / bnorm;
+            if (st->hist) st->hist[0] = res;
+            if (!isfinite(res)) st->status = kBreakdown;
+            else if (res <= st->tol) st->status = kConverged;
+            else if (st->max_iter <= 0) st->status = kCapped;
+            else st->status = kRunning;
+        }
+    } else {
+        st->rr_true = s1;
+    }
+}
+
+// ---------------------------------------------------------------- CRS
+
+template <typename T, int L, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ col,
+                                                     const T *__restrict__ val, Epi<T> E, CgState *st,
+                                                     double *partials) {
+    if (MODE == kSpmvDot) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->xpending = 0;
+        if (st->status != kRunning) return;
+    }
+    constexpr int R = kBlock / L;  // rows per tile
+    const int g = threadIdx.x / L, sub = threadIdx.x % L;
+    const long ntiles = (m + R - 1) / R;
+    double d1 = 0.0, d2 = 0.0;
+    for (TileRange tr = xcd_tiles(ntiles); tr.t < tr.end; tr.t += tr.step) {
+        const int64_t row = tr.t * R + g;
+        T sum = 0;
+        if (row < m) {
+            const int32_t lo = ptr[row], hi = ptr[row + 1];
+            for (int32_t j = lo + sub; j < hi; j += L) sum += stream_load(val + j) * E.x[stream_load(col + j)];
+        }
+#pragma unroll
+        for (int off = L / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, L);
+        if (sub == 0 && row < m) finish_row<T, MODE>(E, row, sum, d1, d2);
+    }
+    reduce_epilogue<MODE>(d1, d2, st, partials);
+}
+
+// ---------------------------------------------------------------- 1x3 BCRS
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
+                                                     const int32_t *__restrict__ jas,
+                                                     const T *__restrict__ val, Epi<T> E, CgState *st,
+                                                     double *partials) {
+    if (MODE == kSpmvDot) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) st->xpending = 0;
+        if (st->status != kRunning) return;
+    }
+    const long ntiles = (m + kBlock - 1) / kBlock;
+    double d1 = 0.0, d2 = 0.0;
+    for (TileRange tr = xcd_tiles(ntiles); tr.t < tr.end; tr.t += tr.step) {
+        const int64_t row = tr.t * kBlock + threadIdx.x;
+        if (row >= m) continue;
+        const int64_t s = row >> 6;
+        const int lane = (int)(row & 63);
+        const int64_t k0 = slot_base[s], k1 = slot_base[s + 1];
+        const int32_t *jp = jas + k0 * 64 + lane;
+        const T *vp = val + k0 * 192 + lane;
+        T sum = 0;
+        if (k1 - k0 == 9) {
+            // interior slices: 9 blocks per row (3 y-lines x 3 z-planes)
+            int32_t c[9];
+            T v[27];
+#pragma unroll
+            for (int k = 0; k < 9; ++k) c[k] = stream_load(jp + k * 64);
+#pragma unroll
+            for (int k = 0; k < 27; ++k) v[k] = stream_load(vp + k * 64);
+#pragma unroll
+            for (int k = 0; k < 9; ++k) {
+                const T *xp = E.x + c[k];
+                sum += v[3 * k] * xp[0];
+                sum += v[3 * k + 1] * xp[1];
+                sum += v[3 * k + 2] * xp[2];
+            }
+        } else {
+            for (int64_t k = 0; k < k1 - k0; ++k) {
+                const T *xp = E.x + stream_load(jp + k * 64);
+                sum += stream_load(vp + (3 * k) * 64) * xp[0];
+                sum += stream_load(vp + (3 * k + 1) * 64) * xp[1];
+                sum += stream_load(vp + (3 * k + 2) * 64) * xp[2];
+            }
+        }
+        finish_row<T, MODE>(E, row, sum, d1, d2);
+    }
+    reduce_epilogue<MODE>(d1, d2, st, partials);
+}
+
+// ---------------------------------------------------------------- launch
+
+template <typename K>
+int grid_for(K kernel, long ntiles, int num_cu) {
+    const long g = (long)num_cu * resident_per_cu((const void *)kernel);
+    return resident_grid(g, ntiles);
+}
+
+template <typename T, int MODE>
+int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s) {
+    // 32 lanes per row: a row of the 27-point matrix is one contiguous
+    // 216-byte run of values, read by one half-wavefront.
+    constexpr int L = 32;
+    const T *val = std::is_same<T, double>::value ? (const T *)P->val64.ptr : (const T *)P->val32.ptr;
+    auto kern = k_spmv_csr<T, L, MODE>;
+    const long ntiles = (P->m + kBlock / L - 1) / (kBlock / L);
+    const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, val, E, st, partials);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+template <typename T, int MODE>
+int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s) {
+    const T *val = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
+    auto kern = k_spmv_b13<T, MODE>;
+    const long ntiles = (P->m + kBlock - 1) / kBlock;
+    const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
+                       (const int32_t *)P->jas.ptr, val, E, st, partials);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+template <typename T, int MODE>
+int launch_mode(const mfe_problem *P, int format, const SpmvArgs &a, hipStream_t s) {
+    Epi<T> E{(const T *)a.x, (T *)a.y, (T *)a.p_out, a.b};
+    if (format == MFE_CSR) return launch_csr<T, MODE>(P, E, a.st, a.partials, s);
+    return launch_b13<T, MODE>(P, E, a.st, a.partials, s);
+}
+
+}  // namespace
+
+int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const SpmvArgs &a,
+                hipStream_t s) {
+    if (f32) {
+        switch (mode) {
+            case kSpmvPlain: return launch_mode<float, kSpmvPlain>(P, format, a, s);
+            case kSpmvDot: return launch_mode<float, kSpmvDot>(P, format, a, s);
+            default: break;  // residuals are always evaluated in FP64
+        }
+        set_error("internal: FP32 residual SpMV requested");
+        return MFE_EINVAL;
+    }
+    switch (mode) {
+        case kSpmvPlain: return launch_mode<double, kSpmvPlain>(P, format, a, s);
+        case kSpmvDot: return launch_mode<double, kSpmvDot>(P, format, a, s);
+        case kSpmvResid: return launch_mode<double, kSpmvResid>(P, format, a, s);
+        case kSpmvTrue: return launch_mode<double, kSpmvTrue>(P, format, a, s);
+    }
+    return MFE_EINVAL;
+}
+
+}  // namespace mfe

@@ -1,0 +1,271 @@
+"""Thin Python layer over the C ABI: PyTorch supplies device memory and the stream.
+
+Nothing here computes: every step runs in the HIP kernels of libmfe.so.  The
+classes only turn torch tensors into device pointers and status codes into
+exceptions.
+"""
+import atexit
+import contextlib
+import ctypes
+import sys
+import weakref
+
+import torch
+
+from . import _lib
+from ._lib import (MFE_BCRS13, MFE_CSR, MFE_F32, MFE_F64, MFE_NOT_CONVERGED, MFE_OK, MFE_EBREAKDOWN,
+                   check, mfe_cg_stats)
+
+FORMATS = {"csr": MFE_CSR, "bcrs13": MFE_BCRS13}
+
+
+def _fmt(fmt):
+    return FORMATS[fmt] if isinstance(fmt, str) else int(fmt)
+
+
+def _ptr(t, dtype, n=None, name="tensor"):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous {dtype} CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"{name} must have {n} elements, has {t.numel()}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+_LIVE = weakref.WeakSet()  # contexts and problems still holding library objects
+
+
+@atexit.register
+def _close_all():
+    """Release library objects while torch (which owns their memory) is alive."""
+    objs = list(_LIVE)
+    for o in objs:
+        if isinstance(o, Problem):
+            o.close()
+    for o in objs:
+        if isinstance(o, Context):
+            o.close()
+
+
+@contextlib.contextmanager
+def _on(ctx):
+    """Order library work on ctx.stream after the caller's current stream, and
+    the caller's later work after it (the library stream is non-blocking)."""
+    cur = torch.cuda.current_stream(ctx.device)
+    same = cur == ctx.stream
+    if not same:
+        ctx.stream.wait_stream(cur)
+    with torch.cuda.stream(ctx.stream):
+        yield
+    if not same:
+        cur.wait_stream(ctx.stream)
+
+
+class _TorchAllocator:
+    """Device memory for the library's own storage, taken from torch's caching allocator."""
+
+    def __init__(self, device):
+        self.device = device
+        self.live = {}
+        self.alloc_cb = _lib.mfe_alloc_fn(self._alloc)
+        self.free_cb = _lib.mfe_free_fn(self._free)
+
+    def _alloc(self, nbytes, user):
+        try:
+            t = torch.empty(int(nbytes), dtype=torch.uint8, device=self.device)
+        except RuntimeError:
+            return None
+        self.live[t.data_ptr()] = t
+        return t.data_ptr()
+
+    def _free(self, ptr, user):
+        self.live.pop(ptr, None)
+
+
+class Context:
+    """One device and one stream.  All work of its problems is ordered on `stream`."""
+
+    def __init__(self, device=0, stream=None, torch_memory=True):
+        self.lib = _lib.load()
+        self.device = torch.device("cuda", device)
+        torch.cuda.set_device(self.device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(self.device)
+        self._allocator = _TorchAllocator(self.device) if torch_memory else None
+        h = ctypes.c_void_p()
+        a = self._allocator
+        check(self.lib.mfe_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream),
+                                      a.alloc_cb if a else _lib.mfe_alloc_fn(),
+                                      a.free_cb if a else _lib.mfe_free_fn(), None, ctypes.byref(h)),
+              "mfe_ctx_create")
+        self.handle = h
+        self.problems = weakref.WeakSet()
+        _LIVE.add(self)
+
+    def dot(self, x, y):
+        n = x.numel()
+        out = ctypes.c_double()
+        with _on(self):
+            check(self.lib.mfe_dot(self.handle, n, _ptr(x, torch.float64, n, "x"),
+                                   _ptr(y, torch.float64, n, "y"), ctypes.byref(out)), "mfe_dot")
+        return out.value
+
+    def close(self):
+        if self.handle:
+            for p in list(self.problems):
+                p.close()
+            self.stream.synchronize()
+            self.lib.mfe_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Problem:
+    """An assembled system A x = b held by the library (CSR, optionally 1x3 BCRS, FP64/FP32)."""
+
+    def __init__(self, ctx, handle, mesh=None):
+        self.ctx, self.handle, self.mesh = ctx, handle, mesh
+        m, nnz, nb = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        check(ctx.lib.mfe_problem_info(handle, ctypes.byref(m), ctypes.byref(nnz), ctypes.byref(nb)),
+              "mfe_problem_info")
+        self.m, self.nnz, self.nblocks = m.value, nnz.value, nb.value
+        ctx.problems.add(self)
+        _LIVE.add(self)
+
+    @classmethod
+    def mesh(cls, ctx, Nx, Ny, Nz, face_vals=None, node_g=None, formats=("csr", "bcrs13"),
+             precisions=("f64",)):
+        fl = 0
+        for f in formats:
+            fl |= _fmt(f)
+        pr = 0
+        for p in precisions:
+            pr |= {"f64": MFE_F64, "f32": MFE_F32}[p]
+        fv = None
+        if face_vals is not None:
+            fv = (ctypes.c_double * 6)(*[float(v) for v in face_vals])
+        m = (Nx + 1) * (Ny + 1) * (Nz + 1)
+        h = ctypes.c_void_p()
+        with _on(ctx):
+            check(ctx.lib.mfe_problem_create(ctx.handle, Nx, Ny, Nz, fv, _ptr(node_g, torch.float64, m, "node_g"),
+                                             fl, pr, ctypes.byref(h)), "mfe_problem_create")
+        return cls(ctx, h, mesh=(Nx, Ny, Nz))
+
+    @classmethod
+    def from_csr(cls, ctx, ptr, col, val, b=None, formats=("csr",), precisions=("f64",)):
+        fl = 0
+        for f in formats:
+            fl |= _fmt(f)
+        pr = 0
+        for p in precisions:
+            pr |= {"f64": MFE_F64, "f32": MFE_F32}[p]
+        m = ptr.numel() - 1
+        h = ctypes.c_void_p()
+        with _on(ctx):
+            check(ctx.lib.mfe_problem_from_csr(ctx.handle, m, _ptr(ptr, torch.int32, None, "ptr"),
+                                               _ptr(col, torch.int32, None, "col"),
+                                               _ptr(val, torch.float64, None, "val"),
+                                               _ptr(b, torch.float64, m, "b"), fl, pr, ctypes.byref(h)),
+                  "mfe_problem_from_csr")
+        return cls(ctx, h)
+
+    # -- data out -------------------------------------------------------------------------
+    def export_csr(self):
+        d = self.ctx.device
+        ptr = torch.empty(self.m + 1, dtype=torch.int32, device=d)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=d)
+        val = torch.empty(self.nnz, dtype=torch.float64, device=d)
+        b = torch.empty(self.m, dtype=torch.float64, device=d)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_problem_export_csr(self.handle, _ptr(ptr, torch.int32), _ptr(col, torch.int32),
+                                                      _ptr(val, torch.float64), _ptr(b, torch.float64)),
+                  "mfe_problem_export_csr")
+        self.ctx.stream.synchronize()
+        return ptr, col, val, b
+
+    def export_bcrs13(self):
+        d = self.ctx.device
+        bptr = torch.empty(self.m + 1, dtype=torch.int32, device=d)
+        bcol = torch.empty(self.nblocks, dtype=torch.int32, device=d)
+        bval = torch.empty(3 * self.nblocks, dtype=torch.float64, device=d)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_problem_export_bcrs13(self.handle, _ptr(bptr, torch.int32),
+                                                         _ptr(bcol, torch.int32), _ptr(bval, torch.float64)),
+                  "mfe_problem_export_bcrs13")
+        self.ctx.stream.synchronize()
+        return bptr, bcol, bval
+
+    def set_bc(self, face_vals=None, node_g=None):
+        fv = None if face_vals is None else (ctypes.c_double * 6)(*[float(v) for v in face_vals])
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_problem_set_bc(self.handle, fv, _ptr(node_g, torch.float64, self.m, "node_g")),
+                  "mfe_problem_set_bc")
+
+    # -- operations -----------------------------------------------------------------------
+    def spmv(self, x, y=None, fmt="bcrs13"):
+        if y is None:
+            y = torch.empty_like(x)
+        if x.dtype == torch.float32:
+            fn, dt, name = self.ctx.lib.mfe_spmv_f32, torch.float32, "mfe_spmv_f32"
+        else:
+            fn, dt, name = self.ctx.lib.mfe_spmv, torch.float64, "mfe_spmv"
+        with _on(self.ctx):
+            check(fn(self.handle, _fmt(fmt), _ptr(x, dt, self.m, "x"), _ptr(y, dt, self.m, "y")), name)
+        return y
+
+    def spmv_dot(self, p, q=None, pq=None, fmt="bcrs13", events=None):
+        """q = A p and p.q (into the device scalar pq) by the fused CG kernel.
+        events = (before, after) torch.cuda.Event pair recorded around the kernel."""
+        if q is None:
+            q = torch.empty_like(p)
+        if pq is None:
+            pq = torch.zeros(1, dtype=torch.float64, device=p.device)
+        ev = (None, None)
+        if events is not None:
+            for e in events:  # materialise the HIP event handles on this stream
+                if not e.cuda_event:
+                    e.record(self.ctx.stream)
+            ev = (ctypes.c_void_p(events[0].cuda_event), ctypes.c_void_p(events[1].cuda_event))
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_spmv_dot(self.handle, _fmt(fmt), _ptr(p, torch.float64, self.m, "p"),
+                                            _ptr(q, torch.float64, self.m, "q"), _ptr(pq, torch.float64, 1, "pq"),
+                                            ev[0], ev[1]), "mfe_spmv_dot")
+        return q, pq
+
+    def cg(self, x=None, tol=1e-8, max_iter=200, fmt="bcrs13", history=False, raise_on_breakdown=True):
+        """Unpreconditioned CG from x (zero if None).  Returns (x, stats dict)."""
+        d = self.ctx.device
+        if x is None:
+            with _on(self.ctx):
+                x = torch.zeros(self.m, dtype=torch.float64, device=d)
+        hist = torch.zeros(max_iter + 1, dtype=torch.float64, device=d) if history else None
+        st = mfe_cg_stats()
+        with _on(self.ctx):
+            rc = self.ctx.lib.mfe_cg(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"), float(tol),
+                                     int(max_iter), _ptr(hist, torch.float64), ctypes.byref(st))
+        ok = (MFE_OK, MFE_NOT_CONVERGED) + (() if raise_on_breakdown else (MFE_EBREAKDOWN,))
+        check(rc, "mfe_cg", ok)
+        out = st.as_dict()
+        if history:
+            out["history"] = hist[: st.iterations + 1].cpu()
+        return x, out
+
+    def close(self):
+        if self.handle and self.ctx.handle:
+            self.ctx.lib.mfe_problem_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,344 @@
+"""GPU parity of the HIP path (through the C ABI) against the CPU oracle.
+
+Same seeded inputs on both sides (paper_1505_08023_amd.inputs); the oracle
+assembles its own matrix, so assembly, format conversion, SpMV and CG are
+each compared end to end.
+
+Tolerances
+  assembly   ptr/col bit-exact; values |d| <= 8 eps max|A| (the GPU uses the
+             closed-form element matrix, the oracle Gauss quadrature: both
+             exact, they differ by rounding only); b |d| <= 64 eps max(|b|, h)
+  SpMV       per row |d_i| <= 1e-12 sum_j |A_ij x_j| and ||d||_2 <= 1e-12 ||y||_2
+  CG         both reach ||r||/||b|| <= tol; iteration counts within 2; the
+             first 4 recurrence residuals (k = 0..3) within 1e-10 relative; the two
+             solutions within ||A^-1|| (||r_gpu|| + ||r_oracle||) of each
+             other, with true residuals and the exact smallest eigenvalue of A.
+             Only the first residuals are compared entry by entry: the
+             identity rows of the Dirichlet nodes put an isolated eigenvalue 1
+             far above the rest of the spectrum, and rounding differences in
+             its direction grow by orders of magnitude per iteration until CG
+             re-converges them (visible as bumps in the residual history); the growth
+             starts earlier on finer meshes (from k = 7 at 20^3, k = 5 at 128^3).  The
+             oracle against a third-party CG (scipy matvec, numpy dots) shows
+             the same O(1) gaps at the bumps.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1505_08023_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1505_08023_amd.mfe import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def np_(t):
+    return t.detach().cpu().numpy()
+
+
+def mesh_problem(ctx, N, **kw):
+    from paper_1505_08023_amd.mfe import Problem
+    return Problem.mesh(ctx, *N, **kw)
+
+
+MESHES = [(1, 1, 1), (2, 2, 2), (2, 3, 4), (4, 4, 4), (5, 3, 7), (20, 20, 20), (33, 33, 33)]
+
+
+def bc_variants(N, seed=0):
+    m = oracle.num_rows(*N)
+    rng = np.random.default_rng(seed)
+    field = inputs.node_field(*N, inputs.smooth_faces(seed))
+    return [dict(), dict(face_vals=rng.uniform(0, 1, 6)), dict(node_g=field)]
+
+
+def gpu_kw(ctx, kw):
+    if "node_g" in kw:
+        return dict(node_g=torch.tensor(kw["node_g"], dtype=torch.float64, device=ctx.device))
+    return dict(kw)
+
+
+# ---------------------------------------------------------------- assembly + Dirichlet
+
+@pytest.mark.parametrize("N", MESHES)
+def test_assembly_matches_oracle(ctx, N):
+    for kw in bc_variants(N):
+        print("assembly", N, list(kw), flush=True)
+        A = oracle.assemble(*N, **kw)
+        P = mesh_problem(ctx, N, **gpu_kw(ctx, kw))
+        ptr, col, val, b = (np_(t) for t in P.export_csr())
+        assert P.m == A.m and P.nnz == A.nnz
+        assert np.array_equal(ptr, A.ptr.astype(np.int32))
+        assert np.array_equal(col, A.col)
+        amax = np.abs(A.val).max()
+        assert np.abs(val - A.val).max() <= 8 * EPS * amax
+        h = 1.0 / max(N)
+        assert np.abs(b - A.b).max() <= 64 * EPS * max(np.abs(A.b).max(), h)
+        P.close()
+
+
+@pytest.mark.parametrize("N", MESHES)
+def test_bcrs13_matches_oracle(ctx, N):
+    A = oracle.assemble(*N)
+    bptr, bcol, bval = oracle.bcrs13(A)
+    P = mesh_problem(ctx, N)
+    gptr, gcol, gval = (np_(t) for t in P.export_bcrs13())
+    assert P.nblocks == len(bcol)
+    assert np.array_equal(gptr, bptr.astype(np.int32))
+    assert np.array_equal(gcol, bcol)
+    assert np.abs(gval - bval).max() <= 8 * EPS * np.abs(A.val).max()
+    P.close()
+
+
+def test_set_bc_matches_fresh_assembly(ctx):
+    N = (9, 7, 8)
+    fv = np.random.default_rng(5).uniform(0, 1, 6)
+    P = mesh_problem(ctx, N)
+    P.set_bc(face_vals=fv)
+    Q = mesh_problem(ctx, N, face_vals=fv)
+    assert torch.equal(P.export_csr()[3], Q.export_csr()[3])
+    field = inputs.node_field(*N, inputs.smooth_faces(11))
+    P.set_bc(node_g=torch.tensor(field, dtype=torch.float64, device=ctx.device))
+    A = oracle.assemble(*N, node_g=field)
+    assert np.abs(np_(P.export_csr()[3]) - A.b).max() <= 64 * EPS * np.abs(A.b).max()
+
+
+# ---------------------------------------------------------------- SpMV
+
+def check_spmv(y_gpu, A, x, y_ref):
+    scale = np.abs(A.val) * np.abs(x[A.col])
+    rowscale = np.add.reduceat(scale, A.ptr[:-1]) if A.nnz else np.zeros(A.m)
+    rowscale[np.diff(A.ptr) == 0] = 0
+    d = np.abs(y_gpu - y_ref)
+    assert np.all(d <= 1e-12 * rowscale + 1e-300), (d / np.maximum(rowscale, 1e-300)).max()
+    assert np.linalg.norm(y_gpu - y_ref) <= 1e-12 * np.linalg.norm(y_ref)
+
+
+@pytest.mark.parametrize("N", MESHES + [(64, 64, 64), (128, 128, 128)])
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_spmv_matches_oracle(ctx, N, fmt):
+    print("spmv", N, fmt, flush=True)
+    A = oracle.assemble(*N)
+    x = inputs.spmv_vector(A.m, seed=0)
+    y_ref = oracle.csr_spmv(A, x)
+    P = mesh_problem(ctx, N)
+    xg = torch.tensor(x, device=ctx.device)
+    y = np_(P.spmv(xg, fmt=fmt))
+    check_spmv(y, A, x, y_ref)
+    # deterministic: a second product is bitwise equal
+    assert np.array_equal(np_(P.spmv(xg, fmt=fmt)), y)
+    P.close()
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_spmv_full_size_sampled_rows(ctx, fmt):
+    """256^3 in the launch configuration of the benchmark; rows sampled and
+    rebuilt one by one by the oracle."""
+    N = (256, 256, 256)
+    P = mesh_problem(ctx, N, formats=(fmt,))
+    m = P.m
+    x = inputs.spmv_vector(m, seed=0)
+    y = np_(P.spmv(torch.tensor(x, device=ctx.device), fmt=fmt))
+    rng = np.random.default_rng(7)
+    rows = np.unique(np.concatenate([rng.integers(0, m, 3000), np.arange(0, 300), np.arange(m - 300, m),
+                                     np.arange(m // 2 - 200, m // 2 + 200)]))
+    got, _ = oracle.assemble_rows(*N, rows)
+    for r, (c, v) in zip(rows, got):
+        ref = 0.0
+        for cc, vv in zip(c, v):
+            ref += vv * x[cc]
+        scale = float(np.sum(np.abs(v) * np.abs(x[c])))
+        assert abs(y[r] - ref) <= 1e-12 * scale + 1e-300, (r, y[r], ref)
+    P.close()
+
+
+def test_spmv_generic_csr_ragged(ctx):
+    """Rows of length 0..60 with random columns (empty rows, long rows, ragged tail)."""
+    from paper_1505_08023_amd.mfe import Problem
+    rng = np.random.default_rng(2)
+    m = 1000 + 37
+    lens = rng.integers(0, 61, m)
+    lens[::17] = 0
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate([np.sort(rng.choice(m, l, replace=False)) for l in lens]).astype(np.int32)
+    val = rng.uniform(-1, 1, ptr[-1])
+    A = oracle.CSR(ptr, col, val, np.zeros(m))
+    x = inputs.spmv_vector(m, seed=4)
+    y_ref = oracle.csr_spmv(A, x)
+    d = ctx.device
+    P = Problem.from_csr(ctx, torch.tensor(ptr.astype(np.int32), device=d), torch.tensor(col, device=d),
+                         torch.tensor(val, device=d), formats=("csr", "bcrs13"))
+    xg = torch.tensor(x, device=d)
+    for fmt in ("csr", "bcrs13"):
+        check_spmv(np_(P.spmv(xg, fmt=fmt)), A, x, y_ref)
+    P.close()
+
+
+def test_from_csr_rejects_bad_structure(ctx):
+    from paper_1505_08023_amd._lib import MfeError
+    from paper_1505_08023_amd.mfe import Problem
+    d = ctx.device
+    ptr = torch.tensor([0, 2, 3], dtype=torch.int32, device=d)
+    for col in ([1, 0, 1], [0, 5, 1]):  # descending / out of range
+        with pytest.raises(MfeError, match="EINVAL"):
+            Problem.from_csr(ctx, ptr, torch.tensor(col, dtype=torch.int32, device=d),
+                             torch.ones(3, dtype=torch.float64, device=d))
+
+
+def test_dot_matches_oracle_and_is_reproducible(ctx):
+    for n in (0, 1, 63, 1000, 2_000_003):
+        x = inputs.spmv_vector(n, seed=1)
+        y = inputs.spmv_vector(n, seed=2)
+        ref = math.fsum(x * y)
+        xg, yg = torch.tensor(x, device=ctx.device), torch.tensor(y, device=ctx.device)
+        got = ctx.dot(xg, yg)
+        assert abs(got - ref) <= 1e-13 * max(1.0, float(np.sum(np.abs(x * y))))
+        assert ctx.dot(xg, yg) == got
+
+
+# ---------------------------------------------------------------- CG
+
+def lam_min(N):
+    """Smallest eigenvalue of the assembled A (closed form).  The free block
+    is S(x)M(x)M + M(x)S(x)M + M(x)M(x)S of 1-D linear-element stiffness S and
+    mass M with Dirichlet ends, whose eigenvectors are sine modes:
+    s(h) = (2 - 2 cos(pi h)) / h, m(h) = h (4 + 2 cos(pi h)) / 6 at mode 1.
+    The Dirichlet identity rows add the eigenvalue 1."""
+    def s(h):
+        return (2 - 2 * math.cos(math.pi * h)) / h
+
+    def m(h):
+        return h * (4 + 2 * math.cos(math.pi * h)) / 6
+    hx, hy, hz = (1.0 / n for n in N)
+    lf = s(hx) * m(hy) * m(hz) + m(hx) * s(hy) * m(hz) + m(hx) * m(hy) * s(hz)
+    return min(lf, 1.0) if min(N) >= 2 else 1.0
+
+
+def check_solution_gap(x, ref, st, N, A):
+    """||x - x_ref|| <= ||A^-1|| (||r|| + ||r_ref|| + rounding of the two
+    residual evaluations, 27 eps || |A| |x| || each)."""
+    bnorm = np.linalg.norm(A.b)
+    absAx = np.add.reduceat(np.abs(A.val) * np.abs(ref["x"][A.col]), A.ptr[:-1])
+    floor = 2 * 27 * EPS * (np.linalg.norm(absAx) + bnorm)
+    bound = ((st["rel_res_true"] + ref["rel_res_true"]) * bnorm + floor) / lam_min(N)
+    gap = float(np.linalg.norm(x - ref["x"]))
+    assert gap <= bound * (1 + 1e-6) + 1e-300, (gap, bound)
+    return gap, bound
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+@pytest.mark.parametrize("N", [(4, 4, 4), (20, 20, 20), (17, 9, 23)])
+def test_cg_matches_oracle(ctx, N, fmt):
+    print("cg", N, fmt, flush=True)
+    tol, cap = 1e-8, 200
+    A = oracle.assemble(*N)
+    ref = oracle.cg(A, tol=tol, max_iter=cap, history=True)
+    P = mesh_problem(ctx, N)
+    x, st = P.cg(tol=tol, max_iter=cap, fmt=fmt, history=True)
+    x = np_(x)
+    assert ref["status"] == oracle.OK and st["status"] == 0
+    assert abs(st["iterations"] - ref["iterations"]) <= 2
+    assert st["rel_res_true"] <= tol and st["rel_res_recurrence"] <= tol
+    h, hr = st["history"].numpy(), ref["history"]
+    k = min(4, len(h), len(hr))
+    assert np.all(np.abs(h[:k] - hr[:k]) <= 1e-10 * hr[:k])
+    gap, bound = check_solution_gap(x, ref, st, N, A)
+    print("cg", N, fmt, "iters", st["iterations"], ref["iterations"], "solution gap", gap, "bound", bound)
+    # bitwise reproducible run to run
+    x2, st2 = P.cg(tol=tol, max_iter=cap, fmt=fmt)
+    assert np.array_equal(np_(x2), x) and st2["iterations"] == st["iterations"]
+    P.close()
+
+
+def test_cg_128_capped_matches_oracle(ctx):
+    """128^3, FP64, CSR and 1x3 BCRS, capped at 200 iterations."""
+    N = (128, 128, 128)
+    A = oracle.assemble(*N)
+    ref = oracle.cg(A, tol=1e-8, max_iter=200, history=True)
+    P = mesh_problem(ctx, N)
+    for fmt in ("csr", "bcrs13"):
+        x, st = P.cg(tol=1e-8, max_iter=200, fmt=fmt, history=True)
+        assert st["iterations"] == ref["iterations"] == 200
+        assert st["status"] == ref["status"] == oracle.NOT_CONVERGED
+        h, hr = st["history"].numpy(), ref["history"]
+        assert np.all(np.abs(h[:4] - hr[:4]) <= 1e-10 * hr[:4])
+        # the residual levels reached agree to within the bump amplitude
+        assert 0.1 < st["rel_res_true"] / ref["rel_res_true"] < 10
+        gap, bound = check_solution_gap(np_(x), ref, st, N, A)
+        print("128^3", fmt, "res", st["rel_res_true"], ref["rel_res_true"], "gap", gap, "bound", bound)
+    P.close()
+
+
+def test_cg_256_properties(ctx):
+    """256^3 to 1e-8 in the benchmark's configuration: properties that hold at any size,
+    plus sampled residual rows rebuilt by the oracle."""
+    N = (256, 256, 256)
+    P = mesh_problem(ctx, N, formats=("bcrs13",))
+    x, st = P.cg(tol=1e-8, max_iter=5000, fmt="bcrs13")
+    assert st["status"] == 0 and st["rel_res_true"] <= 1e-8
+    u = x.view(257, 257, 257)
+    assert float(u.min()) >= -1e-6 and float(u.max()) <= 1 + 1e-6  # maximum principle
+    assert float((u - u.flip(1)).abs().max()) <= 1e-6             # y -> 1-y symmetry
+    c = float(u[128, 128, 128])
+    assert abs(c - oracle.analytic_u(0.5, 0.5, 0.5)) <= 1e-4      # FE error O(h^2) at the centre
+    xs = np_(x)
+    rows = np.random.default_rng(9).integers(0, P.m, 2000)
+    got, b = oracle.assemble_rows(*N, rows)
+    # ||b||: 1 on the (N+1)^2 nodes of x = 1, h on the (N-1)^2 free nodes next to it
+    bn = math.sqrt(257 ** 2 + 255 ** 2 / 256 ** 2)
+    for (cols, vals), bi in zip(got, b):
+        r = bi - sum(v * xs[cc] for cc, v in zip(cols, vals))
+        assert abs(r) <= 1e-8 * bn
+    P.close()
+
+
+def test_cg_edge_cases(ctx):
+    N = (6, 6, 6)
+    P = mesh_problem(ctx, N)
+    # max_iter = 0: nothing happens, not converged
+    x, st = P.cg(tol=1e-8, max_iter=0)
+    assert st["iterations"] == 0 and st["status"] == 1 and float(x.abs().max()) == 0.0
+    # loose tolerance met at the start
+    x, st = P.cg(tol=2.0, max_iter=10)
+    assert st["iterations"] == 0 and st["status"] == 0
+    # b = 0: x = 0 whatever x0
+    Z = mesh_problem(ctx, N, face_vals=[0.0] * 6)
+    x0 = torch.ones(Z.m, dtype=torch.float64, device=ctx.device)
+    x, st = Z.cg(x=x0, tol=1e-8, max_iter=10)
+    assert st["status"] == 0 and float(x.abs().max()) == 0.0
+    # warm start at the solution: converged at k = 0
+    A = oracle.assemble(*N)
+    xs = torch.tensor(oracle.cg(A, tol=1e-14, max_iter=500)["x"], device=ctx.device)
+    x, st = P.cg(x=xs.clone(), tol=1e-8, max_iter=10)
+    assert st["iterations"] == 0
+    # capped run: same count and status as the oracle's capped run
+    ref = oracle.cg(A, tol=1e-12, max_iter=7, history=True)
+    x, st = P.cg(tol=1e-12, max_iter=7, history=True)
+    assert st["status"] == 1 and st["iterations"] == 7 and ref["status"] == oracle.NOT_CONVERGED
+    h, hr = st["history"].numpy(), ref["history"]
+    assert np.all(np.abs(h[:4] - hr[:4]) <= 1e-10 * hr[:4])
+    check_solution_gap(np_(x), ref, st, N, A)
+
+
+def test_cg_breakdown_on_indefinite_matrix(ctx):
+    from paper_1505_08023_amd.mfe import Problem
+    d = ctx.device
+    # diag(1, -1): p.Ap = 0 for b = (1, 1)
+    ptr = torch.tensor([0, 1, 2], dtype=torch.int32, device=d)
+    col = torch.tensor([0, 1], dtype=torch.int32, device=d)
+    val = torch.tensor([1.0, -1.0], dtype=torch.float64, device=d)
+    b = torch.tensor([1.0, 1.0], dtype=torch.float64, device=d)
+    P = Problem.from_csr(ctx, ptr, col, val, b)
+    x, st = P.cg(tol=1e-10, max_iter=10, fmt="csr", raise_on_breakdown=False)
+    assert st["status"] == -4 and st["iterations"] == 0

@@ -140,6 +140,20 @@ def test_dirichlet_rhs_and_identity_rows(N):
     assert np.abs(D[deep].sum(axis=1)).max() <= 1e-15
 
 
+@pytest.mark.parametrize("N", [(1, 1, 1), (3, 5, 4), (8, 8, 8)])
+def test_row_assembly_matches_full_assembly(N):
+    m = oracle.num_rows(*N)
+    rng = np.random.default_rng(3)
+    for kw in (dict(), dict(face_vals=rng.uniform(0, 1, 6)), dict(node_g=rng.uniform(0, 1, m))):
+        A = oracle.assemble(*N, **kw)
+        rows = np.arange(m)
+        got, b = oracle.assemble_rows(*N, rows, **kw)
+        assert np.array_equal(b, A.b)
+        for i, (c, v) in enumerate(got):
+            assert np.array_equal(c, A.col[A.ptr[i]:A.ptr[i + 1]])
+            assert np.array_equal(v, A.val[A.ptr[i]:A.ptr[i + 1]])
+
+
 # ---------------------------------------------------------------- SpMV (Figs 3.1-3.3)
 
 @pytest.mark.parametrize("N", [(1, 1, 1), (2, 2, 2), (3, 4, 2), (4, 4, 4), (2, 5, 3)])
