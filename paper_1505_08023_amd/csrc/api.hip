@@ -423,9 +423,10 @@ int mfe_spmv_dot(const mfe_problem *p, int format, const double *p_dev, double *
     MFE_TRY(launch_state_reset(st, pq_dev, ctx->stream));
     if (ev_before) MFE_HIP_TRY(hipEventRecord((hipEvent_t)ev_before, ctx->stream));
     SpmvArgs a{p_dev, q_dev, nullptr, nullptr, st, (double *)ctx->scratch.ptr};
-    MFE_TRY(launch_spmv(p, format, false, kSpmvDot, a, ctx->stream));
+    int n = 0;
+    MFE_TRY(launch_spmv(p, format, false, kSpmvDot, a, ctx->stream, &n));
     if (ev_after) MFE_HIP_TRY(hipEventRecord((hipEvent_t)ev_after, ctx->stream));
-    return MFE_OK;
+    return launch_finalize(kFinDot, (const double *)ctx->scratch.ptr, n, st, ctx->stream);
 }
 
 int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, double *out_host) {
@@ -436,7 +437,10 @@ int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, d
     }
     MFE_TRY(set_device(ctx));
     CgState *st = (CgState *)ctx->dot_state.ptr;
-    MFE_TRY(launch_dot(ctx, n, x_dev, y_dev, (double *)ctx->scratch.ptr, st, ctx->stream));
+    int g = 0;
+    MFE_TRY(launch_dot(ctx, n, x_dev, y_dev, (double *)ctx->scratch.ptr, ctx->stream, &g));
+    MFE_TRY(launch_state_reset(st, nullptr, ctx->stream));
+    MFE_TRY(launch_finalize(kFinDot, (const double *)ctx->scratch.ptr, g, st, ctx->stream));
     CgState *pin = (CgState *)ctx->pinned;
     MFE_HIP_TRY(hipMemcpyAsync(&pin[3], st, sizeof(CgState), hipMemcpyDeviceToHost, ctx->stream));
     MFE_HIP_TRY(hipStreamSynchronize(ctx->stream));

@@ -4,9 +4,9 @@
 // iteration ending in a synchronisation of all processes for the dot
 // products.  Here one iteration is three kernels, all scalars stay in device
 // memory, and the host never waits per iteration:
-//   spmv_dot  : q = A p, p.q, alpha = rho / p.q          (last workgroup)
-//   update_r  : r -= alpha q, rho_new = r.r, stop test, beta (last workgroup)
-//   update_xp : x += alpha p, p = r + beta p
+//   spmv_dot  : q = A p, partials of p.q
+//   update_r  : alpha = rho / p.q; r -= alpha q, partials of r.r
+//   update_xp : beta = r.r / rho; x += alpha p, p = r + beta p; stop test
 // K iterations are captured once into a HIP graph and replayed.  The host
 // keeps one graph ahead and polls a pinned copy of the solver state after
 // each; once the state leaves "running" every kernel returns at entry, so
@@ -43,7 +43,7 @@ int ensure_workspace(mfe_problem *P) {
         MFE_TRY(dev_alloc(ctx, &P->state, sizeof(CgState)));
         MFE_HIP_TRY(hipMemsetAsync(P->state.ptr, 0, sizeof(CgState), ctx->stream));
     }
-    if (!P->partials.ptr) MFE_TRY(dev_alloc(ctx, &P->partials, 2 * kMaxPartials * sizeof(double)));
+    if (!P->partials.ptr) MFE_TRY(dev_alloc(ctx, &P->partials, 3 * kMaxPartials * sizeof(double)));
     if (!P->graphs) P->graphs = new mfe_graph_cache();
     return MFE_OK;
 }
@@ -56,11 +56,13 @@ int capture(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, voi
     double *partials = (double *)P->partials.ptr;
     MFE_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = MFE_OK;
+    double *pq_part = partials, *rr_part = partials + 2 * kMaxPartials;
     for (int i = 0; i < k && rc == MFE_OK; ++i) {
-        SpmvArgs a{p, q, nullptr, nullptr, st, partials};
-        rc = launch_spmv(P, format, f32, kSpmvDot, a, cs);
-        if (rc == MFE_OK) rc = launch_update_r(P, f32, r, q, st, partials, cs);
-        if (rc == MFE_OK) rc = launch_update_xp(P, f32, x, p, r, st, cs);
+        SpmvArgs a{p, q, nullptr, nullptr, st, pq_part};
+        int n_pq = 0, n_rr = 0;
+        rc = launch_spmv(P, format, f32, kSpmvDot, a, cs, &n_pq);
+        if (rc == MFE_OK) rc = launch_update_r(P, f32, r, q, st, pq_part, n_pq, rr_part, cs, &n_rr);
+        if (rc == MFE_OK) rc = launch_update_xp(P, f32, x, p, r, st, rr_part, n_rr, cs);
     }
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(cs, &g);
@@ -161,7 +163,9 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
     MFE_HIP_TRY(hipMemcpyAsync(st, &pin[2], sizeof(CgState), hipMemcpyHostToDevice, s));
     // r = b - A x0, p = r, rho, ||b||, start test
     SpmvArgs a0{x, P->r.ptr, P->p.ptr, (const double *)P->b.ptr, st, partials};
-    MFE_TRY(launch_spmv(P, format, false, kSpmvResid, a0, s));
+    int n0 = 0;
+    MFE_TRY(launch_spmv(P, format, false, kSpmvResid, a0, s, &n0));
+    MFE_TRY(launch_finalize(kFinStart, partials, n0, st, s));
     MFE_TRY(launch_zero_if(P->m, x, st, ctx->num_cu, s));
     MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
@@ -176,7 +180,9 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
     }
     // true residual ||b - A x|| in FP64
     SpmvArgs a1{x, nullptr, nullptr, (const double *)P->b.ptr, st, partials};
-    MFE_TRY(launch_spmv(P, format, false, kSpmvTrue, a1, s));
+    int n1 = 0;
+    MFE_TRY(launch_spmv(P, format, false, kSpmvTrue, a1, s, &n1));
+    MFE_TRY(launch_finalize(kFinTrue, partials, n1, st, s));
     MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     ++spmvs;

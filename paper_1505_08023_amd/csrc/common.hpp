@@ -46,24 +46,26 @@ enum CgStatus : int { kRunning = 0, kConverged = 1, kCapped = 2, kBreakdown = -4
 
 // One per solve (one per system in a batched solve).  Lives in device memory;
 // every scalar the CG recurrences need stays on the device.
+//
+// Within one kernel, workgroup 0 writes only fields that no workgroup of that
+// kernel reads; the next kernel sees them (kernel boundaries order memory).
 struct CgState {
-    double rho;       // r.r of the current residual
-    double alpha;     // rho / p.q of the current iteration
-    double beta;      // rho_new / rho
+    double rho;       // r.r of the current residual       (written by update_xp)
+    double rho_old;   // rho at the start of the iteration (written by update_r)
+    double alpha;     // rho / p.q of the current iteration (written by update_r)
     double bnorm;     // ||b||_2
     double tol;       // relative tolerance on ||r||/||b||
     double pq;        // last p.q
     double rr_true;   // ||b - A x||^2 evaluated at exit
     double scale;     // mixed precision: ||r|| of the outer residual
     double *hist;     // optional: hist[k] = ||r_k||/||b||, k = 0..max_iter
-    double *dot_out;  // optional: the fused SpMV's p.q is also written here
-    int status;       // CgStatus
-    int iters;        // completed iterations
+    double *dot_out;  // optional: a finalized p.q is also written here
+    int status;       // CgStatus                          (written by update_xp / update_r)
+    int iters;        // completed iterations               (written by update_xp)
     int max_iter;
-    int xpending;     // set when the x/p update of the current iteration is due
+    int active;       // 1 once update_r has run in the current iteration (cleared by the SpMV)
     int zero_x;       // b = 0: the solution is x = 0
     int pad_;
-    unsigned int counter[4];  // arrival counters of the last-workgroup reductions (0 when idle)
 };
 
 // ------------------------------------------------------------------ matrix views
@@ -167,22 +169,28 @@ struct SpmvArgs {
     double *partials;
 };
 
+// *grid (optional) receives the number of workgroups, i.e. of partials written.
 int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const SpmvArgs &a,
-                hipStream_t s);
+                hipStream_t s, int *grid = nullptr);
 
 // CG driver (cg.hip)
 int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st);
 void release_graphs(mfe_problem *P);
 
-// vector kernels (vector.hip)
-int launch_update_r(const mfe_problem *P, bool f32, void *r, const void *q, CgState *st, double *partials,
-                    hipStream_t s);
+// vector kernels (vector.hip).  update_r consumes the n_pq partials of p.q
+// at pq_partials and writes its r.r partials to rr_partials (*grid of them);
+// update_xp consumes those.
+int launch_update_r(const mfe_problem *P, bool f32, void *r, const void *q, CgState *st,
+                    const double *pq_partials, int n_pq, double *rr_partials, hipStream_t s, int *grid);
 int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const void *r, CgState *st,
-                     hipStream_t s);
+                     const double *rr_partials, int n_rr, hipStream_t s);
+// one-workgroup reductions of partials into the state
+enum FinalizeKind : int { kFinStart = 0, kFinTrue = 1, kFinDot = 2 };
+int launch_finalize(FinalizeKind kind, const double *partials, int n, CgState *st, hipStream_t s);
 int launch_state_reset(CgState *st, double *dot_out, hipStream_t s);
 int launch_zero_if(int64_t m, double *x, const CgState *st, int num_cu, hipStream_t s);
-int launch_dot(mfe_ctx *ctx, int64_t n, const double *x, const double *y, double *partials, CgState *st,
-               hipStream_t s);
+int launch_dot(mfe_ctx *ctx, int64_t n, const double *x, const double *y, double *partials, hipStream_t s,
+               int *grid);
 
 // Grid sizing shared by the launchers.  resident_per_cu: workgroups of
 // kBlock threads of `kernel` that fit on one CU (cached per kernel).

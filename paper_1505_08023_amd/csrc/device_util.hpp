@@ -33,38 +33,20 @@ __device__ __forceinline__ double block_sum(double v) {
     return s;
 }
 
-// Partials cross workgroups (and XCDs, whose L2s are not coherent with one
-// another), so they are written and read with device-scope atomics.
-__device__ __forceinline__ void put_partial(double *p, int i, double v) {
-    __hip_atomic_store(p + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-__device__ __forceinline__ double get_partial(const double *p, int i) {
-    return __hip_atomic_load(const_cast<double *>(p) + i, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Called by every thread of every workgroup after thread 0 stored the
-// workgroup's partial(s).  Returns true in exactly one workgroup: the last to
-// arrive, which then sees every partial.  The counter is back at 0 on return
-// of the last workgroup, ready for the next kernel.
-__device__ __forceinline__ bool arrive_last(unsigned int *counter) {
-    __shared__ int last;
-    if (threadIdx.x == 0) {
-        __threadfence();
-        unsigned int prev =
-            __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-        last = (prev == gridDim.x - 1);
-        if (last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    }
-    __syncthreads();
-    if (last) __threadfence();
-    return last != 0;
-}
-
-// Fixed-order sum of n partials by one workgroup (result in thread 0).
-__device__ __forceinline__ double sum_partials(const double *p, int n) {
+// Sum of the n partials written by the previous kernel, in a fixed order
+// (lane-strided, then the workgroup tree), returned to every thread.  Every
+// workgroup that calls it gets the bitwise-same value, so a scalar that a
+// kernel needs (alpha, beta) is formed redundantly in each workgroup instead
+// of by a separate launch or a cross-workgroup handshake.  Kernel
+// boundaries make the previous kernel's stores visible on every XCD.
+__device__ __forceinline__ double sum_partials(const double *__restrict__ p, int n) {
+    __shared__ double total;
     double s = 0.0;
-    for (int i = threadIdx.x; i < n; i += kBlock) s += get_partial(p, i);
-    return block_sum(s);
+    for (int i = threadIdx.x; i < n; i += kBlock) s += p[i];
+    s = block_sum(s);
+    if (threadIdx.x == 0) total = s;
+    __syncthreads();
+    return total;
 }
 
 // Tile range of this workgroup.  Workgroups are dispatched to the 8 XCDs

@@ -49,49 +49,24 @@ __device__ __forceinline__ void finish_row(const Epi<T> &E, int64_t row, T sum, 
     }
 }
 
-// Workgroup partial(s), then the last workgroup finishes the reduction and
-// updates the solver scalars.
+// Workgroup partial(s) of the fused reductions; the consumer (the next
+// kernel, or a finalize kernel) sums them.
 template <int MODE>
-__device__ __forceinline__ void reduce_epilogue(double d1, double d2, CgState *st, double *partials) {
+__device__ __forceinline__ void store_partials(double d1, double d2, double *partials) {
     if (MODE == kSpmvPlain) return;
     d1 = block_sum(d1);
     if (MODE == kSpmvResid) d2 = block_sum(d2);
     if (threadIdx.x == 0) {
-        put_partial(partials, blockIdx.x, d1);
-        if (MODE == kSpmvResid) put_partial(partials, kMaxPartials + blockIdx.x, d2);
+        partials[blockIdx.x] = d1;
+        if (MODE == kSpmvResid) partials[kMaxPartials + blockIdx.x] = d2;
     }
-    if (!arrive_last(&st->counter[0])) return;
-    const double s1 = sum_partials(partials, gridDim.x);
-    double s2 = 0.0;
-    if (MODE == kSpmvResid) s2 = sum_partials(partials + kMaxPartials, gridDim.x);
-    if (threadIdx.x != 0) return;
-    if (MODE == kSpmvDot) {
-        st->pq = s1;
-        if (st->dot_out) *st->dot_out = s1;
-        if (!(s1 > 0.0) || !isfinite(s1)) st->status = kBreakdown;
-        else st->alpha = st->rho / s1;
-    } else if (MODE == kSpmvResid) {
-        const double bnorm = sqrt(s2);
-        st->bnorm = bnorm;
-        st->iters = 0;
-        st->xpending = 0;
-        if (bnorm == 0.0) {
-            st->rho = 0.0;
-            st->zero_x = 1;
-            st->status = kConverged;
-            if (st->hist) st->hist[0] = 0.0;
-        } else {
-            st->rho = s1;
-            const double res = sqrt(s1) / bnorm;
-            if (st->hist) st->hist[0] = res;
-            if (!isfinite(res)) st->status = kBreakdown;
-            else if (res <= st->tol) st->status = kConverged;
-            else if (st->max_iter <= 0) st->status = kCapped;
-            else st->status = kRunning;
-        }
-    } else {
-        st->rr_true = s1;
-    }
+}
+
+// In the CG loop the product runs only while the solve is running; it also
+// opens the iteration (the vector updates check `active`).
+__device__ __forceinline__ bool cg_gate(CgState *st) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->active = 0;
+    return st->status == kRunning;
 }
 
 // ---------------------------------------------------------------- CRS
@@ -101,10 +76,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
                                                      const int32_t *__restrict__ col,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
-    if (MODE == kSpmvDot) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->xpending = 0;
-        if (st->status != kRunning) return;
-    }
+    if (MODE == kSpmvDot && st && !cg_gate(st)) return;
     constexpr int R = kBlock / L;  // rows per tile
     const int g = threadIdx.x / L, sub = threadIdx.x % L;
     const long ntiles = (m + R - 1) / R;
@@ -120,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
         for (int off = L / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, L);
         if (sub == 0 && row < m) finish_row<T, MODE>(E, row, sum, d1, d2);
     }
-    reduce_epilogue<MODE>(d1, d2, st, partials);
+    store_partials<MODE>(d1, d2, partials);
 }
 
 // ---------------------------------------------------------------- 1x3 BCRS
@@ -130,10 +102,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_b13(int64_t m, const int32_t *_
                                                      const int32_t *__restrict__ jas,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
-    if (MODE == kSpmvDot) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) st->xpending = 0;
-        if (st->status != kRunning) return;
-    }
+    if (MODE == kSpmvDot && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
     double d1 = 0.0, d2 = 0.0;
     for (TileRange tr = xcd_tiles(ntiles); tr.t < tr.end; tr.t += tr.step) {
@@ -170,7 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_b13(int64_t m, const int32_t *_
         }
         finish_row<T, MODE>(E, row, sum, d1, d2);
     }
-    reduce_epilogue<MODE>(d1, d2, st, partials);
+    store_partials<MODE>(d1, d2, partials);
 }
 
 // ---------------------------------------------------------------- launch
@@ -182,7 +151,7 @@ int grid_for(K kernel, long ntiles, int num_cu) {
 }
 
 template <typename T, int MODE>
-int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s) {
+int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
     // 32 lanes per row: a row of the 27-point matrix is one contiguous
     // 216-byte run of values, read by one half-wavefront.
     constexpr int L = 32;
@@ -193,11 +162,12 @@ int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *parti
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->ptr.ptr,
                        (const int32_t *)P->col.ptr, val, E, st, partials);
     MFE_HIP_TRY(hipGetLastError());
+    if (grid_out) *grid_out = grid;
     return MFE_OK;
 }
 
 template <typename T, int MODE>
-int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s) {
+int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
     auto kern = k_spmv_b13<T, MODE>;
     const long ntiles = (P->m + kBlock - 1) / kBlock;
@@ -205,34 +175,35 @@ int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *parti
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
                        (const int32_t *)P->jas.ptr, val, E, st, partials);
     MFE_HIP_TRY(hipGetLastError());
+    if (grid_out) *grid_out = grid;
     return MFE_OK;
 }
 
 template <typename T, int MODE>
-int launch_mode(const mfe_problem *P, int format, const SpmvArgs &a, hipStream_t s) {
+int launch_mode(const mfe_problem *P, int format, const SpmvArgs &a, hipStream_t s, int *grid) {
     Epi<T> E{(const T *)a.x, (T *)a.y, (T *)a.p_out, a.b};
-    if (format == MFE_CSR) return launch_csr<T, MODE>(P, E, a.st, a.partials, s);
-    return launch_b13<T, MODE>(P, E, a.st, a.partials, s);
+    if (format == MFE_CSR) return launch_csr<T, MODE>(P, E, a.st, a.partials, s, grid);
+    return launch_b13<T, MODE>(P, E, a.st, a.partials, s, grid);
 }
 
 }  // namespace
 
 int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const SpmvArgs &a,
-                hipStream_t s) {
+                hipStream_t s, int *grid) {
     if (f32) {
         switch (mode) {
-            case kSpmvPlain: return launch_mode<float, kSpmvPlain>(P, format, a, s);
-            case kSpmvDot: return launch_mode<float, kSpmvDot>(P, format, a, s);
+            case kSpmvPlain: return launch_mode<float, kSpmvPlain>(P, format, a, s, grid);
+            case kSpmvDot: return launch_mode<float, kSpmvDot>(P, format, a, s, grid);
             default: break;  // residuals are always evaluated in FP64
         }
         set_error("internal: FP32 residual SpMV requested");
         return MFE_EINVAL;
     }
     switch (mode) {
-        case kSpmvPlain: return launch_mode<double, kSpmvPlain>(P, format, a, s);
-        case kSpmvDot: return launch_mode<double, kSpmvDot>(P, format, a, s);
-        case kSpmvResid: return launch_mode<double, kSpmvResid>(P, format, a, s);
-        case kSpmvTrue: return launch_mode<double, kSpmvTrue>(P, format, a, s);
+        case kSpmvPlain: return launch_mode<double, kSpmvPlain>(P, format, a, s, grid);
+        case kSpmvDot: return launch_mode<double, kSpmvDot>(P, format, a, s, grid);
+        case kSpmvResid: return launch_mode<double, kSpmvResid>(P, format, a, s, grid);
+        case kSpmvTrue: return launch_mode<double, kSpmvTrue>(P, format, a, s, grid);
     }
     return MFE_EINVAL;
 }

@@ -1,12 +1,16 @@
 // CG vector operations (Sec. 1 CG module: WAXPY and DOT) with the scalar
 // recurrences kept on the device.
 //
-// Per iteration, after the fused SpMV + p.q kernel has set alpha:
-//   update_r : r -= alpha q, partial r.r; the last workgroup forms rho_new,
-//              the stopping test, beta = rho_new / rho.     (reads r,q; writes r)
-//   update_xp: x += alpha p; p = r + beta p.                 (reads x,p,r; writes x,p)
-// 64 bytes per row per iteration in FP64, the fewest for the two-reduction
-// recurrence since q must be stored between the p.q and r.r reductions.
+// One iteration is three kernels; each reduction is written as per-workgroup
+// partials and summed, in a fixed order, at the start of every workgroup of
+// the kernel that needs it (no atomics, no fences, no extra launch):
+//   spmv_dot  : q = A p, partials of p.q                         (spmv.hip)
+//   update_r  : pi = sum(p.q), alpha = rho / pi (breakdown test);
+//               r -= alpha q, partials of r.r                  (reads r,q; writes r)
+//   update_xp : rho' = sum(r.r), beta = rho' / rho;
+//               x += alpha p, p = r + beta p; stopping test       (reads x,p,r; writes x,p)
+// 64 bytes per row per iteration in FP64: the fewest for the two-reduction
+// recurrence, since q must be stored between the p.q and r.r reductions.
 #include "common.hpp"
 #include "device_util.hpp"
 
@@ -15,9 +19,26 @@ namespace {
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ r, const T *__restrict__ q,
-                                                     CgState *st, double *partials) {
+                                                     CgState *st, const double *__restrict__ pq_part, int n_pq,
+                                                     double *__restrict__ rr_part) {
     if (st->status != kRunning) return;
-    const T a = (T)st->alpha;
+    const double pq = sum_partials(pq_part, n_pq);
+    const double rho = st->rho;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->status = kBreakdown;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq = pq;
+        st->alpha = alpha;
+        st->rho_old = rho;
+        st->active = 1;
+    }
+    const T a = (T)alpha;
     double d = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
@@ -26,37 +47,70 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ 
         d += (double)ri * (double)ri;
     }
     d = block_sum(d);
-    if (threadIdx.x == 0) put_partial(partials, blockIdx.x, d);
-    if (!arrive_last(&st->counter[0])) return;
-    const double rho_new = sum_partials(partials, gridDim.x);
-    if (threadIdx.x != 0) return;
-    const int it = st->iters + 1;
-    st->iters = it;
-    const double res = sqrt(rho_new) / st->bnorm;
-    if (st->hist) st->hist[it] = res;
-    st->beta = rho_new / st->rho;
-    st->rho = rho_new;
-    st->xpending = 1;
-    if (!isfinite(res)) st->status = kBreakdown;
-    else if (res <= st->tol) st->status = kConverged;
-    else if (it >= st->max_iter) st->status = kCapped;
+    if (threadIdx.x == 0) rr_part[blockIdx.x] = d;
 }
 
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__ x, T *__restrict__ p,
-                                                      const T *__restrict__ r, const CgState *st) {
-    if (!st->xpending) return;
-    const T a = (T)st->alpha, be = (T)st->beta;
-    const bool next = st->status == kRunning;  // p is needed only if another iteration follows
+                                                      const T *__restrict__ r, CgState *st,
+                                                      const double *__restrict__ rr_part, int n_rr) {
+    if (!st->active) return;
+    const double rho_new = sum_partials(rr_part, n_rr);
+    const double alpha = st->alpha, rho_old = st->rho_old;
+    const double beta = rho_new / rho_old;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int it = st->iters + 1;
+        const double res = sqrt(rho_new) / st->bnorm;
+        st->iters = it;
+        st->rho = rho_new;
+        if (st->hist) st->hist[it] = res;
+        if (!isfinite(res)) st->status = kBreakdown;
+        else if (res <= st->tol) st->status = kConverged;
+        else if (it >= st->max_iter) st->status = kCapped;
+    }
+    // p is updated even on the last iteration: the update is not needed then,
+    // but deciding it would need the stopping test in every workgroup
+    const T a = (T)alpha, be = (T)beta;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    if (next) {
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
-            const T pi = p[i];
-            x[i] += a * pi;
-            p[i] = r[i] + be * pi;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        const T pi = p[i];
+        x[i] += a * pi;
+        p[i] = r[i] + be * pi;
+    }
+}
+
+// One workgroup: reduce partials into the solver state.
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ part, int n, CgState *st) {
+    const double s1 = sum_partials(part, n);
+    double s2 = 0.0;
+    if (KIND == kFinStart) s2 = sum_partials(part + kMaxPartials, n);
+    if (threadIdx.x != 0) return;
+    if (KIND == kFinStart) {
+        // s1 = r0.r0, s2 = b.b: the start test of CG
+        const double bnorm = sqrt(s2);
+        st->bnorm = bnorm;
+        st->iters = 0;
+        st->active = 0;
+        if (bnorm == 0.0) {
+            st->rho = 0.0;
+            st->zero_x = 1;
+            st->status = kConverged;
+            if (st->hist) st->hist[0] = 0.0;
+        } else {
+            st->rho = s1;
+            const double res = sqrt(s1) / bnorm;
+            if (st->hist) st->hist[0] = res;
+            if (!isfinite(res)) st->status = kBreakdown;
+            else if (res <= st->tol) st->status = kConverged;
+            else if (st->max_iter <= 0) st->status = kCapped;
+            else st->status = kRunning;
         }
+    } else if (KIND == kFinTrue) {
+        st->rr_true = s1;
     } else {
-        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) x[i] += a * p[i];
+        st->pq = s1;
+        if (st->dot_out) *st->dot_out = s1;
     }
 }
 
@@ -67,15 +121,12 @@ __global__ __launch_bounds__(kBlock) void k_zero_if(int64_t m, double *__restric
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ x,
-                                                const double *__restrict__ y, CgState *st, double *partials) {
+                                                const double *__restrict__ y, double *__restrict__ part) {
     double d = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) d += x[i] * y[i];
     d = block_sum(d);
-    if (threadIdx.x == 0) put_partial(partials, blockIdx.x, d);
-    if (!arrive_last(&st->counter[0])) return;
-    const double s = sum_partials(partials, gridDim.x);
-    if (threadIdx.x == 0) st->pq = s;
+    if (threadIdx.x == 0) part[blockIdx.x] = d;
 }
 
 __global__ void k_state_reset(CgState *st, double *dot_out) {
@@ -90,31 +141,49 @@ int vec_grid(const void *kern, int64_t m, int num_cu) {
 
 }  // namespace
 
-int launch_update_r(const mfe_problem *P, bool f32, void *r, const void *q, CgState *st, double *partials,
-                    hipStream_t s) {
+int launch_update_r(const mfe_problem *P, bool f32, void *r, const void *q, CgState *st,
+                    const double *pq_partials, int n_pq, double *rr_partials, hipStream_t s, int *grid) {
+    int g;
     if (f32) {
-        const int g = vec_grid((const void *)k_update_r<float>, P->m, P->ctx->num_cu);
+        g = vec_grid((const void *)k_update_r<float>, P->m, P->ctx->num_cu);
         hipLaunchKernelGGL(k_update_r<float>, dim3(g), dim3(kBlock), 0, s, P->m, (float *)r, (const float *)q,
-                           st, partials);
+                           st, pq_partials, n_pq, rr_partials);
     } else {
-        const int g = vec_grid((const void *)k_update_r<double>, P->m, P->ctx->num_cu);
+        g = vec_grid((const void *)k_update_r<double>, P->m, P->ctx->num_cu);
         hipLaunchKernelGGL(k_update_r<double>, dim3(g), dim3(kBlock), 0, s, P->m, (double *)r,
-                           (const double *)q, st, partials);
+                           (const double *)q, st, pq_partials, n_pq, rr_partials);
+    }
+    MFE_HIP_TRY(hipGetLastError());
+    if (grid) *grid = g;
+    return MFE_OK;
+}
+
+int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const void *r, CgState *st,
+                     const double *rr_partials, int n_rr, hipStream_t s) {
+    if (f32) {
+        const int g = vec_grid((const void *)k_update_xp<float>, P->m, P->ctx->num_cu);
+        hipLaunchKernelGGL(k_update_xp<float>, dim3(g), dim3(kBlock), 0, s, P->m, (float *)x, (float *)p,
+                           (const float *)r, st, rr_partials, n_rr);
+    } else {
+        const int g = vec_grid((const void *)k_update_xp<double>, P->m, P->ctx->num_cu);
+        hipLaunchKernelGGL(k_update_xp<double>, dim3(g), dim3(kBlock), 0, s, P->m, (double *)x, (double *)p,
+                           (const double *)r, st, rr_partials, n_rr);
     }
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
 }
 
-int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const void *r, CgState *st,
-                     hipStream_t s) {
-    if (f32) {
-        const int g = vec_grid((const void *)k_update_xp<float>, P->m, P->ctx->num_cu);
-        hipLaunchKernelGGL(k_update_xp<float>, dim3(g), dim3(kBlock), 0, s, P->m, (float *)x, (float *)p,
-                           (const float *)r, st);
-    } else {
-        const int g = vec_grid((const void *)k_update_xp<double>, P->m, P->ctx->num_cu);
-        hipLaunchKernelGGL(k_update_xp<double>, dim3(g), dim3(kBlock), 0, s, P->m, (double *)x, (double *)p,
-                           (const double *)r, st);
+int launch_finalize(FinalizeKind kind, const double *partials, int n, CgState *st, hipStream_t s) {
+    switch (kind) {
+        case kFinStart:
+            hipLaunchKernelGGL(k_finalize<kFinStart>, dim3(1), dim3(kBlock), 0, s, partials, n, st);
+            break;
+        case kFinTrue:
+            hipLaunchKernelGGL(k_finalize<kFinTrue>, dim3(1), dim3(kBlock), 0, s, partials, n, st);
+            break;
+        case kFinDot:
+            hipLaunchKernelGGL(k_finalize<kFinDot>, dim3(1), dim3(kBlock), 0, s, partials, n, st);
+            break;
     }
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
@@ -133,11 +202,12 @@ int launch_state_reset(CgState *st, double *dot_out, hipStream_t s) {
     return MFE_OK;
 }
 
-int launch_dot(mfe_ctx *ctx, int64_t n, const double *x, const double *y, double *partials, CgState *st,
-               hipStream_t s) {
+int launch_dot(mfe_ctx *ctx, int64_t n, const double *x, const double *y, double *partials, hipStream_t s,
+               int *grid) {
     const int g = vec_grid((const void *)k_dot, n, ctx->num_cu);
-    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kBlock), 0, s, n, x, y, st, partials);
+    hipLaunchKernelGGL(k_dot, dim3(g), dim3(kBlock), 0, s, n, x, y, partials);
     MFE_HIP_TRY(hipGetLastError());
+    if (grid) *grid = g;
     return MFE_OK;
 }
 
