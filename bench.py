@@ -98,7 +98,7 @@ def main():
     N = args.n
     ctx = Context(0)
     t = time.perf_counter()
-    P = Problem.mesh(ctx, N, N, N, formats=("csr", "bcrs13"))
+    P = Problem.mesh(ctx, N, N, N, formats=("csr", "bcrs13"), precisions=("f64", "f32"))
     log(f"[bench] assembled {N}^3 on the GPU (m={P.m}, nnz={P.nnz}, 1x3 blocks={P.nblocks}) "
         f"in {time.perf_counter() - t:.2f} s")
     x = torch.zeros(P.m, dtype=torch.float64, device=ctx.device)
@@ -157,6 +157,24 @@ def main():
                "effective_GBps": its / elapsed * it_bytes / 1e9},
         "spmv": spmv,
     }
+    # mixed precision against FP64 CG at equal accuracy (1e-10)
+    mixed = {}
+    for name, fn in (("fp64_cg", lambda: P.cg(x, tol=1e-10, max_iter=args.max_iter, fmt=args.fmt)[1]),
+                     ("fp32_inner_fp64_refine", lambda: P.cg_mixed(x, tol=1e-10, inner_tol=1e-4, fmt=args.fmt)[1])):
+        with torch.cuda.stream(ctx.stream):
+            x.zero_()
+        fn()  # warm-up (graph capture)
+        with torch.cuda.stream(ctx.stream):
+            x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = fn()
+        torch.cuda.synchronize()
+        mixed[name] = dict(seconds=time.perf_counter() - t, iterations=st["iterations"], outer=st["outer"],
+                           rel_res_true=st["rel_res_true"])
+        log(f"[bench] {name} to 1e-10: {mixed[name]}")
+    mixed["speedup"] = mixed["fp64_cg"]["seconds"] / mixed["fp32_inner_fp64_refine"]["seconds"]
+    line["mixed_precision_1e-10"] = mixed
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample) ...")
         line["cpu_baseline"] = cpu_baseline(N)

@@ -172,6 +172,21 @@ int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, d
 int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
            double *hist_dev, mfe_cg_stats *stats);
 
+/* Mixed precision CG (FP32-inner / FP64-refinement extension of the CG
+ * module of Sec. 1).  Outer loop in FP64: r = b - A x with the FP64 matrix,
+ * stop when ||r||_2/||b||_2 <= tol, s = ||r||; inner unpreconditioned CG in
+ * FP32 on A32 d = fl32(r/s) from d = 0 (FP32 matrix values, SpMV sums and
+ * vector updates; FP64 dot-product accumulation and alpha/beta) until its
+ * relative residual is <= inner_tol or max_inner iterations; then x += s d
+ * in FP64.  A refinement step that does not halve ||r||, or an inner
+ * breakdown, continues with FP64 CG (mfe_cg) from the current x.  Needs
+ * MFE_F32 at create.  stats->iterations sums all CG iterations (inner and
+ * fallback), stats->outer counts refinement steps, rel_res_true is the
+ * final FP64 ||b - A x||/||b||.  0 <= tol, 0 < inner_tol < 1, max_outer >= 1,
+ * max_inner >= 1.  Returns MFE_OK or MFE_NOT_CONVERGED (max_outer reached). */
+int mfe_cg_mixed(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol,
+                 int max_outer, int max_inner, mfe_cg_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -51,6 +51,7 @@ SIGNATURES = {
     "mfe_spmv_dot": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "mfe_dot": (c_int, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(c_dbl)]),
     "mfe_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
+    "mfe_cg_mixed": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
 }
 
 _lib = None

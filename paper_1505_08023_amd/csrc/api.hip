@@ -464,4 +464,25 @@ int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_
     return cg_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, max_iter, hist_dev, stats);
 }
 
+int mfe_cg_mixed(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol, int max_outer,
+                 int max_inner, mfe_cg_stats *stats) {
+    clear_error();
+    if (!p || !x_dev) {
+        set_error("problem and x must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (!(tol >= 0.0) || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1 || max_inner < 1) {
+        set_error("need tol >= 0, 0 < inner_tol < 1, max_outer >= 1, max_inner >= 1");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(check_format(p, format));
+    if (!(p->precisions & MFE_F32)) {
+        set_error("FP32 values were not built for this problem");
+        return MFE_EUNSUPPORTED;
+    }
+    MFE_TRY(set_device(p->ctx));
+    return cg_mixed_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, inner_tol, max_outer, max_inner,
+                          stats);
+}
+
 }  // extern "C"

@@ -23,15 +23,13 @@ struct mfe_graph_cache {
         bool f32;
         const void *x;
         int k;
+        const void *st;
         hipGraphExec_t exec;
     };
     std::vector<Entry> entries;
 };
 
 namespace mfe {
-namespace {
-
-constexpr int kGraphIters = 16;  // CG iterations per captured graph
 
 int ensure_workspace(mfe_problem *P) {
     mfe_ctx *ctx = P->ctx;
@@ -40,19 +38,21 @@ int ensure_workspace(mfe_problem *P) {
     if (!P->p.ptr) MFE_TRY(dev_alloc(ctx, &P->p, vb));
     if (!P->q.ptr) MFE_TRY(dev_alloc(ctx, &P->q, vb));
     if (!P->state.ptr) {
-        MFE_TRY(dev_alloc(ctx, &P->state, sizeof(CgState)));
-        MFE_HIP_TRY(hipMemsetAsync(P->state.ptr, 0, sizeof(CgState), ctx->stream));
+        // [0]: the FP64 solve (or the outer refinement), [1]: the inner FP32 solve
+        MFE_TRY(dev_alloc(ctx, &P->state, 2 * sizeof(CgState)));
+        MFE_HIP_TRY(hipMemsetAsync(P->state.ptr, 0, 2 * sizeof(CgState), ctx->stream));
     }
     if (!P->partials.ptr) MFE_TRY(dev_alloc(ctx, &P->partials, 3 * kMaxPartials * sizeof(double)));
     if (!P->graphs) P->graphs = new mfe_graph_cache();
     return MFE_OK;
 }
 
+namespace {
+
 // Capture k CG iterations on the context's private capture stream.
-int capture(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, int k,
+int capture(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
             hipGraphExec_t *out) {
     hipStream_t cs = P->ctx->cap_stream;
-    CgState *st = (CgState *)P->state.ptr;
     double *partials = (double *)P->partials.ptr;
     MFE_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = MFE_OK;
@@ -83,21 +83,21 @@ int capture(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, voi
     return MFE_OK;
 }
 
-int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, int k,
+}  // namespace
+
+int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
               hipGraphExec_t *out) {
     for (auto &e : P->graphs->entries)
-        if (e.format == format && e.f32 == f32 && e.x == x && e.k == k) {
+        if (e.format == format && e.f32 == f32 && e.x == x && e.k == k && e.st == st) {
             *out = e.exec;
             return MFE_OK;
         }
     hipGraphExec_t ex = nullptr;
-    MFE_TRY(capture(P, format, f32, x, r, p, q, k, &ex));
-    P->graphs->entries.push_back({format, f32, x, k, ex});
+    MFE_TRY(capture(P, format, f32, x, r, p, q, st, k, &ex));
+    P->graphs->entries.push_back({format, f32, x, k, st, ex});
     *out = ex;
     return MFE_OK;
 }
-
-}  // namespace
 
 void release_graphs(mfe_problem *P) {
     if (!P->graphs) return;
@@ -108,11 +108,10 @@ void release_graphs(mfe_problem *P) {
 
 // Replay the iteration graph until the device state stops running.  On
 // return *fin holds the final state.
-int run_iterations(mfe_problem *P, hipGraphExec_t exec, int k, int max_iter, CgState *fin) {
+int run_iterations(mfe_problem *P, hipGraphExec_t exec, const CgState *st, int k, int max_iter, CgState *fin) {
     mfe_ctx *ctx = P->ctx;
     hipStream_t s = ctx->stream;
     CgState *pin = (CgState *)ctx->pinned;
-    const CgState *st = (const CgState *)P->state.ptr;
     const long limit = (long)max_iter / k + 3;  // the device cap ends the loop well before this
     long launched = 0;
     int slot = 0;
@@ -174,8 +173,8 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
     if (fin.status == kRunning) {
         const int k = kGraphIters < max_iter ? kGraphIters : max_iter;
         hipGraphExec_t exec = nullptr;
-        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, k, &exec));
-        MFE_TRY(run_iterations(P, exec, k, max_iter, &fin));
+        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, k, &exec));
+        MFE_TRY(run_iterations(P, exec, st, k, max_iter, &fin));
         spmvs += fin.iters + (fin.status == kBreakdown ? 1 : 0);
     }
     // true residual ||b - A x|| in FP64

@@ -68,25 +68,7 @@ struct CgState {
     int pad_;
 };
 
-// ------------------------------------------------------------------ matrix views
-
-struct CsrView {
-    int64_t m;
-    const int32_t *ptr;
-    const int32_t *col;
-    const void *val;  // double or float
-};
-
-// 1x3 BCRS in 64-row slices.  Slice s owns slot rows slot_base[s] ..
-// slot_base[s+1]-1; in slot row k, lane l (row 64 s + l) has its block's
-// first column at jas[64 k + l] and its three values at val[(3 k + j) 64 + l].
-struct B13View {
-    int64_t m;
-    int64_t nslices;
-    const int32_t *slot_base;  // [nslices + 1]
-    const int32_t *jas;        // [64 * nslots]
-    const void *val;           // [3 * 64 * nslots], double or float
-};
+// (the 1x3 BCRS slice layout is described in b13_layout.hpp)
 
 // ------------------------------------------------------------------ context / problem
 
@@ -174,8 +156,17 @@ int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const
                 hipStream_t s, int *grid = nullptr);
 
 // CG driver (cg.hip)
+constexpr int kGraphIters = 16;  // CG iterations per captured graph
+int ensure_workspace(mfe_problem *P);
+int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
+              hipGraphExec_t *out);
+int run_iterations(mfe_problem *P, hipGraphExec_t exec, const CgState *st, int k, int max_iter, CgState *fin);
 int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st);
 void release_graphs(mfe_problem *P);
+
+// mixed precision (mixed.hip)
+int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inner_tol, int max_outer,
+                   int max_inner, mfe_cg_stats *st);
 
 // vector kernels (vector.hip).  update_r consumes the n_pq partials of p.q
 // at pq_partials and writes its r.r partials to rr_partials (*grid of them);

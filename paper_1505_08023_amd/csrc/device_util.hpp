@@ -6,6 +6,13 @@
 
 #include "common.hpp"
 
+#ifndef MFE_XCD_REMAP
+#define MFE_XCD_REMAP 1  // XCD-contiguous tile ranges (see tile_range)
+#endif
+#ifndef MFE_MATRIX_NT
+#define MFE_MATRIX_NT 1  // non-temporal loads for matrix streams
+#endif
+
 namespace mfe {
 
 // Sum over the 64 lanes of a wavefront by an xor butterfly: every lane ends
@@ -57,22 +64,32 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ p, int
 struct TileRange {
     long t, end, step;
 };
-__device__ __forceinline__ TileRange xcd_tiles(long ntiles) {
+__device__ __forceinline__ TileRange tile_range(long ntiles) {
+    TileRange r;
+#if MFE_XCD_REMAP
     const int xcd = blockIdx.x % kNumXcd;
     const int lid = blockIdx.x / kNumXcd;
     const int per = gridDim.x / kNumXcd;
-    TileRange r;
     r.t = ntiles * xcd / kNumXcd + lid;
     r.end = ntiles * (xcd + 1) / kNumXcd;
     r.step = per;
+#else
+    r.t = blockIdx.x;
+    r.end = ntiles;
+    r.step = gridDim.x;
+#endif
     return r;
 }
 
 // Matrix streams are read once per product: load them non-temporally so
 // they do not evict the x entries that the gathers reuse.
 template <typename T>
-__device__ __forceinline__ T stream_load(const T *p) {
+__device__ __forceinline__ T matrix_load(const T *p) {
+#if MFE_MATRIX_NT
     return __builtin_nontemporal_load(p);
+#else
+    return *p;
+#endif
 }
 
 }  // namespace mfe

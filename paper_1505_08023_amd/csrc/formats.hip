@@ -7,7 +7,9 @@
 // (the length of almost every segment of this matrix) and shorter segments
 // are zero padded: no offsets array, no branch.  Rows are grouped in slices
 // of 64 (one wavefront); inside a slice the k-th block of every row is stored
-// contiguously, so each block load of a wavefront is one coalesced access.
+// contiguously, so each block load of a wavefront is one coalesced access
+// (layout in b13_layout.hpp).
+#include "b13_layout.hpp"
 #include "common.hpp"
 #include "device_util.hpp"
 
@@ -99,24 +101,19 @@ __global__ __launch_bounds__(kBlock) void k_b13_fill(int64_t m, const int32_t *_
     const int64_t s = i >> 6;
     const int lane = (int)(i & 63);
     if (s * 64 >= m) return;
-    const int64_t k0 = slot_base[s], k1 = slot_base[s + 1];
+    const B13Slice sl = b13_slice(slot_base[s], slot_base[s + 1]);
     int32_t last_c = 0;
     int nb = 0;
     if (i < m) {
         nb = row_blocks(col, val, ptr[i], ptr[i + 1], m, [&](int blk, int32_t c, const double *v) {
-            const int64_t k = k0 + blk;
-            jas[k * 64 + lane] = c;
-            bval[(k * 3 + 0) * 64 + lane] = (T)v[0];
-            bval[(k * 3 + 1) * 64 + lane] = (T)v[1];
-            bval[(k * 3 + 2) * 64 + lane] = (T)v[2];
+            jas[b13_jas(sl, blk, lane)] = c;
+            for (int j = 0; j < 3; ++j) bval[b13_val(sl, blk, j, lane)] = (T)v[j];
             last_c = c;
         });
     }
-    for (int64_t k = k0 + nb; k < k1; ++k) {
-        jas[k * 64 + lane] = last_c;
-        bval[(k * 3 + 0) * 64 + lane] = (T)0;
-        bval[(k * 3 + 1) * 64 + lane] = (T)0;
-        bval[(k * 3 + 2) * 64 + lane] = (T)0;
+    for (int k = nb; k < sl.S; ++k) {
+        jas[b13_jas(sl, k, lane)] = last_c;
+        for (int j = 0; j < 3; ++j) bval[b13_val(sl, k, j, lane)] = (T)0;
     }
 }
 
@@ -138,12 +135,12 @@ __global__ __launch_bounds__(kBlock) void k_b13_export(int64_t m, const int32_t 
     if (i >= m) return;
     const int64_t s = i >> 6;
     const int lane = (int)(i & 63);
-    const int64_t k0 = slot_base[s];
+    const B13Slice sl = b13_slice(slot_base[s], slot_base[s + 1]);
     for (int blk = 0; blk < rowblocks[i]; ++blk) {
-        const int64_t k = k0 + blk, o = bptr[i] + blk;
-        if (bcol) bcol[o] = jas[k * 64 + lane];
+        const int64_t o = bptr[i] + blk;
+        if (bcol) bcol[o] = jas[b13_jas(sl, blk, lane)];
         if (bval)
-            for (int j = 0; j < 3; ++j) bval[3 * o + j] = bv[(k * 3 + j) * 64 + lane];
+            for (int j = 0; j < 3; ++j) bval[3 * o + j] = bv[b13_val(sl, blk, j, lane)];
     }
 }
 

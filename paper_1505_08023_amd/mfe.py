@@ -257,6 +257,19 @@ class Problem:
             out["history"] = hist[: st.iterations + 1].cpu()
         return x, out
 
+    def cg_mixed(self, x=None, tol=1e-10, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13"):
+        """FP32-inner CG inside FP64 iterative refinement.  Returns (x, stats dict)."""
+        d = self.ctx.device
+        if x is None:
+            with _on(self.ctx):
+                x = torch.zeros(self.m, dtype=torch.float64, device=d)
+        st = mfe_cg_stats()
+        with _on(self.ctx):
+            rc = self.ctx.lib.mfe_cg_mixed(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"), float(tol),
+                                           float(inner_tol), int(max_outer), int(max_inner), ctypes.byref(st))
+        check(rc, "mfe_cg_mixed", (MFE_OK, MFE_NOT_CONVERGED))
+        return x, st.as_dict()
+
     def close(self):
         if self.handle and self.ctx.handle:
             self.ctx.lib.mfe_problem_destroy(self.handle)
