@@ -177,8 +177,8 @@ int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_
  * stop when ||r||_2/||b||_2 <= tol, s = ||r||; inner unpreconditioned CG in
  * FP32 on A32 d = fl32(r/s) from d = 0 (FP32 matrix values, SpMV sums and
  * vector updates; FP64 dot-product accumulation and alpha/beta) until its
- * relative residual is <= inner_tol or max_inner iterations; then x += s d
- * in FP64.  A refinement step that does not halve ||r||, or an inner
+ * relative residual is <= max(inner_tol, tol ||b|| / (2 s)) or max_inner
+ * iterations; then x += s d in FP64.  A refinement step that does not halve ||r||, or an inner
  * breakdown, continues with FP64 CG (mfe_cg) from the current x.  Needs
  * MFE_F32 at create.  stats->iterations sums all CG iterations (inner and
  * fallback), stats->outer counts refinement steps, rel_res_true is the
@@ -186,6 +186,43 @@ int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_
  * max_inner >= 1.  Returns MFE_OK or MFE_NOT_CONVERGED (max_outer reached). */
 int mfe_cg_mixed(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol,
                  int max_outer, int max_inner, mfe_cg_stats *stats);
+
+/* ---------------------------------------------------------------------
+ * Batched solves: many box meshes of uneven size solved together (the
+ * batched extension of the Sec. 1 CG module).  Each system follows exactly
+ * the single-system recurrence (own alpha, beta, ||b||, stopping test) and
+ * is frozen once converged.  The systems are stored as one block-diagonal
+ * matrix; vectors are the concatenation of the systems' vectors (system j
+ * occupies rows row_offsets[j] .. row_offsets[j+1]-1, node numbering inside
+ * a system as for a single mesh).
+ * ------------------------------------------------------------------- */
+typedef struct mfe_batch mfe_batch;
+
+/* sizes: host int32[3*nsys] (Nx, Ny, Nz per system, each >= 1); face_vals:
+ * host double[6*nsys] (per system, order as in mfe_problem_create) or NULL
+ * for the paper's values.  MFE_EUNSUPPORTED when the total nnz >= 2^31.
+ * Destroy a batch before its context. */
+int mfe_batch_create(mfe_ctx *ctx, int nsys, const int32_t *sizes, const double *face_vals, int formats,
+                     int precisions, mfe_batch **out);
+int mfe_batch_destroy(mfe_batch *b);
+/* Total rows, total stored entries, row_offsets (host int64[nsys+1]); any may be NULL. */
+int mfe_batch_info(const mfe_batch *b, int64_t *m_total, int64_t *nnz_total, int64_t *row_offsets);
+/* FP64 CRS of the block-diagonal matrix and b (device buffers, as mfe_problem_export_csr). */
+int mfe_batch_export_csr(const mfe_batch *b, int32_t *ptr_dev, int32_t *col_dev, double *val_dev, double *b_dev);
+/* Times the batched SpMV for each candidate launch shape (CRS lanes per row
+ * 8/16/32, i.e. rows per wavefront 8/4/2, and grid = 1, 2 or 4 times the
+ * resident workgroups) on this batch and keeps the fastest for later solves
+ * in `format`.  *lanes_out / *factor_out (may be NULL) receive the choice. */
+int mfe_batch_autotune(mfe_batch *b, int format, int *lanes_out, int *factor_out);
+/* FP64 CG on every system from x_dev (length m_total): per system stop at
+ * ||r||/||b|| <= tol or max_iter iterations.  stats: host array of nsys.
+ * Returns MFE_OK when every system converged, MFE_NOT_CONVERGED if one hit
+ * the cap, MFE_EBREAKDOWN if one broke down. */
+int mfe_batch_cg(mfe_batch *b, int format, double *x_dev, double tol, int max_iter, mfe_cg_stats *stats);
+/* FP32-inner / FP64-refinement CG (as mfe_cg_mixed) on every system
+ * together; needs MFE_F32 at create. */
+int mfe_batch_cg_mixed(mfe_batch *b, int format, double *x_dev, double tol, double inner_tol, int max_outer,
+                       int max_inner, mfe_cg_stats *stats);
 
 #ifdef __cplusplus
 }

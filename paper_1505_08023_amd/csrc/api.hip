@@ -79,6 +79,10 @@ int set_device(const mfe_ctx *ctx) {
     return MFE_OK;
 }
 
+}  // namespace
+
+namespace mfe {
+
 void free_problem_storage(mfe_problem *P) {
     mfe_ctx *ctx = P->ctx;
     release_graphs(P);
@@ -95,6 +99,10 @@ int finish_problem(mfe_problem *P) {
     MFE_HIP_TRY(hipStreamSynchronize(P->ctx->stream));
     return MFE_OK;
 }
+
+}  // namespace mfe
+
+namespace {
 
 int check_format(const mfe_problem *p, int format) {
     if (format != MFE_CSR && format != MFE_BCRS13) {

@@ -70,10 +70,13 @@ __device__ __forceinline__ int shared_elements(int i, int s, int N) {
 }
 
 // One thread per row.  mode 0: structure + values + rhs; mode 1: rhs only.
-__global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int32_t *__restrict__ ptr,
-                                                     int32_t *__restrict__ col,
-                                                     double *__restrict__ val,
-                                                     double *__restrict__ b, int rhs_only) {
+// The mesh's rows and entries are written at offsets row_off / nnz_off of
+// the arrays (column indices shifted by row_off), so several meshes can form
+// one block-diagonal matrix.
+__global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int64_t row_off, int64_t nnz_off,
+                                                     int32_t *__restrict__ ptr, int32_t *__restrict__ col,
+                                                     double *__restrict__ val, double *__restrict__ b,
+                                                     int rhs_only) {
     const int64_t m = (int64_t)M.nx * M.ny * M.nz;
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (i >= m) return;
@@ -86,8 +89,8 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int32_t *__restrict
     const int64_t start = SX * SY * line_prefix(iz) + SX * line_prefix(iy) * cz +
                           line_prefix(ix) * (int64_t)cy * cz;
     if (!rhs_only) {
-        ptr[i] = (int32_t)start;
-        if (i == m - 1) ptr[m] = (int32_t)(start + (int64_t)line_count(ix, M.Nx) * cy * cz);
+        ptr[row_off + i] = (int32_t)(nnz_off + start);
+        if (i == m - 1) ptr[row_off + m] = (int32_t)(nnz_off + start + (int64_t)line_count(ix, M.Nx) * cy * cz);
     }
 
     double gi;
@@ -121,39 +124,46 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int32_t *__restrict
                     }
                 }
                 if (!rhs_only) {
-                    col[k] = (int32_t)j;
-                    val[k] = v;
+                    col[nnz_off + k] = (int32_t)(row_off + j);
+                    val[nnz_off + k] = v;
                 }
                 ++k;
             }
         }
     }
-    b[i] = dir_i ? gi : bi;
+    b[row_off + i] = dir_i ? gi : bi;
 }
 
 }  // namespace
 
-int launch_assemble(mfe_problem *P, const double *face_vals, const double *node_g, bool values_and_rhs,
-                    bool rhs_only) {
-    (void)values_and_rhs;
+int launch_assemble_into(hipStream_t s, int Nx, int Ny, int Nz, const double *face_vals, const double *node_g,
+                         int64_t row_off, int64_t nnz_off, int32_t *ptr, int32_t *col, double *val, double *b,
+                         bool rhs_only) {
     Mesh M{};
-    M.Nx = P->Nx;
-    M.Ny = P->Ny;
-    M.Nz = P->Nz;
-    M.nx = P->Nx + 1;
-    M.ny = P->Ny + 1;
-    M.nz = P->Nz + 1;
-    element_patterns(1.0 / P->Nx, 1.0 / P->Ny, 1.0 / P->Nz, M.kpat);
+    M.Nx = Nx;
+    M.Ny = Ny;
+    M.Nz = Nz;
+    M.nx = Nx + 1;
+    M.ny = Ny + 1;
+    M.nz = Nz + 1;
+    element_patterns(1.0 / Nx, 1.0 / Ny, 1.0 / Nz, M.kpat);
     static const double paper_faces[6] = {0.0, 1.0, 0.0, 0.0, 0.0, 0.0};
     const double *f = face_vals ? face_vals : paper_faces;
     for (int i = 0; i < 6; ++i) M.face[i] = f[i];
     M.node_g = node_g;
-    const int64_t grid = (P->m + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)grid), dim3(kBlock), 0, P->ctx->stream, M,
-                       (int32_t *)P->ptr.ptr, (int32_t *)P->col.ptr, (double *)P->val64.ptr,
-                       (double *)P->b.ptr, rhs_only ? 1 : 0);
+    const int64_t m = (int64_t)M.nx * M.ny * M.nz;
+    const int64_t grid = (m + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)grid), dim3(kBlock), 0, s, M, row_off, nnz_off, ptr, col, val, b,
+                       rhs_only ? 1 : 0);
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
+}
+
+int launch_assemble(mfe_problem *P, const double *face_vals, const double *node_g, bool values_and_rhs,
+                    bool rhs_only) {
+    (void)values_and_rhs;
+    return launch_assemble_into(P->ctx->stream, P->Nx, P->Ny, P->Nz, face_vals, node_g, 0, 0, (int32_t *)P->ptr.ptr,
+                                (int32_t *)P->col.ptr, (double *)P->val64.ptr, (double *)P->b.ptr, rhs_only);
 }
 
 }  // namespace mfe

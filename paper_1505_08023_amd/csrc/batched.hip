@@ -1,0 +1,869 @@
+// Batched CG over many box meshes of uneven size (the batched extension of
+// the Sec. 1 CG module): every system follows exactly the single-system CG
+// recurrence with its own alpha, beta, norm and stopping test, and a
+// converged system is frozen while the others continue.
+//
+// The systems are assembled into one block-diagonal matrix.  Workgroups are
+// assigned to systems in proportion to their rows (each workgroup owns one
+// contiguous row chunk of one system), so every per-system reduction is the
+// fixed-order sum of that system's workgroup partials, formed at the start of
+// the consuming kernel by each of the system's workgroups: one iteration of
+// all systems is three kernels (SpMV + p.q, r update + r.r, x/p update), K
+// iterations are captured in one HIP graph, and the host polls the system
+// states once per graph.  The grid is a multiple of the resident capacity so
+// that CUs freed by frozen systems take on the remaining work.  An autotuner
+// picks the CRS lanes per row (rows per wavefront) and the grid multiple by
+// timing the SpMV kernel on the batch itself.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "device_util.hpp"
+#include "spmv_rows.hpp"
+
+namespace mfe {
+namespace {
+
+struct Map {
+    const int32_t *wg_sys;  // system of each workgroup
+    const int64_t *wg_lo;   // first row of each workgroup's chunk
+    const int64_t *wg_hi;   // one past its last row
+    const int32_t *sys_wg;  // first workgroup of each system [nsys + 1]
+};
+
+struct Tuning {
+    int lanes = 32;   // CRS lanes per row
+    int factor = 1;   // grid = factor x resident workgroups
+};
+
+// Sum of the partials of system `sys` (its workgroups' entries), fixed order,
+// returned to every thread.
+__device__ __forceinline__ double sys_sum(const double *__restrict__ part, const Map &M, int sys) {
+    return sum_partials(part + M.sys_wg[sys], M.sys_wg[sys + 1] - M.sys_wg[sys]);
+}
+
+// ------------------------------------------------------------------ SpMV
+
+template <typename T, int FMT, int L, int MODE>
+__global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                                  const T *__restrict__ cval, const int32_t *__restrict__ slot_base,
+                                                  const int32_t *__restrict__ jas, const T *__restrict__ bval,
+                                                  const T *__restrict__ x, T *__restrict__ y, T *__restrict__ pout,
+                                                  const double *__restrict__ b, CgState *st, Map M,
+                                                  double *__restrict__ part, int nwg) {
+    const int w = blockIdx.x;
+    const int sys = M.wg_sys[w];
+    if (MODE == kSpmvDot) {
+        if (w == M.sys_wg[sys] && threadIdx.x == 0) st[sys].active = 0;
+        if (st[sys].status != kRunning) return;
+    }
+    const int64_t lo = M.wg_lo[w], hi = M.wg_hi[w];
+    constexpr int R = FMT == MFE_BCRS13 ? kBlock : kBlock / L;  // rows per pass
+    const int g = FMT == MFE_BCRS13 ? threadIdx.x : threadIdx.x / L;
+    const int sub = FMT == MFE_BCRS13 ? 0 : threadIdx.x % L;
+    double d1 = 0.0, d2 = 0.0;
+    for (int64_t base = lo; base < hi; base += R) {
+        const int64_t row = base + g;
+        T sum;
+        if (FMT == MFE_BCRS13) {
+            if (row >= hi) continue;
+            sum = b13_row(slot_base, jas, bval, row, x);
+        } else {
+            sum = csr_row<T, L>(ptr, col, cval, row < hi ? row : -1, sub, x);
+            if (sub != 0 || row >= hi) continue;
+        }
+        if (MODE == kSpmvDot) {
+            y[row] = sum;
+            d1 += (double)x[row] * (double)sum;
+        } else if (MODE == kSpmvResid) {
+            const double bi = b[row], r = bi - (double)sum;
+            y[row] = (T)r;
+            pout[row] = (T)r;
+            d1 += r * r;
+            d2 += bi * bi;
+        } else {  // kSpmvTrue
+            const double r = b[row] - (double)sum;
+            d1 += r * r;
+        }
+    }
+    d1 = block_sum(d1);
+    if (MODE == kSpmvResid) d2 = block_sum(d2);
+    if (threadIdx.x == 0) {
+        part[w] = d1;
+        if (MODE == kSpmvResid) part[nwg + w] = d2;
+    }
+}
+
+// ------------------------------------------------------------------ vector updates
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bupdate_r(T *__restrict__ r, const T *__restrict__ q, CgState *st, Map M,
+                                                      const double *__restrict__ pq_part,
+                                                      double *__restrict__ rr_part) {
+    const int w = blockIdx.x;
+    const int sys = M.wg_sys[w];
+    CgState &S = st[sys];
+    if (S.status != kRunning) return;
+    const double pq = sys_sum(pq_part, M, sys);
+    const double rho = S.rho;
+    const bool first = w == M.sys_wg[sys] && threadIdx.x == 0;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (first) {
+            S.pq = pq;
+            S.status = kBreakdown;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    if (first) {
+        S.pq = pq;
+        S.alpha = alpha;
+        S.rho_old = rho;
+        S.active = 1;
+    }
+    const T a = (T)alpha;
+    double d = 0.0;
+    for (int64_t i = M.wg_lo[w] + threadIdx.x; i < M.wg_hi[w]; i += kBlock) {
+        const T ri = r[i] - a * q[i];
+        r[i] = ri;
+        d += (double)ri * (double)ri;
+    }
+    d = block_sum(d);
+    if (threadIdx.x == 0) rr_part[w] = d;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_bupdate_xp(T *__restrict__ x, T *__restrict__ p, const T *__restrict__ r,
+                                                       CgState *st, Map M, const double *__restrict__ rr_part) {
+    const int w = blockIdx.x;
+    const int sys = M.wg_sys[w];
+    CgState &S = st[sys];
+    if (!S.active) return;
+    const double rho_new = sys_sum(rr_part, M, sys);
+    const double alpha = S.alpha, beta = rho_new / S.rho_old;
+    if (w == M.sys_wg[sys] && threadIdx.x == 0) {
+        const int it = S.iters + 1;
+        const double res = sqrt(rho_new) / S.bnorm;
+        S.iters = it;
+        S.rho = rho_new;
+        if (S.hist) S.hist[it] = res;
+        if (!isfinite(res)) S.status = kBreakdown;
+        else if (res <= S.tol) S.status = kConverged;
+        else if (it >= S.max_iter) S.status = kCapped;
+    }
+    const T a = (T)alpha, be = (T)beta;
+    for (int64_t i = M.wg_lo[w] + threadIdx.x; i < M.wg_hi[w]; i += kBlock) {
+        const T pi = p[i];
+        x[i] += a * pi;
+        p[i] = r[i] + be * pi;
+    }
+}
+
+// One workgroup per system.  kind kFinStart: the CG start test from the
+// partials (r.r, b.b); kFinTrue: ||b - A x||^2.  With `gate` non-null a
+// system whose gate state is not running is marked converged (frozen).
+template <int KIND>
+__global__ __launch_bounds__(kBlock) void k_bfinalize(const double *__restrict__ part, int nwg, CgState *st, Map M,
+                                                      const CgState *gate) {
+    const int sys = blockIdx.x;
+    const double s1 = sys_sum(part, M, sys);
+    double s2 = 0.0;
+    if (KIND == kFinStart) s2 = sys_sum(part + nwg, M, sys);
+    if (threadIdx.x != 0) return;
+    CgState &S = st[sys];
+    if (KIND == kFinTrue) {
+        S.rr_true = s1;
+        return;
+    }
+    if (gate && gate[sys].status != kRunning) {
+        S.status = kConverged;
+        S.iters = 0;
+        S.active = 0;
+        return;
+    }
+    const double bnorm = sqrt(s2);
+    S.bnorm = bnorm;
+    S.iters = 0;
+    S.active = 0;
+    if (bnorm == 0.0) {
+        S.rho = 0.0;
+        S.zero_x = 1;
+        S.status = kConverged;
+    } else {
+        S.rho = s1;
+        const double res = sqrt(s1) / bnorm;
+        if (!isfinite(res)) S.status = kBreakdown;
+        else if (res <= S.tol) S.status = kConverged;
+        else if (S.max_iter <= 0) S.status = kCapped;
+        else S.status = kRunning;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_bzero_if(double *__restrict__ x, const CgState *st, Map M) {
+    const int w = blockIdx.x;
+    if (!st[M.wg_sys[w]].zero_x) return;
+    for (int64_t i = M.wg_lo[w] + threadIdx.x; i < M.wg_hi[w]; i += kBlock) x[i] = 0.0;
+}
+
+// mixed precision: r32 = fl32(r / s_sys), p32 = r32, d32 = 0 for running systems
+__global__ __launch_bounds__(kBlock) void k_bmixed_start(const double *__restrict__ r, const CgState *outer, Map M,
+                                                         float *__restrict__ r32, float *__restrict__ p32,
+                                                         float *__restrict__ d32, double *__restrict__ part, int nwg) {
+    const int w = blockIdx.x;
+    const int sys = M.wg_sys[w];
+    double acc = 0.0;
+    if (outer[sys].status == kRunning) {
+        const double s = sqrt(outer[sys].rho);
+        for (int64_t i = M.wg_lo[w] + threadIdx.x; i < M.wg_hi[w]; i += kBlock) {
+            const float v = (float)(r[i] / s);
+            r32[i] = v;
+            p32[i] = v;
+            d32[i] = 0.0f;
+            acc += (double)v * (double)v;
+        }
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) {
+        part[w] = acc;
+        part[nwg + w] = acc;
+    }
+}
+
+// x += s_sys d for systems refined in this outer step
+__global__ __launch_bounds__(kBlock) void k_bmixed_update(double *__restrict__ x, const float *__restrict__ d32,
+                                                          const CgState *outer, Map M) {
+    const int w = blockIdx.x;
+    const int sys = M.wg_sys[w];
+    if (outer[sys].status != kRunning) return;
+    const double s = sqrt(outer[sys].rho);
+    for (int64_t i = M.wg_lo[w] + threadIdx.x; i < M.wg_hi[w]; i += kBlock) x[i] += s * (double)d32[i];
+}
+
+}  // namespace
+}  // namespace mfe
+
+using namespace mfe;
+
+struct mfe_batch {
+    mfe_ctx *ctx = nullptr;
+    int nsys = 0;
+    std::vector<int> N;         // 3 per system
+    std::vector<int64_t> row0;  // nsys + 1
+    mfe_problem *P = nullptr;   // block-diagonal matrix and workspace
+    Buffer wg_sys, wg_lo, wg_hi, sys_wg, states, part_a, part_b, r32, p32, q32, d32;
+    int nwg = 0;
+    int map_format = 0;
+    Tuning map_tuning;
+    Tuning tuned[3];  // per format (index = format flag)
+    bool has_tuning[3] = {false, false, false};
+    void *pinned = nullptr;  // nsys CgState
+    struct GraphEntry {
+        int format, lanes, factor, k;
+        bool f32;
+        const void *x;
+        const void *st;
+        hipGraphExec_t exec;
+    };
+    std::vector<GraphEntry> graphs;
+};
+
+namespace mfe {
+namespace {
+
+Map map_of(const mfe_batch *B) {
+    return Map{(const int32_t *)B->wg_sys.ptr, (const int64_t *)B->wg_lo.ptr, (const int64_t *)B->wg_hi.ptr,
+               (const int32_t *)B->sys_wg.ptr};
+}
+
+template <typename T, int FMT, int L, int MODE>
+const void *bspmv_kernel() {
+    return (const void *)k_bspmv<T, FMT, L, MODE>;
+}
+
+int resident_for(int format, int lanes) {
+    const void *k = format == MFE_BCRS13 ? bspmv_kernel<double, MFE_BCRS13, 1, kSpmvDot>()
+                    : lanes == 8        ? bspmv_kernel<double, MFE_CSR, 8, kSpmvDot>()
+                    : lanes == 16       ? bspmv_kernel<double, MFE_CSR, 16, kSpmvDot>()
+                                        : bspmv_kernel<double, MFE_CSR, 32, kSpmvDot>();
+    return resident_per_cu(k);
+}
+
+void release_batch_graphs(mfe_batch *B) {
+    for (auto &g : B->graphs) (void)hipGraphExecDestroy(g.exec);
+    B->graphs.clear();
+}
+
+// Workgroup -> (system, row chunk) map for a grid of about `target` groups.
+int build_map(mfe_batch *B, int format, const Tuning &t) {
+    if (B->nwg > 0 && B->map_format == format && B->map_tuning.lanes == t.lanes && B->map_tuning.factor == t.factor)
+        return MFE_OK;
+    mfe_ctx *ctx = B->ctx;
+    const int64_t mt = B->row0[B->nsys];
+    const long target = (long)ctx->num_cu * resident_for(format, t.lanes) * t.factor;
+    std::vector<int32_t> wsys, swg(B->nsys + 1);
+    std::vector<int64_t> wlo, whi;
+    for (int j = 0; j < B->nsys; ++j) {
+        const int64_t mj = B->row0[j + 1] - B->row0[j];
+        int64_t gj = (int64_t)std::llround((double)target * (double)mj / (double)mt);
+        if (gj < 1) gj = 1;
+        int64_t chunk = (mj + gj - 1) / gj;
+        chunk = (chunk + 63) / 64 * 64;
+        swg[j] = (int32_t)wsys.size();
+        for (int64_t a = 0; a < mj; a += chunk) {
+            wsys.push_back(j);
+            wlo.push_back(B->row0[j] + a);
+            whi.push_back(B->row0[j] + std::min(mj, a + chunk));
+        }
+    }
+    swg[B->nsys] = (int32_t)wsys.size();
+    const int nwg = (int)wsys.size();
+    if (nwg > B->nwg || !B->wg_sys.ptr) {
+        dev_free(ctx, &B->wg_sys);
+        dev_free(ctx, &B->wg_lo);
+        dev_free(ctx, &B->wg_hi);
+        dev_free(ctx, &B->part_a);
+        dev_free(ctx, &B->part_b);
+        MFE_TRY(dev_alloc(ctx, &B->wg_sys, nwg * sizeof(int32_t)));
+        MFE_TRY(dev_alloc(ctx, &B->wg_lo, nwg * sizeof(int64_t)));
+        MFE_TRY(dev_alloc(ctx, &B->wg_hi, nwg * sizeof(int64_t)));
+        MFE_TRY(dev_alloc(ctx, &B->part_a, 2 * nwg * sizeof(double)));
+        MFE_TRY(dev_alloc(ctx, &B->part_b, 2 * nwg * sizeof(double)));
+    }
+    hipStream_t s = ctx->stream;
+    MFE_HIP_TRY(hipMemcpyAsync(B->wg_sys.ptr, wsys.data(), nwg * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipMemcpyAsync(B->wg_lo.ptr, wlo.data(), nwg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipMemcpyAsync(B->wg_hi.ptr, whi.data(), nwg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipMemcpyAsync(B->sys_wg.ptr, swg.data(), (B->nsys + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    B->nwg = nwg;
+    B->map_format = format;
+    B->map_tuning = t;
+    release_batch_graphs(B);  // graphs bake the old map's grid size
+    return MFE_OK;
+}
+
+template <typename T, int FMT, int L, int MODE>
+void launch_b(const mfe_batch *B, const T *x, T *y, T *pout, const double *b, CgState *st, double *part,
+              hipStream_t s) {
+    const mfe_problem *P = B->P;
+    const T *cval = std::is_same<T, double>::value ? (const T *)P->val64.ptr : (const T *)P->val32.ptr;
+    const T *bval = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
+    hipLaunchKernelGGL((k_bspmv<T, FMT, L, MODE>), dim3(B->nwg), dim3(kBlock), 0, s, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, cval, (const int32_t *)P->slot_base.ptr,
+                       (const int32_t *)P->jas.ptr, bval, x, y, pout, b, st, map_of(B), part, B->nwg);
+}
+
+template <typename T, int MODE>
+int bspmv(const mfe_batch *B, int format, const Tuning &t, const void *x, void *y, void *pout, const double *b,
+          CgState *st, double *part, hipStream_t s) {
+    const T *xx = (const T *)x;
+    T *yy = (T *)y, *pp = (T *)pout;
+    if (format == MFE_BCRS13) launch_b<T, MFE_BCRS13, 1, MODE>(B, xx, yy, pp, b, st, part, s);
+    else if (t.lanes == 8) launch_b<T, MFE_CSR, 8, MODE>(B, xx, yy, pp, b, st, part, s);
+    else if (t.lanes == 16) launch_b<T, MFE_CSR, 16, MODE>(B, xx, yy, pp, b, st, part, s);
+    else launch_b<T, MFE_CSR, 32, MODE>(B, xx, yy, pp, b, st, part, s);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int bfinalize(const mfe_batch *B, FinalizeKind kind, const double *part, CgState *st, const CgState *gate,
+              hipStream_t s) {
+    if (kind == kFinStart)
+        hipLaunchKernelGGL(k_bfinalize<kFinStart>, dim3(B->nsys), dim3(kBlock), 0, s, part, B->nwg, st, map_of(B),
+                           gate);
+    else
+        hipLaunchKernelGGL(k_bfinalize<kFinTrue>, dim3(B->nsys), dim3(kBlock), 0, s, part, B->nwg, st, map_of(B),
+                           gate);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+template <typename T>
+int capture_iterations(mfe_batch *B, int format, const Tuning &t, T *x, T *r, T *p, T *q, CgState *st, int k,
+                       hipGraphExec_t *out) {
+    hipStream_t cs = B->ctx->cap_stream;
+    double *pa = (double *)B->part_a.ptr, *pb = (double *)B->part_b.ptr;
+    MFE_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    int rc = MFE_OK;
+    const Map M = map_of(B);
+    for (int i = 0; i < k && rc == MFE_OK; ++i) {
+        rc = bspmv<T, kSpmvDot>(B, format, t, p, q, nullptr, nullptr, st, pa, cs);
+        if (rc == MFE_OK) {
+            hipLaunchKernelGGL(k_bupdate_r<T>, dim3(B->nwg), dim3(kBlock), 0, cs, r, (const T *)q, st, M,
+                               (const double *)pa, pb);
+            hipLaunchKernelGGL(k_bupdate_xp<T>, dim3(B->nwg), dim3(kBlock), 0, cs, x, p, (const T *)r, st, M,
+                               (const double *)pb);
+            if (hipGetLastError() != hipSuccess) rc = MFE_EHIP;
+        }
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != MFE_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        set_error("batched iteration capture failed");
+        return rc != MFE_OK ? rc : MFE_EHIP;
+    }
+    const hipError_t e2 = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        set_error(std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e2));
+        return MFE_EHIP;
+    }
+    return MFE_OK;
+}
+
+template <typename T>
+int graph_for_batch(mfe_batch *B, int format, const Tuning &t, bool f32, T *x, T *r, T *p, T *q, CgState *st, int k,
+                    hipGraphExec_t *out) {
+    for (auto &g : B->graphs)
+        if (g.format == format && g.lanes == t.lanes && g.factor == t.factor && g.k == k && g.f32 == f32 &&
+            g.x == x && g.st == st) {
+            *out = g.exec;
+            return MFE_OK;
+        }
+    hipGraphExec_t ex = nullptr;
+    MFE_TRY(capture_iterations<T>(B, format, t, x, r, p, q, st, k, &ex));
+    B->graphs.push_back({format, t.lanes, t.factor, k, f32, x, st, ex});
+    *out = ex;
+    return MFE_OK;
+}
+
+// Copy all system states to the host.
+int read_states(mfe_batch *B, const CgState *st, std::vector<CgState> &out) {
+    hipStream_t s = B->ctx->stream;
+    MFE_HIP_TRY(hipMemcpyAsync(B->pinned, st, B->nsys * sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    const CgState *h = (const CgState *)B->pinned;
+    out.assign(h, h + B->nsys);
+    return MFE_OK;
+}
+
+int set_states(mfe_batch *B, CgState *st, double tol, int max_iter, const std::vector<double> *tols = nullptr) {
+    std::vector<CgState> h(B->nsys);
+    for (int j = 0; j < B->nsys; ++j) {
+        CgState &x = h[j];
+        x = CgState{};
+        x.tol = tols ? (*tols)[j] : tol;
+        x.max_iter = max_iter;
+        x.status = kRunning;
+    }
+    CgState *pin = (CgState *)B->pinned;
+    std::copy(h.begin(), h.end(), pin);
+    MFE_HIP_TRY(hipMemcpyAsync(st, pin, B->nsys * sizeof(CgState), hipMemcpyHostToDevice, B->ctx->stream));
+    MFE_HIP_TRY(hipStreamSynchronize(B->ctx->stream));
+    return MFE_OK;
+}
+
+bool any_running(const std::vector<CgState> &v) {
+    for (const auto &s : v)
+        if (s.status == kRunning) return true;
+    return false;
+}
+
+// Replay the iteration graph until no system runs.
+int run_batch(mfe_batch *B, hipGraphExec_t exec, const CgState *st, int k, int max_iter, std::vector<CgState> &fin) {
+    hipStream_t s = B->ctx->stream;
+    const long limit = (long)max_iter / k + 2;
+    for (long launched = 0;; ++launched) {
+        if (launched > limit) {
+            set_error("batched CG still running after the iteration cap");
+            return MFE_EHIP;
+        }
+        MFE_HIP_TRY(hipGraphLaunch(exec, s));
+        MFE_TRY(read_states(B, st, fin));
+        if (!any_running(fin)) return MFE_OK;
+    }
+}
+
+// FP64 batched CG on all systems from x.  out_states: final states.
+int batch_cg_fp64(mfe_batch *B, int format, const Tuning &t, double *x, double tol, int max_iter,
+                  std::vector<CgState> &fin, std::vector<double> &rel_true) {
+    mfe_problem *P = B->P;
+    hipStream_t s = B->ctx->stream;
+    CgState *st = (CgState *)B->states.ptr;
+    double *pa = (double *)B->part_a.ptr;
+    MFE_TRY(set_states(B, st, tol, max_iter));
+    MFE_TRY(bspmv<double, kSpmvResid>(B, format, t, x, P->r.ptr, P->p.ptr, (const double *)P->b.ptr, st, pa, s));
+    MFE_TRY(bfinalize(B, kFinStart, pa, st, nullptr, s));
+    hipLaunchKernelGGL(k_bzero_if, dim3(B->nwg), dim3(kBlock), 0, s, x, (const CgState *)st, map_of(B));
+    MFE_HIP_TRY(hipGetLastError());
+    MFE_TRY(read_states(B, st, fin));
+    if (any_running(fin)) {
+        const int k = std::min(kGraphIters, max_iter);
+        hipGraphExec_t exec = nullptr;
+        MFE_TRY(graph_for_batch<double>(B, format, t, false, x, (double *)P->r.ptr, (double *)P->p.ptr,
+                                        (double *)P->q.ptr, st, k, &exec));
+        MFE_TRY(run_batch(B, exec, st, k, max_iter, fin));
+    }
+    MFE_TRY(bspmv<double, kSpmvTrue>(B, format, t, x, nullptr, nullptr, (const double *)P->b.ptr, st, pa, s));
+    MFE_TRY(bfinalize(B, kFinTrue, pa, st, nullptr, s));
+    std::vector<CgState> tr;
+    MFE_TRY(read_states(B, st, tr));
+    rel_true.resize(B->nsys);
+    for (int j = 0; j < B->nsys; ++j)
+        rel_true[j] = fin[j].bnorm > 0 ? std::sqrt(tr[j].rr_true) / fin[j].bnorm : 0.0;
+    return MFE_OK;
+}
+
+int ensure_batch_ws(mfe_batch *B, bool mixed) {
+    MFE_TRY(ensure_workspace(B->P));
+    mfe_ctx *ctx = B->ctx;
+    if (!B->states.ptr) MFE_TRY(dev_alloc(ctx, &B->states, 2 * B->nsys * sizeof(CgState)));
+    if (mixed) {
+        const size_t fb = (size_t)B->P->m * sizeof(float);
+        if (!B->r32.ptr) MFE_TRY(dev_alloc(ctx, &B->r32, fb));
+        if (!B->p32.ptr) MFE_TRY(dev_alloc(ctx, &B->p32, fb));
+        if (!B->q32.ptr) MFE_TRY(dev_alloc(ctx, &B->q32, fb));
+        if (!B->d32.ptr) MFE_TRY(dev_alloc(ctx, &B->d32, fb));
+    }
+    return MFE_OK;
+}
+
+int status_of(const CgState &s) {
+    if (s.status == kCapped) return MFE_NOT_CONVERGED;
+    if (s.status == kBreakdown) return MFE_EBREAKDOWN;
+    return MFE_OK;
+}
+
+// Time the batched SpMV kernel under tuning t (ms per launch).
+int time_spmv(mfe_batch *B, int format, const Tuning &t, double *ms) {
+    MFE_TRY(build_map(B, format, t));
+    MFE_TRY(ensure_batch_ws(B, false));
+    mfe_problem *P = B->P;
+    hipStream_t s = B->ctx->stream;
+    CgState *st = (CgState *)B->states.ptr;
+    MFE_TRY(set_states(B, st, 0.0, 1));  // running states so the Dot kernel works
+    hipEvent_t e0, e1;
+    MFE_HIP_TRY(hipEventCreate(&e0));
+    MFE_HIP_TRY(hipEventCreate(&e1));
+    const int reps = 5;
+    int rc = bspmv<double, kSpmvDot>(B, format, t, P->b.ptr, P->q.ptr, nullptr, nullptr, st,
+                                     (double *)B->part_a.ptr, s);  // warm-up
+    if (rc == MFE_OK && hipEventRecord(e0, s) != hipSuccess) rc = MFE_EHIP;
+    for (int i = 0; i < reps && rc == MFE_OK; ++i)
+        rc = bspmv<double, kSpmvDot>(B, format, t, P->b.ptr, P->q.ptr, nullptr, nullptr, st, (double *)B->part_a.ptr,
+                                     s);
+    float f = 0.f;
+    if (rc == MFE_OK && (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                         hipEventElapsedTime(&f, e0, e1) != hipSuccess))
+        rc = MFE_EHIP;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rc != MFE_OK) {
+        if (rc == MFE_EHIP) set_error("autotune timing failed");
+        return rc;
+    }
+    *ms = f / reps;
+    return MFE_OK;
+}
+
+int tuning_for(mfe_batch *B, int format, Tuning *t) {
+    if (B->has_tuning[format]) {
+        *t = B->tuned[format];
+        return MFE_OK;
+    }
+    *t = Tuning{};
+    return MFE_OK;
+}
+
+}  // namespace
+}  // namespace mfe
+
+extern "C" {
+
+int mfe_batch_create(mfe_ctx *ctx, int nsys, const int32_t *sizes, const double *face_vals, int formats,
+                     int precisions, mfe_batch **out) {
+    clear_error();
+    if (!ctx || !out || !sizes || nsys < 1) {
+        set_error("ctx, sizes and out must be non-NULL and nsys >= 1");
+        return MFE_EINVAL;
+    }
+    *out = nullptr;
+    if ((formats & ~(MFE_CSR | MFE_BCRS13)) || (precisions & ~(MFE_F64 | MFE_F32))) {
+        set_error("unknown format or precision flag");
+        return MFE_EINVAL;
+    }
+    std::vector<int64_t> row0(nsys + 1, 0), nnz0(nsys + 1, 0);
+    for (int j = 0; j < nsys; ++j) {
+        const int Nx = sizes[3 * j], Ny = sizes[3 * j + 1], Nz = sizes[3 * j + 2];
+        if (Nx < 1 || Ny < 1 || Nz < 1) {
+            set_error("every mesh needs Nx, Ny, Nz >= 1");
+            return MFE_EINVAL;
+        }
+        row0[j + 1] = row0[j] + (int64_t)(Nx + 1) * (Ny + 1) * (Nz + 1);
+        nnz0[j + 1] = nnz0[j] + (3 * (int64_t)Nx + 1) * (3 * (int64_t)Ny + 1) * (3 * (int64_t)Nz + 1);
+    }
+    if (nnz0[nsys] >= ((int64_t)1 << 31) - 1 || row0[nsys] >= ((int64_t)1 << 31) - 1) {
+        set_error("batch too large for 32-bit row pointers");
+        return MFE_EUNSUPPORTED;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return MFE_EHIP;
+    }
+    mfe_batch *B = new (std::nothrow) mfe_batch();
+    mfe_problem *P = new (std::nothrow) mfe_problem();
+    if (!B || !P) {
+        delete B;
+        delete P;
+        set_error("host allocation failed");
+        return MFE_ENOMEM;
+    }
+    B->ctx = ctx;
+    B->nsys = nsys;
+    B->N.assign(sizes, sizes + 3 * nsys);
+    B->row0 = row0;
+    B->P = P;
+    P->ctx = ctx;
+    P->m = row0[nsys];
+    P->nnz = nnz0[nsys];
+    P->formats = formats | MFE_CSR;
+    P->precisions = precisions | MFE_F64;
+    int rc = dev_alloc(ctx, &P->ptr, (size_t)(P->m + 1) * sizeof(int32_t));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->col, (size_t)P->nnz * sizeof(int32_t));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->val64, (size_t)P->nnz * sizeof(double));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->b, (size_t)P->m * sizeof(double));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &B->sys_wg, (nsys + 1) * sizeof(int32_t));
+    for (int j = 0; j < nsys && rc == MFE_OK; ++j)
+        rc = launch_assemble_into(ctx->stream, sizes[3 * j], sizes[3 * j + 1], sizes[3 * j + 2],
+                                  face_vals ? face_vals + 6 * j : nullptr, nullptr, row0[j], nnz0[j],
+                                  (int32_t *)P->ptr.ptr, (int32_t *)P->col.ptr, (double *)P->val64.ptr,
+                                  (double *)P->b.ptr, false);
+    if (rc == MFE_OK) rc = finish_problem(P);
+    if (rc == MFE_OK && hipHostMalloc(&B->pinned, nsys * sizeof(CgState), hipHostMallocDefault) != hipSuccess) {
+        set_error("hipHostMalloc failed");
+        rc = MFE_EHIP;
+    }
+    if (rc != MFE_OK) {
+        mfe_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return MFE_OK;
+}
+
+int mfe_batch_destroy(mfe_batch *B) {
+    if (!B) return MFE_OK;
+    mfe_ctx *ctx = B->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    release_batch_graphs(B);
+    Buffer *bufs[] = {&B->wg_sys, &B->wg_lo, &B->wg_hi, &B->sys_wg, &B->states, &B->part_a, &B->part_b,
+                      &B->r32,    &B->p32,   &B->q32,   &B->d32};
+    for (Buffer *b : bufs) dev_free(ctx, b);
+    if (B->P) {
+        free_problem_storage(B->P);
+        delete B->P;
+    }
+    if (B->pinned) (void)hipHostFree(B->pinned);
+    delete B;
+    return MFE_OK;
+}
+
+int mfe_batch_info(const mfe_batch *B, int64_t *m_total, int64_t *nnz_total, int64_t *row_offsets) {
+    clear_error();
+    if (!B) {
+        set_error("batch is NULL");
+        return MFE_EINVAL;
+    }
+    if (m_total) *m_total = B->P->m;
+    if (nnz_total) *nnz_total = B->P->nnz;
+    if (row_offsets)
+        for (int j = 0; j <= B->nsys; ++j) row_offsets[j] = B->row0[j];
+    return MFE_OK;
+}
+
+int mfe_batch_export_csr(const mfe_batch *B, int32_t *ptr_dev, int32_t *col_dev, double *val_dev, double *b_dev) {
+    clear_error();
+    if (!B) {
+        set_error("batch is NULL");
+        return MFE_EINVAL;
+    }
+    return mfe_problem_export_csr(B->P, ptr_dev, col_dev, val_dev, b_dev);
+}
+
+int mfe_batch_autotune(mfe_batch *B, int format, int *lanes_out, int *factor_out) {
+    clear_error();
+    if (!B || (format != MFE_CSR && format != MFE_BCRS13) || !(B->P->formats & format)) {
+        set_error("batch must be non-NULL and the format built");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return MFE_EHIP;
+    static const int lanes_c[3] = {8, 16, 32};
+    static const int factors[3] = {1, 2, 4};
+    Tuning best{};
+    double best_ms = 1e300;
+    for (int li = 0; li < 3; ++li) {
+        if (format == MFE_BCRS13 && li > 0) break;  // one lane per row
+        for (int fi = 0; fi < 3; ++fi) {
+            Tuning t;
+            t.lanes = format == MFE_BCRS13 ? 1 : lanes_c[li];
+            t.factor = factors[fi];
+            double ms = 0;
+            MFE_TRY(time_spmv(B, format, t, &ms));
+            if (ms < best_ms) {
+                best_ms = ms;
+                best = t;
+            }
+        }
+    }
+    B->tuned[format] = best;
+    B->has_tuning[format] = true;
+    if (lanes_out) *lanes_out = best.lanes;
+    if (factor_out) *factor_out = best.factor;
+    return MFE_OK;
+}
+
+int mfe_batch_cg(mfe_batch *B, int format, double *x_dev, double tol, int max_iter, mfe_cg_stats *stats) {
+    clear_error();
+    if (!B || !x_dev || !(tol >= 0.0) || max_iter < 0 || (format != MFE_CSR && format != MFE_BCRS13) ||
+        !(B->P->formats & format)) {
+        set_error("need batch, x, tol >= 0, max_iter >= 0 and a built format");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return MFE_EHIP;
+    const auto t0 = std::chrono::steady_clock::now();
+    Tuning t;
+    MFE_TRY(tuning_for(B, format, &t));
+    MFE_TRY(build_map(B, format, t));
+    MFE_TRY(ensure_batch_ws(B, false));
+    std::vector<CgState> fin;
+    std::vector<double> rel;
+    MFE_TRY(batch_cg_fp64(B, format, t, x_dev, tol, max_iter, fin, rel));
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int rc = MFE_OK;
+    for (int j = 0; j < B->nsys; ++j) {
+        const int sj = status_of(fin[j]);
+        if (sj == MFE_EBREAKDOWN || (sj == MFE_NOT_CONVERGED && rc == MFE_OK)) rc = sj;
+        if (stats) {
+            stats[j].status = sj;
+            stats[j].iterations = fin[j].iters;
+            stats[j].outer = 0;
+            stats[j].spmv_count = fin[j].iters + 2;
+            stats[j].rel_res_recurrence = fin[j].bnorm > 0 ? std::sqrt(fin[j].rho) / fin[j].bnorm : 0.0;
+            stats[j].rel_res_true = rel[j];
+            stats[j].seconds = secs;
+        }
+    }
+    return rc;
+}
+
+int mfe_batch_cg_mixed(mfe_batch *B, int format, double *x_dev, double tol, double inner_tol, int max_outer,
+                       int max_inner, mfe_cg_stats *stats) {
+    clear_error();
+    if (!B || !x_dev || !(tol >= 0.0) || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1 || max_inner < 1 ||
+        (format != MFE_CSR && format != MFE_BCRS13) || !(B->P->formats & format)) {
+        set_error("need batch, x, tol >= 0, 0 < inner_tol < 1, max_outer, max_inner >= 1 and a built format");
+        return MFE_EINVAL;
+    }
+    if (!(B->P->precisions & MFE_F32)) {
+        set_error("FP32 values were not built for this batch");
+        return MFE_EUNSUPPORTED;
+    }
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return MFE_EHIP;
+    const auto t0 = std::chrono::steady_clock::now();
+    Tuning t;
+    MFE_TRY(tuning_for(B, format, &t));
+    MFE_TRY(build_map(B, format, t));
+    MFE_TRY(ensure_batch_ws(B, true));
+    mfe_problem *P = B->P;
+    hipStream_t s = B->ctx->stream;
+    const int ns = B->nsys;
+    CgState *outer = (CgState *)B->states.ptr, *inner = outer + ns;
+    double *pa = (double *)B->part_a.ptr;
+    const Map M = map_of(B);
+    std::vector<int> outer_steps(ns, 0), inner_its(ns, 0);
+    std::vector<CgState> o, in;
+    std::vector<double> bnorm(ns), prev(ns);
+    auto outer_residual = [&]() -> int {
+        MFE_TRY(set_states(B, outer, tol, 1));
+        MFE_TRY(bspmv<double, kSpmvResid>(B, format, t, x_dev, P->r.ptr, P->p.ptr, (const double *)P->b.ptr, outer,
+                                          pa, s));
+        MFE_TRY(bfinalize(B, kFinStart, pa, outer, nullptr, s));
+        return read_states(B, outer, o);
+    };
+    MFE_TRY(outer_residual());
+    hipLaunchKernelGGL(k_bzero_if, dim3(B->nwg), dim3(kBlock), 0, s, x_dev, (const CgState *)outer, M);
+    for (int j = 0; j < ns; ++j) {
+        bnorm[j] = o[j].bnorm;
+        prev[j] = std::sqrt(o[j].rho);
+    }
+    bool fallback = false;
+    int step = 0;
+    while (any_running(o)) {
+        if (step >= max_outer) break;
+        // per-system inner tolerance: no tighter than its outer target needs
+        std::vector<double> eff(ns, inner_tol);
+        for (int j = 0; j < ns; ++j)
+            if (o[j].status == kRunning && prev[j] > 0)
+                eff[j] = std::min(0.5, std::max(inner_tol, 0.5 * tol * bnorm[j] / prev[j]));
+        MFE_TRY(set_states(B, inner, inner_tol, max_inner, &eff));
+        hipLaunchKernelGGL(k_bmixed_start, dim3(B->nwg), dim3(kBlock), 0, s, (const double *)P->r.ptr,
+                           (const CgState *)outer, M, (float *)B->r32.ptr, (float *)B->p32.ptr, (float *)B->d32.ptr, pa,
+                           B->nwg);
+        MFE_HIP_TRY(hipGetLastError());
+        MFE_TRY(bfinalize(B, kFinStart, pa, inner, outer, s));
+        const int k = std::min(kGraphIters, max_inner);
+        hipGraphExec_t exec = nullptr;
+        MFE_TRY(graph_for_batch<float>(B, format, t, true, (float *)B->d32.ptr, (float *)B->r32.ptr,
+                                       (float *)B->p32.ptr, (float *)B->q32.ptr, inner, k, &exec));
+        MFE_TRY(run_batch(B, exec, inner, k, max_inner, in));
+        bool breakdown = false;
+        for (int j = 0; j < ns; ++j)
+            if (o[j].status == kRunning) {
+                inner_its[j] += in[j].iters;
+                outer_steps[j] += 1;
+                breakdown = breakdown || in[j].status == kBreakdown;
+            }
+        hipLaunchKernelGGL(k_bmixed_update, dim3(B->nwg), dim3(kBlock), 0, s, x_dev, (const float *)B->d32.ptr,
+                           (const CgState *)outer, M);
+        MFE_HIP_TRY(hipGetLastError());
+        ++step;
+        std::vector<CgState> before = o;
+        MFE_TRY(outer_residual());
+        bool stagnated = false;
+        for (int j = 0; j < ns; ++j)
+            if (before[j].status == kRunning) {
+                const double cur = std::sqrt(o[j].rho);
+                if (o[j].status == kRunning && !(cur <= 0.5 * prev[j])) stagnated = true;
+                prev[j] = cur;
+            }
+        if (breakdown || stagnated) {
+            fallback = true;
+            break;
+        }
+    }
+    std::vector<double> rel(ns);
+    for (int j = 0; j < ns; ++j) rel[j] = bnorm[j] > 0 ? std::sqrt(o[j].rho) / bnorm[j] : 0.0;
+    std::vector<int> st_code(ns, MFE_OK), fb_its(ns, 0);
+    for (int j = 0; j < ns; ++j)
+        if (o[j].status == kRunning) st_code[j] = MFE_NOT_CONVERGED;
+    if (fallback) {
+        std::vector<CgState> fin;
+        MFE_TRY(batch_cg_fp64(B, format, t, x_dev, tol, max_inner * max_outer, fin, rel));
+        for (int j = 0; j < ns; ++j) {
+            st_code[j] = status_of(fin[j]);
+            fb_its[j] = fin[j].iters;
+        }
+    }
+    const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    int rc = MFE_OK;
+    for (int j = 0; j < ns; ++j) {
+        if (st_code[j] == MFE_EBREAKDOWN || (st_code[j] == MFE_NOT_CONVERGED && rc == MFE_OK)) rc = st_code[j];
+        if (stats) {
+            stats[j].status = st_code[j];
+            stats[j].iterations = inner_its[j] + fb_its[j];
+            stats[j].outer = outer_steps[j];
+            stats[j].spmv_count = inner_its[j] + fb_its[j] + outer_steps[j] + 1;
+            stats[j].rel_res_recurrence = rel[j];
+            stats[j].rel_res_true = rel[j];
+            stats[j].seconds = secs;
+        }
+    }
+    return rc;
+}
+
+}  // extern "C"

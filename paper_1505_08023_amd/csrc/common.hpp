@@ -26,9 +26,9 @@ void clear_error();
         }                                                                         \
     } while (0)
 
-#define MFE_TRY(expr)            \
-    do {                         \
-        int s_ = (expr);         \
+#define MFE_TRY(...)                 \
+    do {                             \
+        int s_ = (__VA_ARGS__);      \
         if (s_ != MFE_OK) return s_; \
     } while (0)
 
@@ -127,6 +127,9 @@ namespace mfe {
 // assembly (assemble.hip)
 int launch_assemble(mfe_problem *P, const double *face_vals, const double *node_g, bool values_and_rhs,
                     bool rhs_only);
+int launch_assemble_into(hipStream_t s, int Nx, int Ny, int Nz, const double *face_vals, const double *node_g,
+                         int64_t row_off, int64_t nnz_off, int32_t *ptr, int32_t *col, double *val, double *b,
+                         bool rhs_only);
 
 // formats (formats.hip)
 int build_bcrs13(mfe_problem *P);
@@ -154,6 +157,10 @@ struct SpmvArgs {
 // *grid (optional) receives the number of workgroups, i.e. of partials written.
 int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const SpmvArgs &a,
                 hipStream_t s, int *grid = nullptr);
+
+// problem storage (api.hip)
+void free_problem_storage(mfe_problem *P);
+int finish_problem(mfe_problem *P);
 
 // CG driver (cg.hip)
 constexpr int kGraphIters = 16;  // CG iterations per captured graph

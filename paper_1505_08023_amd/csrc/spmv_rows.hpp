@@ -1,0 +1,84 @@
+// Row-level SpMV building blocks shared by the single-system and batched
+// kernels (Sec. 3.1: CRS row of Fig 3.1; 1x3 segments of Figs 3.2/3.3).
+#pragma once
+
+#include "b13_layout.hpp"
+#include "common.hpp"
+#include "device_util.hpp"
+
+namespace mfe {
+
+// CRS row by L lanes (L a power of two dividing 64): lane `sub` takes
+// entries sub, sub+L, ...; the xor butterfly leaves the row sum in every lane
+// of the group.  row < 0: no row (the lanes still join the butterfly).
+template <typename T, int L>
+__device__ __forceinline__ T csr_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                     const T *__restrict__ val, int64_t row, int sub, const T *__restrict__ x) {
+    T sum = 0;
+    if (row >= 0) {
+        const int32_t lo = ptr[row], hi = ptr[row + 1];
+        for (int32_t j = lo + sub; j < hi; j += L) sum += matrix_load(val + j) * x[matrix_load(col + j)];
+    }
+#pragma unroll
+    for (int off = L / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, L);
+    return sum;
+}
+
+template <typename T>
+using vec2_t = T __attribute__((ext_vector_type(2)));
+typedef int32_t int4_t __attribute__((ext_vector_type(4)));
+
+// Any slice: one block at a time.
+template <typename T>
+__device__ __forceinline__ T b13_row_generic(const int32_t *jas, const T *val, const B13Slice &sl, int lane,
+                                             const T *x) {
+    T sum = 0;
+    for (int k = 0; k < sl.S; ++k) {
+        const T *xp = x + matrix_load(jas + b13_jas(sl, k, lane));
+        sum += matrix_load(val + b13_val(sl, k, 0, lane)) * xp[0];
+        sum += matrix_load(val + b13_val(sl, k, 1, lane)) * xp[1];
+        sum += matrix_load(val + b13_val(sl, k, 2, lane)) * xp[2];
+    }
+    return sum;
+}
+
+// Slices of 9 blocks per row (3 y-lines x 3 z-planes: every row not on a
+// y or z face): 3 column-index loads and 14 value loads per row, then 27
+// gathers of x, the three of a block at consecutive columns.
+template <typename T>
+__device__ __forceinline__ T b13_row9(const int32_t *jas, const T *val, const B13Slice &sl, int lane,
+                                      const T *x) {
+    const int4_t q0 = matrix_load((const int4_t *)(jas + sl.jbase + lane * 4));
+    const int4_t q1 = matrix_load((const int4_t *)(jas + sl.jbase + 256 + lane * 4));
+    const int32_t c8 = matrix_load(jas + sl.jbase + 512 + lane);
+    const int32_t c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, c8};
+    vec2_t<T> a[9], b[4];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = matrix_load((const vec2_t<T> *)(val + sl.vbase + k * 128 + lane * 2));
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        b[p] = matrix_load((const vec2_t<T> *)(val + sl.vbase + 9 * 128 + p * 128 + lane * 2));
+    const T w8 = matrix_load(val + sl.vbase + 13 * 128 + lane);
+    const T v2[9] = {b[0].x, b[0].y, b[1].x, b[1].y, b[2].x, b[2].y, b[3].x, b[3].y, w8};
+    T sum = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const T *xp = x + c[k];
+        sum += a[k].x * xp[0];
+        sum += a[k].y * xp[1];
+        sum += v2[k] * xp[2];
+    }
+    return sum;
+}
+
+// 1x3 BCRS row `row` (one lane per row).
+template <typename T>
+__device__ __forceinline__ T b13_row(const int32_t *__restrict__ slot_base, const int32_t *__restrict__ jas,
+                                     const T *__restrict__ val, int64_t row, const T *__restrict__ x) {
+    const int64_t s = row >> 6;
+    const int lane = (int)(row & 63);
+    const B13Slice sl = b13_slice(slot_base[s], slot_base[s + 1]);
+    return sl.S == 9 ? b13_row9(jas, val, sl, lane, x) : b13_row_generic(jas, val, sl, lane, x);
+}
+
+}  // namespace mfe

@@ -41,7 +41,7 @@ def _close_all():
     """Release library objects while torch (which owns their memory) is alive."""
     objs = list(_LIVE)
     for o in objs:
-        if isinstance(o, Problem):
+        if isinstance(o, (Problem, Batch)):
             o.close()
     for o in objs:
         if isinstance(o, Context):
@@ -274,6 +274,97 @@ class Problem:
         if self.handle and self.ctx.handle:
             self.ctx.lib.mfe_problem_destroy(self.handle)
         self.handle = None
+
+
+class Batch:
+    """Many box meshes solved together (block-diagonal storage, per-system CG)."""
+
+    def __init__(self, ctx, sizes, face_vals=None, formats=("csr", "bcrs13"), precisions=("f64",)):
+        import numpy as np
+        self.ctx = ctx
+        sizes = np.ascontiguousarray(sizes, dtype=np.int32).reshape(-1, 3)
+        self.nsys = sizes.shape[0]
+        fv = None
+        if face_vals is not None:
+            fv = np.ascontiguousarray(face_vals, dtype=np.float64).reshape(self.nsys, 6)
+        fl = 0
+        for f in formats:
+            fl |= _fmt(f)
+        pr = 0
+        for p in precisions:
+            pr |= {"f64": MFE_F64, "f32": MFE_F32}[p]
+        h = ctypes.c_void_p()
+        with _on(ctx):
+            check(ctx.lib.mfe_batch_create(ctx.handle, self.nsys, sizes.ctypes.data_as(ctypes.c_void_p),
+                                           fv.ctypes.data_as(ctypes.c_void_p) if fv is not None else None,
+                                           fl, pr, ctypes.byref(h)), "mfe_batch_create")
+        self.handle = h
+        m, nnz = ctypes.c_int64(), ctypes.c_int64()
+        offs = np.zeros(self.nsys + 1, dtype=np.int64)
+        check(ctx.lib.mfe_batch_info(h, ctypes.byref(m), ctypes.byref(nnz), offs.ctypes.data_as(ctypes.c_void_p)),
+              "mfe_batch_info")
+        self.m, self.nnz, self.row_offsets = m.value, nnz.value, offs
+        ctx.problems.add(self)
+        _LIVE.add(self)
+
+    def export_csr(self):
+        d = self.ctx.device
+        ptr = torch.empty(self.m + 1, dtype=torch.int32, device=d)
+        col = torch.empty(self.nnz, dtype=torch.int32, device=d)
+        val = torch.empty(self.nnz, dtype=torch.float64, device=d)
+        b = torch.empty(self.m, dtype=torch.float64, device=d)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_batch_export_csr(self.handle, _ptr(ptr, torch.int32), _ptr(col, torch.int32),
+                                                    _ptr(val, torch.float64), _ptr(b, torch.float64)),
+                  "mfe_batch_export_csr")
+        self.ctx.stream.synchronize()
+        return ptr, col, val, b
+
+    def autotune(self, fmt="bcrs13"):
+        lanes, factor = ctypes.c_int(), ctypes.c_int()
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_batch_autotune(self.handle, _fmt(fmt), ctypes.byref(lanes), ctypes.byref(factor)),
+                  "mfe_batch_autotune")
+        return lanes.value, factor.value
+
+    def _stats(self):
+        return (mfe_cg_stats * self.nsys)()
+
+    def cg(self, x=None, tol=1e-8, max_iter=5000, fmt="bcrs13"):
+        if x is None:
+            with _on(self.ctx):
+                x = torch.zeros(self.m, dtype=torch.float64, device=self.ctx.device)
+        st = self._stats()
+        with _on(self.ctx):
+            rc = self.ctx.lib.mfe_batch_cg(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"), float(tol),
+                                           int(max_iter), ctypes.cast(st, ctypes.c_void_p))
+        check(rc, "mfe_batch_cg", (MFE_OK, MFE_NOT_CONVERGED))
+        return x, [s.as_dict() for s in st]
+
+    def cg_mixed(self, x=None, tol=1e-8, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13"):
+        if x is None:
+            with _on(self.ctx):
+                x = torch.zeros(self.m, dtype=torch.float64, device=self.ctx.device)
+        st = self._stats()
+        with _on(self.ctx):
+            rc = self.ctx.lib.mfe_batch_cg_mixed(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"),
+                                                 float(tol), float(inner_tol), int(max_outer), int(max_inner),
+                                                 ctypes.cast(st, ctypes.c_void_p))
+        check(rc, "mfe_batch_cg_mixed", (MFE_OK, MFE_NOT_CONVERGED))
+        return x, [s.as_dict() for s in st]
+
+    def close(self):
+        if self.handle and self.ctx.handle:
+            self.ctx.lib.mfe_batch_destroy(self.handle)
+        self.handle = None
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
 
     def __del__(self):
         if sys.is_finalizing():

@@ -1,0 +1,160 @@
+"""GPU parity of batched solves (many uneven meshes at once) against the oracle.
+
+Every system of a batch must behave as an independent solve:
+  assembly   each diagonal block equals the oracle's matrix of that mesh
+             (values within 8 eps max|A|, b within 64 eps max(|b|, h));
+  CG         per system: ||r||/||b|| <= tol, iteration count within 2 of the
+             oracle's, solution within ||A^-1|| (||r|| + ||r_ref||) of the
+             oracle's (lambda_min in closed form, as for single solves).
+Mesh sizes and face values come from the seeded generator shared with the
+oracle side (paper_1505_08023_amd.inputs.batched_meshes).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1505_08023_amd import inputs
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1505_08023_amd.mfe import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def lam_min(N):
+    def s(h):
+        return (2 - 2 * math.cos(math.pi * h)) / h
+
+    def m(h):
+        return h * (4 + 2 * math.cos(math.pi * h)) / 6
+    hx, hy, hz = (1.0 / n for n in N)
+    return min(s(hx) * m(hy) * m(hz) + m(hx) * s(hy) * m(hz) + m(hx) * m(hy) * s(hz), 1.0)
+
+
+def small_batch(seed=1, nsys=7, lo=3, hi=14):
+    return inputs.batched_meshes(nsys=nsys, lo=lo, hi=hi, seed=seed)
+
+
+def test_batch_assembly_blocks(ctx):
+    from paper_1505_08023_amd.mfe import Batch
+    sizes, faces = small_batch()
+    B = Batch(ctx, sizes, faces)
+    ptr, col, val, b = (t.cpu().numpy() for t in B.export_csr())
+    off = B.row_offsets
+    for j, (N, fv) in enumerate(zip(sizes, faces)):
+        A = oracle.assemble(*N, face_vals=fv)
+        r0, r1 = off[j], off[j + 1]
+        p = ptr[r0:r1 + 1] - ptr[r0]
+        assert np.array_equal(p, A.ptr.astype(np.int32))
+        c = col[ptr[r0]:ptr[r1]] - r0
+        assert np.array_equal(c, A.col)
+        assert np.abs(val[ptr[r0]:ptr[r1]] - A.val).max() <= 8 * EPS * np.abs(A.val).max()
+        assert np.abs(b[r0:r1] - A.b).max() <= 64 * EPS * max(np.abs(A.b).max(), 1.0 / max(N))
+    B.close()
+
+
+def check_system(x, off, j, N, fv, st, tol, its_tol=2):
+    A = oracle.assemble(*N, face_vals=fv)
+    ref = oracle.cg(A, tol=tol, max_iter=5000)
+    xs = x[off[j]:off[j + 1]]
+    assert st["status"] == 0 and st["rel_res_true"] <= tol, (j, st)
+    if its_tol is not None:
+        assert abs(st["iterations"] - ref["iterations"]) <= its_tol, (j, st["iterations"], ref["iterations"])
+    bnorm = np.linalg.norm(A.b)
+    bound = (st["rel_res_true"] + ref["rel_res_true"]) * bnorm / lam_min(N) + 1e-12
+    gap = np.linalg.norm(xs - ref["x"])
+    assert gap <= bound, (j, gap, bound)
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_batch_cg_matches_independent_oracle_solves(ctx, fmt):
+    from paper_1505_08023_amd.mfe import Batch
+    sizes, faces = small_batch(seed=2, nsys=9, lo=3, hi=20)
+    B = Batch(ctx, sizes, faces)
+    x, stats = B.cg(tol=1e-8, max_iter=2000, fmt=fmt)
+    x = x.cpu().numpy()
+    for j, (N, fv) in enumerate(zip(sizes, faces)):
+        check_system(x, B.row_offsets, j, tuple(N), fv, stats[j], 1e-8)
+    B.close()
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_batch_autotune_and_resolve(ctx, fmt):
+    from paper_1505_08023_amd.mfe import Batch
+    sizes, faces = small_batch(seed=3, nsys=12, lo=4, hi=24)
+    B = Batch(ctx, sizes, faces)
+    lanes, factor = B.autotune(fmt)
+    assert factor in (1, 2, 4)
+    assert lanes in ((8, 16, 32) if fmt == "csr" else (1,))
+    x, stats = B.cg(tol=1e-8, max_iter=2000, fmt=fmt)
+    x = x.cpu().numpy()
+    for j, (N, fv) in enumerate(zip(sizes, faces)):
+        check_system(x, B.row_offsets, j, tuple(N), fv, stats[j], 1e-8)
+    B.close()
+
+
+def test_batch_mixed(ctx):
+    from paper_1505_08023_amd.mfe import Batch
+    sizes, faces = small_batch(seed=4, nsys=8, lo=4, hi=20)
+    B = Batch(ctx, sizes, faces, precisions=("f64", "f32"))
+    x, stats = B.cg_mixed(tol=1e-8, inner_tol=1e-4)
+    x = x.cpu().numpy()
+    for j, (N, fv) in enumerate(zip(sizes, faces)):
+        assert stats[j]["outer"] >= 1
+        check_system(x, B.row_offsets, j, tuple(N), fv, stats[j], 1e-8, its_tol=None)
+    B.close()
+
+
+def test_batch_edge_cases(ctx):
+    from paper_1505_08023_amd.mfe import Batch
+    # a single system equals the single-mesh solve; an all-zero system is solved by x = 0
+    sizes = np.array([[5, 4, 3], [3, 3, 3]], dtype=np.int32)
+    faces = np.array([[0.1, 0.9, 0.3, 0.2, 0.5, 0.7], [0.0] * 6])
+    B = Batch(ctx, sizes, faces)
+    x0 = torch.ones(B.m, dtype=torch.float64, device=ctx.device)
+    x, stats = B.cg(x=x0, tol=1e-10, max_iter=500)
+    off = B.row_offsets
+    assert stats[1]["status"] == 0 and float(x[off[1]:off[2]].abs().max()) == 0.0
+    check_system(x.cpu().numpy(), off, 0, (5, 4, 3), faces[0], stats[0], 1e-10, its_tol=None)
+    # capped: every system reports the cap
+    x, stats = B.cg(tol=1e-14, max_iter=3)
+    assert stats[0]["status"] == 1 and stats[0]["iterations"] == 3
+    B.close()
+
+
+def test_batch_full_config(ctx):
+    """64 meshes with Nx, Ny, Nz ~ U{16..96} (seed 0), FP64 and mixed, to 1e-8."""
+    from paper_1505_08023_amd.mfe import Batch
+    sizes, faces = inputs.batched_meshes(nsys=64, lo=16, hi=96, seed=0)
+    B = Batch(ctx, sizes, faces, precisions=("f64", "f32"))
+    B.autotune("bcrs13")
+    for solver in ("cg", "cg_mixed"):
+        x, stats = getattr(B, solver)(tol=1e-8)
+        assert all(s["status"] == 0 and s["rel_res_true"] <= 1e-8 for s in stats), solver
+        xs = x.cpu().numpy()
+        off = B.row_offsets
+        rng = np.random.default_rng(5)
+        for j in range(0, 64, 7):  # sampled residual rows rebuilt by the oracle
+            N = tuple(int(v) for v in sizes[j])
+            m = off[j + 1] - off[j]
+            rows = np.unique(np.concatenate([rng.integers(0, m, 60), [0, m - 1]]))
+            got, b = oracle.assemble_rows(*N, rows, face_vals=faces[j])
+            dirm, g = oracle.boundary(*N, face_vals=faces[j])
+            bnorm = np.linalg.norm(g[dirm]) * 1.01  # ||b|| is ||g|| on the Dirichlet rows up to O(h^2)
+            u = xs[off[j]:off[j + 1]]
+            for (cols, vals), bi in zip(got, b):
+                assert abs(bi - float(np.dot(vals, u[cols]))) <= 1e-8 * bnorm
+        # the three smallest systems against independent oracle solves
+        for j in np.argsort((sizes + 1).prod(axis=1))[:3]:
+            check_system(xs, off, j, tuple(sizes[j]), faces[j], stats[j], 1e-8,
+                         its_tol=2 if solver == "cg" else None)
+    B.close()
