@@ -23,6 +23,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+# HBM bytes per launch of the fused SpMV + dot kernels from FETCH_SIZE (x 2.0)
+# and WRITE_SIZE (x 1.0) counter runs, scaled by streaming kernels of known
+# size (profiles/spmv_b13_fp64_256cubed_hbm_counters.md).  Reset to None
+# whenever the kernel changes.
+MEASURED_TRAFFIC = {("bcrs13", 256): 4.818e9, ("csr", 256): None}
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
 
 
@@ -85,6 +90,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--spmv-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the mixed-precision and batched sections (for profiler runs)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -148,7 +155,7 @@ def main():
                    "rows": P.m, "nnz": P.nnz, "blocks_1x3": P.nblocks, "format": args.fmt,
                    "tol": args.tol, "x0": "zero", "step": "one CG solve to tol"},
         "roofline": {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get((args.fmt, N)),
                      "kernel": f"k_spmv_{'b13' if args.fmt == 'bcrs13' else 'csr'}<double, dot>",
                      "bytes_per_launch": dom["bytes"], "mean_launch_ms": dom["mean_ms"]},
         "cg": {"iterations_per_solve": stats[-1]["iterations"], "time_to_tol_s": elapsed / args.steps,
@@ -157,6 +164,38 @@ def main():
                "effective_GBps": its / elapsed * it_bytes / 1e9},
         "spmv": spmv,
     }
+    # a plain 1 GiB device copy: the measured streaming ceiling, and the
+    # known-size kernel that scales the HBM byte counters of a profiler run
+    line["copy_probe"] = copy_probe(torch, ctx.device)
+    log(f"[bench] copy probe: {line['copy_probe']['GBps']:.0f} GB/s")
+    if not args.no_extras:
+        extras(args, ctx, P, x, line, torch)
+    if not args.no_cpu_baseline:
+        log("[bench] CPU oracle baseline (bounded sample) ...")
+        line["cpu_baseline"] = cpu_baseline(N)
+        log(f"[bench] oracle {line['cpu_baseline']['value']:.3f} it/s")
+    print(json.dumps(line), flush=True)
+
+
+def copy_probe(torch, device, nbytes=1 << 30):
+    """Bandwidth of a plain device-to-device copy of nbytes (read + write)."""
+    a = torch.empty(nbytes // 8, dtype=torch.float64, device=device).fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / 10
+    return dict(bytes_moved=2 * nbytes, ms=ms, GBps=2 * nbytes / (ms * 1e-3) / 1e9)
+
+
+def extras(args, ctx, P, x, line, torch):
+    from paper_1505_08023_amd import inputs
+    from paper_1505_08023_amd.mfe import Batch
+
     # mixed precision against FP64 CG at equal accuracy (1e-10)
     mixed = {}
     for name, fn in (("fp64_cg", lambda: P.cg(x, tol=1e-10, max_iter=args.max_iter, fmt=args.fmt)[1]),
@@ -175,11 +214,31 @@ def main():
         log(f"[bench] {name} to 1e-10: {mixed[name]}")
     mixed["speedup"] = mixed["fp64_cg"]["seconds"] / mixed["fp32_inner_fp64_refine"]["seconds"]
     line["mixed_precision_1e-10"] = mixed
-    if not args.no_cpu_baseline:
-        log("[bench] CPU oracle baseline (bounded sample) ...")
-        line["cpu_baseline"] = cpu_baseline(N)
-        log(f"[bench] oracle {line['cpu_baseline']['value']:.3f} it/s")
-    print(json.dumps(line), flush=True)
+
+    # batched uneven solves: 64 meshes, Nx, Ny, Nz ~ U{16..96}, seed 0, to 1e-8 each
+    sizes, faces = inputs.batched_meshes(nsys=64, lo=16, hi=96, seed=0)
+    B = Batch(ctx, sizes, faces, precisions=("f64", "f32"))
+    lanes, factor = B.autotune(args.fmt)
+    bat = {"systems": 64, "rows": B.m, "nnz": B.nnz, "autotune": {"lanes_per_row": lanes, "grid_factor": factor}}
+    xb = torch.zeros(B.m, dtype=torch.float64, device=ctx.device)
+    for name, fn in (("fp64", lambda: B.cg(xb, tol=1e-8, fmt=args.fmt)[1]),
+                     ("fp32_inner_fp64_refine", lambda: B.cg_mixed(xb, tol=1e-8, fmt=args.fmt)[1])):
+        with torch.cuda.stream(ctx.stream):
+            xb.zero_()
+        fn()
+        with torch.cuda.stream(ctx.stream):
+            xb.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = fn()
+        torch.cuda.synchronize()
+        its = [s["iterations"] for s in st]
+        bat[name] = dict(seconds=time.perf_counter() - t, max_iterations=max(its), sum_iterations=sum(its),
+                         worst_rel_res_true=max(s["rel_res_true"] for s in st),
+                         all_converged=all(s["status"] == 0 for s in st))
+        log(f"[bench] batched {name}: {bat[name]}")
+    line["batched_64_meshes_1e-8"] = bat
+    B.close()
 
 
 if __name__ == "__main__":
