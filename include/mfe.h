@@ -224,6 +224,54 @@ int mfe_batch_cg(mfe_batch *b, int format, double *x_dev, double tol, int max_it
 int mfe_batch_cg_mixed(mfe_batch *b, int format, double *x_dev, double tol, double inner_tol, int max_outer,
                        int max_inner, mfe_cg_stats *stats);
 
+/* ---------------------------------------------------------------------
+ * Learned initial guess (extension of the CG module): a 3-D convolutional
+ * encoder-decoder on the node grid of a G x G x G node box mesh (G - 1
+ * divisible by 8), BF16 weights and activations, FP32 accumulation on the
+ * matrix cores, FP32 master weights and Adam.  Architecture (channels):
+ * input 8 (boundary value, boundary mask, 6 zero) -> 16 -> 16 -> [stride 2]
+ * 32 -> 32 -> [stride 2] 64 -> 64 -> [stride 2] 128 -> 128 -> [transposed
+ * stride 2] 64 (+ skip) -> 64 -> 32 (+ skip) -> 32 -> 16 (+ skip) -> 8, all
+ * 3x3x3 convolutions with bias, ReLU after every layer but the last;
+ * channel 0 of the last layer is the prediction.  Node values are indexed
+ * as the mesh's nodes (x fastest); batches are concatenated.
+ * ------------------------------------------------------------------- */
+typedef struct mfe_net mfe_net;
+
+int mfe_net_create(mfe_ctx *ctx, int G, int batch_max, mfe_net **out);
+int mfe_net_destroy(mfe_net *net);
+/* Parameter count in the natural layout: for each layer W[o][27][c] (tap
+ * d = dx + 3 dy + 9 dz) followed by b[o]. */
+int mfe_net_num_params(const mfe_net *net, int64_t *n);
+/* Host FP32 arrays in the natural layout.  set also resets the Adam state. */
+int mfe_net_set_params(mfe_net *net, const float *params_host);
+int mfe_net_get_params(const mfe_net *net, float *params_host);
+/* Forward pass on batch boundary fields g_dev (FP64 [batch][G^3]; interior
+ * entries ignored); pred_dev (FP32 [batch][G^3], may be NULL) gets channel 0. */
+int mfe_net_forward(mfe_net *net, int batch, const double *g_dev, float *pred_dev);
+/* Forward, mean squared error over interior nodes against target_dev (FP32
+ * [batch][G^3]), and backward into the parameter gradient (kept for
+ * mfe_net_adam_step).  loss_host and grad_host (natural layout) may be NULL. */
+int mfe_net_loss_grad(mfe_net *net, int batch, const double *g_dev, const float *target_dev, double *loss_host,
+                      float *grad_host);
+/* One Adam update with the gradient of the last mfe_net_loss_grad. */
+int mfe_net_adam_step(mfe_net *net, float lr, float beta1, float beta2, float eps);
+/* x0_dev (FP64 [G^3]) = g on boundary nodes, the network's prediction inside. */
+int mfe_net_predict_x0(mfe_net *net, const double *g_dev, double *x0_dev);
+
+/* Single 3x3x3 convolution on the matrix cores (the network's building
+ * block, exposed for testing): in/out bf16 channels-last [batch][G^3][c],
+ * mode 0 stride 1, 1 stride 2, 2 transposed stride 2; w_host FP32
+ * [cout][27][cin] (rounded to bf16), bias_host FP32 [cout] or NULL, relu 0/1;
+ * out32_dev (FP32, may be NULL) gets the unrounded result.  Channels must be
+ * 8, 16, 32, 64 or 128.  Synchronises. */
+int mfe_conv3d_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *in_dev, int cout,
+                    const float *w_host, const float *bias_host, int relu, void *out_dev, float *out32_dev);
+/* Weight gradient of that convolution: dw_host[o][27][c] = sum over samples
+ * and output voxels of gy[v][o] x[src(v, d)][c].  Synchronises. */
+int mfe_conv3d_wgrad_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *x_dev, int cout,
+                          const void *gy_dev, float *dw_host);
+
 #ifdef __cplusplus
 }
 #endif

@@ -59,6 +59,17 @@ SIGNATURES = {
     "mfe_batch_autotune": (c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "mfe_batch_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp]),
     "mfe_batch_cg_mixed": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, c_vp]),
+    "mfe_net_create": (c_int, [c_vp, c_int, c_int, PP]),
+    "mfe_net_destroy": (c_int, [c_vp]),
+    "mfe_net_num_params": (c_int, [c_vp, ctypes.POINTER(c_i64)]),
+    "mfe_net_set_params": (c_int, [c_vp, c_vp]),
+    "mfe_net_get_params": (c_int, [c_vp, c_vp]),
+    "mfe_net_forward": (c_int, [c_vp, c_int, c_vp, c_vp]),
+    "mfe_net_loss_grad": (c_int, [c_vp, c_int, c_vp, c_vp, ctypes.POINTER(c_dbl), c_vp]),
+    "mfe_net_adam_step": (c_int, [c_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "mfe_net_predict_x0": (c_int, [c_vp, c_vp, c_vp]),
+    "mfe_conv3d_bf16": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp]),
+    "mfe_conv3d_wgrad_bf16": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_vp]),
 }
 
 _lib = None

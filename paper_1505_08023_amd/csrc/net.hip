@@ -1,0 +1,878 @@
+// Learned initial guess for CG: a 3-D convolutional encoder-decoder on the
+// node grid of a box mesh, trained on solutions of the plain method and run
+// in BF16 on the matrix cores (v_mfma_f32_16x16x32_bf16, FP32 accumulation).
+//
+// Layout: activations channels-last, act[n][voxel][c] (bf16), voxel index
+// x + G (y + G z) like the mesh's node ids; channel counts are multiples of 8
+// so that 8 consecutive reduction indices k = d Cin + c (d the tap) are 8
+// contiguous channels of one source voxel: one 16-byte load per MFMA lane.
+//
+// Convolution (one kernel for every use): out[n][p][o] = sum_{d,c}
+// W[o][d Cin + c] in[n][src(p, d)][c] with three tap patterns per axis
+//   s1: src = p + d - 1      s2: src = 2p + d - 1
+//   t2: src = (p + 1 - d)/2  where p + 1 - d is even (transposed stride 2)
+// and zero outside the grid.  The input gradient of an s1 layer is an s1
+// convolution with the taps mirrored, that of s2 is t2 and that of t2 is s2
+// (same taps), each with the weights transposed in (o, c): the backward pass
+// reuses the forward kernel on a re-laid-out weight copy.  Weight gradients
+// are an MFMA GEMM over voxels through LDS-transposed tiles, reduced in a
+// fixed order over voxel splits (deterministic).  Master weights and Adam
+// state are FP32.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.hpp"
+#include "device_util.hpp"
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+namespace mfe {
+namespace {
+
+enum ConvMode : int { kS1 = 0, kS2 = 1, kT2 = 2 };
+
+__device__ __forceinline__ bf16x8 zero8() { return __builtin_bit_cast(bf16x8, (u32x4)(0u)); }
+
+__device__ __forceinline__ bf16x8 load8(const bf16 *p) {
+    return __builtin_bit_cast(bf16x8, *(const u32x4 *)p);
+}
+
+// Source index along one axis, or -1.
+template <int MODE>
+__device__ __forceinline__ int src_axis(int p, int d, int Gi) {
+    int i;
+    if (MODE == kS1) {
+        i = p + d - 1;
+    } else if (MODE == kS2) {
+        i = 2 * p + d - 1;
+    } else {
+        const int t = p + 1 - d;
+        if (t & 1) return -1;
+        i = t >> 1;
+    }
+    return (i >= 0 && i < Gi) ? i : -1;
+}
+
+// Flat source voxel of output voxel (pz, py, px) for tap d, or -1.
+template <int MODE>
+__device__ __forceinline__ int64_t src_voxel(int pz, int py, int px, int d, int Gi) {
+    const int iz = src_axis<MODE>(pz, d / 9, Gi);
+    const int iy = src_axis<MODE>(py, (d / 3) % 3, Gi);
+    const int ix = src_axis<MODE>(px, d % 3, Gi);
+    if ((iz | iy | ix) < 0) return -1;
+    return ((int64_t)iz * Gi + iy) * Gi + ix;
+}
+
+// ------------------------------------------------------------------ convolution (forward and input gradient)
+
+// One wavefront computes MT tiles of 16 output voxels x 16 NT output
+// channels.  W is [16 NT][Kpad] with zero rows beyond Cout and zero columns
+// beyond Kreal = 27 Cin.  Epilogue: + bias[o], + add[v][o] (a skip connection
+// or an accumulating gradient, may alias out), ReLU, store bf16 (and FP32).
+template <int MODE, int NT, int MT>
+__global__ __launch_bounds__(256) void k_conv(const bf16 *__restrict__ in, int Gi, int cin_log2,
+                                              const bf16 *__restrict__ W, int Kpad, int Kreal, int Cout, int Go,
+                                              int64_t total, const float *__restrict__ bias, const bf16 *add,
+                                              int relu, bf16 *out, float *__restrict__ out32) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int64_t base = wave * 16 * MT;
+    if (base >= total) return;
+    const int row = lane & 15, kg = lane >> 4;
+    const int64_t Vo = (int64_t)Go * Go * Go, Vi = (int64_t)Gi * Gi * Gi;
+    int pz[MT], py[MT], px[MT];
+    int64_t nb[MT];
+    bool rv[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int64_t v = base + mt * 16 + row;
+        rv[mt] = v < total;
+        const int64_t vv = rv[mt] ? v : 0;
+        const int64_t n = vv / Vo, p = vv % Vo;
+        px[mt] = (int)(p % Go);
+        py[mt] = (int)((p / Go) % Go);
+        pz[mt] = (int)(p / ((int64_t)Go * Go));
+        nb[mt] = n * Vi;
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = (f32x4)(0.0f);
+    const int cmask = (1 << cin_log2) - 1;
+    for (int kc = 0; kc < Kpad; kc += 32) {
+        const int k = kc + 8 * kg;
+        const int d = k >> cin_log2, c0 = k & cmask;
+        bf16x8 a[MT];
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            int64_t s = -1;
+            if (rv[mt] && k < Kreal) s = src_voxel<MODE>(pz[mt], py[mt], px[mt], d, Gi);
+            a[mt] = s >= 0 ? load8(in + ((nb[mt] + s) << cin_log2) + c0) : zero8();
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) {
+            const bf16x8 b = load8(W + (int64_t)(nt * 16 + row) * Kpad + k);
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][nt], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t v = base + mt * 16 + 4 * kg + j;
+                const int o = nt * 16 + row;
+                if (v >= total || o >= Cout) continue;
+                float val = acc[mt][nt][j];
+                if (bias) val += bias[o];
+                const int64_t idx = v * Cout + o;
+                if (add) val += (float)add[idx];
+                if (relu) val = fmaxf(val, 0.0f);
+                out[idx] = (bf16)val;
+                if (out32) out32[idx] = val;
+            }
+}
+
+// ------------------------------------------------------------------ weight gradient
+
+// part[split][o][k] = sum over this split's voxels of gy[v][o] * X[src(v, d)][c],
+// k = d Cin + c, for k in this workgroup's 64-wide block.  Tiles of 32 voxels
+// are staged transposed in LDS; wave w owns k-fragment w of the block and all
+// NT o-fragments.
+template <int MODE, int NT>
+__global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ gy, int Go, int Cout,
+                                               const bf16 *__restrict__ X, int Gi, int cin_log2, int Kreal,
+                                               int Kpad, int64_t total, int64_t per_split,
+                                               float *__restrict__ part) {
+    __shared__ __attribute__((aligned(16))) bf16 gyT[16 * NT][40];
+    __shared__ __attribute__((aligned(16))) bf16 xT[64][40];
+    const int kb = blockIdx.x, split = blockIdx.y;
+    const int64_t v_lo = (int64_t)split * per_split;
+    const int64_t v_hi = v_lo + per_split < total ? v_lo + per_split : total;
+    const int t = threadIdx.x, lane = t & 63, wave = t >> 6, row = lane & 15, kg = lane >> 4;
+    const int64_t Vo = (int64_t)Go * Go * Go, Vi = (int64_t)Gi * Gi * Gi;
+    const int cmask = (1 << cin_log2) - 1;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int i = 0; i < NT; ++i) acc[i] = (f32x4)(0.0f);
+    for (int64_t v0 = v_lo; v0 < v_hi; v0 += 32) {
+        const int vv = t & 31, grp = t >> 5;
+        const int64_t v = v0 + vv;
+        // gy tile, transposed: gyT[o][voxel]
+        if (grp < NT) {
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int o = grp * 16 + q;
+                gyT[o][vv] = (v < v_hi && o < Cout) ? gy[v * Cout + o] : (bf16)0.0f;
+            }
+        }
+        // gathered input tile, transposed: xT[k][voxel]
+        {
+            const int k = kb * 64 + grp * 8;
+            bf16x8 val = zero8();
+            if (v < v_hi && k < Kreal) {
+                const int64_t n = v / Vo, p = v % Vo;
+                const int px = (int)(p % Go), py = (int)((p / Go) % Go), pz = (int)(p / ((int64_t)Go * Go));
+                const int64_t s = src_voxel<MODE>(pz, py, px, k >> cin_log2, Gi);
+                if (s >= 0) val = load8(X + ((n * Vi + s) << cin_log2) + (k & cmask));
+            }
+#pragma unroll
+            for (int j = 0; j < 8; ++j) xT[grp * 8 + j][vv] = val[j];
+        }
+        __syncthreads();
+        const bf16x8 b = *(const bf16x8 *)&xT[wave * 16 + row][8 * kg];
+#pragma unroll
+        for (int i = 0; i < NT; ++i) {
+            const bf16x8 a = *(const bf16x8 *)&gyT[i * 16 + row][8 * kg];
+            acc[i] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[i], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    const int k = kb * 64 + wave * 16 + row;
+#pragma unroll
+    for (int i = 0; i < NT; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int o = i * 16 + 4 * kg + j;
+            part[((int64_t)split * 16 * NT + o) * Kpad + k] = acc[i][j];
+        }
+}
+
+// out[i] = sum_s part[s][i], fixed order
+__global__ __launch_bounds__(256) void k_sum_splits(const float *__restrict__ part, int nsplit, int64_t n,
+                                                    float *__restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        float s = 0.0f;
+        for (int q = 0; q < nsplit; ++q) s += part[(int64_t)q * n + i];
+        out[i] = s;
+    }
+}
+
+// bias gradient partials: part[split][o] = sum over the split's voxels of gy[v][o]
+__global__ __launch_bounds__(256) void k_bias_part(const bf16 *__restrict__ gy, int Cout, int64_t total,
+                                                   int64_t per_split, float *__restrict__ part) {
+    __shared__ float red[256];
+    const int t = threadIdx.x;
+    const int o = t % Cout, r = t / Cout, R = 256 / Cout;
+    const int64_t lo = (int64_t)blockIdx.x * per_split;
+    const int64_t hi = lo + per_split < total ? lo + per_split : total;
+    float s = 0.0f;
+    if (r < R)
+        for (int64_t v = lo + r; v < hi; v += R) s += (float)gy[v * Cout + o];
+    red[t] = s;
+    __syncthreads();
+    if (t < Cout) {
+        float a = 0.0f;
+        for (int q = 0; q < R; ++q) a += red[q * Cout + t];
+        part[(int64_t)blockIdx.x * Cout + t] = a;
+    }
+}
+
+// ------------------------------------------------------------------ elementwise
+
+__global__ __launch_bounds__(256) void k_relu_bwd(int64_t n, const bf16 *__restrict__ gy, const bf16 *__restrict__ y,
+                                                  bf16 *__restrict__ g) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        g[i] = (float)y[i] > 0.0f ? gy[i] : (bf16)0.0f;
+}
+
+__global__ __launch_bounds__(256) void k_add_bf16(int64_t n, bf16 *__restrict__ a, const bf16 *__restrict__ b) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        a[i] = (bf16)((float)a[i] + (float)b[i]);
+}
+
+__global__ __launch_bounds__(256) void k_fill_bf16(int64_t n, bf16 *__restrict__ a) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) a[i] = (bf16)0.0f;
+}
+
+__device__ __forceinline__ bool on_boundary(int64_t p, int G) {
+    const int x = (int)(p % G), y = (int)((p / G) % G), z = (int)(p / ((int64_t)G * G));
+    return x == 0 || y == 0 || z == 0 || x == G - 1 || y == G - 1 || z == G - 1;
+}
+
+// input channels: 0 boundary value (0 inside), 1 boundary mask, 2..7 zero
+__global__ __launch_bounds__(256) void k_net_input(int64_t total, int G, const double *__restrict__ g,
+                                                   bf16 *__restrict__ in) {
+    const int64_t V = (int64_t)G * G * G;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const bool bd = on_boundary(i % V, G);
+        bf16 *q = in + i * 8;
+        q[0] = (bf16)(bd ? (float)g[i] : 0.0f);
+        q[1] = (bf16)(bd ? 1.0f : 0.0f);
+        for (int c = 2; c < 8; ++c) q[c] = (bf16)0.0f;
+    }
+}
+
+// MSE over interior nodes: gradient into channel 0 of g (stride 8), partials of the squared error
+__global__ __launch_bounds__(256) void k_mse(int64_t total, int G, const float *__restrict__ pred,
+                                             const float *__restrict__ target, double inv_count,
+                                             bf16 *__restrict__ g, double *__restrict__ part) {
+    const int64_t V = (int64_t)G * G * G;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        double e = 0.0;
+        if (!on_boundary(i % V, G)) e = (double)pred[i * 8] - (double)target[i];
+        acc += e * e;
+        g[i * 8] = (bf16)(2.0 * e * inv_count);
+        for (int c = 1; c < 8; ++c) g[i * 8 + c] = (bf16)0.0f;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
+// prediction (channel 0) out of the stride-8 output, FP32
+__global__ __launch_bounds__(256) void k_pred(int64_t total, const float *__restrict__ out32, float *__restrict__ pred) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+        pred[i] = out32[i * 8];
+}
+
+// x0 = g on boundary nodes (exact), the prediction inside
+__global__ __launch_bounds__(256) void k_net_x0(int G, const double *__restrict__ g, const float *__restrict__ out32,
+                                                double *__restrict__ x0) {
+    const int64_t V = (int64_t)G * G * G;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < V; i += (int64_t)gridDim.x * 256)
+        x0[i] = on_boundary(i, G) ? g[i] : (double)out32[i * 8];
+}
+
+__global__ __launch_bounds__(256) void k_adam(int64_t n, float *__restrict__ p, float *__restrict__ m,
+                                              float *__restrict__ v, const float *__restrict__ g, float lr, float b1,
+                                              float b2, float eps, float bc1, float bc2) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    }
+}
+
+// bf16 copies of one layer's weights: W[o][k] (forward) and the transposed,
+// tap-permuted Wa[c][d' Cout + o] = W[o][d Cin + c] (input gradient), with
+// d' = 26 - d for s1 (mirrored taps) and d' = d for s2 / t2.
+__global__ __launch_bounds__(256) void k_layer_weights(const float *__restrict__ W32, int Cin, int Cout, int Kpad,
+                                                       int KpadA, int rowsA, int mirror, bf16 *__restrict__ W,
+                                                       bf16 *__restrict__ Wa) {
+    const int64_t n = (int64_t)((Cout + 15) / 16 * 16) * Kpad;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) W[i] = (bf16)W32[i];
+    const int64_t na = (int64_t)rowsA * KpadA;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < na; i += (int64_t)gridDim.x * 256) {
+        const int c = (int)(i / KpadA), kk = (int)(i % KpadA);
+        float val = 0.0f;
+        if (c < Cin && kk < 27 * Cout) {
+            const int dp = kk / Cout, o = kk % Cout;
+            const int d = mirror ? 26 - dp : dp;
+            val = W32[(int64_t)o * Kpad + d * Cin + c];
+        }
+        Wa[i] = (bf16)val;
+    }
+}
+
+int ilog2(int v) {
+    int l = 0;
+    while ((1 << l) < v) ++l;
+    return l;
+}
+
+int pad64(int v) { return (v + 63) / 64 * 64; }
+
+}  // namespace
+
+// ------------------------------------------------------------------ host-side launchers
+
+namespace {
+
+int grid_of(int64_t n) {
+    int64_t g = (n + 255) / 256;
+    return (int)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
+}
+
+template <int MODE>
+int conv_mode(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *W, int Kpad, int Cout, int Go,
+              int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32) {
+    const int64_t total = (int64_t)batch * Go * Go * Go;
+    const int nt = (Cout + 15) / 16;
+    const int cl = ilog2(Cin), Kreal = 27 * Cin;
+#define MFE_CONV_CASE(NT_, MT_)                                                                               \
+    {                                                                                                       \
+        const int64_t waves = (total + 16 * MT_ - 1) / (16 * MT_);                                          \
+        hipLaunchKernelGGL((k_conv<MODE, NT_, MT_>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, in, \
+                           Gi, cl, W, Kpad, Kreal, Cout, Go, total, bias, add, relu, out, out32);           \
+    }
+    // the weight buffer holds exactly 16 nt rows: the tile count must match it
+    if (nt == 1) MFE_CONV_CASE(1, 4)
+    else if (nt == 2) MFE_CONV_CASE(2, 4)
+    else if (nt == 4) MFE_CONV_CASE(4, 2)
+    else if (nt == 8) MFE_CONV_CASE(8, 1)
+    else {
+        set_error("conv3d: output channels must be 8, 16, 32, 64 or 128");
+        return MFE_EUNSUPPORTED;
+    }
+#undef MFE_CONV_CASE
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int conv(hipStream_t s, int mode, const bf16 *in, int Gi, int Cin, const bf16 *W, int Kpad, int Cout, int Go,
+         int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32) {
+    if (mode == kS1) return conv_mode<kS1>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32);
+    if (mode == kS2) return conv_mode<kS2>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32);
+    return conv_mode<kT2>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32);
+}
+
+// number of voxel splits of a weight-gradient launch
+int wgrad_splits(int64_t total, int kblocks) {
+    int64_t s = 2048 / (kblocks > 0 ? kblocks : 1);
+    const int64_t max_by_work = (total + 255) / 256;  // at least 256 voxels per split
+    if (s > max_by_work) s = max_by_work;
+    return (int)(s < 1 ? 1 : s);
+}
+
+template <int MODE>
+int wgrad_mode(hipStream_t s, const bf16 *gy, int Go, int Cout, const bf16 *X, int Gi, int Cin, int Kpad, int batch,
+               float *part, int nsplit) {
+    const int64_t total = (int64_t)batch * Go * Go * Go;
+    const int64_t per = ((total + nsplit - 1) / nsplit + 31) / 32 * 32;
+    const int nt = (Cout + 15) / 16, cl = ilog2(Cin);
+    const dim3 grid(Kpad / 64, nsplit);
+#define MFE_WG_CASE(NT_)                                                                                      \
+    hipLaunchKernelGGL((k_wgrad<MODE, NT_>), grid, dim3(256), 0, s, gy, Go, Cout, X, Gi, cl, 27 * Cin, Kpad, \
+                       total, per, part);
+    if (nt == 1) MFE_WG_CASE(1)
+    else if (nt == 2) MFE_WG_CASE(2)
+    else if (nt == 4) MFE_WG_CASE(4)
+    else if (nt == 8) MFE_WG_CASE(8)
+    else {
+        set_error("conv3d weight gradient: output channels must be 8, 16, 32, 64 or 128");
+        return MFE_EUNSUPPORTED;
+    }
+#undef MFE_WG_CASE
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int wgrad(hipStream_t s, int mode, const bf16 *gy, int Go, int Cout, const bf16 *X, int Gi, int Cin, int Kpad,
+          int batch, float *part, int nsplit) {
+    if (mode == kS1) return wgrad_mode<kS1>(s, gy, Go, Cout, X, Gi, Cin, Kpad, batch, part, nsplit);
+    if (mode == kS2) return wgrad_mode<kS2>(s, gy, Go, Cout, X, Gi, Cin, Kpad, batch, part, nsplit);
+    return wgrad_mode<kT2>(s, gy, Go, Cout, X, Gi, Cin, Kpad, batch, part, nsplit);
+}
+
+int out_size(int G, int mode) { return mode == kS1 ? G : mode == kS2 ? (G - 1) / 2 + 1 : 2 * (G - 1) + 1; }
+int adjoint_mode(int mode) { return mode == kS1 ? kS1 : mode == kS2 ? kT2 : kS2; }
+
+bool valid_channels(int c) { return c == 8 || c == 16 || c == 32 || c == 64 || c == 128; }
+
+}  // namespace
+}  // namespace mfe
+
+using namespace mfe;
+
+// ------------------------------------------------------------------ the network object
+
+namespace {
+
+struct LayerDef {
+    int cin, cout, mode, relu, skip;
+};
+// encoder 8 -> 16 -> 32 -> 64 -> 128 (three stride-2 levels), decoder by
+// transposed stride-2 convolutions with skip connections added before the ReLU
+const LayerDef kLayers[] = {
+    {8, 16, kS1, 1, -1},    {16, 16, kS1, 1, -1},  {16, 32, kS2, 1, -1}, {32, 32, kS1, 1, -1},
+    {32, 64, kS2, 1, -1},   {64, 64, kS1, 1, -1},  {64, 128, kS2, 1, -1}, {128, 128, kS1, 1, -1},
+    {128, 64, kT2, 1, 5},   {64, 64, kS1, 1, -1},  {64, 32, kT2, 1, 3},  {32, 32, kS1, 1, -1},
+    {32, 16, kT2, 1, 1},    {16, 8, kS1, 0, -1},
+};
+constexpr int kNumLayers = sizeof(kLayers) / sizeof(kLayers[0]);
+
+struct Layer {
+    LayerDef def;
+    int Gi, Go;
+    int Kpad, rows;     // forward weights [rows][Kpad]
+    int KpadA, rowsA;   // input-gradient weights [rowsA][KpadA]
+    int64_t woff, boff; // offsets (floats) of W and b in the master parameter buffer
+    Buffer act, gact, w, wa;
+};
+
+}  // namespace
+
+struct mfe_net {
+    mfe_ctx *ctx = nullptr;
+    int G = 0, bmax = 0;
+    Layer L[kNumLayers];
+    int64_t nparam_dev = 0;  // padded device layout
+    int64_t nparam = 0;      // natural layout [o][27][c] + b per layer
+    Buffer p32, g32, m32, v32, in, out32, gpre, part, bpart, lpart;
+    int64_t part_floats = 0, bpart_floats = 0;
+    int64_t step = 0;
+};
+
+namespace {
+
+int64_t voxels(int G) { return (int64_t)G * G * G; }
+
+int upload_weights(mfe_net *N) {
+    hipStream_t s = N->ctx->stream;
+    for (auto &l : N->L) {
+        const int64_t n = std::max((int64_t)l.rows * l.Kpad, (int64_t)l.rowsA * l.KpadA);
+        hipLaunchKernelGGL(k_layer_weights, dim3(grid_of(n)), dim3(256), 0, s, (const float *)N->p32.ptr + l.woff,
+                           l.def.cin, l.def.cout, l.Kpad, l.KpadA, l.rowsA, l.def.mode == kS1 ? 1 : 0,
+                           (bf16 *)l.w.ptr, (bf16 *)l.wa.ptr);
+        MFE_HIP_TRY(hipGetLastError());
+    }
+    return MFE_OK;
+}
+
+int forward(mfe_net *N, int batch, const double *g) {
+    hipStream_t s = N->ctx->stream;
+    const int64_t total = (int64_t)batch * voxels(N->G);
+    hipLaunchKernelGGL(k_net_input, dim3(grid_of(total)), dim3(256), 0, s, total, N->G, g, (bf16 *)N->in.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    for (int li = 0; li < kNumLayers; ++li) {
+        Layer &l = N->L[li];
+        const bf16 *x = li == 0 ? (const bf16 *)N->in.ptr : (const bf16 *)N->L[li - 1].act.ptr;
+        const bf16 *add = l.def.skip >= 0 ? (const bf16 *)N->L[l.def.skip].act.ptr : nullptr;
+        MFE_TRY(conv(s, l.def.mode, x, l.Gi, l.def.cin, (const bf16 *)l.w.ptr, l.Kpad, l.def.cout, l.Go, batch,
+                     (const float *)N->p32.ptr + l.boff, add, l.def.relu, (bf16 *)l.act.ptr,
+                     li == kNumLayers - 1 ? (float *)N->out32.ptr : nullptr));
+    }
+    return MFE_OK;
+}
+
+// Backward pass into g32 (padded device layout).  gact of the last layer holds dL/dout.
+int backward(mfe_net *N, int batch) {
+    hipStream_t s = N->ctx->stream;
+    for (int li = 0; li < kNumLayers - 1; ++li) {
+        const int64_t n = (int64_t)batch * voxels(N->L[li].Go) * N->L[li].def.cout;
+        hipLaunchKernelGGL(k_fill_bf16, dim3(grid_of(n)), dim3(256), 0, s, n, (bf16 *)N->L[li].gact.ptr);
+    }
+    for (int li = kNumLayers - 1; li >= 0; --li) {
+        Layer &l = N->L[li];
+        const int64_t total = (int64_t)batch * voxels(l.Go);
+        const int64_t n = total * l.def.cout;
+        const bf16 *gp = (const bf16 *)l.gact.ptr;
+        if (l.def.relu) {
+            hipLaunchKernelGGL(k_relu_bwd, dim3(grid_of(n)), dim3(256), 0, s, n, (const bf16 *)l.gact.ptr,
+                               (const bf16 *)l.act.ptr, (bf16 *)N->gpre.ptr);
+            MFE_HIP_TRY(hipGetLastError());
+            gp = (const bf16 *)N->gpre.ptr;
+        }
+        const bf16 *x = li == 0 ? (const bf16 *)N->in.ptr : (const bf16 *)N->L[li - 1].act.ptr;
+        // weight gradient
+        const int nsplit = wgrad_splits(total, l.Kpad / 64);
+        MFE_TRY(wgrad(s, l.def.mode, gp, l.Go, l.def.cout, x, l.Gi, l.def.cin, l.Kpad, batch, (float *)N->part.ptr,
+                      nsplit));
+        const int64_t nw = (int64_t)l.rows * l.Kpad;
+        hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(nw)), dim3(256), 0, s, (const float *)N->part.ptr, nsplit, nw,
+                           (float *)N->g32.ptr + l.woff);
+        // bias gradient
+        const int bs = (int)std::min<int64_t>(1024, (total + 255) / 256);
+        const int64_t per = (total + bs - 1) / bs;
+        hipLaunchKernelGGL(k_bias_part, dim3(bs), dim3(256), 0, s, gp, l.def.cout, total, per,
+                           (float *)N->bpart.ptr);
+        hipLaunchKernelGGL(k_sum_splits, dim3(1), dim3(256), 0, s, (const float *)N->bpart.ptr, bs,
+                           (int64_t)l.def.cout, (float *)N->g32.ptr + l.boff);
+        MFE_HIP_TRY(hipGetLastError());
+        // gradient into the skip source
+        if (l.def.skip >= 0) {
+            hipLaunchKernelGGL(k_add_bf16, dim3(grid_of(n)), dim3(256), 0, s, n, (bf16 *)N->L[l.def.skip].gact.ptr,
+                               gp);
+            MFE_HIP_TRY(hipGetLastError());
+        }
+        // input gradient, accumulated into the previous layer's output gradient
+        if (li > 0) {
+            bf16 *gx = (bf16 *)N->L[li - 1].gact.ptr;
+            MFE_TRY(conv(s, adjoint_mode(l.def.mode), gp, l.Go, l.def.cout, (const bf16 *)l.wa.ptr, l.KpadA,
+                         l.def.cin, l.Gi, batch, nullptr, gx, 0, gx, nullptr));
+        }
+    }
+    return MFE_OK;
+}
+
+int check_net(const mfe_net *N, int batch) {
+    if (!N || batch < 1 || batch > N->bmax) {
+        set_error("net is NULL or batch outside 1..batch_max");
+        return MFE_EINVAL;
+    }
+    return MFE_OK;
+}
+
+// natural layout <-> padded device layout (host side)
+void natural_to_dev(const mfe_net *N, const float *nat, std::vector<float> &dev) {
+    dev.assign(N->nparam_dev, 0.0f);
+    int64_t q = 0;
+    for (const auto &l : N->L) {
+        const int ci = l.def.cin, co = l.def.cout;
+        for (int o = 0; o < co; ++o)
+            for (int d = 0; d < 27; ++d)
+                for (int c = 0; c < ci; ++c) dev[l.woff + (int64_t)o * l.Kpad + d * ci + c] = nat[q++];
+        for (int o = 0; o < co; ++o) dev[l.boff + o] = nat[q++];
+    }
+}
+
+void dev_to_natural(const mfe_net *N, const std::vector<float> &dev, float *nat) {
+    int64_t q = 0;
+    for (const auto &l : N->L) {
+        const int ci = l.def.cin, co = l.def.cout;
+        for (int o = 0; o < co; ++o)
+            for (int d = 0; d < 27; ++d)
+                for (int c = 0; c < ci; ++c) nat[q++] = dev[l.woff + (int64_t)o * l.Kpad + d * ci + c];
+        for (int o = 0; o < co; ++o) nat[q++] = dev[l.boff + o];
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfe_net_create(mfe_ctx *ctx, int G, int batch_max, mfe_net **out) {
+    clear_error();
+    if (!ctx || !out || G < 9 || (G - 1) % 8 != 0 || batch_max < 1) {
+        set_error("need ctx, out, G >= 9 with G - 1 divisible by 8, batch_max >= 1");
+        return MFE_EINVAL;
+    }
+    *out = nullptr;
+    if (hipSetDevice(ctx->device) != hipSuccess) return MFE_EHIP;
+    mfe_net *N = new (std::nothrow) mfe_net();
+    if (!N) return MFE_ENOMEM;
+    N->ctx = ctx;
+    N->G = G;
+    N->bmax = batch_max;
+    int Gc = G;
+    int64_t off = 0, nat = 0, max_part = 0, max_act = 0;
+    for (int li = 0; li < kNumLayers; ++li) {
+        Layer &l = N->L[li];
+        l.def = kLayers[li];
+        l.Gi = Gc;
+        l.Go = out_size(Gc, l.def.mode);
+        Gc = l.Go;
+        l.Kpad = pad64(27 * l.def.cin);
+        l.rows = (l.def.cout + 15) / 16 * 16;
+        l.KpadA = pad64(27 * l.def.cout);
+        l.rowsA = (l.def.cin + 15) / 16 * 16;
+        l.woff = off;
+        off += (int64_t)l.rows * l.Kpad;
+        l.boff = off;
+        off += (l.def.cout + 3) / 4 * 4;
+        nat += (int64_t)l.def.cout * 27 * l.def.cin + l.def.cout;
+        const int nsplit = wgrad_splits((int64_t)batch_max * voxels(l.Go), l.Kpad / 64);
+        max_part = std::max(max_part, (int64_t)nsplit * l.rows * l.Kpad);
+        max_act = std::max(max_act, (int64_t)batch_max * voxels(l.Go) * l.def.cout);
+    }
+    N->nparam_dev = off;
+    N->nparam = nat;
+    int rc = MFE_OK;
+    auto A = [&](Buffer *b, size_t bytes) {
+        if (rc == MFE_OK) rc = dev_alloc(ctx, b, bytes);
+    };
+    for (auto &l : N->L) {
+        const int64_t n = (int64_t)batch_max * voxels(l.Go) * l.def.cout;
+        A(&l.act, n * sizeof(bf16));
+        A(&l.gact, n * sizeof(bf16));
+        A(&l.w, (size_t)l.rows * l.Kpad * sizeof(bf16));
+        A(&l.wa, (size_t)l.rowsA * l.KpadA * sizeof(bf16));
+    }
+    A(&N->p32, off * sizeof(float));
+    A(&N->g32, off * sizeof(float));
+    A(&N->m32, off * sizeof(float));
+    A(&N->v32, off * sizeof(float));
+    A(&N->in, (size_t)batch_max * voxels(G) * 8 * sizeof(bf16));
+    A(&N->out32, (size_t)batch_max * voxels(G) * 8 * sizeof(float));
+    A(&N->gpre, max_act * sizeof(bf16));
+    A(&N->part, max_part * sizeof(float));
+    A(&N->bpart, 1024 * 128 * sizeof(float));
+    A(&N->lpart, 8192 * sizeof(double));
+    if (rc == MFE_OK) {
+        hipStream_t s = ctx->stream;
+        for (Buffer *b : {&N->p32, &N->g32, &N->m32, &N->v32})
+            if (hipMemsetAsync(b->ptr, 0, b->bytes, s) != hipSuccess) rc = MFE_EHIP;
+        if (rc == MFE_OK && upload_weights(N) != MFE_OK) rc = MFE_EHIP;
+        if (rc == MFE_OK && hipStreamSynchronize(s) != hipSuccess) rc = MFE_EHIP;
+    }
+    if (rc != MFE_OK) {
+        mfe_net_destroy(N);
+        return rc;
+    }
+    *out = N;
+    return MFE_OK;
+}
+
+int mfe_net_destroy(mfe_net *N) {
+    if (!N) return MFE_OK;
+    mfe_ctx *ctx = N->ctx;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &l : N->L)
+        for (Buffer *b : {&l.act, &l.gact, &l.w, &l.wa}) dev_free(ctx, b);
+    for (Buffer *b : {&N->p32, &N->g32, &N->m32, &N->v32, &N->in, &N->out32, &N->gpre, &N->part, &N->bpart, &N->lpart})
+        dev_free(ctx, b);
+    delete N;
+    return MFE_OK;
+}
+
+int mfe_net_num_params(const mfe_net *N, int64_t *n) {
+    clear_error();
+    if (!N || !n) {
+        set_error("net and n must be non-NULL");
+        return MFE_EINVAL;
+    }
+    *n = N->nparam;
+    return MFE_OK;
+}
+
+int mfe_net_set_params(mfe_net *N, const float *params_host) {
+    clear_error();
+    if (!N || !params_host) {
+        set_error("net and params must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(N->ctx->device) != hipSuccess) return MFE_EHIP;
+    std::vector<float> dev;
+    natural_to_dev(N, params_host, dev);
+    hipStream_t s = N->ctx->stream;
+    MFE_HIP_TRY(hipMemcpyAsync(N->p32.ptr, dev.data(), dev.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipMemsetAsync(N->m32.ptr, 0, N->m32.bytes, s));
+    MFE_HIP_TRY(hipMemsetAsync(N->v32.ptr, 0, N->v32.bytes, s));
+    N->step = 0;
+    MFE_TRY(upload_weights(N));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    return MFE_OK;
+}
+
+int mfe_net_get_params(const mfe_net *N, float *params_host) {
+    clear_error();
+    if (!N || !params_host) {
+        set_error("net and params must be non-NULL");
+        return MFE_EINVAL;
+    }
+    std::vector<float> dev(N->nparam_dev);
+    MFE_HIP_TRY(hipMemcpyAsync(dev.data(), N->p32.ptr, dev.size() * sizeof(float), hipMemcpyDeviceToHost,
+                               N->ctx->stream));
+    MFE_HIP_TRY(hipStreamSynchronize(N->ctx->stream));
+    dev_to_natural(N, dev, params_host);
+    return MFE_OK;
+}
+
+int mfe_net_forward(mfe_net *N, int batch, const double *g_dev, float *pred_dev) {
+    clear_error();
+    MFE_TRY(check_net(N, batch));
+    if (!g_dev) {
+        set_error("g must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(N->ctx->device) != hipSuccess) return MFE_EHIP;
+    MFE_TRY(forward(N, batch, g_dev));
+    if (pred_dev) {
+        const int64_t total = (int64_t)batch * voxels(N->G);
+        hipLaunchKernelGGL(k_pred, dim3(grid_of(total)), dim3(256), 0, N->ctx->stream, total,
+                           (const float *)N->out32.ptr, pred_dev);
+        MFE_HIP_TRY(hipGetLastError());
+    }
+    return MFE_OK;
+}
+
+int mfe_net_loss_grad(mfe_net *N, int batch, const double *g_dev, const float *target_dev, double *loss_host,
+                      float *grad_host) {
+    clear_error();
+    MFE_TRY(check_net(N, batch));
+    if (!g_dev || !target_dev) {
+        set_error("g and target must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(N->ctx->device) != hipSuccess) return MFE_EHIP;
+    hipStream_t s = N->ctx->stream;
+    MFE_TRY(forward(N, batch, g_dev));
+    const int64_t total = (int64_t)batch * voxels(N->G);
+    const int64_t inner = (int64_t)(N->G - 2) * (N->G - 2) * (N->G - 2);
+    const int lg = std::min(1024, grid_of(total));
+    hipLaunchKernelGGL(k_mse, dim3(lg), dim3(256), 0, s, total, N->G, (const float *)N->out32.ptr, target_dev,
+                       1.0 / ((double)batch * inner), (bf16 *)N->L[kNumLayers - 1].gact.ptr, (double *)N->lpart.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    MFE_TRY(backward(N, batch));
+    if (loss_host) {
+        std::vector<double> lp(lg);
+        MFE_HIP_TRY(hipMemcpyAsync(lp.data(), N->lpart.ptr, lg * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFE_HIP_TRY(hipStreamSynchronize(s));
+        double acc = 0.0;
+        for (double v : lp) acc += v;
+        *loss_host = acc / ((double)batch * inner);
+    }
+    if (grad_host) {
+        std::vector<float> dev(N->nparam_dev);
+        MFE_HIP_TRY(hipMemcpyAsync(dev.data(), N->g32.ptr, dev.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+        MFE_HIP_TRY(hipStreamSynchronize(s));
+        dev_to_natural(N, dev, grad_host);
+    }
+    return MFE_OK;
+}
+
+int mfe_net_adam_step(mfe_net *N, float lr, float beta1, float beta2, float eps) {
+    clear_error();
+    if (!N || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) {
+        set_error("need net, lr >= 0, 0 <= beta1, beta2 < 1, eps > 0");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(N->ctx->device) != hipSuccess) return MFE_EHIP;
+    N->step += 1;
+    const float bc1 = 1.0f - std::pow(beta1, (float)N->step), bc2 = 1.0f - std::pow(beta2, (float)N->step);
+    hipLaunchKernelGGL(k_adam, dim3(grid_of(N->nparam_dev)), dim3(256), 0, N->ctx->stream, N->nparam_dev,
+                       (float *)N->p32.ptr, (float *)N->m32.ptr, (float *)N->v32.ptr, (const float *)N->g32.ptr, lr,
+                       beta1, beta2, eps, bc1, bc2);
+    MFE_HIP_TRY(hipGetLastError());
+    return upload_weights(N);
+}
+
+int mfe_net_predict_x0(mfe_net *N, const double *g_dev, double *x0_dev) {
+    clear_error();
+    MFE_TRY(check_net(N, 1));
+    if (!g_dev || !x0_dev) {
+        set_error("g and x0 must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(N->ctx->device) != hipSuccess) return MFE_EHIP;
+    MFE_TRY(forward(N, 1, g_dev));
+    hipLaunchKernelGGL(k_net_x0, dim3(grid_of(voxels(N->G))), dim3(256), 0, N->ctx->stream, N->G, g_dev,
+                       (const float *)N->out32.ptr, x0_dev);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int mfe_conv3d_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *in_dev, int cout,
+                    const float *w_host, const float *bias_host, int relu, void *out_dev, float *out32_dev) {
+    clear_error();
+    if (!ctx || !in_dev || !w_host || !out_dev || batch < 1 || Gi < 2 || mode < 0 || mode > 2 ||
+        !valid_channels(cin) || !valid_channels(cout)) {
+        set_error("need ctx, in, w, out, batch >= 1, Gi >= 2, mode 0..2, channels in {8, 16, 32, 64, 128}");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return MFE_EHIP;
+    const int Kpad = pad64(27 * cin), rows = (cout + 15) / 16 * 16;
+    std::vector<bf16> w((size_t)rows * Kpad, (bf16)0.0f);
+    for (int o = 0; o < cout; ++o)
+        for (int k = 0; k < 27 * cin; ++k) w[(size_t)o * Kpad + k] = (bf16)w_host[(size_t)o * 27 * cin + k];
+    Buffer wb, bb;
+    MFE_TRY(dev_alloc(ctx, &wb, w.size() * sizeof(bf16)));
+    MFE_TRY(dev_alloc(ctx, &bb, cout * sizeof(float)));
+    hipStream_t s = ctx->stream;
+    int rc = MFE_OK;
+    if (hipMemcpyAsync(wb.ptr, w.data(), w.size() * sizeof(bf16), hipMemcpyHostToDevice, s) != hipSuccess ||
+        (bias_host && hipMemcpyAsync(bb.ptr, bias_host, cout * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess))
+        rc = MFE_EHIP;
+    if (rc == MFE_OK)
+        rc = conv(s, mode, (const bf16 *)in_dev, Gi, cin, (const bf16 *)wb.ptr, Kpad, cout, out_size(Gi, mode), batch,
+                  bias_host ? (const float *)bb.ptr : nullptr, nullptr, relu, (bf16 *)out_dev, out32_dev);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == MFE_OK) rc = MFE_EHIP;
+    dev_free(ctx, &wb);
+    dev_free(ctx, &bb);
+    return rc;
+}
+
+int mfe_conv3d_wgrad_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *x_dev, int cout,
+                          const void *gy_dev, float *dw_host) {
+    clear_error();
+    if (!ctx || !x_dev || !gy_dev || !dw_host || batch < 1 || Gi < 2 || mode < 0 || mode > 2 ||
+        !valid_channels(cin) || !valid_channels(cout)) {
+        set_error("need ctx, x, gy, dw, batch >= 1, Gi >= 2, mode 0..2, channels in {8, 16, 32, 64, 128}");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return MFE_EHIP;
+    const int Go = out_size(Gi, mode);
+    const int Kpad = pad64(27 * cin), rows = (cout + 15) / 16 * 16;
+    const int64_t total = (int64_t)batch * voxels(Go);
+    const int nsplit = wgrad_splits(total, Kpad / 64);
+    Buffer part, sum;
+    MFE_TRY(dev_alloc(ctx, &part, (size_t)nsplit * rows * Kpad * sizeof(float)));
+    MFE_TRY(dev_alloc(ctx, &sum, (size_t)rows * Kpad * sizeof(float)));
+    hipStream_t s = ctx->stream;
+    int rc = wgrad(s, mode, (const bf16 *)gy_dev, Go, cout, (const bf16 *)x_dev, Gi, cin, Kpad, batch,
+                   (float *)part.ptr, nsplit);
+    std::vector<float> h((size_t)rows * Kpad);
+    if (rc == MFE_OK) {
+        const int64_t n = (int64_t)rows * Kpad;
+        hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(n)), dim3(256), 0, s, (const float *)part.ptr, nsplit, n,
+                           (float *)sum.ptr);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(h.data(), sum.ptr, h.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = MFE_EHIP;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == MFE_OK) rc = MFE_EHIP;
+    if (rc == MFE_OK)
+        for (int o = 0; o < cout; ++o)
+            for (int k = 0; k < 27 * cin; ++k) dw_host[(size_t)o * 27 * cin + k] = h[(size_t)o * Kpad + k];
+    dev_free(ctx, &part);
+    dev_free(ctx, &sum);
+    return rc;
+}
+
+}  // extern "C"

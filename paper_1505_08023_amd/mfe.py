@@ -41,7 +41,7 @@ def _close_all():
     """Release library objects while torch (which owns their memory) is alive."""
     objs = list(_LIVE)
     for o in objs:
-        if isinstance(o, (Problem, Batch)):
+        if isinstance(o, (Problem, Batch, Net)):
             o.close()
     for o in objs:
         if isinstance(o, Context):
@@ -365,6 +365,121 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+    def __del__(self):
+        if sys.is_finalizing():
+            return
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+CONV_MODES = {"s1": 0, "s2": 1, "t2": 2}
+
+
+def conv3d(ctx, mode, x, w, bias=None, relu=False, out32=False):
+    """One 3x3x3 convolution on the matrix cores.  x: bf16 CUDA tensor
+    [batch, G, G, G, cin]; w: FP32 array-like [cout, 27, cin]."""
+    import numpy as np
+    if x.dtype != torch.bfloat16 or not x.is_contiguous() or x.dim() != 5:
+        raise ValueError("x must be a contiguous bf16 tensor [batch, G, G, G, cin]")
+    b, G, cin = x.shape[0], x.shape[1], x.shape[4]
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    cout = w.shape[0]
+    Go = {"s1": G, "s2": (G - 1) // 2 + 1, "t2": 2 * (G - 1) + 1}[mode]
+    y = torch.empty((b, Go, Go, Go, cout), dtype=torch.bfloat16, device=x.device)
+    y32 = torch.empty((b, Go, Go, Go, cout), dtype=torch.float32, device=x.device) if out32 else None
+    bh = None if bias is None else np.ascontiguousarray(bias, dtype=np.float32)
+    with _on(ctx):
+        check(ctx.lib.mfe_conv3d_bf16(ctx.handle, CONV_MODES[mode], b, G, cin, ctypes.c_void_p(x.data_ptr()), cout,
+                                      w.ctypes.data_as(ctypes.c_void_p),
+                                      bh.ctypes.data_as(ctypes.c_void_p) if bh is not None else None, int(relu),
+                                      ctypes.c_void_p(y.data_ptr()),
+                                      ctypes.c_void_p(y32.data_ptr()) if y32 is not None else None), "mfe_conv3d_bf16")
+    return (y, y32) if out32 else y
+
+
+def conv3d_wgrad(ctx, mode, x, gy):
+    """Weight gradient [cout, 27, cin] (numpy FP32) of conv3d(mode, x) for output gradient gy."""
+    import numpy as np
+    b, G, cin = x.shape[0], x.shape[1], x.shape[4]
+    cout = gy.shape[4]
+    dw = np.zeros((cout, 27, cin), dtype=np.float32)
+    with _on(ctx):
+        check(ctx.lib.mfe_conv3d_wgrad_bf16(ctx.handle, CONV_MODES[mode], b, G, cin, ctypes.c_void_p(x.data_ptr()),
+                                            cout, ctypes.c_void_p(gy.data_ptr()), dw.ctypes.data_as(ctypes.c_void_p)),
+              "mfe_conv3d_wgrad_bf16")
+    return dw
+
+
+class Net:
+    """The encoder-decoder that predicts the CG initial guess (include/mfe.h)."""
+
+    def __init__(self, ctx, G, batch_max):
+        self.ctx, self.G, self.batch_max = ctx, G, batch_max
+        h = ctypes.c_void_p()
+        with _on(ctx):
+            check(ctx.lib.mfe_net_create(ctx.handle, G, batch_max, ctypes.byref(h)), "mfe_net_create")
+        self.handle = h
+        n = ctypes.c_int64()
+        check(ctx.lib.mfe_net_num_params(h, ctypes.byref(n)), "mfe_net_num_params")
+        self.nparams = n.value
+        ctx.problems.add(self)
+        _LIVE.add(self)
+
+    def set_params(self, flat):
+        import numpy as np
+        flat = np.ascontiguousarray(flat, dtype=np.float32)
+        assert flat.size == self.nparams
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_net_set_params(self.handle, flat.ctypes.data_as(ctypes.c_void_p)),
+                  "mfe_net_set_params")
+
+    def get_params(self):
+        import numpy as np
+        out = np.zeros(self.nparams, dtype=np.float32)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_net_get_params(self.handle, out.ctypes.data_as(ctypes.c_void_p)),
+                  "mfe_net_get_params")
+        return out
+
+    def forward(self, g):
+        b = g.numel() // self.G ** 3
+        pred = torch.empty(g.numel(), dtype=torch.float32, device=g.device)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_net_forward(self.handle, b, _ptr(g, torch.float64), _ptr(pred, torch.float32)),
+                  "mfe_net_forward")
+        return pred
+
+    def loss_grad(self, g, target, want_grad=False):
+        import numpy as np
+        b = g.numel() // self.G ** 3
+        loss = ctypes.c_double()
+        grad = np.zeros(self.nparams, dtype=np.float32) if want_grad else None
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_net_loss_grad(self.handle, b, _ptr(g, torch.float64), _ptr(target, torch.float32),
+                                                 ctypes.byref(loss),
+                                                 grad.ctypes.data_as(ctypes.c_void_p) if want_grad else None),
+                  "mfe_net_loss_grad")
+        return (loss.value, grad) if want_grad else loss.value
+
+    def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_net_adam_step(self.handle, lr, beta1, beta2, eps), "mfe_net_adam_step")
+
+    def predict_x0(self, g, x0=None):
+        if x0 is None:
+            x0 = torch.empty_like(g)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_net_predict_x0(self.handle, _ptr(g, torch.float64), _ptr(x0, torch.float64)),
+                  "mfe_net_predict_x0")
+        return x0
+
+    def close(self):
+        if self.handle and self.ctx.handle:
+            self.ctx.lib.mfe_net_destroy(self.handle)
+        self.handle = None
 
     def __del__(self):
         if sys.is_finalizing():

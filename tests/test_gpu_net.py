@@ -1,0 +1,163 @@
+"""GPU parity of the BF16 matrix-core convolutions and the learned-guess
+network against the FP64 conv oracle (oracle/conv.py).
+
+Inputs and weights are rounded to bfloat16 on the host first, so the oracle
+sees exactly the operands the matrix cores multiply; the GPU accumulates in
+FP32:
+  conv forward   |y32 - ref| <= 1e-5 * sum |w| |x| (+ the bf16 store: 2^-8 |ref|)
+  weight grad    |dw - ref|  <= 1e-5 * sum |gy| |x| over the reduction
+  network        the whole-network gradient against the FP64 chain rule on
+                 the same parameters: per layer relative L2 error <= 0.1 and
+                 cosine >= 0.99 (activations and gradients are stored in
+                 bfloat16 on the GPU, 2^-8 relative per value)
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import conv
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1505_08023_amd.mfe import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def to_bf16_tensor(a, device):
+    return torch.tensor(np.asarray(a, np.float32), device=device).to(torch.bfloat16)
+
+
+CASES = [("s1", 9, 8, 16), ("s1", 9, 16, 16), ("s1", 5, 128, 128), ("s2", 17, 16, 32), ("s2", 9, 64, 128),
+         ("t2", 9, 32, 16), ("t2", 5, 128, 64), ("s1", 9, 16, 8)]
+
+
+@pytest.mark.parametrize("mode,G,cin,cout", CASES)
+def test_conv_forward(ctx, mode, G, cin, cout):
+    from paper_1505_08023_amd.mfe import conv3d
+    rng = np.random.default_rng(hash((mode, G, cin, cout)) % 2 ** 32)
+    x = conv.bf16(rng.standard_normal((2, G, G, G, cin)))
+    w = conv.bf16(rng.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
+    b = rng.standard_normal(cout).astype(np.float32)
+    xg = to_bf16_tensor(x, ctx.device)
+    y, y32 = conv3d(ctx, mode, xg, w, b, relu=False, out32=True)
+    ref = conv.conv3d(x, w, mode, b.astype(np.float64))
+    scale = conv.conv3d(np.abs(x), np.abs(w), mode) + np.abs(b)
+    y32 = y32.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(y32 - ref) <= 1e-5 * scale + 1e-6)
+    yb = y.float().cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(yb - ref) <= 2 ** -8 * np.abs(ref) + 1e-5 * scale + 1e-6)
+    # ReLU epilogue
+    yr = conv3d(ctx, mode, xg, w, b, relu=True).float().cpu().numpy()
+    assert np.all(np.abs(yr - np.maximum(yb, 0)) <= 1e-6 + 2 ** -8 * np.abs(yb))
+
+
+@pytest.mark.parametrize("mode,G,cin,cout", CASES)
+def test_conv_weight_gradient(ctx, mode, G, cin, cout):
+    from paper_1505_08023_amd.mfe import conv3d_wgrad
+    rng = np.random.default_rng(7 + hash((mode, G, cin, cout)) % 2 ** 30)
+    x = conv.bf16(rng.standard_normal((2, G, G, G, cin)))
+    Go = conv.out_size(G, mode)
+    gy = conv.bf16(rng.standard_normal((2, Go, Go, Go, cout)))
+    dw = conv3d_wgrad(ctx, mode, to_bf16_tensor(x, ctx.device), to_bf16_tensor(gy, ctx.device)).astype(np.float64)
+    ref = conv.conv3d_weight_grad(gy, x, mode)
+    scale = conv.conv3d_weight_grad(np.abs(gy), np.abs(x), mode)
+    assert np.all(np.abs(dw - ref) <= 1e-5 * scale + 1e-6)
+
+
+def he_params(rng, scale=1.0):
+    return [(rng.standard_normal((co, 27, ci)) * scale * np.sqrt(2.0 / (27 * ci)), rng.standard_normal(co) * 0.01)
+            for ci, co, *_ in conv.LAYERS]
+
+
+def flatten(params):
+    return np.concatenate([np.concatenate([w.ravel(), b]) for w, b in params]).astype(np.float32)
+
+
+def unflatten(flat):
+    out, q = [], 0
+    for ci, co, *_ in conv.LAYERS:
+        w = flat[q:q + co * 27 * ci].reshape(co, 27, ci)
+        q += co * 27 * ci
+        b = flat[q:q + co]
+        q += co
+        out.append((w.astype(np.float64), b.astype(np.float64)))
+    return out
+
+
+def boundary_mask(G):
+    m = np.zeros((G, G, G), bool)
+    m[0], m[-1], m[:, 0], m[:, -1], m[:, :, 0], m[:, :, -1] = (True,) * 6
+    return m
+
+
+def test_network_parameters_roundtrip(ctx):
+    from paper_1505_08023_amd.mfe import Net
+    net = Net(ctx, 17, 2)
+    p = flatten(he_params(np.random.default_rng(0)))
+    assert net.nparams == p.size
+    net.set_params(p)
+    assert np.array_equal(net.get_params(), p)
+    net.close()
+
+
+def test_network_forward_and_gradient(ctx):
+    from paper_1505_08023_amd.mfe import Net
+    G, B = 17, 2
+    rng = np.random.default_rng(1)
+    params = unflatten(flatten(he_params(rng)))
+    pb = [(conv.bf16(w), b) for w, b in params]  # the GPU multiplies bf16 weights
+    mask = boundary_mask(G)
+    g = rng.uniform(0, 1, (B, G, G, G))
+    target = rng.uniform(0, 1, (B, G, G, G)).astype(np.float32)
+    x = np.stack([conv.net_input(g[i], mask) for i in range(B)])
+    interior = np.broadcast_to(~mask, (B, G, G, G)).astype(float)
+    net = Net(ctx, G, B)
+    net.set_params(flatten(params))
+    gt = torch.tensor(g.reshape(-1), device=ctx.device)
+    tt = torch.tensor(target.reshape(-1), device=ctx.device)
+    pred = net.forward(gt).cpu().numpy().reshape(B, G, G, G)
+    acts = conv.net_forward(pb, x, round_bf16=True)
+    ref_pred = acts[-1][..., 0]
+    rel = np.linalg.norm(pred - ref_pred) / np.linalg.norm(ref_pred)
+    assert rel <= 0.02, rel
+    loss, grad = net.loss_grad(gt, tt, want_grad=True)
+    ref_loss, _ = conv.net_loss(pb, x, target.astype(np.float64), interior, round_bf16=True)
+    assert abs(loss - ref_loss) <= 0.02 * ref_loss
+    ref_grads = conv.net_grads(pb, x, target.astype(np.float64), interior)
+    got = unflatten(grad)
+    for li, ((gw, gb), (rw, rb)) in enumerate(zip(got, ref_grads)):
+        a = np.concatenate([gw.ravel(), gb])
+        r = np.concatenate([rw.ravel(), rb])
+        err = np.linalg.norm(a - r) / np.linalg.norm(r)
+        cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+        print("layer", li, "rel err", err, "cos", cos)
+        assert err <= 0.1 and cos >= 0.99, (li, err, cos)
+    net.close()
+
+
+def test_network_training_reduces_loss(ctx):
+    from paper_1505_08023_amd.mfe import Net
+    G, B = 17, 4
+    rng = np.random.default_rng(2)
+    net = Net(ctx, G, B)
+    net.set_params(flatten(he_params(rng)))
+    # a smooth target that depends on the boundary data: the average face value
+    g = rng.uniform(0, 1, (B, G, G, G))
+    target = np.repeat(g.reshape(B, -1).mean(axis=1), G ** 3).astype(np.float32)
+    gt = torch.tensor(g.reshape(-1), device=ctx.device)
+    tt = torch.tensor(target, device=ctx.device)
+    losses = []
+    for _ in range(60):
+        losses.append(net.loss_grad(gt, tt))
+        net.adam_step(1e-3)
+    assert losses[-1] < 0.2 * losses[0], losses[::10]
+    # predict_x0 keeps the boundary values exactly
+    x0 = net.predict_x0(gt[:G ** 3].contiguous()).cpu().numpy().reshape(G, G, G)
+    m = boundary_mask(G)
+    assert np.array_equal(x0[m], g[0][m])
+    net.close()
