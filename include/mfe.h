@@ -207,6 +207,11 @@ int mfe_batch_create(mfe_ctx *ctx, int nsys, const int32_t *sizes, const double 
 int mfe_batch_destroy(mfe_batch *b);
 /* Total rows, total stored entries, row_offsets (host int64[nsys+1]); any may be NULL. */
 int mfe_batch_info(const mfe_batch *b, int64_t *m_total, int64_t *nnz_total, int64_t *row_offsets);
+/* New Dirichlet data for every system without re-assembly (as
+ * mfe_problem_set_bc): node_g_dev (device, length m_total, concatenated per
+ * system, boundary entries used) if non-NULL, else face_vals (host
+ * double[6*nsys]) if non-NULL, else the paper's values. */
+int mfe_batch_set_bc(mfe_batch *b, const double *face_vals, const double *node_g_dev);
 /* FP64 CRS of the block-diagonal matrix and b (device buffers, as mfe_problem_export_csr). */
 int mfe_batch_export_csr(const mfe_batch *b, int32_t *ptr_dev, int32_t *col_dev, double *val_dev, double *b_dev);
 /* Times the batched SpMV for each candidate launch shape (CRS lanes per row
@@ -249,10 +254,11 @@ int mfe_net_get_params(const mfe_net *net, float *params_host);
 /* Forward pass on batch boundary fields g_dev (FP64 [batch][G^3]; interior
  * entries ignored); pred_dev (FP32 [batch][G^3], may be NULL) gets channel 0. */
 int mfe_net_forward(mfe_net *net, int batch, const double *g_dev, float *pred_dev);
-/* Forward, mean squared error over interior nodes against target_dev (FP32
- * [batch][G^3]), and backward into the parameter gradient (kept for
- * mfe_net_adam_step).  loss_host and grad_host (natural layout) may be NULL. */
-int mfe_net_loss_grad(mfe_net *net, int batch, const double *g_dev, const float *target_dev, double *loss_host,
+/* Forward, mean squared error over interior nodes against target_dev (FP64
+ * [batch][G^3], e.g. CG solutions), and backward into the parameter gradient
+ * (kept for mfe_net_adam_step).  loss_host and grad_host (natural layout) may
+ * be NULL. */
+int mfe_net_loss_grad(mfe_net *net, int batch, const double *g_dev, const double *target_dev, double *loss_host,
                       float *grad_host);
 /* One Adam update with the gradient of the last mfe_net_loss_grad. */
 int mfe_net_adam_step(mfe_net *net, float lr, float beta1, float beta2, float eps);

@@ -56,6 +56,7 @@ SIGNATURES = {
     "mfe_batch_destroy": (c_int, [c_vp]),
     "mfe_batch_info": (c_int, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), c_vp]),
     "mfe_batch_export_csr": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "mfe_batch_set_bc": (c_int, [c_vp, c_vp, c_vp]),
     "mfe_batch_autotune": (c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "mfe_batch_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp]),
     "mfe_batch_cg_mixed": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, c_vp]),

@@ -685,6 +685,23 @@ int mfe_batch_export_csr(const mfe_batch *B, int32_t *ptr_dev, int32_t *col_dev,
     return mfe_problem_export_csr(B->P, ptr_dev, col_dev, val_dev, b_dev);
 }
 
+int mfe_batch_set_bc(mfe_batch *B, const double *face_vals, const double *node_g_dev) {
+    clear_error();
+    if (!B) {
+        set_error("batch is NULL");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(B->ctx->device) != hipSuccess) return MFE_EHIP;
+    mfe_problem *P = B->P;
+    for (int j = 0; j < B->nsys; ++j)
+        MFE_TRY(launch_assemble_into(B->ctx->stream, B->N[3 * j], B->N[3 * j + 1], B->N[3 * j + 2],
+                                     face_vals ? face_vals + 6 * j : nullptr,
+                                     node_g_dev ? node_g_dev + B->row0[j] : nullptr, B->row0[j], 0,
+                                     (int32_t *)P->ptr.ptr, (int32_t *)P->col.ptr, (double *)P->val64.ptr,
+                                     (double *)P->b.ptr, true));
+    return MFE_OK;
+}
+
 int mfe_batch_autotune(mfe_batch *B, int format, int *lanes_out, int *factor_out) {
     clear_error();
     if (!B || (format != MFE_CSR && format != MFE_BCRS13) || !(B->P->formats & format)) {

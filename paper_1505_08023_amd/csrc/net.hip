@@ -276,13 +276,13 @@ __global__ __launch_bounds__(256) void k_net_input(int64_t total, int G, const d
 
 // MSE over interior nodes: gradient into channel 0 of g (stride 8), partials of the squared error
 __global__ __launch_bounds__(256) void k_mse(int64_t total, int G, const float *__restrict__ pred,
-                                             const float *__restrict__ target, double inv_count,
+                                             const double *__restrict__ target, double inv_count,
                                              bf16 *__restrict__ g, double *__restrict__ part) {
     const int64_t V = (int64_t)G * G * G;
     double acc = 0.0;
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
         double e = 0.0;
-        if (!on_boundary(i % V, G)) e = (double)pred[i * 8] - (double)target[i];
+        if (!on_boundary(i % V, G)) e = (double)pred[i * 8] - target[i];
         acc += e * e;
         g[i * 8] = (bf16)(2.0 * e * inv_count);
         for (int c = 1; c < 8; ++c) g[i * 8 + c] = (bf16)0.0f;
@@ -742,7 +742,7 @@ int mfe_net_forward(mfe_net *N, int batch, const double *g_dev, float *pred_dev)
     return MFE_OK;
 }
 
-int mfe_net_loss_grad(mfe_net *N, int batch, const double *g_dev, const float *target_dev, double *loss_host,
+int mfe_net_loss_grad(mfe_net *N, int batch, const double *g_dev, const double *target_dev, double *loss_host,
                       float *grad_host) {
     clear_error();
     MFE_TRY(check_net(N, batch));

@@ -45,28 +45,26 @@ def smooth_faces(seed, modes=8):
     return dict(c=c, a=a, p=p, q=q)
 
 
-def _face_value(prm, f, s, t):
-    v = np.full(np.broadcast(s, t).shape, prm["c"][f])
-    for k in range(prm["a"].shape[1]):
-        v = v + prm["a"][f, k] * np.sin(prm["p"][f, k] * np.pi * s) * np.sin(prm["q"][f, k] * np.pi * t)
-    return v
+def _face_grid(prm, f, s, t):
+    """g_f on the tensor grid s (len S) x t (len T), returned as [T, S]."""
+    a = prm["a"][f]
+    S = np.sin(np.pi * np.outer(prm["p"][f], s))  # [modes, S]
+    Tm = np.sin(np.pi * np.outer(prm["q"][f], t))  # [modes, T]
+    return prm["c"][f] + (Tm * a[:, None]).T @ S
 
 
 def node_field(Nx, Ny, Nz, prm):
-    """Boundary values on every node of the (Nx+1)(Ny+1)(Nz+1) mesh, x fastest."""
-    ix = np.arange(Nx + 1)
-    iy = np.arange(Ny + 1)
-    iz = np.arange(Nz + 1)
-    Z, Y, X = np.meshgrid(iz, iy, ix, indexing="ij")
-    x, y, z = X / Nx, Y / Ny, Z / Nz
-    g = np.zeros(X.shape)
-    done = np.zeros(X.shape, bool)
-    # (face index into FACES, mask, in-plane coordinates)
-    order = ((1, X == Nx, y, z), (0, X == 0, y, z),
-             (3, Y == Ny, x, z), (2, Y == 0, x, z),
-             (5, Z == Nz, x, y), (4, Z == 0, x, y))
-    for f, mask, s, t in order:
-        sel = mask & ~done
-        g[sel] = _face_value(prm, f, s[sel], t[sel])
-        done |= sel
+    """Boundary values on every node of the (Nx+1)(Ny+1)(Nz+1) mesh, x fastest
+    (interior nodes 0).  Faces are written in reverse priority order so that a
+    node on several faces ends with the first of x=1, x=0, y=1, y=0, z=1, z=0."""
+    x = np.arange(Nx + 1) / Nx
+    y = np.arange(Ny + 1) / Ny
+    z = np.arange(Nz + 1) / Nz
+    g = np.zeros((Nz + 1, Ny + 1, Nx + 1))
+    g[0, :, :] = _face_grid(prm, 4, x, y)        # z = 0, (s, t) = (x, y)
+    g[Nz, :, :] = _face_grid(prm, 5, x, y)       # z = 1
+    g[:, 0, :] = _face_grid(prm, 2, x, z)        # y = 0, (s, t) = (x, z)
+    g[:, Ny, :] = _face_grid(prm, 3, x, z)       # y = 1
+    g[:, :, 0] = _face_grid(prm, 0, y, z)        # x = 0, (s, t) = (y, z)
+    g[:, :, Nx] = _face_grid(prm, 1, y, z)       # x = 1
     return g.reshape(-1)

@@ -1,0 +1,203 @@
+"""Learned initial guess for CG: data generation with the plain method,
+training of the encoder-decoder on the GPU, and evaluation against the zero
+start.  Every arithmetic step runs in libmfe's kernels (CG, network forward,
+backward and Adam); this module only moves data and schedules steps.
+
+    python -m paper_1505_08023_amd.learned --n 64 --train 20000 --epochs 4 \\
+        --eval 1000 --out weights.npz
+
+Boundary data: per face, c + sum_{k<8} a_k sin(p_k pi s) sin(q_k pi t) (see
+inputs.smooth_faces), seeds 0..train-1 for training, 10^6.. for evaluation.
+Targets: FP64 CG solutions to 1e-8 of the Nx = Ny = Nz = n mesh.
+"""
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+import torch
+
+from . import inputs
+from .mfe import Batch, Context, Net, Problem
+
+HELD_OUT_BASE = 10 ** 6
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def layer_shapes():
+    """(cin, cout) per layer, in the order of include/mfe.h."""
+    return [(8, 16), (16, 16), (16, 32), (32, 32), (32, 64), (64, 64), (64, 128), (128, 128), (128, 64), (64, 64),
+            (64, 32), (32, 32), (32, 16), (16, 8)]
+
+
+def he_init(seed=0):
+    """Flat FP32 parameters (natural layout W[o][27][c], b[o] per layer)."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for cin, cout in layer_shapes():
+        parts.append(rng.standard_normal(cout * 27 * cin) * math.sqrt(2.0 / (27 * cin)))
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def fields(n, seeds):
+    """Boundary fields of several seeds, concatenated (host FP64)."""
+    return np.concatenate([inputs.node_field(n, n, n, inputs.smooth_faces(int(s))) for s in seeds])
+
+
+def generate(ctx, n, seeds, chunk=32, tol=1e-8):
+    """Solve the plain problem for every seed (chunk systems at a time with the
+    batched CG).  Returns (g, u): FP64 CUDA tensors [len(seeds), (n+1)^3]."""
+    V = (n + 1) ** 3
+    S = len(seeds)
+    g_all = torch.empty((S, V), dtype=torch.float64, device=ctx.device)
+    u_all = torch.empty((S, V), dtype=torch.float64, device=ctx.device)
+    B = Batch(ctx, np.full((chunk, 3), n), formats=("bcrs13",))
+    B.autotune("bcrs13")
+    x = torch.zeros(B.m, dtype=torch.float64, device=ctx.device)
+    t0 = time.time()
+    its = []
+    for c0 in range(0, S, chunk):
+        ids = seeds[c0:c0 + chunk]
+        k = len(ids)
+        g = np.zeros(chunk * V)
+        g[:k * V] = fields(n, ids)
+        gt = torch.tensor(g, device=ctx.device)
+        B.set_bc(node_g=gt)
+        x.zero_()
+        x, st = B.cg(x, tol=tol, max_iter=20000)
+        if any(s["status"] != 0 for s in st[:k]):
+            raise RuntimeError("CG did not converge while generating data")
+        its += [s["iterations"] for s in st[:k]]
+        g_all[c0:c0 + k] = gt[:k * V].view(k, V)
+        u_all[c0:c0 + k] = x[:k * V].view(k, V)
+        if (c0 // chunk) % 50 == 0:
+            log(f"[learned] generated {c0 + k}/{S} solutions ({time.time() - t0:.0f} s, mean its {np.mean(its):.1f})")
+    B.close()
+    return g_all, u_all
+
+
+def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0):
+    S = g.shape[0]
+    rng = np.random.default_rng(seed)
+    steps_per_epoch = S // batch
+    total = epochs * steps_per_epoch
+    step, t0, last = 0, time.time(), time.time()
+    history = []
+    for ep in range(epochs):
+        perm = torch.tensor(rng.permutation(S), device=g.device)
+        run = 0.0
+        for i in range(steps_per_epoch):
+            idx = perm[i * batch:(i + 1) * batch]
+            gb = g.index_select(0, idx).reshape(-1)
+            ub = u.index_select(0, idx).reshape(-1)
+            loss = net.loss_grad(gb, ub)
+            cur = lr * 0.5 * (1 + math.cos(math.pi * step / total))  # cosine decay
+            net.adam_step(cur)
+            run += loss
+            step += 1
+            if time.time() - last > log_every:
+                last = time.time()
+                log(f"[learned] epoch {ep} step {i}/{steps_per_epoch} loss {loss:.3e} ({time.time() - t0:.0f} s)")
+        history.append(run / steps_per_epoch)
+        log(f"[learned] epoch {ep} mean loss {history[-1]:.3e}")
+    return history
+
+
+def evaluate(ctx, net, n, seeds, tol=1e-8):
+    """Per held-out seed: plain CG from x0 = 0 against CG from the network's
+    guess (inference included in its time; zero start kept when the guess's
+    residual is not below ||b||).  Times are host wall clock, GPU-synchronised."""
+    V = (n + 1) ** 3
+    P = Problem.mesh(ctx, n, n, n, formats=("bcrs13",))
+    x = torch.zeros(V, dtype=torch.float64, device=ctx.device)
+    x0 = torch.zeros(V, dtype=torch.float64, device=ctx.device)
+    rows = []
+    for s in seeds:
+        g = torch.tensor(inputs.node_field(n, n, n, inputs.smooth_faces(int(s))), device=ctx.device)
+        P.set_bc(node_g=g)
+        # plain
+        x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        _, st0 = P.cg(x, tol=tol, max_iter=20000)
+        torch.cuda.synchronize()
+        t_plain = time.perf_counter() - t
+        # learned
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        net.predict_x0(g, x0)
+        _, chk = P.cg(x0, tol=tol, max_iter=0)  # ||b - A x0|| / ||b||, no iteration
+        used = chk["rel_res_true"] < 1.0
+        if not used:
+            x0.zero_()
+        _, st1 = P.cg(x0, tol=tol, max_iter=20000)
+        torch.cuda.synchronize()
+        t_learned = time.perf_counter() - t
+        rows.append(dict(seed=int(s), its_plain=st0["iterations"], its_learned=st1["iterations"],
+                         t_plain=t_plain, t_learned=t_learned, guess_rel_res=chk["rel_res_true"], used=used,
+                         res_plain=st0["rel_res_true"], res_learned=st1["rel_res_true"]))
+    P.close()
+    a = lambda k: float(np.mean([r[k] for r in rows]))
+    return dict(samples=len(rows), mean_its_plain=a("its_plain"), mean_its_learned=a("its_learned"),
+                mean_time_plain_s=a("t_plain"), mean_time_learned_s=a("t_learned"),
+                mean_guess_rel_res=a("guess_rel_res"), guesses_used=int(sum(r["used"] for r in rows)),
+                worst_res_learned=max(r["res_learned"] for r in rows),
+                speedup_time=a("t_plain") / a("t_learned"), rows=rows)
+
+
+def save(path, params, meta):
+    np.savez_compressed(path, params=params, meta=json.dumps(meta))
+
+
+def load(path):
+    with np.load(path, allow_pickle=False) as f:
+        return f["params"].astype(np.float32), json.loads(str(f["meta"]))
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--n", type=int, default=64, help="elements per axis")
+    ap.add_argument("--train", type=int, default=20000)
+    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batch", type=int, default=8)
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--eval", type=int, default=1000)
+    ap.add_argument("--init", default=None, help="start from these weights (.npz)")
+    ap.add_argument("--out", default=None)
+    args = ap.parse_args(argv)
+    ctx = Context(0)
+    n = args.n
+    net = Net(ctx, n + 1, args.batch)
+    if args.init:
+        p, _ = load(args.init)
+        net.set_params(p)
+    else:
+        net.set_params(he_init(0))
+    result = {"n": n}
+    if args.train > 0:
+        t = time.time()
+        g, u = generate(ctx, n, np.arange(args.train))
+        result["generate_s"] = time.time() - t
+        t = time.time()
+        result["loss_history"] = train(net, g, u, args.epochs, args.batch, args.lr)
+        result["train_s"] = time.time() - t
+        del g, u
+        torch.cuda.empty_cache()
+        if args.out:
+            save(args.out, net.get_params(), dict(n=n, train=args.train, epochs=args.epochs, batch=args.batch,
+                                                  lr=args.lr, loss_history=result["loss_history"]))
+    if args.eval > 0:
+        ev = evaluate(ctx, net, n, np.arange(HELD_OUT_BASE, HELD_OUT_BASE + args.eval))
+        ev.pop("rows")
+        result["eval"] = ev
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -320,6 +320,13 @@ class Batch:
         self.ctx.stream.synchronize()
         return ptr, col, val, b
 
+    def set_bc(self, face_vals=None, node_g=None):
+        import numpy as np
+        fv = None if face_vals is None else np.ascontiguousarray(face_vals, dtype=np.float64).reshape(self.nsys, 6)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_batch_set_bc(self.handle, fv.ctypes.data_as(ctypes.c_void_p) if fv is not None else None,
+                                                _ptr(node_g, torch.float64, self.m, "node_g")), "mfe_batch_set_bc")
+
     def autotune(self, fmt="bcrs13"):
         lanes, factor = ctypes.c_int(), ctypes.c_int()
         with _on(self.ctx):
@@ -458,7 +465,7 @@ class Net:
         loss = ctypes.c_double()
         grad = np.zeros(self.nparams, dtype=np.float32) if want_grad else None
         with _on(self.ctx):
-            check(self.ctx.lib.mfe_net_loss_grad(self.handle, b, _ptr(g, torch.float64), _ptr(target, torch.float32),
+            check(self.ctx.lib.mfe_net_loss_grad(self.handle, b, _ptr(g, torch.float64), _ptr(target, torch.float64),
                                                  ctypes.byref(loss),
                                                  grad.ctypes.data_as(ctypes.c_void_p) if want_grad else None),
                   "mfe_net_loss_grad")

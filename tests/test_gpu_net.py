@@ -113,7 +113,7 @@ def test_network_forward_and_gradient(ctx):
     pb = [(conv.bf16(w), b) for w, b in params]  # the GPU multiplies bf16 weights
     mask = boundary_mask(G)
     g = rng.uniform(0, 1, (B, G, G, G))
-    target = rng.uniform(0, 1, (B, G, G, G)).astype(np.float32)
+    target = rng.uniform(0, 1, (B, G, G, G))
     x = np.stack([conv.net_input(g[i], mask) for i in range(B)])
     interior = np.broadcast_to(~mask, (B, G, G, G)).astype(float)
     net = Net(ctx, G, B)
@@ -126,9 +126,9 @@ def test_network_forward_and_gradient(ctx):
     rel = np.linalg.norm(pred - ref_pred) / np.linalg.norm(ref_pred)
     assert rel <= 0.02, rel
     loss, grad = net.loss_grad(gt, tt, want_grad=True)
-    ref_loss, _ = conv.net_loss(pb, x, target.astype(np.float64), interior, round_bf16=True)
+    ref_loss, _ = conv.net_loss(pb, x, target, interior, round_bf16=True)
     assert abs(loss - ref_loss) <= 0.02 * ref_loss
-    ref_grads = conv.net_grads(pb, x, target.astype(np.float64), interior)
+    ref_grads = conv.net_grads(pb, x, target, interior)
     got = unflatten(grad)
     for li, ((gw, gb), (rw, rb)) in enumerate(zip(got, ref_grads)):
         a = np.concatenate([gw.ravel(), gb])
@@ -148,7 +148,7 @@ def test_network_training_reduces_loss(ctx):
     net.set_params(flatten(he_params(rng)))
     # a smooth target that depends on the boundary data: the average face value
     g = rng.uniform(0, 1, (B, G, G, G))
-    target = np.repeat(g.reshape(B, -1).mean(axis=1), G ** 3).astype(np.float32)
+    target = np.repeat(g.reshape(B, -1).mean(axis=1), G ** 3)
     gt = torch.tensor(g.reshape(-1), device=ctx.device)
     tt = torch.tensor(target, device=ctx.device)
     losses = []
