@@ -90,6 +90,7 @@ def main():
     ap.add_argument("--max-iter", type=int, default=20000)
     ap.add_argument("--spmv-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--learned-samples", type=int, default=50, help="held-out seeds in the learned section")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision and batched sections (for profiler runs)")
     args = ap.parse_args()
@@ -194,7 +195,7 @@ def copy_probe(torch, device, nbytes=1 << 30):
 
 def extras(args, ctx, P, x, line, torch):
     from paper_1505_08023_amd import inputs
-    from paper_1505_08023_amd.mfe import Batch
+    from paper_1505_08023_amd.mfe import Batch, Problem
 
     # mixed precision against FP64 CG at equal accuracy (1e-10)
     mixed = {}
@@ -239,6 +240,46 @@ def extras(args, ctx, P, x, line, torch):
         log(f"[bench] batched {name}: {bat[name]}")
     line["batched_64_meshes_1e-8"] = bat
     B.close()
+
+    # 128^3 plain CG for exactly 200 iterations (tol 0), both formats
+    P2 = Problem.mesh(ctx, 128, 128, 128, formats=("csr", "bcrs13"))
+    x2 = torch.zeros(P2.m, dtype=torch.float64, device=ctx.device)
+    c2 = {"rows": P2.m, "nnz": P2.nnz, "iterations": 200}
+    for fmt in ("bcrs13", "csr"):
+        best = None
+        for _ in range(3):
+            with torch.cuda.stream(ctx.stream):
+                x2.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            st = P2.cg(x2, tol=0.0, max_iter=200, fmt=fmt)[1]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        assert st["iterations"] == 200
+        it_bytes = spmv_bytes(fmt, P2.m, P2.nnz, P2.nblocks) + 64 * P2.m
+        c2[fmt] = dict(it_per_s=200 / best, seconds=best, effective_GBps=200 * it_bytes / best / 1e9)
+        log(f"[bench] 128^3 CG x200 {fmt}: {c2[fmt]}")
+    line["cg_128cubed_200_iterations"] = c2
+    P2.close()
+
+    # learned warm start against the zero start, 64^3, held-out boundary data
+    wpath = os.path.join(ROOT, "paper_1505_08023_amd", "weights", "net64.npz")
+    if os.path.exists(wpath):
+        from paper_1505_08023_amd import learned
+        from paper_1505_08023_amd.mfe import Net
+        params, meta = learned.load(wpath)
+        net = Net(ctx, 65, 1)
+        net.set_params(params)
+        seeds = list(range(learned.HELD_OUT_BASE, learned.HELD_OUT_BASE + args.learned_samples))
+        learned.evaluate(ctx, net, 64, seeds[:2])  # warm-up (graph capture)
+        ev = learned.evaluate(ctx, net, 64, seeds)
+        ev.pop("rows")
+        ev["weights"] = os.path.relpath(wpath, ROOT)
+        ev["trained_on"] = {k: meta[k] for k in ("train", "epochs", "batch", "lr") if k in meta}
+        line["learned_warm_start_64cubed_1e-8"] = ev
+        log(f"[bench] learned vs plain: {ev}")
+        net.close()
 
 
 if __name__ == "__main__":

@@ -77,6 +77,8 @@ typedef struct mfe_cg_stats {
     double rel_res_recurrence; /* sqrt(r.r)/||b|| of the recurrence residual at exit */
     double rel_res_true;       /* ||b - A x||_2 / ||b||_2 recomputed in FP64 at exit */
     double seconds;            /* host wall time of the call */
+    int32_t guess_rejected;    /* mfe_cg_warm: 1 if the solve started from x = 0 instead of the guess */
+    int32_t reserved_;
 } mfe_cg_stats;
 
 /* Message for the calling thread's last error ("" if none). */
@@ -171,6 +173,15 @@ int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, d
  * holds the last iterate).  Calls on one problem must not overlap. */
 int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
            double *hist_dev, mfe_cg_stats *stats);
+
+/* mfe_cg from an initial guess that may be poor (for instance a learned
+ * prediction): with r0 = b - A x0, if ||r0||_2 >= ||b||_2 (the zero start is
+ * at least as close) the solve starts from x0 = 0 instead, so it is never
+ * worse than plain CG from zero.  The choice is made on the device in the
+ * same kernels that start mfe_cg (no extra host round trip);
+ * stats->guess_rejected reports it.  Arguments and return values as mfe_cg. */
+int mfe_cg_warm(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
+                double *hist_dev, mfe_cg_stats *stats);
 
 /* Mixed precision CG (FP32-inner / FP64-refinement extension of the CG
  * module of Sec. 1).  Outer loop in FP64: r = b - A x with the FP64 matrix,

@@ -22,7 +22,8 @@ c_int, c_i32, c_i64, c_dbl, c_vp, c_size = (ctypes.c_int, ctypes.c_int32, ctypes
 
 class mfe_cg_stats(ctypes.Structure):
     _fields_ = [("status", c_i32), ("iterations", c_i32), ("outer", c_i32), ("spmv_count", c_i32),
-                ("rel_res_recurrence", c_dbl), ("rel_res_true", c_dbl), ("seconds", c_dbl)]
+                ("rel_res_recurrence", c_dbl), ("rel_res_true", c_dbl), ("seconds", c_dbl),
+                ("guess_rejected", c_i32), ("reserved_", c_i32)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -51,6 +52,7 @@ SIGNATURES = {
     "mfe_spmv_dot": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "mfe_dot": (c_int, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(c_dbl)]),
     "mfe_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
+    "mfe_cg_warm": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_cg_mixed": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_batch_create": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_int, PP]),
     "mfe_batch_destroy": (c_int, [c_vp]),

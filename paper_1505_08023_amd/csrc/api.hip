@@ -122,7 +122,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 1; }
+int mfe_version(void) { return 2; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -469,7 +469,23 @@ int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_
     }
     MFE_TRY(check_format(p, format));
     MFE_TRY(set_device(p->ctx));
-    return cg_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, max_iter, hist_dev, stats);
+    return cg_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, max_iter, hist_dev, stats, false);
+}
+
+int mfe_cg_warm(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter, double *hist_dev,
+                mfe_cg_stats *stats) {
+    clear_error();
+    if (!p || !x_dev) {
+        set_error("problem and x must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (!(tol >= 0.0) || max_iter < 0) {
+        set_error("tol must be >= 0 and max_iter >= 0");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(check_format(p, format));
+    MFE_TRY(set_device(p->ctx));
+    return cg_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, max_iter, hist_dev, stats, true);
 }
 
 int mfe_cg_mixed(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol, int max_outer,

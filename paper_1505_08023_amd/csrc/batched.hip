@@ -763,6 +763,8 @@ int mfe_batch_cg(mfe_batch *B, int format, double *x_dev, double tol, int max_it
             stats[j].rel_res_recurrence = fin[j].bnorm > 0 ? std::sqrt(fin[j].rho) / fin[j].bnorm : 0.0;
             stats[j].rel_res_true = rel[j];
             stats[j].seconds = secs;
+            stats[j].guess_rejected = 0;
+            stats[j].reserved_ = 0;
         }
     }
     return rc;
@@ -878,6 +880,8 @@ int mfe_batch_cg_mixed(mfe_batch *B, int format, double *x_dev, double tol, doub
             stats[j].rel_res_recurrence = rel[j];
             stats[j].rel_res_true = rel[j];
             stats[j].seconds = secs;
+            stats[j].guess_rejected = 0;
+            stats[j].reserved_ = 0;
         }
     }
     return rc;

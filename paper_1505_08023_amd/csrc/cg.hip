@@ -143,7 +143,7 @@ int run_iterations(mfe_problem *P, hipGraphExec_t exec, const CgState *st, int k
 }
 
 int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist,
-             mfe_cg_stats *stats) {
+             mfe_cg_stats *stats, bool warm) {
     const auto t0 = std::chrono::steady_clock::now();
     mfe_ctx *ctx = P->ctx;
     hipStream_t s = ctx->stream;
@@ -158,6 +158,7 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
     h.max_iter = max_iter;
     h.hist = hist;
     h.status = kRunning;
+    h.warm = warm ? 1 : 0;
     pin[2] = h;
     MFE_HIP_TRY(hipMemcpyAsync(st, &pin[2], sizeof(CgState), hipMemcpyHostToDevice, s));
     // r = b - A x0, p = r, rho, ||b||, start test
@@ -165,7 +166,8 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
     int n0 = 0;
     MFE_TRY(launch_spmv(P, format, false, kSpmvResid, a0, s, &n0));
     MFE_TRY(launch_finalize(kFinStart, partials, n0, st, s));
-    MFE_TRY(launch_zero_if(P->m, x, st, ctx->num_cu, s));
+    MFE_TRY(launch_zero_if(P->m, x, (double *)P->r.ptr, (double *)P->p.ptr, (const double *)P->b.ptr, st,
+                           ctx->num_cu, s));
     MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     CgState fin = pin[0];
@@ -198,6 +200,8 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
         stats->rel_res_recurrence = bn > 0.0 ? std::sqrt(fin.rho) / bn : 0.0;
         stats->rel_res_true = bn > 0.0 ? std::sqrt(rr_true) / bn : 0.0;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->guess_rejected = fin.zero_x == 2 ? 1 : 0;
+        stats->reserved_ = 0;
     }
     if (rc == MFE_EBREAKDOWN) set_error("CG breakdown: p.Ap <= 0 or not finite");
     return rc;

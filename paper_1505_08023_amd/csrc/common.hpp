@@ -64,8 +64,8 @@ struct CgState {
     int iters;        // completed iterations               (written by update_xp)
     int max_iter;
     int active;       // 1 once update_r has run in the current iteration (cleared by the SpMV)
-    int zero_x;       // b = 0: the solution is x = 0
-    int pad_;
+    int zero_x;       // 1: b = 0, the solution is x = 0; 2: the guess was rejected, restart from x = 0
+    int warm;         // set by the host: reject x0 when ||b - A x0|| >= ||b||
 };
 
 // (the 1x3 BCRS slice layout is described in b13_layout.hpp)
@@ -168,7 +168,8 @@ int ensure_workspace(mfe_problem *P);
 int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
               hipGraphExec_t *out);
 int run_iterations(mfe_problem *P, hipGraphExec_t exec, const CgState *st, int k, int max_iter, CgState *fin);
-int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st);
+int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st,
+             bool warm = false);
 void release_graphs(mfe_problem *P);
 
 // mixed precision (mixed.hip)
@@ -186,7 +187,9 @@ int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const voi
 enum FinalizeKind : int { kFinStart = 0, kFinTrue = 1, kFinDot = 2 };
 int launch_finalize(FinalizeKind kind, const double *partials, int n, CgState *st, hipStream_t s);
 int launch_state_reset(CgState *st, double *dot_out, hipStream_t s);
-int launch_zero_if(int64_t m, double *x, const CgState *st, int num_cu, hipStream_t s);
+// x = 0 when the state asks for it; on a rejected guess also r = p = b (r, p, b may be NULL otherwise)
+int launch_zero_if(int64_t m, double *x, double *r, double *p, const double *b, const CgState *st, int num_cu,
+                   hipStream_t s);
 int launch_dot(mfe_ctx *ctx, int64_t n, const double *x, const double *y, double *partials, hipStream_t s,
                int *grid);
 

@@ -118,7 +118,7 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
     int nouter = 0, inner_its = 0, spmvs = 1, rc = MFE_OK;
     bool fallback = false;
     double prev = o.bnorm > 0 ? std::sqrt(o.rho) : 0.0;
-    if (o.zero_x) MFE_TRY(launch_zero_if(P->m, x, outer, ctx->num_cu, s));
+    if (o.zero_x) MFE_TRY(launch_zero_if(P->m, x, nullptr, nullptr, nullptr, outer, ctx->num_cu, s));
     while (o.status == kRunning) {
         if (nouter >= max_outer) {
             rc = MFE_NOT_CONVERGED;
@@ -178,6 +178,8 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
         stats->rel_res_recurrence = rel_true;
         stats->rel_res_true = rel_true;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->guess_rejected = 0;
+        stats->reserved_ = 0;
     }
     return rc;
 }

@@ -23,6 +23,8 @@
 #include <cmath>
 #include <cstring>
 #include <new>
+#include <string>
+#include <utility>
 #include <vector>
 
 #include "common.hpp"
@@ -73,18 +75,27 @@ __device__ __forceinline__ int64_t src_voxel(int pz, int py, int px, int d, int 
 // ------------------------------------------------------------------ convolution (forward and input gradient)
 
 // One wavefront computes MT tiles of 16 output voxels x 16 NT output
-// channels.  W is [16 NT][Kpad] with zero rows beyond Cout and zero columns
-// beyond Kreal = 27 Cin.  Epilogue: + bias[o], + add[v][o] (a skip connection
-// or an accumulating gradient, may alias out), ReLU, store bf16 (and FP32).
+// channels (channel group blockIdx.y) over the reduction steps of split
+// blockIdx.z.  W is [16 nt][Kpad] with zero rows beyond Cout and zero columns
+// beyond Kreal = 27 Cin.  The operands of step i + 1 are requested before the
+// matrix-core products of step i, so one step's loads overlap the previous
+// step's products.  With part == nullptr the epilogue runs here: + bias[o],
+// + add[v][o] (a skip connection or an accumulating gradient, may alias out),
+// ReLU, store bf16 (and FP32).  Otherwise the split's FP32 sums go to
+// part[split][v][o] and k_conv_reduce finishes.
 template <int MODE, int NT, int MT>
 __global__ __launch_bounds__(256) void k_conv(const bf16 *__restrict__ in, int Gi, int cin_log2,
                                               const bf16 *__restrict__ W, int Kpad, int Kreal, int Cout, int Go,
-                                              int64_t total, const float *__restrict__ bias, const bf16 *add,
-                                              int relu, bf16 *out, float *__restrict__ out32) {
+                                              int64_t total, int steps_per_split, const float *__restrict__ bias,
+                                              const bf16 *add, int relu, bf16 *out, float *__restrict__ out32,
+                                              float *__restrict__ part) {
     const int lane = threadIdx.x & 63;
     const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int64_t base = wave * 16 * MT;
     if (base >= total) return;
+    const int o0 = blockIdx.y * 16 * NT;
+    const int s0 = blockIdx.z * steps_per_split;
+    const int s1 = min(s0 + steps_per_split, Kpad >> 5);
     const int row = lane & 15, kg = lane >> 4;
     const int64_t Vo = (int64_t)Go * Go * Go, Vi = (int64_t)Gi * Gi * Gi;
     int pz[MT], py[MT], px[MT];
@@ -107,22 +118,35 @@ __global__ __launch_bounds__(256) void k_conv(const bf16 *__restrict__ in, int G
 #pragma unroll
         for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = (f32x4)(0.0f);
     const int cmask = (1 << cin_log2) - 1;
-    for (int kc = 0; kc < Kpad; kc += 32) {
-        const int k = kc + 8 * kg;
+    const bf16 *Wrow = W + (int64_t)(o0 + row) * Kpad;
+    auto load_step = [&](int st, bf16x8(&a)[MT], bf16x8(&b)[NT]) {
+        const int k = st * 32 + 8 * kg;
         const int d = k >> cin_log2, c0 = k & cmask;
-        bf16x8 a[MT];
 #pragma unroll
         for (int mt = 0; mt < MT; ++mt) {
-            int64_t s = -1;
-            if (rv[mt] && k < Kreal) s = src_voxel<MODE>(pz[mt], py[mt], px[mt], d, Gi);
-            a[mt] = s >= 0 ? load8(in + ((nb[mt] + s) << cin_log2) + c0) : zero8();
+            int64_t sv = -1;
+            if (rv[mt] && k < Kreal) sv = src_voxel<MODE>(pz[mt], py[mt], px[mt], d, Gi);
+            a[mt] = sv >= 0 ? load8(in + ((nb[mt] + sv) << cin_log2) + c0) : zero8();
         }
 #pragma unroll
-        for (int nt = 0; nt < NT; ++nt) {
-            const bf16x8 b = load8(W + (int64_t)(nt * 16 + row) * Kpad + k);
+        for (int nt = 0; nt < NT; ++nt) b[nt] = load8(Wrow + (int64_t)nt * 16 * Kpad + k);
+    };
+    bf16x8 a0[MT], b0[NT];
+    if (s0 < s1) load_step(s0, a0, b0);
+    for (int st = s0; st < s1; ++st) {
+        const bool more = st + 1 < s1;
+        bf16x8 a1[MT], b1[NT];
+        if (more) load_step(st + 1, a1, b1);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
             for (int mt = 0; mt < MT; ++mt)
-                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b, acc[mt][nt], 0, 0, 0);
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[mt], b0[nt], acc[mt][nt], 0, 0, 0);
+        if (more) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) a0[mt] = a1[mt];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b0[nt] = b1[nt];
         }
     }
 #pragma unroll
@@ -132,16 +156,200 @@ __global__ __launch_bounds__(256) void k_conv(const bf16 *__restrict__ in, int G
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int64_t v = base + mt * 16 + 4 * kg + j;
-                const int o = nt * 16 + row;
+                const int o = o0 + nt * 16 + row;
                 if (v >= total || o >= Cout) continue;
                 float val = acc[mt][nt][j];
-                if (bias) val += bias[o];
                 const int64_t idx = v * Cout + o;
+                if (part) {
+                    part[(int64_t)blockIdx.z * total * Cout + idx] = val;
+                    continue;
+                }
+                if (bias) val += bias[o];
                 if (add) val += (float)add[idx];
                 if (relu) val = fmaxf(val, 0.0f);
                 out[idx] = (bf16)val;
                 if (out32) out32[idx] = val;
             }
+}
+
+// Sum of the reduction splits in split order, then the epilogue of k_conv.
+__global__ __launch_bounds__(256) void k_conv_reduce(const float *__restrict__ part, int nsplit, int64_t n,
+                                                     int Cout, const float *__restrict__ bias, const bf16 *add,
+                                                     int relu, bf16 *out, float *__restrict__ out32) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
+        float val = 0.0f;
+        for (int z = 0; z < nsplit; ++z) val += part[(int64_t)z * n + i];
+        if (bias) val += bias[i % Cout];
+        if (add) val += (float)add[i];
+        if (relu) val = fmaxf(val, 0.0f);
+        out[i] = (bf16)val;
+        if (out32) out32[i] = val;
+    }
+}
+
+// ------------------------------------------------------------------ transposed stride 2 by parity class
+
+// Along one axis an output p = 2j + q of the t2 pattern receives tap d = 1
+// from source j when q = 0, and taps d = 0 (source j + 1) and d = 2 (source
+// j) when q = 1; every source is inside the grid.  Splitting the outputs
+// into the 8 parity classes (qx, qy, qz) leaves each class a dense
+// convolution over its (1 + qx)(1 + qy)(1 + qz) live taps: a class tap t
+// enumerates (tx, ty, tz), tx in {0, qx} fastest, and the reduction index is
+// t Cin + c.  Class c = qx + 2 qy + 4 qz has (Gi - qx)(Gi - qy)(Gi - qz)
+// output voxels per sample.
+__host__ __device__ __forceinline__ int t2_ntaps(int c) { return (1 + (c & 1)) * (1 + ((c >> 1) & 1)) * (1 + (c >> 2)); }
+
+__host__ __device__ __forceinline__ void t2_tap(int c, int t, int &tx, int &ty, int &tz) {
+    const int qx = c & 1, qy = (c >> 1) & 1, qz = c >> 2;
+    tx = qx ? (t & 1) : 0;
+    t = qx ? t >> 1 : t;
+    ty = qy ? (t & 1) : 0;
+    tz = qy ? t >> 1 : t;
+    if (!qz) tz = 0;
+}
+
+// class weights: per class c, [rows][kcpad[c]] at element offset woff[c]
+struct T2Layout {
+    int64_t woff[9];
+    int kcpad[8];
+};
+
+__host__ __device__ inline T2Layout t2_layout(int Cin, int rows) {
+    T2Layout L;
+    L.woff[0] = 0;
+    for (int c = 0; c < 8; ++c) {
+        L.kcpad[c] = (t2_ntaps(c) * Cin + 31) / 32 * 32;
+        L.woff[c + 1] = L.woff[c] + (int64_t)rows * L.kcpad[c];
+    }
+    return L;
+}
+
+// Class matrices out of a full [rows][Kpad] matrix (reduction index d Cin + c).
+__global__ __launch_bounds__(256) void k_t2_class_weights(const bf16 *__restrict__ M, int rows, int Kpad, int Cin,
+                                                          T2Layout L, bf16 *__restrict__ MC) {
+    const int64_t n = L.woff[8];
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        int c = 0;
+        while (i >= L.woff[c + 1]) ++c;
+        const int64_t j = i - L.woff[c];
+        const int r = (int)(j / L.kcpad[c]), kk = (int)(j % L.kcpad[c]);
+        const int t = kk / Cin, ch = kk % Cin;
+        bf16 v = (bf16)0.0f;
+        if (t < t2_ntaps(c)) {
+            int tx, ty, tz;
+            t2_tap(c, t, tx, ty, tz);
+            const int dx = (c & 1) ? 2 * tx : 1, dy = ((c >> 1) & 1) ? 2 * ty : 1, dz = (c >> 2) ? 2 * tz : 1;
+            v = M[(int64_t)r * Kpad + (dx + 3 * dy + 9 * dz) * Cin + ch];
+        }
+        MC[i] = v;
+    }
+}
+
+// wave-tile prefix over the classes
+struct T2Tiles {
+    int64_t tile0[9];
+};
+
+// The t2 convolution over all parity classes in one launch: wave tiles are
+// numbered class by class; otherwise as k_conv (no reduction split: a class
+// has at most 8 Cin reduction indices).
+template <int NT, int MT>
+__global__ __launch_bounds__(256) void k_conv_t2(const bf16 *__restrict__ in, int Gi, int cin_log2,
+                                                 const bf16 *__restrict__ WC, T2Layout L, T2Tiles T, int Cout,
+                                                 int batch, const float *__restrict__ bias, const bf16 *add, int relu,
+                                                 bf16 *out, float *__restrict__ out32) {
+    const int lane = threadIdx.x & 63;
+    const int64_t wave = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (wave >= T.tile0[8]) return;
+    int c = 0;
+    while (wave >= T.tile0[c + 1]) ++c;
+    const int qx = c & 1, qy = (c >> 1) & 1, qz = c >> 2;
+    const int ex = Gi - qx, ey = Gi - qy, ez = Gi - qz;
+    const int64_t cvox = (int64_t)ex * ey * ez, count = (int64_t)batch * cvox;
+    const int64_t base = (wave - T.tile0[c]) * 16 * MT;
+    const int Go = 2 * Gi - 1;
+    const int64_t Vi = (int64_t)Gi * Gi * Gi, Vo = (int64_t)Go * Go * Go;
+    const int o0 = blockIdx.y * 16 * NT;
+    const int row = lane & 15, kg = lane >> 4;
+    const int Kc = t2_ntaps(c) << cin_log2, Kcpad = L.kcpad[c];
+    const int cmask = (1 << cin_log2) - 1;
+    int jx[MT], jy[MT], jz[MT];
+    int64_t nb[MT];
+    bool rv[MT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+        const int64_t v = base + mt * 16 + row;
+        rv[mt] = v < count;
+        const int64_t vv = rv[mt] ? v : 0;
+        const int64_t n = vv / cvox, r = vv % cvox;
+        jx[mt] = (int)(r % ex);
+        jy[mt] = (int)((r / ex) % ey);
+        jz[mt] = (int)(r / ((int64_t)ex * ey));
+        nb[mt] = n * Vi;
+    }
+    f32x4 acc[MT][NT];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = (f32x4)(0.0f);
+    const bf16 *Wrow = WC + L.woff[c] + (int64_t)(o0 + row) * Kcpad;
+    auto load_step = [&](int st, bf16x8(&a)[MT], bf16x8(&b)[NT]) {
+        const int k = st * 32 + 8 * kg;
+        const int t = k >> cin_log2, ch = k & cmask;
+        int tx, ty, tz;
+        t2_tap(c, t, tx, ty, tz);
+        const int ox = (qx && tx == 0) ? 1 : 0, oy = (qy && ty == 0) ? 1 : 0, oz = (qz && tz == 0) ? 1 : 0;
+#pragma unroll
+        for (int mt = 0; mt < MT; ++mt) {
+            const int64_t sv = ((int64_t)(jz[mt] + oz) * Gi + (jy[mt] + oy)) * Gi + (jx[mt] + ox);
+            a[mt] = (rv[mt] && k < Kc) ? load8(in + ((nb[mt] + sv) << cin_log2) + ch) : zero8();
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) b[nt] = load8(Wrow + (int64_t)nt * 16 * Kcpad + k);
+    };
+    const int nsteps = Kcpad >> 5;
+    bf16x8 a0[MT], b0[NT];
+    load_step(0, a0, b0);
+    for (int st = 0; st < nsteps; ++st) {
+        const bool more = st + 1 < nsteps;
+        bf16x8 a1[MT], b1[NT];
+        if (more) load_step(st + 1, a1, b1);
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0[mt], b0[nt], acc[mt][nt], 0, 0, 0);
+        if (more) {
+#pragma unroll
+            for (int mt = 0; mt < MT; ++mt) a0[mt] = a1[mt];
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) b0[nt] = b1[nt];
+        }
+    }
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int64_t v = base + mt * 16 + 4 * kg + j;
+            if (v >= count) continue;
+            const int64_t n = v / cvox, r = v % cvox;
+            const int px = 2 * (int)(r % ex) + qx, py = 2 * (int)((r / ex) % ey) + qy,
+                      pz = 2 * (int)(r / ((int64_t)ex * ey)) + qz;
+            const int64_t ov = n * Vo + ((int64_t)pz * Go + py) * Go + px;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int o = o0 + nt * 16 + row;
+                if (o >= Cout) continue;
+                float val = acc[mt][nt][j];
+                const int64_t idx = ov * Cout + o;
+                if (bias) val += bias[o];
+                if (add) val += (float)add[idx];
+                if (relu) val = fmaxf(val, 0.0f);
+                out[idx] = (bf16)val;
+                if (out32) out32[idx] = val;
+            }
+        }
 }
 
 // ------------------------------------------------------------------ weight gradient
@@ -358,37 +566,145 @@ int grid_of(int64_t n) {
     return (int)(g < 8192 ? (g < 1 ? 1 : g) : 8192);
 }
 
+// Launch shape of one convolution: wave tile (NT channel fragments, MT voxel
+// fragments) and reduction splits.  Larger tiles reuse each loaded operand
+// for more products; they are taken while the grid still has kConvWaves
+// wavefronts, and below that the reduction is split (small grids: the deep
+// levels, and batch-1 inference).
+constexpr int64_t kConvWaves = 4096;
+constexpr int64_t kConvWsFloats = 4 << 20;  // split workspace, floats
+
+struct ConvPlan {
+    int NT, MT, nsplit, steps;  // steps per split
+};
+
+ConvPlan conv_plan(int64_t total, int Cout, int Kpad, int64_t ws_floats) {
+    const int nt = (Cout + 15) / 16;
+    static const int cand[4][4][2] = {
+        {{1, 4}, {1, 2}, {1, 1}, {1, 1}},  // nt = 1
+        {{2, 4}, {2, 2}, {2, 1}, {1, 1}},  // nt = 2
+        {{4, 2}, {2, 2}, {2, 1}, {1, 1}},  // nt = 4
+        {{4, 2}, {4, 1}, {2, 1}, {1, 1}},  // nt = 8
+    };
+    const int row = nt == 1 ? 0 : nt == 2 ? 1 : nt == 4 ? 2 : 3;
+    const int nsteps = Kpad / 32;
+    ConvPlan p{1, 1, 1, nsteps};
+    int64_t waves = 0;
+    for (int c = 0; c < 4; ++c) {
+        p.NT = cand[row][c][0];
+        p.MT = cand[row][c][1];
+        waves = (total + 16 * p.MT - 1) / (16 * p.MT) * (nt / p.NT);
+        if (waves >= kConvWaves) return p;
+    }
+    // split the reduction: at least 4 steps per split, workspace permitting
+    int64_t ns = (kConvWaves + waves - 1) / waves;
+    ns = std::min<int64_t>(ns, std::max(1, nsteps / 4));
+    const int64_t per = total * Cout;
+    ns = std::min<int64_t>(ns, per > 0 ? ws_floats / per : 1);
+    if (ns <= 1) return p;
+    p.steps = (int)((nsteps + ns - 1) / ns);
+    p.nsplit = (nsteps + p.steps - 1) / p.steps;  // every split non-empty
+    return p;
+}
+
 template <int MODE>
 int conv_mode(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *W, int Kpad, int Cout, int Go,
-              int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32) {
+              int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32, float *ws,
+              int64_t ws_floats) {
     const int64_t total = (int64_t)batch * Go * Go * Go;
     const int nt = (Cout + 15) / 16;
-    const int cl = ilog2(Cin), Kreal = 27 * Cin;
-#define MFE_CONV_CASE(NT_, MT_)                                                                               \
-    {                                                                                                       \
-        const int64_t waves = (total + 16 * MT_ - 1) / (16 * MT_);                                          \
-        hipLaunchKernelGGL((k_conv<MODE, NT_, MT_>), dim3((unsigned)((waves + 3) / 4)), dim3(256), 0, s, in, \
-                           Gi, cl, W, Kpad, Kreal, Cout, Go, total, bias, add, relu, out, out32);           \
-    }
-    // the weight buffer holds exactly 16 nt rows: the tile count must match it
-    if (nt == 1) MFE_CONV_CASE(1, 4)
-    else if (nt == 2) MFE_CONV_CASE(2, 4)
-    else if (nt == 4) MFE_CONV_CASE(4, 2)
-    else if (nt == 8) MFE_CONV_CASE(8, 1)
-    else {
+    if (nt != 1 && nt != 2 && nt != 4 && nt != 8) {
         set_error("conv3d: output channels must be 8, 16, 32, 64 or 128");
         return MFE_EUNSUPPORTED;
     }
+    const int cl = ilog2(Cin), Kreal = 27 * Cin;
+    const ConvPlan pl = conv_plan(total, Cout, Kpad, ws ? ws_floats : 0);
+    float *part = pl.nsplit > 1 ? ws : nullptr;
+#define MFE_CONV_CASE(NT_, MT_)                                                                                 \
+    if (pl.NT == NT_ && pl.MT == MT_) {                                                                       \
+        const int64_t waves = (total + 16 * MT_ - 1) / (16 * MT_);                                            \
+        const dim3 grid((unsigned)((waves + 3) / 4), (unsigned)(nt / NT_), (unsigned)pl.nsplit);              \
+        hipLaunchKernelGGL((k_conv<MODE, NT_, MT_>), grid, dim3(256), 0, s, in, Gi, cl, W, Kpad, Kreal, Cout, \
+                           Go, total, pl.steps, bias, add, relu, out, out32, part);                           \
+    }
+    MFE_CONV_CASE(1, 1)
+    MFE_CONV_CASE(1, 2)
+    MFE_CONV_CASE(1, 4)
+    MFE_CONV_CASE(2, 1)
+    MFE_CONV_CASE(2, 2)
+    MFE_CONV_CASE(2, 4)
+    MFE_CONV_CASE(4, 1)
+    MFE_CONV_CASE(4, 2)
 #undef MFE_CONV_CASE
+    MFE_HIP_TRY(hipGetLastError());
+    if (part) {
+        const int64_t n = total * Cout;
+        hipLaunchKernelGGL(k_conv_reduce, dim3(grid_of(n)), dim3(256), 0, s, part, pl.nsplit, n, Cout, bias, add,
+                           relu, out, out32);
+        MFE_HIP_TRY(hipGetLastError());
+    }
+    return MFE_OK;
+}
+
+// t2 over its parity classes (WC: class weights of t2_layout(Cin, rows))
+int conv_t2(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *WC, int Cout, int batch,
+            const float *bias, const bf16 *add, int relu, bf16 *out, float *out32) {
+    const int nt = (Cout + 15) / 16;
+    if (nt != 1 && nt != 2 && nt != 4 && nt != 8) {
+        set_error("conv3d: output channels must be 8, 16, 32, 64 or 128");
+        return MFE_EUNSUPPORTED;
+    }
+    const T2Layout L = t2_layout(Cin, nt * 16);
+    const int64_t total = (int64_t)batch * (2 * Gi - 1) * (2 * Gi - 1) * (2 * Gi - 1);
+    const ConvPlan pl = conv_plan(total, Cout, 64, 0);  // tile shape only
+    T2Tiles T;
+    T.tile0[0] = 0;
+    for (int c = 0; c < 8; ++c) {
+        const int64_t cnt = (int64_t)batch * (Gi - (c & 1)) * (Gi - ((c >> 1) & 1)) * (Gi - (c >> 2));
+        T.tile0[c + 1] = T.tile0[c] + (cnt + 16 * pl.MT - 1) / (16 * pl.MT);
+    }
+    const int cl = ilog2(Cin);
+#define MFE_T2_CASE(NT_, MT_)                                                                                  \
+    if (pl.NT == NT_ && pl.MT == MT_) {                                                                        \
+        const dim3 grid((unsigned)((T.tile0[8] + 3) / 4), (unsigned)(nt / NT_));                               \
+        hipLaunchKernelGGL((k_conv_t2<NT_, MT_>), grid, dim3(256), 0, s, in, Gi, cl, WC, L, T, Cout, batch, bias, \
+                           add, relu, out, out32);                                                             \
+    }
+    MFE_T2_CASE(1, 1)
+    MFE_T2_CASE(1, 2)
+    MFE_T2_CASE(1, 4)
+    MFE_T2_CASE(2, 1)
+    MFE_T2_CASE(2, 2)
+    MFE_T2_CASE(2, 4)
+    MFE_T2_CASE(4, 1)
+    MFE_T2_CASE(4, 2)
+#undef MFE_T2_CASE
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
 }
 
-int conv(hipStream_t s, int mode, const bf16 *in, int Gi, int Cin, const bf16 *W, int Kpad, int Cout, int Go,
-         int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32) {
-    if (mode == kS1) return conv_mode<kS1>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32);
-    if (mode == kS2) return conv_mode<kS2>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32);
-    return conv_mode<kT2>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32);
+int build_t2_classes(hipStream_t s, const bf16 *M, int rows, int Kpad, int Cin, bf16 *MC) {
+    const T2Layout L = t2_layout(Cin, rows);
+    hipLaunchKernelGGL(k_t2_class_weights, dim3(grid_of(L.woff[8])), dim3(256), 0, s, M, rows, Kpad, Cin, L, MC);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int64_t t2_class_elems(int Cin, int rows) { return t2_layout(Cin, rows).woff[8]; }
+
+// W: [rows][Kpad] weights; WC: their class matrices, needed for t2
+int conv(hipStream_t s, int mode, const bf16 *in, int Gi, int Cin, const bf16 *W, const bf16 *WC, int Kpad,
+         int Cout, int Go, int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32,
+         float *ws, int64_t ws_floats) {
+    if (mode == kS1)
+        return conv_mode<kS1>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32, ws, ws_floats);
+    if (mode == kS2)
+        return conv_mode<kS2>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32, ws, ws_floats);
+    if (!WC) {
+        set_error("internal: t2 convolution without class weights");
+        return MFE_EINVAL;
+    }
+    return conv_t2(s, in, Gi, Cin, WC, Cout, batch, bias, add, relu, out, out32);
 }
 
 // number of voxel splits of a weight-gradient launch
@@ -463,6 +779,7 @@ struct Layer {
     int KpadA, rowsA;   // input-gradient weights [rowsA][KpadA]
     int64_t woff, boff; // offsets (floats) of W and b in the master parameter buffer
     Buffer act, gact, w, wa;
+    Buffer wc;          // class matrices of W (t2 layers) or of Wa (s2 layers, whose adjoint is t2)
 };
 
 }  // namespace
@@ -476,6 +793,7 @@ struct mfe_net {
     Buffer p32, g32, m32, v32, in, out32, gpre, part, bpart, lpart;
     int64_t part_floats = 0, bpart_floats = 0;
     int64_t step = 0;
+    std::vector<std::pair<int, hipGraphExec_t>> fwd_graphs, bwd_graphs;  // per batch size
 };
 
 namespace {
@@ -490,29 +808,31 @@ int upload_weights(mfe_net *N) {
                            l.def.cin, l.def.cout, l.Kpad, l.KpadA, l.rowsA, l.def.mode == kS1 ? 1 : 0,
                            (bf16 *)l.w.ptr, (bf16 *)l.wa.ptr);
         MFE_HIP_TRY(hipGetLastError());
+        if (l.def.mode == kT2)
+            MFE_TRY(build_t2_classes(s, (const bf16 *)l.w.ptr, l.rows, l.Kpad, l.def.cin, (bf16 *)l.wc.ptr));
+        else if (l.def.mode == kS2)
+            MFE_TRY(build_t2_classes(s, (const bf16 *)l.wa.ptr, l.rowsA, l.KpadA, l.def.cout, (bf16 *)l.wc.ptr));
     }
     return MFE_OK;
 }
 
-int forward(mfe_net *N, int batch, const double *g) {
-    hipStream_t s = N->ctx->stream;
-    const int64_t total = (int64_t)batch * voxels(N->G);
-    hipLaunchKernelGGL(k_net_input, dim3(grid_of(total)), dim3(256), 0, s, total, N->G, g, (bf16 *)N->in.ptr);
-    MFE_HIP_TRY(hipGetLastError());
+// The layer stack, from the staged input to out32.
+int forward_layers(mfe_net *N, int batch, hipStream_t s) {
     for (int li = 0; li < kNumLayers; ++li) {
         Layer &l = N->L[li];
         const bf16 *x = li == 0 ? (const bf16 *)N->in.ptr : (const bf16 *)N->L[li - 1].act.ptr;
         const bf16 *add = l.def.skip >= 0 ? (const bf16 *)N->L[l.def.skip].act.ptr : nullptr;
-        MFE_TRY(conv(s, l.def.mode, x, l.Gi, l.def.cin, (const bf16 *)l.w.ptr, l.Kpad, l.def.cout, l.Go, batch,
+        MFE_TRY(conv(s, l.def.mode, x, l.Gi, l.def.cin, (const bf16 *)l.w.ptr, (const bf16 *)l.wc.ptr, l.Kpad,
+                     l.def.cout, l.Go, batch,
                      (const float *)N->p32.ptr + l.boff, add, l.def.relu, (bf16 *)l.act.ptr,
-                     li == kNumLayers - 1 ? (float *)N->out32.ptr : nullptr));
+                     li == kNumLayers - 1 ? (float *)N->out32.ptr : nullptr, (float *)N->part.ptr,
+                     N->part_floats));
     }
     return MFE_OK;
 }
 
 // Backward pass into g32 (padded device layout).  gact of the last layer holds dL/dout.
-int backward(mfe_net *N, int batch) {
-    hipStream_t s = N->ctx->stream;
+int backward(mfe_net *N, int batch, hipStream_t s) {
     for (int li = 0; li < kNumLayers - 1; ++li) {
         const int64_t n = (int64_t)batch * voxels(N->L[li].Go) * N->L[li].def.cout;
         hipLaunchKernelGGL(k_fill_bf16, dim3(grid_of(n)), dim3(256), 0, s, n, (bf16 *)N->L[li].gact.ptr);
@@ -553,11 +873,63 @@ int backward(mfe_net *N, int batch) {
         // input gradient, accumulated into the previous layer's output gradient
         if (li > 0) {
             bf16 *gx = (bf16 *)N->L[li - 1].gact.ptr;
-            MFE_TRY(conv(s, adjoint_mode(l.def.mode), gp, l.Go, l.def.cout, (const bf16 *)l.wa.ptr, l.KpadA,
-                         l.def.cin, l.Gi, batch, nullptr, gx, 0, gx, nullptr));
+            MFE_TRY(conv(s, adjoint_mode(l.def.mode), gp, l.Go, l.def.cout, (const bf16 *)l.wa.ptr,
+                         (const bf16 *)l.wc.ptr, l.KpadA,
+                         l.def.cin, l.Gi, batch, nullptr, gx, 0, gx, nullptr, (float *)N->part.ptr,
+                         N->part_floats));
         }
     }
     return MFE_OK;
+}
+
+// The forward layer stack and the backward pass launch a few dozen kernels
+// each; per batch size they are captured once into HIP graphs and replayed
+// (every buffer they touch is owned by the net, so the graphs stay valid for
+// its lifetime; weights are read at replay).
+int net_graph(mfe_net *N, bool bwd, int batch, hipGraphExec_t *out) {
+    auto &cache = bwd ? N->bwd_graphs : N->fwd_graphs;
+    for (auto &e : cache)
+        if (e.first == batch) {
+            *out = e.second;
+            return MFE_OK;
+        }
+    hipStream_t cs = N->ctx->cap_stream;
+    MFE_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+    const int rc = bwd ? backward(N, batch, cs) : forward_layers(N, batch, cs);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(cs, &g);
+    if (rc != MFE_OK || e != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        if (rc != MFE_OK) return rc;
+        set_error(std::string("hipStreamEndCapture failed: ") + hipGetErrorString(e));
+        return MFE_EHIP;
+    }
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) {
+        set_error(std::string("hipGraphInstantiate failed: ") + hipGetErrorString(e2));
+        return MFE_EHIP;
+    }
+    cache.push_back({batch, ex});
+    *out = ex;
+    return MFE_OK;
+}
+
+int run_net_graph(mfe_net *N, bool bwd, int batch) {
+    hipGraphExec_t ex = nullptr;
+    MFE_TRY(net_graph(N, bwd, batch, &ex));
+    MFE_HIP_TRY(hipGraphLaunch(ex, N->ctx->stream));
+    return MFE_OK;
+}
+
+// Stage the boundary data as the network input, then run the layer stack.
+int forward(mfe_net *N, int batch, const double *g) {
+    hipStream_t s = N->ctx->stream;
+    const int64_t total = (int64_t)batch * voxels(N->G);
+    hipLaunchKernelGGL(k_net_input, dim3(grid_of(total)), dim3(256), 0, s, total, N->G, g, (bf16 *)N->in.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    return run_net_graph(N, false, batch);
 }
 
 int check_net(const mfe_net *N, int batch) {
@@ -642,6 +1014,8 @@ int mfe_net_create(mfe_ctx *ctx, int G, int batch_max, mfe_net **out) {
         A(&l.gact, n * sizeof(bf16));
         A(&l.w, (size_t)l.rows * l.Kpad * sizeof(bf16));
         A(&l.wa, (size_t)l.rowsA * l.KpadA * sizeof(bf16));
+        if (l.def.mode == kT2) A(&l.wc, (size_t)t2_class_elems(l.def.cin, l.rows) * sizeof(bf16));
+        if (l.def.mode == kS2) A(&l.wc, (size_t)t2_class_elems(l.def.cout, l.rowsA) * sizeof(bf16));
     }
     A(&N->p32, off * sizeof(float));
     A(&N->g32, off * sizeof(float));
@@ -650,6 +1024,8 @@ int mfe_net_create(mfe_ctx *ctx, int G, int batch_max, mfe_net **out) {
     A(&N->in, (size_t)batch_max * voxels(G) * 8 * sizeof(bf16));
     A(&N->out32, (size_t)batch_max * voxels(G) * 8 * sizeof(float));
     A(&N->gpre, max_act * sizeof(bf16));
+    max_part = std::max<int64_t>(max_part, kConvWsFloats);
+    N->part_floats = max_part;
     A(&N->part, max_part * sizeof(float));
     A(&N->bpart, 1024 * 128 * sizeof(float));
     A(&N->lpart, 8192 * sizeof(double));
@@ -673,8 +1049,10 @@ int mfe_net_destroy(mfe_net *N) {
     mfe_ctx *ctx = N->ctx;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    for (auto *c : {&N->fwd_graphs, &N->bwd_graphs})
+        for (auto &e : *c) (void)hipGraphExecDestroy(e.second);
     for (auto &l : N->L)
-        for (Buffer *b : {&l.act, &l.gact, &l.w, &l.wa}) dev_free(ctx, b);
+        for (Buffer *b : {&l.act, &l.gact, &l.w, &l.wa, &l.wc}) dev_free(ctx, b);
     for (Buffer *b : {&N->p32, &N->g32, &N->m32, &N->v32, &N->in, &N->out32, &N->gpre, &N->part, &N->bpart, &N->lpart})
         dev_free(ctx, b);
     delete N;
@@ -759,7 +1137,7 @@ int mfe_net_loss_grad(mfe_net *N, int batch, const double *g_dev, const double *
     hipLaunchKernelGGL(k_mse, dim3(lg), dim3(256), 0, s, total, N->G, (const float *)N->out32.ptr, target_dev,
                        1.0 / ((double)batch * inner), (bf16 *)N->L[kNumLayers - 1].gact.ptr, (double *)N->lpart.ptr);
     MFE_HIP_TRY(hipGetLastError());
-    MFE_TRY(backward(N, batch));
+    MFE_TRY(run_net_graph(N, true, batch));
     if (loss_host) {
         std::vector<double> lp(lg);
         MFE_HIP_TRY(hipMemcpyAsync(lp.data(), N->lpart.ptr, lg * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -821,20 +1199,27 @@ int mfe_conv3d_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const vo
     std::vector<bf16> w((size_t)rows * Kpad, (bf16)0.0f);
     for (int o = 0; o < cout; ++o)
         for (int k = 0; k < 27 * cin; ++k) w[(size_t)o * Kpad + k] = (bf16)w_host[(size_t)o * 27 * cin + k];
-    Buffer wb, bb;
-    MFE_TRY(dev_alloc(ctx, &wb, w.size() * sizeof(bf16)));
-    MFE_TRY(dev_alloc(ctx, &bb, cout * sizeof(float)));
+    Buffer wb, bb, ws, wc;
+    int rc = dev_alloc(ctx, &wb, w.size() * sizeof(bf16));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &bb, cout * sizeof(float));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &ws, kConvWsFloats * sizeof(float));
+    if (rc == MFE_OK && mode == kT2) rc = dev_alloc(ctx, &wc, t2_class_elems(cin, rows) * sizeof(bf16));
     hipStream_t s = ctx->stream;
-    int rc = MFE_OK;
-    if (hipMemcpyAsync(wb.ptr, w.data(), w.size() * sizeof(bf16), hipMemcpyHostToDevice, s) != hipSuccess ||
-        (bias_host && hipMemcpyAsync(bb.ptr, bias_host, cout * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess))
+    if (rc == MFE_OK &&
+        (hipMemcpyAsync(wb.ptr, w.data(), w.size() * sizeof(bf16), hipMemcpyHostToDevice, s) != hipSuccess ||
+         (bias_host && hipMemcpyAsync(bb.ptr, bias_host, cout * sizeof(float), hipMemcpyHostToDevice, s) != hipSuccess)))
         rc = MFE_EHIP;
+    if (rc == MFE_OK && mode == kT2) rc = build_t2_classes(s, (const bf16 *)wb.ptr, rows, Kpad, cin, (bf16 *)wc.ptr);
     if (rc == MFE_OK)
-        rc = conv(s, mode, (const bf16 *)in_dev, Gi, cin, (const bf16 *)wb.ptr, Kpad, cout, out_size(Gi, mode), batch,
-                  bias_host ? (const float *)bb.ptr : nullptr, nullptr, relu, (bf16 *)out_dev, out32_dev);
+        rc = conv(s, mode, (const bf16 *)in_dev, Gi, cin, (const bf16 *)wb.ptr, (const bf16 *)wc.ptr, Kpad, cout,
+                  out_size(Gi, mode), batch,
+                  bias_host ? (const float *)bb.ptr : nullptr, nullptr, relu, (bf16 *)out_dev, out32_dev,
+                  (float *)ws.ptr, kConvWsFloats);
     if (hipStreamSynchronize(s) != hipSuccess && rc == MFE_OK) rc = MFE_EHIP;
     dev_free(ctx, &wb);
     dev_free(ctx, &bb);
+    dev_free(ctx, &ws);
+    dev_free(ctx, &wc);
     return rc;
 }
 

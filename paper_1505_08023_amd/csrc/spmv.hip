@@ -23,6 +23,12 @@
 #ifndef MFE_CSR_LANES
 #define MFE_CSR_LANES 32      // lanes per row of the CRS kernel
 #endif
+#ifndef MFE_B13_PIPE
+#define MFE_B13_PIPE 0        // software-pipelined 1x3 BCRS walk
+#endif
+#ifndef MFE_B13_WAVES
+#define MFE_B13_WAVES 0       // waves per SIMD requested from the register allocator (0: default)
+#endif
 #ifndef MFE_SPMV_WG_PER_CU
 #define MFE_SPMV_WG_PER_CU 0  // resident workgroups per CU (0: as many as fit)
 #endif
@@ -101,8 +107,55 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
 
 // ---------------------------------------------------------------- 1x3 BCRS
 
+#if MFE_B13_WAVES > 0
+#define MFE_B13_ATTR __attribute__((amdgpu_waves_per_eu(MFE_B13_WAVES)))
+#else
+#define MFE_B13_ATTR
+#endif
+
+#if MFE_B13_PIPE
+// Software-pipelined walk: a wavefront owns slice 4t + w of tile t.  The
+// slice bounds come from scalar loads (the slice index is wavefront-uniform)
+// and the next tile's column indices are requested before the current
+// tile's values and gathers, so the index -> gather dependency of one tile
+// overlaps the streaming of the previous one.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
+__global__ __launch_bounds__(kBlock) MFE_B13_ATTR void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
+                                                     const int32_t *__restrict__ jas,
+                                                     const T *__restrict__ val, Epi<T> E, CgState *st,
+                                                     double *partials) {
+    if (MODE == kSpmvDot && st && !cg_gate(st)) return;
+    const long ntiles = (m + kBlock - 1) / kBlock;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    double d1 = 0.0, d2 = 0.0;
+    TileRange tr = tile_range(ntiles);
+    B13Idx cur, nxt;
+    auto fetch = [&](long t, B13Idx &r) {
+        const int64_t s = (int64_t)t * (kBlock / 64) + wave;
+        const int64_t row = s * 64 + lane;
+        r.sl.S = 0;
+        if (s * 64 >= m) return;
+        r.sl = b13_slice(slot_base[s], slot_base[s + 1]);
+        if (row < m) b13_load_idx(jas, lane, r);
+    };
+    if (tr.t < tr.end) fetch(tr.t, cur);
+    for (; tr.t < tr.end; tr.t += tr.step) {
+        const long tn = tr.t + tr.step;
+        nxt.sl.S = 0;
+        if (tn < tr.end) fetch(tn, nxt);
+        const int64_t row = tr.t * kBlock + threadIdx.x;
+        if (row < m) {
+            const T sum = cur.sl.S == 9 ? b13_row9_idx(cur.c, val, cur.sl, lane, E.x)
+                                        : b13_row_generic(jas, val, cur.sl, lane, E.x);
+            finish_row<T, MODE>(E, row, sum, d1, d2);
+        }
+        cur = nxt;
+    }
+    store_partials<MODE>(d1, d2, partials);
+}
+#else
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) MFE_B13_ATTR void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
                                                      const int32_t *__restrict__ jas,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
@@ -117,6 +170,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_b13(int64_t m, const int32_t *_
     }
     store_partials<MODE>(d1, d2, partials);
 }
+#endif
 
 // ---------------------------------------------------------------- launch
 

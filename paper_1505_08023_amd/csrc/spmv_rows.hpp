@@ -71,6 +71,45 @@ __device__ __forceinline__ T b13_row9(const int32_t *jas, const T *val, const B1
     return sum;
 }
 
+// Column indices of one row of a 9-slot slice, loaded ahead of its values so
+// that the next row's index loads overlap the current row's gathers.
+struct B13Idx {
+    B13Slice sl;
+    int32_t c[9];
+};
+
+__device__ __forceinline__ void b13_load_idx(const int32_t *__restrict__ jas, int lane, B13Idx &r) {
+    if (r.sl.S != 9) return;
+    const int4_t q0 = matrix_load((const int4_t *)(jas + r.sl.jbase + lane * 4));
+    const int4_t q1 = matrix_load((const int4_t *)(jas + r.sl.jbase + 256 + lane * 4));
+    r.c[0] = q0.x, r.c[1] = q0.y, r.c[2] = q0.z, r.c[3] = q0.w;
+    r.c[4] = q1.x, r.c[5] = q1.y, r.c[6] = q1.z, r.c[7] = q1.w;
+    r.c[8] = matrix_load(jas + r.sl.jbase + 512 + lane);
+}
+
+// Values and gathers of a 9-slot row whose indices are already loaded.
+template <typename T>
+__device__ __forceinline__ T b13_row9_idx(const int32_t *c, const T *val, const B13Slice &sl, int lane,
+                                          const T *x) {
+    vec2_t<T> a[9], b[4];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a[k] = matrix_load((const vec2_t<T> *)(val + sl.vbase + k * 128 + lane * 2));
+#pragma unroll
+    for (int p = 0; p < 4; ++p)
+        b[p] = matrix_load((const vec2_t<T> *)(val + sl.vbase + 9 * 128 + p * 128 + lane * 2));
+    const T w8 = matrix_load(val + sl.vbase + 13 * 128 + lane);
+    const T v2[9] = {b[0].x, b[0].y, b[1].x, b[1].y, b[2].x, b[2].y, b[3].x, b[3].y, w8};
+    T sum = 0;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) {
+        const T *xp = x + c[k];
+        sum += a[k].x * xp[0];
+        sum += a[k].y * xp[1];
+        sum += v2[k] * xp[2];
+    }
+    return sum;
+}
+
 // 1x3 BCRS row `row` (one lane per row).
 template <typename T>
 __device__ __forceinline__ T b13_row(const int32_t *__restrict__ slot_base, const int32_t *__restrict__ jas,

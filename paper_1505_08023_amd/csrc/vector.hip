@@ -98,8 +98,14 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
             st->status = kConverged;
             if (st->hist) st->hist[0] = 0.0;
         } else {
-            st->rho = s1;
-            const double res = sqrt(s1) / bnorm;
+            double rho = s1;
+            if (st->warm && s1 >= s2) {
+                // the guess is no closer than x0 = 0: restart from zero (r = b)
+                st->zero_x = 2;
+                rho = s2;
+            }
+            st->rho = rho;
+            const double res = sqrt(rho) / bnorm;
             if (st->hist) st->hist[0] = res;
             if (!isfinite(res)) st->status = kBreakdown;
             else if (res <= st->tol) st->status = kConverged;
@@ -114,10 +120,20 @@ __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ 
     }
 }
 
-__global__ __launch_bounds__(kBlock) void k_zero_if(int64_t m, double *__restrict__ x, const CgState *st) {
-    if (!st->zero_x) return;
+__global__ __launch_bounds__(kBlock) void k_zero_if(int64_t m, double *__restrict__ x, double *__restrict__ r,
+                                                    double *__restrict__ p, const double *__restrict__ b,
+                                                    const CgState *st) {
+    const int z = st->zero_x;
+    if (!z) return;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) x[i] = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        x[i] = 0.0;
+        if (z == 2) {
+            const double bi = b[i];
+            r[i] = bi;
+            p[i] = bi;
+        }
+    }
 }
 
 __global__ __launch_bounds__(kBlock) void k_dot(int64_t n, const double *__restrict__ x,
@@ -189,9 +205,10 @@ int launch_finalize(FinalizeKind kind, const double *partials, int n, CgState *s
     return MFE_OK;
 }
 
-int launch_zero_if(int64_t m, double *x, const CgState *st, int num_cu, hipStream_t s) {
+int launch_zero_if(int64_t m, double *x, double *r, double *p, const double *b, const CgState *st, int num_cu,
+                   hipStream_t s) {
     const int g = vec_grid((const void *)k_zero_if, m, num_cu);
-    hipLaunchKernelGGL(k_zero_if, dim3(g), dim3(kBlock), 0, s, m, x, st);
+    hipLaunchKernelGGL(k_zero_if, dim3(g), dim3(kBlock), 0, s, m, x, r, p, b, st);
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
 }

@@ -239,19 +239,24 @@ class Problem:
                                             ev[0], ev[1]), "mfe_spmv_dot")
         return q, pq
 
-    def cg(self, x=None, tol=1e-8, max_iter=200, fmt="bcrs13", history=False, raise_on_breakdown=True):
-        """Unpreconditioned CG from x (zero if None).  Returns (x, stats dict)."""
+    def cg(self, x=None, tol=1e-8, max_iter=200, fmt="bcrs13", history=False, raise_on_breakdown=True,
+           warm=False):
+        """Unpreconditioned CG from x (zero if None).  warm=True: x is a guess
+        that the solve replaces by zero when ||b - A x|| >= ||b||
+        (mfe_cg_warm).  Returns (x, stats dict)."""
         d = self.ctx.device
         if x is None:
             with _on(self.ctx):
                 x = torch.zeros(self.m, dtype=torch.float64, device=d)
         hist = torch.zeros(max_iter + 1, dtype=torch.float64, device=d) if history else None
         st = mfe_cg_stats()
+        name = "mfe_cg_warm" if warm else "mfe_cg"
         with _on(self.ctx):
-            rc = self.ctx.lib.mfe_cg(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"), float(tol),
-                                     int(max_iter), _ptr(hist, torch.float64), ctypes.byref(st))
+            rc = getattr(self.ctx.lib, name)(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"),
+                                             float(tol), int(max_iter), _ptr(hist, torch.float64),
+                                             ctypes.byref(st))
         ok = (MFE_OK, MFE_NOT_CONVERGED) + (() if raise_on_breakdown else (MFE_EBREAKDOWN,))
-        check(rc, "mfe_cg", ok)
+        check(rc, name, ok)
         out = st.as_dict()
         if history:
             out["history"] = hist[: st.iterations + 1].cpu()

@@ -331,6 +331,46 @@ def test_cg_edge_cases(ctx):
     check_solution_gap(np_(x), ref, st, N, A)
 
 
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_cg_warm_start(ctx, fmt):
+    """mfe_cg_warm keeps a guess closer than x0 = 0 and otherwise solves from
+    zero, bitwise as mfe_cg from zero (the same kernels see r0 = b)."""
+    N = (20, 20, 20)
+    A = oracle.assemble(*N)
+    ref = oracle.cg(A, tol=1e-12, max_iter=1000)
+    P = mesh_problem(ctx, N)
+    x_zero, st_zero = P.cg(tol=1e-8, max_iter=500, fmt=fmt, history=True)
+    # a guess near the solution: kept, fewer iterations, same stopping rule
+    rng = np.random.default_rng(4)
+    guess = ref["x"] + 1e-4 * rng.standard_normal(P.m)
+    dirichlet = oracle.boundary(*N)[0] != 0
+    guess[dirichlet] = ref["x"][dirichlet]  # Dirichlet values exact, as a predicted guess keeps them
+    g = torch.tensor(guess, device=ctx.device)
+    x, st = P.cg(x=g, tol=1e-8, max_iter=500, fmt=fmt, warm=True, history=True)
+    assert st["guess_rejected"] == 0 and st["status"] == 0
+    assert st["iterations"] < st_zero["iterations"]
+    assert st["rel_res_true"] <= 1e-8
+    r0 = A.b - oracle.csr_spmv(A, guess)
+    assert abs(float(st["history"][0]) - np.linalg.norm(r0) / np.linalg.norm(A.b)) <= 1e-12
+    check_solution_gap(np_(x), ref, st, N, A)
+    # a poor guess: rejected, then identical to the zero start
+    bad = torch.tensor(10.0 * rng.standard_normal(P.m), device=ctx.device)
+    x, st = P.cg(x=bad, tol=1e-8, max_iter=500, fmt=fmt, warm=True, history=True)
+    assert st["guess_rejected"] == 1
+    assert st["iterations"] == st_zero["iterations"]
+    assert np.array_equal(np_(x), np_(x_zero))
+    assert np.array_equal(st["history"].numpy(), st_zero["history"].numpy())
+    # the plain entry point never rejects
+    x, st = P.cg(x=torch.tensor(10.0 * rng.standard_normal(P.m), device=ctx.device), tol=1e-8, max_iter=500,
+                 fmt=fmt)
+    assert st["guess_rejected"] == 0
+    # x0 = 0 itself (||r0|| = ||b||) counts as rejected and changes nothing
+    x, st = P.cg(x=torch.zeros(P.m, dtype=torch.float64, device=ctx.device), tol=1e-8, max_iter=500, fmt=fmt,
+                 warm=True)
+    assert st["guess_rejected"] == 1 and np.array_equal(np_(x), np_(x_zero))
+    P.close()
+
+
 def test_cg_breakdown_on_indefinite_matrix(ctx):
     from paper_1505_08023_amd.mfe import Problem
     d = ctx.device

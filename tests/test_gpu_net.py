@@ -34,13 +34,16 @@ def to_bf16_tensor(a, device):
 
 CASES = [("s1", 9, 8, 16), ("s1", 9, 16, 16), ("s1", 5, 128, 128), ("s2", 17, 16, 32), ("s2", 9, 64, 128),
          ("t2", 9, 32, 16), ("t2", 5, 128, 64), ("s1", 9, 16, 8)]
+# small grids split the reduction over several workgroups (summed in a fixed
+# order afterwards); these larger ones run unsplit with the wider wave tiles
+LARGE = [("s1", 65, 8, 16, 1), ("s1", 33, 16, 32, 2), ("t2", 33, 32, 16, 1)]
 
 
-@pytest.mark.parametrize("mode,G,cin,cout", CASES)
-def test_conv_forward(ctx, mode, G, cin, cout):
+@pytest.mark.parametrize("mode,G,cin,cout,batch", [c + (2,) for c in CASES] + LARGE)
+def test_conv_forward(ctx, mode, G, cin, cout, batch):
     from paper_1505_08023_amd.mfe import conv3d
     rng = np.random.default_rng(hash((mode, G, cin, cout)) % 2 ** 32)
-    x = conv.bf16(rng.standard_normal((2, G, G, G, cin)))
+    x = conv.bf16(rng.standard_normal((batch, G, G, G, cin)))
     w = conv.bf16(rng.standard_normal((cout, 27, cin)) / np.sqrt(27 * cin))
     b = rng.standard_normal(cout).astype(np.float32)
     xg = to_bf16_tensor(x, ctx.device)
@@ -137,6 +140,33 @@ def test_network_forward_and_gradient(ctx):
         cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
         print("layer", li, "rel err", err, "cos", cos)
         assert err <= 0.1 and cos >= 0.99, (li, err, cos)
+    net.close()
+
+
+def test_network_graph_replays(ctx):
+    """The forward and backward passes replay captured graphs: alternating
+    inputs, with other device work in between, reproduce every result
+    bitwise, and a different input gives a different result."""
+    from paper_1505_08023_amd.mfe import Net
+    G, B = 17, 2
+    rng = np.random.default_rng(5)
+    net = Net(ctx, G, B)
+    net.set_params(flatten(he_params(rng)))
+    gs = [torch.tensor(rng.uniform(0, 1, B * G ** 3), device=ctx.device) for _ in range(2)]
+    tt = torch.tensor(rng.uniform(0, 1, B * G ** 3), device=ctx.device)
+    first = []
+    for rep in range(3):
+        for i, g in enumerate(gs):
+            pred = net.forward(g).cpu().numpy()
+            loss, grad = net.loss_grad(g, tt, want_grad=True)
+            junk = torch.randn(1 << 20, device=ctx.device)  # eager work between replays
+            junk.mul_(2.0).sum().item()
+            if rep == 0:
+                first.append((pred, loss, grad))
+            else:
+                assert np.array_equal(pred, first[i][0]) and loss == first[i][1]
+                assert np.array_equal(grad, first[i][2])
+    assert not np.array_equal(first[0][0], first[1][0])
     net.close()
 
 
