@@ -24,6 +24,8 @@
  *   fixed 1x3 zero-padded BCRS build + SpMV (derived from Sec. 3.1)
  *   unpreconditioned CG                     (Sec. 1, CG module)
  *   FP32-inner / FP64-refinement CG         (mixed-precision extension)
+ *   single-reduction CG                     (Chronopoulos-Gear form of the CG
+ *                                            module; Sec. 3, Fig 3.5 discussion)
  *   separation-of-variables series solution (Sec. 1, result verification)
  *
  * Conventions (readings of passages where the paper is silent):
@@ -597,6 +599,86 @@ int orc_cg_mixed(int64_t m, const int64_t *ptr, const int32_t *col, const double
     }
 out:
     free(v32); free(r); free(ax); free(r32); free(d); free(p); free(q);
+    return status;
+}
+
+/* ------------------------------------------------------------------ */
+/* Single-reduction CG (Chronopoulos and Gear, 1989)                    */
+/* ------------------------------------------------------------------ */
+
+/* The CG recurrence rearranged so that both inner products of an iteration
+ * are taken together, right after the product with the matrix: the global
+ * synchronisation after SpMV that the paper measures in its CG module
+ * (Sec. 3, discussion of Fig 3.5) then happens once per iteration instead
+ * of twice.  In exact arithmetic the iterates are those of orc_cg.
+ *
+ * With r = b - A x0, bnorm = ||b||:
+ *   w = A r;  gamma = r.r;  delta = w.r          (one SpMV, two dots)
+ *   stop when sqrt(gamma)/bnorm <= tol (the current r), or after max_iter
+ *   updates;  otherwise
+ *     first update:  beta = 0,  alpha = gamma/delta,  p = r,  s = w
+ *     later:         beta = gamma/gamma_prev,
+ *                    alpha = gamma/(delta - beta gamma/alpha_prev),
+ *                    p = r + beta p,  s = w + beta s        (s = A p)
+ *     x += alpha p;  r -= alpha s
+ * The denominator equals p.Ap in exact arithmetic: a non-positive or
+ * non-finite one is a breakdown.  iterations = updates of x; hist[k] =
+ * ||r_k||/||b||.  At exit the true residual is recomputed. */
+int orc_cg_single_reduction(int64_t m, const int64_t *ptr, const int32_t *col, const double *val,
+                            const double *b, double *x, double tol, int max_iter,
+                            int *iters, double *res_rec, double *res_true, double *hist)
+{
+    double *r = (double *)malloc((size_t)m * sizeof(double));
+    double *w = (double *)malloc((size_t)m * sizeof(double));
+    double *p = (double *)malloc((size_t)m * sizeof(double));
+    double *sv = (double *)malloc((size_t)m * sizeof(double));
+    if (!r || !w || !p || !sv) { free(r); free(w); free(p); free(sv); return ORC_ENOMEM; }
+    int status = ORC_NOT_CONVERGED, k = 0;
+    orc_csr_spmv(m, ptr, col, val, x, w);
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - w[i];
+    double bnorm = sqrt(dot(m, b, b));
+    double gamma = dot(m, r, r), gamma_prev = 0.0, alpha_prev = 0.0;
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < m; ++i) x[i] = 0.0;
+        *iters = 0; *res_rec = 0.0; *res_true = 0.0;
+        if (hist) hist[0] = 0.0;
+        free(r); free(w); free(p); free(sv);
+        return ORC_OK;
+    }
+    if (hist) hist[0] = sqrt(gamma) / bnorm;
+    if (sqrt(gamma) / bnorm <= tol) status = ORC_OK;
+    while (status == ORC_NOT_CONVERGED && k < max_iter) {
+        orc_csr_spmv(m, ptr, col, val, r, w);
+        double delta = dot(m, w, r);
+        double alpha, beta, denom;
+        if (k == 0) {
+            beta = 0.0;
+            denom = delta;
+        } else {
+            beta = gamma / gamma_prev;
+            denom = delta - beta * gamma / alpha_prev;
+        }
+        if (!(denom > 0.0) || !isfinite(denom)) { status = ORC_BREAKDOWN; break; }
+        alpha = gamma / denom;
+        for (int64_t i = 0; i < m; ++i) {
+            p[i] = k == 0 ? r[i] : r[i] + beta * p[i];
+            sv[i] = k == 0 ? w[i] : w[i] + beta * sv[i];
+        }
+        for (int64_t i = 0; i < m; ++i) x[i] += alpha * p[i];
+        for (int64_t i = 0; i < m; ++i) r[i] -= alpha * sv[i];
+        ++k;
+        gamma_prev = gamma;
+        alpha_prev = alpha;
+        gamma = dot(m, r, r);
+        if (hist) hist[k] = sqrt(gamma) / bnorm;
+        if (sqrt(gamma) / bnorm <= tol) status = ORC_OK;
+    }
+    *iters = k;
+    *res_rec = sqrt(gamma) / bnorm;
+    orc_csr_spmv(m, ptr, col, val, x, w);
+    for (int64_t i = 0; i < m; ++i) r[i] = b[i] - w[i];
+    *res_true = sqrt(dot(m, r, r)) / bnorm;
+    free(r); free(w); free(p); free(sv);
     return status;
 }
 

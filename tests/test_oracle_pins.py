@@ -204,6 +204,76 @@ def test_cg_history_and_stop_rule():
     assert zero["iterations"] == 0 and np.all(zero["x"] == 0)
 
 
+def krylov_minimiser(A, x0, k):
+    """x0 + V y minimising the energy norm of the error over the Krylov space
+    K_k(A, r0): the iterate that CG defines after k steps (textbook
+    optimality), computed by brute force with a dense orthonormal basis."""
+    M = A.dense()
+    r0 = A.b - M @ x0
+    K = np.empty((A.m, k))
+    v = r0 / np.linalg.norm(r0)
+    for j in range(k):
+        K[:, j] = v
+        v = M @ v
+        v /= np.linalg.norm(v)
+    V, _ = np.linalg.qr(K)
+    y = np.linalg.solve(V.T @ M @ V, V.T @ r0)
+    return x0 + V @ y
+
+
+@pytest.mark.parametrize("solver", ["cg", "cg_single_reduction"])
+@pytest.mark.parametrize("N", [(2, 2, 2), (3, 2, 4)])
+def test_cg_iterates_are_krylov_minimisers(solver, N):
+    A = oracle.assemble(*N)
+    x0 = np.random.default_rng(1).uniform(-1, 1, A.m)
+    for k in (1, 2, 3, 4):
+        r = getattr(oracle, solver)(A, x0=x0, tol=0.0, max_iter=k)
+        assert r["iterations"] == k and r["status"] == oracle.NOT_CONVERGED
+        ref = krylov_minimiser(A, x0, k)
+        assert np.linalg.norm(r["x"] - ref) <= 1e-9 * np.linalg.norm(ref), (solver, k)
+
+
+@pytest.mark.parametrize("N", [(1, 1, 1), (2, 2, 2), (3, 2, 4), (4, 4, 4)])
+def test_single_reduction_cg_matches_dense_solve(N):
+    A = oracle.assemble(*N)
+    r = oracle.cg_single_reduction(A, tol=1e-14, max_iter=500)
+    assert r["status"] == oracle.OK
+    xs = np.linalg.solve(A.dense(), A.b)
+    assert np.linalg.norm(r["x"] - xs) <= 1e-10 * np.linalg.norm(xs)
+    assert r["rel_res_true"] <= 1e-13
+
+
+def test_single_reduction_cg_stop_rule_and_breakdown():
+    A = oracle.assemble(20, 20, 20)
+    r = oracle.cg_single_reduction(A, tol=1e-8, max_iter=200, history=True)
+    ref = oracle.cg(A, tol=1e-8, max_iter=200, history=True)
+    h = r["history"]
+    assert r["status"] == oracle.OK and h[0] == 1.0
+    assert h[-1] <= 1e-8 and np.all(h[:-1] > 1e-8) and len(h) == r["iterations"] + 1
+    # the same Krylov iterates as CG: residual histories agree until rounding separates them
+    assert np.all(np.abs(h[:6] - ref["history"][:6]) <= 1e-10 * ref["history"][:6])
+    assert abs(r["iterations"] - ref["iterations"]) <= 2
+    capped = oracle.cg_single_reduction(A, tol=1e-8, max_iter=10)
+    assert capped["status"] == oracle.NOT_CONVERGED and capped["iterations"] == 10
+    zero = oracle.cg_single_reduction(A, tol=1e-8, max_iter=0)
+    assert zero["iterations"] == 0 and np.all(zero["x"] == 0)
+    # diag(1, -1), b = (1, 1): r.Ar = 0 at the first step
+    D = oracle.CSR(np.array([0, 1, 2], np.int64), np.array([0, 1], np.int32), np.array([1.0, -1.0]),
+                   np.array([1.0, 1.0]))
+    assert oracle.cg_single_reduction(D, tol=1e-8, max_iter=5)["status"] == oracle.BREAKDOWN
+
+
+@pytest.mark.parametrize("N", [(6, 6, 6), (5, 3, 7)])
+def test_single_reduction_cg_patch_test(N):
+    Nx, Ny, Nz = N
+    n = np.arange(oracle.num_rows(*N))
+    u = 0.3 + 0.7 * (n % (Nx + 1)) / Nx - 0.2 * ((n // (Nx + 1)) % (Ny + 1)) / Ny \
+        + 0.45 * (n // ((Nx + 1) * (Ny + 1))) / Nz
+    A = oracle.assemble(*N, node_g=u)
+    r = oracle.cg_single_reduction(A, tol=1e-13, max_iter=2000)
+    assert r["status"] == oracle.OK and np.abs(r["x"] - u).max() <= 1e-9
+
+
 @pytest.mark.parametrize("N", [(6, 6, 6), (5, 3, 7), (9, 4, 4)])
 def test_patch_test_affine_exact(N):
     """Trilinear elements reproduce affine fields exactly (Galerkin is exact on the FE space)."""
