@@ -67,6 +67,8 @@ def lib():
                              ctypes.POINTER(_c_dbl), ctypes.c_void_p]
         L.orc_cg_single_reduction.restype = _c_int
         L.orc_cg_single_reduction.argtypes = L.orc_cg.argtypes
+        L.orc_cg_jacobi.restype = _c_int
+        L.orc_cg_jacobi.argtypes = L.orc_cg.argtypes
         L.orc_cg_mixed.restype = _c_int
         L.orc_cg_mixed.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_dbl,
                                    _c_int, _c_int, ctypes.POINTER(_c_int),
@@ -245,6 +247,22 @@ def cg_single_reduction(A, b=None, x0=None, tol=1e-8, max_iter=200, history=Fals
     hp = hist.ctypes.data_as(ctypes.c_void_p) if history else None
     st = lib().orc_cg_single_reduction(A.m, A.ptr, A.col, A.val, b, x, tol, max_iter,
                                        ctypes.byref(its), ctypes.byref(rr), ctypes.byref(rt), hp)
+    out = dict(x=x, status=st, iterations=its.value, rel_res_rec=rr.value, rel_res_true=rt.value)
+    if history:
+        out["history"] = hist[: its.value + 1]
+    return out
+
+
+def cg_jacobi(A, b=None, x0=None, tol=1e-8, max_iter=200, history=False):
+    """Jacobi-preconditioned CG (M = diag(A)), stopping on ||r||/||b|| as
+    cg() does.  Same outputs as cg()."""
+    b = A.b if b is None else np.ascontiguousarray(b, np.float64)
+    x = np.zeros(A.m) if x0 is None else np.array(x0, np.float64, copy=True)
+    its, rr, rt = _c_int(0), _c_dbl(0), _c_dbl(0)
+    hist = np.zeros(max_iter + 1) if history else None
+    hp = hist.ctypes.data_as(ctypes.c_void_p) if history else None
+    st = lib().orc_cg_jacobi(A.m, A.ptr, A.col, A.val, b, x, tol, max_iter,
+                             ctypes.byref(its), ctypes.byref(rr), ctypes.byref(rt), hp)
     out = dict(x=x, status=st, iterations=its.value, rel_res_rec=rr.value, rel_res_true=rt.value)
     if history:
         out["history"] = hist[: its.value + 1]

@@ -233,6 +233,60 @@ def test_cg_iterates_are_krylov_minimisers(solver, N):
         assert np.linalg.norm(r["x"] - ref) <= 1e-9 * np.linalg.norm(ref), (solver, k)
 
 
+@pytest.mark.parametrize("N", [(3, 4, 3), (4, 4, 5)])
+def test_jacobi_cg_iterates_are_preconditioned_krylov_minimisers(N):
+    """Preconditioned CG with M = D: x_k minimises the energy norm of the
+    error over x0 + K_k(D^-1 A, D^-1 r0) (brute force, dense basis).  The
+    meshes have several free nodes: with one (2^3 elements) D^-1 A = I."""
+    A = oracle.assemble(*N)
+    M = A.dense()
+    dinv = 1.0 / np.diag(M)
+    x0 = np.random.default_rng(3).uniform(-1, 1, A.m)
+    r0 = A.b - M @ x0
+    for k in (1, 2, 3, 4):
+        r = oracle.cg_jacobi(A, x0=x0, tol=0.0, max_iter=k)
+        assert r["iterations"] == k and r["status"] == oracle.NOT_CONVERGED
+        K = np.empty((A.m, k))
+        v = dinv * r0
+        for j in range(k):
+            K[:, j] = v / np.linalg.norm(v)
+            v = dinv * (M @ K[:, j])
+        V, _ = np.linalg.qr(K)
+        ref = x0 + V @ np.linalg.solve(V.T @ M @ V, V.T @ r0)
+        assert np.linalg.norm(r["x"] - ref) <= 1e-9 * np.linalg.norm(ref), k
+
+
+def test_jacobi_cg_special_cases():
+    # a diagonal matrix is solved exactly in one step
+    d = np.array([2.0, 5.0, 0.5, 7.0])
+    D = oracle.CSR(np.arange(5, dtype=np.int64), np.arange(4, dtype=np.int32), d, np.array([1.0, -2.0, 3.0, 0.5]))
+    r = oracle.cg_jacobi(D, tol=1e-15, max_iter=5)
+    assert r["status"] == oracle.OK and r["iterations"] == 1
+    assert np.allclose(r["x"], D.b / d, rtol=1e-15, atol=0)
+    # dense solve, patch test, and the Dirichlet outlier gone: fewer iterations than CG
+    for N in [(3, 2, 4), (4, 4, 4)]:
+        A = oracle.assemble(*N)
+        xs = np.linalg.solve(A.dense(), A.b)
+        r = oracle.cg_jacobi(A, tol=1e-14, max_iter=500)
+        assert r["status"] == oracle.OK and np.linalg.norm(r["x"] - xs) <= 1e-10 * np.linalg.norm(xs)
+    Nx, Ny, Nz = 6, 5, 7
+    n = np.arange(oracle.num_rows(Nx, Ny, Nz))
+    u = 0.1 + 0.5 * (n % (Nx + 1)) / Nx + 0.3 * ((n // (Nx + 1)) % (Ny + 1)) / Ny \
+        - 0.4 * (n // ((Nx + 1) * (Ny + 1))) / Nz
+    A = oracle.assemble(Nx, Ny, Nz, node_g=u)
+    r = oracle.cg_jacobi(A, tol=1e-13, max_iter=2000)
+    assert r["status"] == oracle.OK and np.abs(r["x"] - u).max() <= 1e-9
+    A = oracle.assemble(20, 20, 20)
+    rj = oracle.cg_jacobi(A, tol=1e-8, max_iter=500, history=True)
+    rc = oracle.cg(A, tol=1e-8, max_iter=500)
+    assert rj["status"] == oracle.OK and rj["history"][0] == 1.0 and rj["rel_res_true"] <= 1e-8
+    assert rj["iterations"] <= rc["iterations"]
+    # a zero diagonal entry is rejected
+    Z = oracle.CSR(np.array([0, 1, 2], np.int64), np.array([1, 0], np.int32), np.array([1.0, 1.0]),
+                   np.array([1.0, 1.0]))
+    assert oracle.cg_jacobi(Z, tol=1e-8, max_iter=5)["status"] == oracle.EINVAL
+
+
 @pytest.mark.parametrize("N", [(1, 1, 1), (2, 2, 2), (3, 2, 4), (4, 4, 4)])
 def test_single_reduction_cg_matches_dense_solve(N):
     A = oracle.assemble(*N)
