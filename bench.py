@@ -241,6 +241,35 @@ def extras(args, ctx, P, x, line, torch):
     line["batched_64_meshes_1e-8"] = bat
     B.close()
 
+    # CG variants to 1e-8 against the two-reduction loop: single-reduction (one
+    # reduction point per iteration) and Jacobi-preconditioned; 256^3 and the
+    # 64^3 mesh of the learned section
+    sr = {}
+    P64 = Problem.mesh(ctx, 64, 64, 64, formats=("bcrs13",))
+    for label, PP, xx in (("256cubed", P, x), ("64cubed", P64, None)):
+        if xx is None:
+            xx = torch.zeros(PP.m, dtype=torch.float64, device=ctx.device)
+        row = {}
+        for variant in ("cg", "single_reduction", "jacobi"):
+            best, st = None, None
+            for _ in range(3):
+                with torch.cuda.stream(ctx.stream):
+                    xx.zero_()
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st = PP.cg(xx, tol=1e-8, max_iter=args.max_iter, fmt=args.fmt, variant=variant)[1]
+                torch.cuda.synchronize()
+                dt = time.perf_counter() - t
+                best = dt if best is None else min(best, dt)
+            row[variant] = dict(seconds=best, iterations=st["iterations"], it_per_s=st["iterations"] / best,
+                                rel_res_true=st["rel_res_true"])
+        row["speedup_single_reduction"] = row["cg"]["seconds"] / row["single_reduction"]["seconds"]
+        row["speedup_jacobi"] = row["cg"]["seconds"] / row["jacobi"]["seconds"]
+        sr[label] = row
+        log(f"[bench] CG variants {label}: {row}")
+    line["cg_variants_1e-8"] = sr
+    P64.close()
+
     # 128^3 plain CG for exactly 200 iterations (tol 0), both formats
     P2 = Problem.mesh(ctx, 128, 128, 128, formats=("csr", "bcrs13"))
     x2 = torch.zeros(P2.m, dtype=torch.float64, device=ctx.device)
@@ -262,6 +291,45 @@ def extras(args, ctx, P, x, line, torch):
         log(f"[bench] 128^3 CG x200 {fmt}: {c2[fmt]}")
     line["cg_128cubed_200_iterations"] = c2
     P2.close()
+
+    # time per module at the paper's mesh sizes: assembly (mesh, CRS
+    # structure, element sums, Dirichlet elimination), CRS -> 1x3 BCRS
+    # conversion, CG to 1e-8 (its SpMV share from the SpMV + dot kernel time),
+    # and the device-side verification against the series solution
+    mods = {}
+    for n in (200, 300):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        Pa = Problem.mesh(ctx, n, n, n, formats=("csr",))
+        torch.cuda.synchronize()
+        t_asm = time.perf_counter() - t
+        Pa.close()
+        t = time.perf_counter()
+        Pb = Problem.mesh(ctx, n, n, n, formats=("csr", "bcrs13"))
+        torch.cuda.synchronize()
+        t_both = time.perf_counter() - t
+        xn = torch.zeros(Pb.m, dtype=torch.float64, device=ctx.device)
+        Pb.cg(xn, tol=1e-8, max_iter=args.max_iter, fmt="bcrs13")  # warm-up (graph capture)
+        with torch.cuda.stream(ctx.stream):
+            xn.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = Pb.cg(xn, tol=1e-8, max_iter=args.max_iter, fmt="bcrs13")[1]
+        torch.cuda.synchronize()
+        t_cg = time.perf_counter() - t
+        spmv_ms = time_spmv_dot(Pb, "bcrs13", 10, torch)[0]
+        t = time.perf_counter()
+        ver = Pb.verify_series(xn, x_max=0.75)
+        t_ver = time.perf_counter() - t
+        mods[f"{n}cubed"] = dict(rows=Pb.m, nnz=Pb.nnz, assembly_s=t_asm, bcrs13_conversion_s=max(t_both - t_asm, 0.0),
+                                 cg_s=t_cg, cg_iterations=st["iterations"], cg_rel_res_true=st["rel_res_true"],
+                                 spmv_share_of_cg=st["iterations"] * spmv_ms * 1e-3 / t_cg,
+                                 verification_s=t_ver, verification_max_err=ver["max_err"],
+                                 verification_rms_err=ver["rms_err"], verification_nodes=ver["count"])
+        log(f"[bench] modules {n}^3: {mods[f'{n}cubed']}")
+        Pb.close()
+        del xn
+    line["module_times"] = mods
 
     # learned warm start against the zero start, 64^3, held-out boundary data
     wpath = os.path.join(ROOT, "paper_1505_08023_amd", "weights", "net64.npz")

@@ -183,6 +183,44 @@ int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_
 int mfe_cg_warm(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
                 double *hist_dev, mfe_cg_stats *stats);
 
+/* Single-reduction CG (the Chronopoulos-Gear form of the CG module of
+ * Sec. 1): the same Krylov iterates as mfe_cg in exact arithmetic, but both
+ * inner products of an iteration (r.r and r.Ar) are taken together in the
+ * kernel that forms w = A r, so an iteration has one reduction point where
+ * mfe_cg has two (Sec. 3, discussion of Fig 3.5: the global synchronisation
+ * after SpMV).  Recurrences: beta = gamma/gamma_prev, alpha = gamma /
+ * (delta - beta gamma/alpha_prev), p = r + beta p, s = w + beta s, x +=
+ * alpha p, r -= alpha s with gamma = r.r, delta = r.w.  FP64 only.  The
+ * stopping rule, hist_dev, stats and return values are those of mfe_cg
+ * (iterations = updates of x); the loop issues iterations + 1 SpMVs since
+ * the residual norm of an iterate is known only after its product.  A
+ * non-positive or non-finite alpha denominator returns MFE_EBREAKDOWN. */
+int mfe_cg_single_reduction(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
+                            double *hist_dev, mfe_cg_stats *stats);
+
+/* Jacobi-preconditioned CG (a comparison variant of the unpreconditioned CG
+ * module of Sec. 1): preconditioner M = diag(A), built once per problem from
+ * the FP64 CRS values (MFE_EINVAL if a diagonal entry is zero, missing or
+ * not finite).  z = D^-1 r, alpha = r.z / p.Ap, p = z + beta p.  The
+ * stopping test, hist_dev (||r_k||/||b||), stats and return values are
+ * those of mfe_cg, so iteration counts compare directly.  FP64 only. */
+int mfe_cg_jacobi(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
+                  double *hist_dev, mfe_cg_stats *stats);
+
+/* Result verification (Sec. 1) for the paper's boundary data (u = 1 on
+ * x = 1, u = 0 on the other faces; the problem must come from
+ * mfe_problem_create, else MFE_EUNSUPPORTED).  On the device, evaluates the
+ * separation-of-variables solution
+ *   u = sum_{p,q odd} 16/(pi^2 p q) sin(p pi y) sin(q pi z) sinh(g x)/sinh(g),
+ *   g = pi sqrt(p^2 + q^2)   (terms summed while their bound exceeds 1e-18)
+ * at every node with x-coordinate <= x_max (0 < x_max < 1; the series
+ * converges slowly next to x = 1) and reduces, over those nodes, max |x - u|
+ * into *max_err, sqrt(mean (x - u)^2) into *rms_err and their number into
+ * *count (host scalars).  u_dev (length m, may be NULL) receives u at those
+ * nodes and NaN elsewhere.  Synchronises the stream. */
+int mfe_verify_series(const mfe_problem *p, const double *x_dev, double x_max, double *u_dev, double *max_err,
+                      double *rms_err, int64_t *count);
+
 /* Mixed precision CG (FP32-inner / FP64-refinement extension of the CG
  * module of Sec. 1).  Outer loop in FP64: r = b - A x with the FP64 matrix,
  * stop when ||r||_2/||b||_2 <= tol, s = ||r||; inner unpreconditioned CG in

@@ -53,6 +53,10 @@ SIGNATURES = {
     "mfe_dot": (c_int, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(c_dbl)]),
     "mfe_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_cg_warm": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
+    "mfe_cg_single_reduction": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
+    "mfe_cg_jacobi": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
+    "mfe_verify_series": (c_int, [c_vp, c_vp, c_dbl, c_vp, ctypes.POINTER(c_dbl), ctypes.POINTER(c_dbl),
+                                  ctypes.POINTER(ctypes.c_int64)]),
     "mfe_cg_mixed": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_batch_create": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_int, PP]),
     "mfe_batch_destroy": (c_int, [c_vp]),

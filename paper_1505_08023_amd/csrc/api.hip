@@ -88,7 +88,7 @@ void free_problem_storage(mfe_problem *P) {
     release_graphs(P);
     Buffer *bufs[] = {&P->ptr, &P->col, &P->val64, &P->val32, &P->b, &P->slot_base, &P->jas, &P->bval64,
                       &P->bval32, &P->rowblocks, &P->r, &P->p, &P->q, &P->state, &P->partials,
-                      &P->r32, &P->p32, &P->q32, &P->d32, &P->ax};
+                      &P->r32, &P->p32, &P->q32, &P->d32, &P->ax, &P->s, &P->dinv};
     for (Buffer *b : bufs) dev_free(ctx, b);
 }
 
@@ -470,6 +470,38 @@ int mfe_cg(const mfe_problem *p, int format, double *x_dev, double tol, int max_
     MFE_TRY(check_format(p, format));
     MFE_TRY(set_device(p->ctx));
     return cg_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, max_iter, hist_dev, stats, false);
+}
+
+int mfe_cg_single_reduction(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter,
+                            double *hist_dev, mfe_cg_stats *stats) {
+    clear_error();
+    if (!p || !x_dev) {
+        set_error("problem and x must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (!(tol >= 0.0) || max_iter < 0) {
+        set_error("tol must be >= 0 and max_iter >= 0");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(check_format(p, format));
+    MFE_TRY(set_device(p->ctx));
+    return cg_sr_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, max_iter, hist_dev, stats);
+}
+
+int mfe_cg_jacobi(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter, double *hist_dev,
+                  mfe_cg_stats *stats) {
+    clear_error();
+    if (!p || !x_dev) {
+        set_error("problem and x must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (!(tol >= 0.0) || max_iter < 0) {
+        set_error("tol must be >= 0 and max_iter >= 0");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(check_format(p, format));
+    MFE_TRY(set_device(p->ctx));
+    return cg_jacobi_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, max_iter, hist_dev, stats);
 }
 
 int mfe_cg_warm(const mfe_problem *p, int format, double *x_dev, double tol, int max_iter, double *hist_dev,

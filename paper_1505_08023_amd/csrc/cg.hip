@@ -19,6 +19,7 @@
 
 struct mfe_graph_cache {
     struct Entry {
+        int kind;  // 0: CG, 1: single-reduction CG, 2: Jacobi-preconditioned CG
         int format;
         bool f32;
         const void *x;
@@ -49,15 +50,37 @@ int ensure_workspace(mfe_problem *P) {
 
 namespace {
 
-// Capture k CG iterations on the context's private capture stream.
-int capture(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
-            hipGraphExec_t *out) {
+// Capture k CG iterations on the context's private capture stream.  kind 0:
+// SpMV + p.q, r update + r.r, x/p update; kind 1 (single reduction, FP64):
+// w = A r with r.w and r.r, then the update of p, s, x, r.
+int capture(mfe_problem *P, int kind, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st,
+            int k, hipGraphExec_t *out) {
     hipStream_t cs = P->ctx->cap_stream;
     double *partials = (double *)P->partials.ptr;
     MFE_HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
     int rc = MFE_OK;
     double *pq_part = partials, *rr_part = partials + 2 * kMaxPartials;
     for (int i = 0; i < k && rc == MFE_OK; ++i) {
+        if (kind == 2) {
+            SpmvArgs a{p, q, nullptr, nullptr, st, pq_part};
+            int n_pq = 0, n = 0;
+            const double *dinv = (const double *)P->dinv.ptr;
+            double *part = partials + kMaxPartials;  // r.z, and r.r one block further
+            rc = launch_spmv(P, format, false, kSpmvDot, a, cs, &n_pq);
+            if (rc == MFE_OK)
+                rc = launch_pupdate_r(P, (double *)r, (const double *)q, dinv, st, pq_part, n_pq, part, &n, cs);
+            if (rc == MFE_OK) rc = launch_pupdate_xp(P, (double *)x, (double *)p, (const double *)r, dinv, st, part, n, cs);
+            continue;
+        }
+        if (kind == 1) {
+            SpmvArgs a{r, q, nullptr, nullptr, st, partials};
+            int n = 0;
+            rc = launch_spmv(P, format, false, kSpmvDot2, a, cs, &n);
+            if (rc == MFE_OK)
+                rc = launch_sr_update(P, (double *)x, (double *)r, (double *)p, (double *)P->s.ptr,
+                                      (const double *)q, st, partials, n, cs);
+            continue;
+        }
         SpmvArgs a{p, q, nullptr, nullptr, st, pq_part};
         int n_pq = 0, n_rr = 0;
         rc = launch_spmv(P, format, f32, kSpmvDot, a, cs, &n_pq);
@@ -86,15 +109,15 @@ int capture(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, voi
 }  // namespace
 
 int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
-              hipGraphExec_t *out) {
+              hipGraphExec_t *out, int kind) {
     for (auto &e : P->graphs->entries)
-        if (e.format == format && e.f32 == f32 && e.x == x && e.k == k && e.st == st) {
+        if (e.kind == kind && e.format == format && e.f32 == f32 && e.x == x && e.k == k && e.st == st) {
             *out = e.exec;
             return MFE_OK;
         }
     hipGraphExec_t ex = nullptr;
-    MFE_TRY(capture(P, format, f32, x, r, p, q, st, k, &ex));
-    P->graphs->entries.push_back({format, f32, x, k, st, ex});
+    MFE_TRY(capture(P, kind, format, f32, x, r, p, q, st, k, &ex));
+    P->graphs->entries.push_back({kind, format, f32, x, k, st, ex});
     *out = ex;
     return MFE_OK;
 }
@@ -204,6 +227,135 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
         stats->reserved_ = 0;
     }
     if (rc == MFE_EBREAKDOWN) set_error("CG breakdown: p.Ap <= 0 or not finite");
+    return rc;
+}
+
+// Single-reduction CG: as cg_solve, with two kernels per iteration.  The
+// loop's last SpMV evaluates the final r.r (the stopping test), so it
+// issues iterations + 1 products.
+int cg_sr_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist,
+                mfe_cg_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    MFE_TRY(ensure_workspace(P));
+    if (!P->s.ptr) MFE_TRY(dev_alloc(ctx, &P->s, (size_t)P->m * sizeof(double)));
+    CgState *st = (CgState *)P->state.ptr;
+    double *partials = (double *)P->partials.ptr;
+    CgState *pin = (CgState *)ctx->pinned;
+    CgState h{};
+    h.tol = tol;
+    h.max_iter = max_iter;
+    h.hist = hist;
+    h.status = kRunning;
+    pin[2] = h;
+    MFE_HIP_TRY(hipMemcpyAsync(st, &pin[2], sizeof(CgState), hipMemcpyHostToDevice, s));
+    SpmvArgs a0{x, P->r.ptr, nullptr, (const double *)P->b.ptr, st, partials};
+    int n0 = 0;
+    MFE_TRY(launch_spmv(P, format, false, kSpmvResid, a0, s, &n0));
+    MFE_TRY(launch_finalize(kFinStart, partials, n0, st, s));
+    MFE_TRY(launch_zero_if(P->m, x, nullptr, nullptr, nullptr, st, ctx->num_cu, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    CgState fin = pin[0];
+    int spmvs = 1;
+    if (fin.status == kRunning) {
+        const int k = kGraphIters < max_iter + 1 ? kGraphIters : max_iter + 1;
+        hipGraphExec_t exec = nullptr;
+        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, k, &exec, 1));
+        MFE_TRY(run_iterations(P, exec, st, k, max_iter + 1, &fin));
+        spmvs += fin.iters + 1;
+    }
+    SpmvArgs a1{x, nullptr, nullptr, (const double *)P->b.ptr, st, partials};
+    int n1 = 0;
+    MFE_TRY(launch_spmv(P, format, false, kSpmvTrue, a1, s, &n1));
+    MFE_TRY(launch_finalize(kFinTrue, partials, n1, st, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    ++spmvs;
+    const double rr_true = pin[0].rr_true;
+    const double bn = fin.bnorm;
+    int rc = MFE_OK;
+    if (fin.status == kCapped) rc = MFE_NOT_CONVERGED;
+    else if (fin.status == kBreakdown) rc = MFE_EBREAKDOWN;
+    if (stats) {
+        stats->status = rc;
+        stats->iterations = fin.iters;
+        stats->outer = 0;
+        stats->spmv_count = spmvs;
+        stats->rel_res_recurrence = bn > 0.0 ? std::sqrt(fin.rho) / bn : 0.0;
+        stats->rel_res_true = bn > 0.0 ? std::sqrt(rr_true) / bn : 0.0;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->guess_rejected = 0;
+        stats->reserved_ = 0;
+    }
+    if (rc == MFE_EBREAKDOWN) set_error("single-reduction CG breakdown: r.Ar - beta r.r / alpha <= 0 or not finite");
+    return rc;
+}
+
+// Jacobi-preconditioned CG: the CG driver with z = D^-1 r; the stopping test
+// stays on the unpreconditioned ||r||/||b||.
+int cg_jacobi_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist,
+                    mfe_cg_stats *stats) {
+    const auto t0 = std::chrono::steady_clock::now();
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    MFE_TRY(ensure_workspace(P));
+    MFE_TRY(build_dinv(P));
+    CgState *st = (CgState *)P->state.ptr;
+    double *partials = (double *)P->partials.ptr;
+    CgState *pin = (CgState *)ctx->pinned;
+    CgState h{};
+    h.tol = tol;
+    h.max_iter = max_iter;
+    h.hist = hist;
+    h.status = kRunning;
+    pin[2] = h;
+    MFE_HIP_TRY(hipMemcpyAsync(st, &pin[2], sizeof(CgState), hipMemcpyHostToDevice, s));
+    // r = b - A x0, start test on r.r; then p = z = D^-1 r, rho = r.z
+    SpmvArgs a0{x, P->r.ptr, nullptr, (const double *)P->b.ptr, st, partials};
+    int n0 = 0;
+    MFE_TRY(launch_spmv(P, format, false, kSpmvResid, a0, s, &n0));
+    MFE_TRY(launch_finalize(kFinStart, partials, n0, st, s));
+    MFE_TRY(launch_zero_if(P->m, x, nullptr, nullptr, nullptr, st, ctx->num_cu, s));
+    MFE_TRY(launch_pcg_start(P, (const double *)P->r.ptr, (double *)P->p.ptr, (const double *)P->dinv.ptr, st,
+                             partials + kMaxPartials, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    CgState fin = pin[0];
+    int spmvs = 1;
+    if (fin.status == kRunning) {
+        const int k = kGraphIters < max_iter ? kGraphIters : max_iter;
+        hipGraphExec_t exec = nullptr;
+        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, k, &exec, 2));
+        MFE_TRY(run_iterations(P, exec, st, k, max_iter, &fin));
+        spmvs += fin.iters + (fin.status == kBreakdown ? 1 : 0);
+    }
+    SpmvArgs a1{x, nullptr, nullptr, (const double *)P->b.ptr, st, partials};
+    int n1 = 0;
+    MFE_TRY(launch_spmv(P, format, false, kSpmvTrue, a1, s, &n1));
+    MFE_TRY(launch_finalize(kFinTrue, partials, n1, st, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    ++spmvs;
+    const double rr_true = pin[0].rr_true;
+    const double bn = fin.bnorm;
+    int rc = MFE_OK;
+    if (fin.status == kCapped) rc = MFE_NOT_CONVERGED;
+    else if (fin.status == kBreakdown) rc = MFE_EBREAKDOWN;
+    if (stats) {
+        stats->status = rc;
+        stats->iterations = fin.iters;
+        stats->outer = 0;
+        stats->spmv_count = spmvs;
+        // with b = 0 the start test ends the solve before rr is set
+        stats->rel_res_recurrence = bn > 0.0 ? std::sqrt(fin.rr) / bn : 0.0;
+        stats->rel_res_true = bn > 0.0 ? std::sqrt(rr_true) / bn : 0.0;
+        stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        stats->guess_rejected = 0;
+        stats->reserved_ = 0;
+    }
+    if (rc == MFE_EBREAKDOWN) set_error("Jacobi-preconditioned CG breakdown: p.Ap or r.z <= 0 or not finite");
     return rc;
 }
 

@@ -66,6 +66,14 @@ struct CgState {
     int active;       // 1 once update_r has run in the current iteration (cleared by the SpMV)
     int zero_x;       // 1: b = 0, the solution is x = 0; 2: the guess was rejected, restart from x = 0
     int warm;         // set by the host: reject x0 when ||b - A x0|| >= ||b||
+    // single-reduction CG: the iteration count and status as the SpMV saw
+    // them (read by the update kernel, which writes iters and status), and
+    // gamma = r.r and alpha of the last two updates, indexed by the parity of
+    // the update
+    int iters_snap;
+    int status_snap;
+    double ring_g[2], ring_a[2];
+    double rr;        // Jacobi-preconditioned CG: r.r of the current residual (rho holds r.z)
 };
 
 // (the 1x3 BCRS slice layout is described in b13_layout.hpp)
@@ -117,6 +125,8 @@ struct mfe_problem {
     // CG workspace (allocated on first solve)
     mfe::Buffer r, p, q, state, partials;
     mfe::Buffer r32, p32, q32, d32, ax;  // mixed precision workspace
+    mfe::Buffer s;                       // single-reduction CG: s = A p
+    mfe::Buffer dinv;                    // Jacobi-preconditioned CG: 1 / diag(A)
     mfe_graph_cache *graphs = nullptr;
 };
 
@@ -138,11 +148,14 @@ int cast_values_f32(mfe_problem *P);
 int export_bcrs13(const mfe_problem *P, int32_t *bptr, int32_t *bcol, double *bval);
 
 // SpMV modes
+// Fused epilogues of the SpMV kernels; reductions leave per-workgroup
+// partials (second one at offset kMaxPartials) for the next kernel to sum.
 enum SpmvMode : int {
     kSpmvPlain = 0,   // y = A x
-    kSpmvDot = 1,     // y = A x, partial x.y, last workgroup: alpha = rho / (x.y)
-    kSpmvResid = 2,   // r = b - A x, p = r, partials r.r and b.b, last workgroup: CG start
-    kSpmvTrue = 3,    // partial ||b - A x||^2, last workgroup: state->rr_true
+    kSpmvDot = 1,     // y = A x, partials of x.y
+    kSpmvResid = 2,   // r = b - A x, p = r, partials of r.r and b.b
+    kSpmvTrue = 3,    // partials of ||b - A x||^2
+    kSpmvDot2 = 4,    // w = A r, partials of r.w and r.r (single-reduction CG)
 };
 
 struct SpmvArgs {
@@ -166,10 +179,24 @@ int finish_problem(mfe_problem *P);
 constexpr int kGraphIters = 16;  // CG iterations per captured graph
 int ensure_workspace(mfe_problem *P);
 int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
-              hipGraphExec_t *out);
+              hipGraphExec_t *out, int kind = 0);
 int run_iterations(mfe_problem *P, hipGraphExec_t exec, const CgState *st, int k, int max_iter, CgState *fin);
 int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st,
              bool warm = false);
+// Jacobi-preconditioned CG (FP64)
+int cg_jacobi_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist,
+                    mfe_cg_stats *st);
+int build_dinv(mfe_problem *P);
+int launch_pcg_start(const mfe_problem *P, const double *r, double *p, const double *dinv, CgState *st,
+                     double *partials, hipStream_t s);
+int launch_pupdate_r(const mfe_problem *P, double *r, const double *q, const double *dinv, CgState *st,
+                     const double *pq_part, int n_pq, double *part, int *grid, hipStream_t s);
+int launch_pupdate_xp(const mfe_problem *P, double *x, double *p, const double *r, const double *dinv, CgState *st,
+                      const double *part, int n, hipStream_t s);
+// single-reduction CG (FP64)
+int cg_sr_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st);
+int launch_sr_update(const mfe_problem *P, double *x, double *r, double *p, double *s, const double *w, CgState *st,
+                     const double *partials, int n, hipStream_t stream);
 void release_graphs(mfe_problem *P);
 
 // mixed precision (mixed.hip)

@@ -46,6 +46,7 @@ __device__ __forceinline__ double block_sum(double v) {
 // kernel needs (alpha, beta) is formed redundantly in each workgroup instead
 // of by a separate launch or a cross-workgroup handshake.  Kernel
 // boundaries make the previous kernel's stores visible on every XCD.
+// Every thread of the workgroup must call it (it synchronises the workgroup).
 __device__ __forceinline__ double sum_partials(const double *__restrict__ p, int n) {
     __shared__ double total;
     double s = 0.0;

@@ -52,6 +52,11 @@ __device__ __forceinline__ void finish_row(const Epi<T> &E, int64_t row, T sum, 
     } else if (MODE == kSpmvDot) {
         E.y[row] = sum;
         d1 += (double)E.x[row] * (double)sum;
+    } else if (MODE == kSpmvDot2) {
+        E.y[row] = sum;
+        const double ri = (double)E.x[row];
+        d1 += ri * (double)sum;
+        d2 += ri * ri;
     } else if (MODE == kSpmvResid) {
         const double bi = E.b[row];
         const double r = bi - (double)sum;
@@ -70,18 +75,24 @@ __device__ __forceinline__ void finish_row(const Epi<T> &E, int64_t row, T sum, 
 template <int MODE>
 __device__ __forceinline__ void store_partials(double d1, double d2, double *partials) {
     if (MODE == kSpmvPlain) return;
+    constexpr bool two = MODE == kSpmvResid || MODE == kSpmvDot2;
     d1 = block_sum(d1);
-    if (MODE == kSpmvResid) d2 = block_sum(d2);
+    if (two) d2 = block_sum(d2);
     if (threadIdx.x == 0) {
         partials[blockIdx.x] = d1;
-        if (MODE == kSpmvResid) partials[kMaxPartials + blockIdx.x] = d2;
+        if (two) partials[kMaxPartials + blockIdx.x] = d2;
     }
 }
 
 // In the CG loop the product runs only while the solve is running; it also
-// opens the iteration (the vector updates check `active`).
+// opens the iteration (the vector updates check `active`) and records the
+// iteration count for the single-reduction update, which rewrites it.
 __device__ __forceinline__ bool cg_gate(CgState *st) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->active = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->active = 0;
+        st->iters_snap = st->iters;
+        st->status_snap = st->status;
+    }
     return st->status == kRunning;
 }
 
@@ -92,7 +103,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
                                                      const int32_t *__restrict__ col,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
-    if (MODE == kSpmvDot && st && !cg_gate(st)) return;
+    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     constexpr int R = kBlock / L;  // rows per tile
     const int g = threadIdx.x / L, sub = threadIdx.x % L;
     const long ntiles = (m + R - 1) / R;
@@ -124,7 +135,7 @@ __global__ __launch_bounds__(kBlock) MFE_B13_ATTR void k_spmv_b13(int64_t m, con
                                                      const int32_t *__restrict__ jas,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
-    if (MODE == kSpmvDot && st && !cg_gate(st)) return;
+    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double d1 = 0.0, d2 = 0.0;
@@ -159,7 +170,7 @@ __global__ __launch_bounds__(kBlock) MFE_B13_ATTR void k_spmv_b13(int64_t m, con
                                                      const int32_t *__restrict__ jas,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
-    if (MODE == kSpmvDot && st && !cg_gate(st)) return;
+    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
     double d1 = 0.0, d2 = 0.0;
     for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
@@ -235,6 +246,7 @@ int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const
         case kSpmvDot: return launch_mode<double, kSpmvDot>(P, format, a, s, grid);
         case kSpmvResid: return launch_mode<double, kSpmvResid>(P, format, a, s, grid);
         case kSpmvTrue: return launch_mode<double, kSpmvTrue>(P, format, a, s, grid);
+        case kSpmvDot2: return launch_mode<double, kSpmvDot2>(P, format, a, s, grid);
     }
     return MFE_EINVAL;
 }

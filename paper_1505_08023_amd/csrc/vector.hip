@@ -79,6 +79,180 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__
     }
 }
 
+// Single-reduction CG update (Chronopoulos-Gear).  The SpMV before it wrote
+// w = A r with the partials of delta = r.w and gamma = r.r of the current r.
+// Every workgroup sums them, applies the stopping test to gamma and, while
+// running, forms
+//   beta = gamma / gamma_prev,  alpha = gamma / (delta - beta gamma / alpha_prev)
+// (beta = 0, alpha = gamma / delta on the first update), then
+//   p = r + beta p,  s = w + beta s,  x += alpha p,  r -= alpha s.
+// The previous gamma and alpha come from the ring slot of the other parity,
+// and the entry test from the status the SpMV recorded: this kernel writes
+// neither, so every wavefront of every workgroup takes the same branch.
+// 72 bytes per row (FP64).
+__global__ __launch_bounds__(kBlock) void k_sr_update(int64_t m, double *__restrict__ x, double *__restrict__ r,
+                                                      double *__restrict__ p, double *__restrict__ s,
+                                                      const double *__restrict__ w, CgState *st,
+                                                      const double *__restrict__ part, int n) {
+    if (st->status_snap != kRunning) return;
+    const double delta = sum_partials(part, n);
+    const double gamma = sum_partials(part + kMaxPartials, n);
+    const int it = st->iters_snap;
+    const double res = sqrt(gamma) / st->bnorm;
+    const bool stop = !isfinite(res) || res <= st->tol || it >= st->max_iter;
+    double beta = 0.0, denom = delta;
+    if (it > 0) {
+        beta = gamma / st->ring_g[(it + 1) & 1];
+        denom = delta - beta * gamma / st->ring_a[(it + 1) & 1];
+    }
+    const bool brk = !stop && (!(denom > 0.0) || !isfinite(denom));
+    const double alpha = gamma / denom;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rho = gamma;
+        if (it > 0 && st->hist) st->hist[it] = res;
+        if (!isfinite(res)) st->status = kBreakdown;
+        else if (res <= st->tol) st->status = kConverged;
+        else if (it >= st->max_iter) st->status = kCapped;
+        else if (brk) st->status = kBreakdown;
+        st->pq = denom;
+        if (!stop && !brk) {
+            st->ring_g[it & 1] = gamma;
+            st->ring_a[it & 1] = alpha;
+            st->alpha = alpha;
+            st->iters = it + 1;
+        }
+    }
+    if (stop || brk) return;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    if (it == 0) {
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+            const double ri = r[i], wi = w[i];
+            p[i] = ri;
+            s[i] = wi;
+            x[i] += alpha * ri;
+            r[i] = ri - alpha * wi;
+        }
+    } else {
+        for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+            const double ri = r[i];
+            const double pi = ri + beta * p[i];
+            const double si = w[i] + beta * s[i];
+            p[i] = pi;
+            s[i] = si;
+            x[i] += alpha * pi;
+            r[i] = ri - alpha * si;
+        }
+    }
+}
+
+// ------------------------------------------------------------ Jacobi-preconditioned CG
+// Same three-kernel iteration as CG with z = D^-1 r formed on the fly:
+//   update_r  : alpha = (r.z) / p.q; r -= alpha q; partials of r.z and r.r
+//   update_xp : rho' = r.z, stop on sqrt(r.r)/||b||; x += alpha p, p = D^-1 r + beta p
+// 80 bytes per row per iteration (the D^-1 vector is read twice).
+
+__global__ __launch_bounds__(kBlock) void k_pcg_start(int64_t m, const double *__restrict__ r, double *__restrict__ p,
+                                                      const double *__restrict__ dinv, CgState *st,
+                                                      double *__restrict__ part) {
+    double d = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        const double ri = r[i], zi = dinv[i] * ri;
+        p[i] = zi;
+        d += ri * zi;
+    }
+    d = block_sum(d);
+    if (threadIdx.x == 0) part[blockIdx.x] = d;
+}
+
+// one workgroup: rr = r.r from the start test, rho = r.z
+__global__ __launch_bounds__(kBlock) void k_pcg_start_fin(const double *__restrict__ part, int n, CgState *st) {
+    const double rz = sum_partials(part, n);
+    if (threadIdx.x != 0) return;
+    st->rr = st->rho;
+    st->rho = rz;
+    if (st->status == kRunning && !(rz > 0.0 && isfinite(rz))) st->status = kBreakdown;
+}
+
+__global__ __launch_bounds__(kBlock) void k_pupdate_r(int64_t m, double *__restrict__ r, const double *__restrict__ q,
+                                                      const double *__restrict__ dinv, CgState *st,
+                                                      const double *__restrict__ pq_part, int n_pq,
+                                                      double *__restrict__ part) {
+    if (st->status != kRunning) return;
+    const double pq = sum_partials(pq_part, n_pq);
+    const double rho = st->rho;
+    if (!(pq > 0.0) || !isfinite(pq)) {
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            st->pq = pq;
+            st->status = kBreakdown;
+        }
+        return;
+    }
+    const double alpha = rho / pq;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->pq = pq;
+        st->alpha = alpha;
+        st->rho_old = rho;
+        st->active = 1;
+    }
+    double rz = 0.0, rr = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        const double ri = r[i] - alpha * q[i];
+        r[i] = ri;
+        rz += ri * (dinv[i] * ri);
+        rr += ri * ri;
+    }
+    rz = block_sum(rz);
+    rr = block_sum(rr);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = rz;
+        part[kMaxPartials + blockIdx.x] = rr;
+    }
+}
+
+__global__ __launch_bounds__(kBlock) void k_pupdate_xp(int64_t m, double *__restrict__ x, double *__restrict__ p,
+                                                       const double *__restrict__ r, const double *__restrict__ dinv,
+                                                       CgState *st, const double *__restrict__ part, int n) {
+    if (!st->active) return;
+    const double rz = sum_partials(part, n);
+    const double rr = sum_partials(part + kMaxPartials, n);  // a workgroup collective: every thread calls it
+    const double alpha = st->alpha, beta = rz / st->rho_old;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int it = st->iters + 1;
+        const double res = sqrt(rr) / st->bnorm;
+        st->iters = it;
+        st->rho = rz;
+        st->rr = rr;
+        if (st->hist) st->hist[it] = res;
+        if (!isfinite(res)) st->status = kBreakdown;
+        else if (res <= st->tol) st->status = kConverged;
+        else if (it >= st->max_iter) st->status = kCapped;
+    }
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        const double pi = p[i];
+        x[i] += alpha * pi;
+        p[i] = dinv[i] * r[i] + beta * pi;
+    }
+}
+
+// 1 / A_ii from the FP64 CRS rows; bad[0] = 1 if a diagonal entry is zero,
+// missing or not finite
+__global__ __launch_bounds__(kBlock) void k_dinv(int64_t m, const int32_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                 double *__restrict__ dinv, int *__restrict__ bad) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        double d = 0.0;
+        for (int32_t j = ptr[i]; j < ptr[i + 1]; ++j)
+            if (col[j] == i) d = val[j];
+        const bool ok = d != 0.0 && isfinite(d);
+        dinv[i] = ok ? 1.0 / d : 0.0;
+        if (!ok) bad[0] = 1;
+    }
+}
+
 // One workgroup: reduce partials into the solver state.
 template <int KIND>
 __global__ __launch_bounds__(kBlock) void k_finalize(const double *__restrict__ part, int n, CgState *st) {
@@ -185,6 +359,63 @@ int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const voi
         hipLaunchKernelGGL(k_update_xp<double>, dim3(g), dim3(kBlock), 0, s, P->m, (double *)x, (double *)p,
                            (const double *)r, st, rr_partials, n_rr);
     }
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int launch_pcg_start(const mfe_problem *P, const double *r, double *p, const double *dinv, CgState *st,
+                     double *partials, hipStream_t s) {
+    const int g = vec_grid((const void *)k_pcg_start, P->m, P->ctx->num_cu);
+    hipLaunchKernelGGL(k_pcg_start, dim3(g), dim3(kBlock), 0, s, P->m, r, p, dinv, st, partials);
+    hipLaunchKernelGGL(k_pcg_start_fin, dim3(1), dim3(kBlock), 0, s, (const double *)partials, g, st);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int launch_pupdate_r(const mfe_problem *P, double *r, const double *q, const double *dinv, CgState *st,
+                     const double *pq_part, int n_pq, double *part, int *grid, hipStream_t s) {
+    const int g = vec_grid((const void *)k_pupdate_r, P->m, P->ctx->num_cu);
+    hipLaunchKernelGGL(k_pupdate_r, dim3(g), dim3(kBlock), 0, s, P->m, r, q, dinv, st, pq_part, n_pq, part);
+    MFE_HIP_TRY(hipGetLastError());
+    if (grid) *grid = g;
+    return MFE_OK;
+}
+
+int launch_pupdate_xp(const mfe_problem *P, double *x, double *p, const double *r, const double *dinv, CgState *st,
+                      const double *part, int n, hipStream_t s) {
+    const int g = vec_grid((const void *)k_pupdate_xp, P->m, P->ctx->num_cu);
+    hipLaunchKernelGGL(k_pupdate_xp, dim3(g), dim3(kBlock), 0, s, P->m, x, p, r, dinv, st, part, n);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+int build_dinv(mfe_problem *P) {
+    if (P->dinv.ptr) return MFE_OK;
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    MFE_TRY(dev_alloc(ctx, &P->dinv, (size_t)P->m * sizeof(double)));
+    int *bad = (int *)ctx->scratch.ptr;
+    int *hbad = (int *)((CgState *)ctx->pinned + 3);
+    *hbad = 0;
+    MFE_HIP_TRY(hipMemcpyAsync(bad, hbad, sizeof(int), hipMemcpyHostToDevice, s));
+    const int g = vec_grid((const void *)k_dinv, P->m, ctx->num_cu);
+    hipLaunchKernelGGL(k_dinv, dim3(g), dim3(kBlock), 0, s, P->m, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, (const double *)P->val64.ptr, (double *)P->dinv.ptr, bad);
+    MFE_HIP_TRY(hipGetLastError());
+    MFE_HIP_TRY(hipMemcpyAsync(hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    if (*hbad) {
+        dev_free(ctx, &P->dinv);
+        set_error("Jacobi preconditioner: a diagonal entry is zero, missing or not finite");
+        return MFE_EINVAL;
+    }
+    return MFE_OK;
+}
+
+int launch_sr_update(const mfe_problem *P, double *x, double *r, double *p, double *s, const double *w, CgState *st,
+                     const double *partials, int n, hipStream_t stream) {
+    const int g = vec_grid((const void *)k_sr_update, P->m, P->ctx->num_cu);
+    hipLaunchKernelGGL(k_sr_update, dim3(g), dim3(kBlock), 0, stream, P->m, x, r, p, s, w, st, partials, n);
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
 }

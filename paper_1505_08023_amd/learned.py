@@ -193,7 +193,8 @@ def main(argv=None):
         torch.cuda.empty_cache()
         if args.out:
             save(args.out, net.get_params(), dict(n=n, train=args.train, epochs=args.epochs, batch=args.batch,
-                                                  lr=args.lr, loss_history=result["loss_history"]))
+                                                  lr=args.lr, init=args.init or "he_init(0)",
+                                                  loss_history=result["loss_history"]))
     if args.eval > 0:
         ev = evaluate(ctx, net, n, np.arange(HELD_OUT_BASE, HELD_OUT_BASE + args.eval))
         ev.pop("rows")

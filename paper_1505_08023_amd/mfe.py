@@ -240,17 +240,24 @@ class Problem:
         return q, pq
 
     def cg(self, x=None, tol=1e-8, max_iter=200, fmt="bcrs13", history=False, raise_on_breakdown=True,
-           warm=False):
+           warm=False, variant="cg"):
         """Unpreconditioned CG from x (zero if None).  warm=True: x is a guess
         that the solve replaces by zero when ||b - A x|| >= ||b||
-        (mfe_cg_warm).  Returns (x, stats dict)."""
+        (mfe_cg_warm).  variant="single_reduction": the Chronopoulos-Gear
+        form with one reduction point per iteration
+        (mfe_cg_single_reduction); variant="jacobi": diagonally
+        preconditioned (mfe_cg_jacobi).  Returns (x, stats dict)."""
         d = self.ctx.device
         if x is None:
             with _on(self.ctx):
                 x = torch.zeros(self.m, dtype=torch.float64, device=d)
         hist = torch.zeros(max_iter + 1, dtype=torch.float64, device=d) if history else None
         st = mfe_cg_stats()
-        name = "mfe_cg_warm" if warm else "mfe_cg"
+        names = {"cg": "mfe_cg_warm" if warm else "mfe_cg", "single_reduction": "mfe_cg_single_reduction",
+                 "jacobi": "mfe_cg_jacobi"}
+        if variant not in names or (warm and variant != "cg"):
+            raise ValueError(f"unsupported CG variant {variant!r} (warm={warm})")
+        name = names[variant]
         with _on(self.ctx):
             rc = getattr(self.ctx.lib, name)(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"),
                                              float(tol), int(max_iter), _ptr(hist, torch.float64),
@@ -261,6 +268,24 @@ class Problem:
         if history:
             out["history"] = hist[: st.iterations + 1].cpu()
         return x, out
+
+    def verify_series(self, x, x_max=0.75, want_u=False):
+        """Nodal error against the series solution of the paper's problem at
+        the nodes with x-coordinate <= x_max (mfe_verify_series).  Returns
+        dict(max_err, rms_err, count[, u])."""
+        u = None
+        if want_u:
+            with _on(self.ctx):
+                u = torch.empty(self.m, dtype=torch.float64, device=self.ctx.device)
+        mx, rms, cnt = ctypes.c_double(), ctypes.c_double(), ctypes.c_int64()
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_verify_series(self.handle, _ptr(x, torch.float64, self.m, "x"), float(x_max),
+                                                 _ptr(u, torch.float64), ctypes.byref(mx), ctypes.byref(rms),
+                                                 ctypes.byref(cnt)), "mfe_verify_series")
+        out = dict(max_err=mx.value, rms_err=rms.value, count=cnt.value)
+        if want_u:
+            out["u"] = u
+        return out
 
     def cg_mixed(self, x=None, tol=1e-10, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13"):
         """FP32-inner CG inside FP64 iterative refinement.  Returns (x, stats dict)."""
