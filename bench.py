@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # and WRITE_SIZE (x 1.0) counter runs, scaled by streaming kernels of known
 # size (profiles/spmv_b13_fp64_256cubed_hbm_counters.md).  Reset to None
 # whenever the kernel changes.
-MEASURED_TRAFFIC = {("bcrs13", 256): 4.818e9, ("csr", 256): None}
+MEASURED_TRAFFIC = {("bcrs13", 256): 4.588e9, ("csr", 256): None}
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
 
 
@@ -44,16 +44,23 @@ def spmv_bytes(fmt, m, nnz, nb, fp=8):
     return (3 * fp + 4) * nb + 4 * (m + 1) + 2 * fp * m
 
 
-def time_spmv_dot(P, fmt, reps, torch):
+def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30):
     """Mean duration of the fused SpMV + dot kernel from HIP event pairs
-    recorded around each launch on the library's stream."""
+    recorded around each launch on the library's stream.  Before each launch
+    flush_bytes of unrelated memory are written on the same stream, as the
+    vector updates of a CG iteration do between two products, so that x is
+    not left in the memory-side cache by the previous launch."""
     from paper_1505_08023_amd import inputs
     x = torch.tensor(inputs.spmv_vector(P.m, seed=0), device=P.ctx.device)
     q = torch.empty_like(x)
     pq = torch.zeros(1, dtype=torch.float64, device=x.device)
+    flush = torch.empty(max(flush_bytes // 8, 1), dtype=torch.float64, device=x.device) if flush_bytes else None
     pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
     P.spmv_dot(x, q, pq, fmt=fmt)  # warm-up
     for ev in pairs:
+        if flush is not None:
+            with torch.cuda.stream(P.ctx.stream):
+                flush.fill_(0.0)
         P.spmv_dot(x, q, pq, fmt=fmt, events=ev)
     P.ctx.stream.synchronize()
     ms = [a.elapsed_time(b) for a, b in pairs]
@@ -157,7 +164,9 @@ def main():
                    "tol": args.tol, "x0": "zero", "step": "one CG solve to tol"},
         "roofline": {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get((args.fmt, N)),
-                     "kernel": f"k_spmv_{'b13' if args.fmt == 'bcrs13' else 'csr'}<double, dot>",
+                     "kernel": "k_spmv_b13p<double, dot>" if args.fmt == "bcrs13" else "k_spmv_csr<double, 32, dot>",
+                     "timing": "HIP events around each launch on the library stream, 1 GiB of other memory "
+                               "written before each, as between two products of a CG iteration",
                      "bytes_per_launch": dom["bytes"], "mean_launch_ms": dom["mean_ms"]},
         "cg": {"iterations_per_solve": stats[-1]["iterations"], "time_to_tol_s": elapsed / args.steps,
                "rel_res_true": stats[-1]["rel_res_true"], "status": stats[-1]["status"],

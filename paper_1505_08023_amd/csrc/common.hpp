@@ -39,6 +39,11 @@ constexpr int kSlice = 64;      // rows per slice of the 1x3 BCRS layout (one wa
 constexpr int kNumXcd = 8;      // accelerator complex dies of an MI355X
 constexpr int kMaxPartials = 4096;  // per-workgroup partial sums one reduction may hold
 constexpr int kPinnedSlots = 4;     // pinned CgState slots per context
+constexpr int64_t kMallBytes = 256ll << 20;  // memory-side (Infinity) cache of an MI355X
+
+// Stream CG vectors non-temporally when the five FP64 vectors an iteration
+// touches exceed the memory-side cache.
+inline bool vectors_stream_nt(int64_t m) { return 40 * m > kMallBytes; }
 
 // ------------------------------------------------------------------ device solver state
 

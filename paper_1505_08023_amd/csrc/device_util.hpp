@@ -82,6 +82,23 @@ __device__ __forceinline__ TileRange tile_range(long ntiles) {
     return r;
 }
 
+// Vector streams whose next use is more than one kernel away (or never).
+// When the vectors of an iteration do not fit in the memory-side cache,
+// loading and storing these non-temporally (nt = true) leaves that cache to
+// the vector that the next SpMV gathers; when they fit, plain accesses keep
+// them all cached.  nt is uniform over the launch.
+template <typename T>
+__device__ __forceinline__ T stream_load(const T *p, bool nt) {
+    return nt ? __builtin_nontemporal_load(p) : *p;
+}
+template <typename T>
+__device__ __forceinline__ void stream_store(T v, T *p, bool nt) {
+    if (nt)
+        __builtin_nontemporal_store(v, p);
+    else
+        *p = v;
+}
+
 // Matrix streams are read once per product: load them non-temporally so
 // they do not evict the x entries that the gathers reuse.
 template <typename T>

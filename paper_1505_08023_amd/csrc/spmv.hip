@@ -23,11 +23,11 @@
 #ifndef MFE_CSR_LANES
 #define MFE_CSR_LANES 32      // lanes per row of the CRS kernel
 #endif
-#ifndef MFE_B13_PIPE
-#define MFE_B13_PIPE 0        // software-pipelined 1x3 BCRS walk
+#ifndef MFE_SPMV_Q_NT
+#define MFE_SPMV_Q_NT 0       // q store of the dot mode: 0 by vector size, 1 always non-temporal, 2 never
 #endif
-#ifndef MFE_B13_WAVES
-#define MFE_B13_WAVES 0       // waves per SIMD requested from the register allocator (0: default)
+#ifndef MFE_B13_PIPE_TILES
+#define MFE_B13_PIPE_TILES 8  // tiles per workgroup from which the pipelined 1x3 BCRS walk is used
 #endif
 #ifndef MFE_SPMV_WG_PER_CU
 #define MFE_SPMV_WG_PER_CU 0  // resident workgroups per CU (0: as many as fit)
@@ -42,6 +42,7 @@ struct Epi {
     T *__restrict__ y;
     T *__restrict__ pout;
     const double *__restrict__ b;
+    bool nt;  // store y non-temporally (dot mode: y is read once, by the r update)
 };
 
 // Per-row epilogue; accumulates the reduction terms in FP64.
@@ -50,7 +51,13 @@ __device__ __forceinline__ void finish_row(const Epi<T> &E, int64_t row, T sum, 
     if (MODE == kSpmvPlain) {
         E.y[row] = sum;
     } else if (MODE == kSpmvDot) {
+#if MFE_SPMV_Q_NT == 1
+        stream_store(sum, E.y + row, true);
+#elif MFE_SPMV_Q_NT == 2
         E.y[row] = sum;
+#else
+        stream_store(sum, E.y + row, E.nt);
+#endif
         d1 += (double)E.x[row] * (double)sum;
     } else if (MODE == kSpmvDot2) {
         E.y[row] = sum;
@@ -118,23 +125,36 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
 
 // ---------------------------------------------------------------- 1x3 BCRS
 
-#if MFE_B13_WAVES > 0
-#define MFE_B13_ATTR __attribute__((amdgpu_waves_per_eu(MFE_B13_WAVES)))
-#else
-#define MFE_B13_ATTR
-#endif
-
-#if MFE_B13_PIPE
-// Software-pipelined walk: a wavefront owns slice 4t + w of tile t.  The
-// slice bounds come from scalar loads (the slice index is wavefront-uniform)
-// and the next tile's column indices are requested before the current
-// tile's values and gathers, so the index -> gather dependency of one tile
-// overlaps the streaming of the previous one.
+// One slice per wavefront per tile: slice bounds, column indices, values,
+// gathers, in that dependent order.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) MFE_B13_ATTR void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
+__global__ __launch_bounds__(kBlock) void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
                                                      const int32_t *__restrict__ jas,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
+    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
+    const long ntiles = (m + kBlock - 1) / kBlock;
+    double d1 = 0.0, d2 = 0.0;
+    for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
+        const int64_t row = tr.t * kBlock + threadIdx.x;
+        if (row >= m) continue;
+        const T sum = b13_row(slot_base, jas, val, row, E.x);
+        finish_row<T, MODE>(E, row, sum, d1, d2);
+    }
+    store_partials<MODE>(d1, d2, partials);
+}
+
+// Software-pipelined walk for grids whose workgroups take several tiles: a
+// wavefront owns slice 4t + w of tile t.  The slice bounds come from scalar
+// loads (the slice index is wavefront-uniform) and the next tile's column
+// indices are requested before the current tile's values and gathers, so the
+// index -> gather dependency of one tile overlaps the streaming of the
+// previous one.  Arithmetic and summation order are those of k_spmv_b13.
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmv_b13p(int64_t m, const int32_t *__restrict__ slot_base,
+                                                      const int32_t *__restrict__ jas,
+                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
+                                                      double *partials) {
     if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -164,24 +184,6 @@ __global__ __launch_bounds__(kBlock) MFE_B13_ATTR void k_spmv_b13(int64_t m, con
     }
     store_partials<MODE>(d1, d2, partials);
 }
-#else
-template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) MFE_B13_ATTR void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
-                                                     const int32_t *__restrict__ jas,
-                                                     const T *__restrict__ val, Epi<T> E, CgState *st,
-                                                     double *partials) {
-    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
-    const long ntiles = (m + kBlock - 1) / kBlock;
-    double d1 = 0.0, d2 = 0.0;
-    for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
-        const int64_t row = tr.t * kBlock + threadIdx.x;
-        if (row >= m) continue;
-        const T sum = b13_row(slot_base, jas, val, row, E.x);
-        finish_row<T, MODE>(E, row, sum, d1, d2);
-    }
-    store_partials<MODE>(d1, d2, partials);
-}
-#endif
 
 // ---------------------------------------------------------------- launch
 
@@ -211,9 +213,14 @@ int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *parti
 template <typename T, int MODE>
 int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
-    auto kern = k_spmv_b13<T, MODE>;
     const long ntiles = (P->m + kBlock - 1) / kBlock;
-    const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
+    // the pipelined walk pays off once each workgroup takes several tiles
+    auto kern = k_spmv_b13p<T, MODE>;
+    int grid = grid_for(kern, ntiles, P->ctx->num_cu);
+    if (ntiles < (long)MFE_B13_PIPE_TILES * grid) {
+        kern = k_spmv_b13<T, MODE>;
+        grid = grid_for(kern, ntiles, P->ctx->num_cu);
+    }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
                        (const int32_t *)P->jas.ptr, val, E, st, partials);
     MFE_HIP_TRY(hipGetLastError());
@@ -223,7 +230,7 @@ int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *parti
 
 template <typename T, int MODE>
 int launch_mode(const mfe_problem *P, int format, const SpmvArgs &a, hipStream_t s, int *grid) {
-    Epi<T> E{(const T *)a.x, (T *)a.y, (T *)a.p_out, a.b};
+    Epi<T> E{(const T *)a.x, (T *)a.y, (T *)a.p_out, a.b, vectors_stream_nt(P->m)};
     if (format == MFE_CSR) return launch_csr<T, MODE>(P, E, a.st, a.partials, s, grid);
     return launch_b13<T, MODE>(P, E, a.st, a.partials, s, grid);
 }

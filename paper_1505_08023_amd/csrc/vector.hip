@@ -17,7 +17,7 @@
 namespace mfe {
 namespace {
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ r, const T *__restrict__ q,
                                                      CgState *st, const double *__restrict__ pq_part, int n_pq,
                                                      double *__restrict__ rr_part) {
@@ -42,7 +42,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ 
     double d = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
-        const T ri = r[i] - a * q[i];
+        const T ri = r[i] - a * stream_load(q + i, NT);
         r[i] = ri;
         d += (double)ri * (double)ri;
     }
@@ -50,7 +50,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ 
     if (threadIdx.x == 0) rr_part[blockIdx.x] = d;
 }
 
-template <typename T>
+template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__ x, T *__restrict__ p,
                                                       const T *__restrict__ r, CgState *st,
                                                       const double *__restrict__ rr_part, int n_rr) {
@@ -74,8 +74,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
         const T pi = p[i];
-        x[i] += a * pi;
-        p[i] = r[i] + be * pi;
+        stream_store(stream_load(x + i, NT) + a * pi, x + i, NT);
+        p[i] = stream_load(r + i, NT) + be * pi;
     }
 }
 
@@ -331,36 +331,45 @@ int vec_grid(const void *kern, int64_t m, int num_cu) {
 
 }  // namespace
 
-int launch_update_r(const mfe_problem *P, bool f32, void *r, const void *q, CgState *st,
-                    const double *pq_partials, int n_pq, double *rr_partials, hipStream_t s, int *grid) {
-    int g;
-    if (f32) {
-        g = vec_grid((const void *)k_update_r<float>, P->m, P->ctx->num_cu);
-        hipLaunchKernelGGL(k_update_r<float>, dim3(g), dim3(kBlock), 0, s, P->m, (float *)r, (const float *)q,
-                           st, pq_partials, n_pq, rr_partials);
-    } else {
-        g = vec_grid((const void *)k_update_r<double>, P->m, P->ctx->num_cu);
-        hipLaunchKernelGGL(k_update_r<double>, dim3(g), dim3(kBlock), 0, s, P->m, (double *)r,
-                           (const double *)q, st, pq_partials, n_pq, rr_partials);
-    }
+template <typename T, bool NT>
+int update_r_as(const mfe_problem *P, void *r, const void *q, CgState *st, const double *pq_partials, int n_pq,
+                double *rr_partials, hipStream_t s, int *grid) {
+    const int g = vec_grid((const void *)k_update_r<T, NT>, P->m, P->ctx->num_cu);
+    hipLaunchKernelGGL((k_update_r<T, NT>), dim3(g), dim3(kBlock), 0, s, P->m, (T *)r, (const T *)q, st, pq_partials,
+                       n_pq, rr_partials);
     MFE_HIP_TRY(hipGetLastError());
     if (grid) *grid = g;
     return MFE_OK;
 }
 
-int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const void *r, CgState *st,
-                     const double *rr_partials, int n_rr, hipStream_t s) {
-    if (f32) {
-        const int g = vec_grid((const void *)k_update_xp<float>, P->m, P->ctx->num_cu);
-        hipLaunchKernelGGL(k_update_xp<float>, dim3(g), dim3(kBlock), 0, s, P->m, (float *)x, (float *)p,
-                           (const float *)r, st, rr_partials, n_rr);
-    } else {
-        const int g = vec_grid((const void *)k_update_xp<double>, P->m, P->ctx->num_cu);
-        hipLaunchKernelGGL(k_update_xp<double>, dim3(g), dim3(kBlock), 0, s, P->m, (double *)x, (double *)p,
-                           (const double *)r, st, rr_partials, n_rr);
-    }
+template <typename T, bool NT>
+int update_xp_as(const mfe_problem *P, void *x, void *p, const void *r, CgState *st, const double *rr_partials,
+                 int n_rr, hipStream_t s) {
+    const int g = vec_grid((const void *)k_update_xp<T, NT>, P->m, P->ctx->num_cu);
+    hipLaunchKernelGGL((k_update_xp<T, NT>), dim3(g), dim3(kBlock), 0, s, P->m, (T *)x, (T *)p, (const T *)r, st,
+                       rr_partials, n_rr);
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
+}
+
+int launch_update_r(const mfe_problem *P, bool f32, void *r, const void *q, CgState *st,
+                    const double *pq_partials, int n_pq, double *rr_partials, hipStream_t s, int *grid) {
+    const bool nt = vectors_stream_nt(P->m);
+    if (f32)
+        return nt ? update_r_as<float, true>(P, r, q, st, pq_partials, n_pq, rr_partials, s, grid)
+                  : update_r_as<float, false>(P, r, q, st, pq_partials, n_pq, rr_partials, s, grid);
+    return nt ? update_r_as<double, true>(P, r, q, st, pq_partials, n_pq, rr_partials, s, grid)
+              : update_r_as<double, false>(P, r, q, st, pq_partials, n_pq, rr_partials, s, grid);
+}
+
+int launch_update_xp(const mfe_problem *P, bool f32, void *x, void *p, const void *r, CgState *st,
+                     const double *rr_partials, int n_rr, hipStream_t s) {
+    const bool nt = vectors_stream_nt(P->m);
+    if (f32)
+        return nt ? update_xp_as<float, true>(P, x, p, r, st, rr_partials, n_rr, s)
+                  : update_xp_as<float, false>(P, x, p, r, st, rr_partials, n_rr, s);
+    return nt ? update_xp_as<double, true>(P, x, p, r, st, rr_partials, n_rr, s)
+              : update_xp_as<double, false>(P, x, p, r, st, rr_partials, n_rr, s);
 }
 
 int launch_pcg_start(const mfe_problem *P, const double *r, double *p, const double *dinv, CgState *st,
