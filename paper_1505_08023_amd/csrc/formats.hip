@@ -88,6 +88,69 @@ __global__ __launch_bounds__(1024) void k_scan1(int64_t n, const int32_t *__rest
     }
 }
 
+// Multi-workgroup exclusive scan of int32 counts: chunks of kScanChunk
+// elements, 8 consecutive ones per thread of a 1024-thread workgroup.
+// Phase 1 writes each chunk's total, k_scan1 scans the chunk totals, phase 2
+// scans inside each chunk from its offset.  Sums are formed in int64.
+constexpr int kScanThreads = 1024, kScanPer = 8, kScanChunk = kScanThreads * kScanPer;
+
+// Exclusive scan of one value per thread over the workgroup; *sum receives
+// the workgroup total (every thread).
+__device__ __forceinline__ int64_t wg_exclusive_scan(int64_t v, int64_t *sum) {
+    __shared__ int64_t wsum[kScanThreads / 64 + 1];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    int64_t x = v;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+        const int64_t y = __shfl_up(x, off, 64);
+        if (lane >= off) x += y;
+    }
+    if (lane == 63) wsum[w] = x;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int64_t acc = 0;
+        for (int k = 0; k < kScanThreads / 64; ++k) {
+            const int64_t t = wsum[k];
+            wsum[k] = acc;
+            acc += t;
+        }
+        wsum[kScanThreads / 64] = acc;
+    }
+    __syncthreads();
+    *sum = wsum[kScanThreads / 64];
+    return wsum[w] + x - v;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_chunks(int64_t n, const int32_t *__restrict__ in,
+                                                              int32_t *__restrict__ chunk_sum) {
+    const int64_t lo = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    int64_t v = 0;
+    for (int j = 0; j < kScanPer; ++j)
+        if (lo + j < n) v += in[lo + j];
+    int64_t total;
+    (void)wg_exclusive_scan(v, &total);
+    if (threadIdx.x == 0) chunk_sum[blockIdx.x] = (int32_t)total;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t n, const int32_t *__restrict__ in,
+                                                             const int32_t *__restrict__ chunk_off,
+                                                             int32_t *__restrict__ out) {
+    const int64_t lo = (int64_t)blockIdx.x * kScanChunk + (int64_t)threadIdx.x * kScanPer;
+    int32_t vals[kScanPer];
+    int64_t v = 0;
+    for (int j = 0; j < kScanPer; ++j) {
+        vals[j] = lo + j < n ? in[lo + j] : 0;
+        v += vals[j];
+    }
+    int64_t total;
+    int64_t acc = chunk_off[blockIdx.x] + wg_exclusive_scan(v, &total);
+    for (int j = 0; j < kScanPer; ++j)
+        if (lo + j < n) {
+            out[lo + j] = (int32_t)acc;
+            acc += vals[j];
+        }
+}
+
 // Write every row's blocks into its slice; pad up to the slice's slot count
 // with zero blocks that point at the row's last block column (a valid index
 // whose x entries are already in cache).
@@ -180,6 +243,32 @@ int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const
     return MFE_OK;
 }
 
+// Exclusive scan of n >= 1 counts into out[0..n] (out may be NULL: total
+// only); *total_dev (device int64) receives the sum.  The sum must fit int32.
+int scan_counts(mfe_ctx *ctx, hipStream_t s, int64_t n, const int32_t *in, int32_t *out, int64_t *total_dev) {
+    const int64_t nchunks = (n + kScanChunk - 1) / kScanChunk;
+    Buffer tmp;
+    MFE_TRY(dev_alloc(ctx, &tmp, (size_t)(2 * nchunks + 1) * sizeof(int32_t)));
+    int32_t *csum = (int32_t *)tmp.ptr, *coff = csum + nchunks;
+    hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(kScanThreads), 0, s, n, in, csum);
+    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, nchunks, (const int32_t *)csum, coff, 1, total_dev);
+    if (out) {
+        hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nchunks), dim3(kScanThreads), 0, s, n, in,
+                           (const int32_t *)coff, out);
+        // out[n] = total
+        MFE_HIP_TRY(hipMemcpyAsync(out + n, coff + nchunks, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+    }
+    const hipError_t e = hipGetLastError();
+    // the stream is ordered: freeing through the allocator after synchronising keeps tmp alive until used
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    dev_free(ctx, &tmp);
+    if (e != hipSuccess) {
+        set_error(std::string("scan launch failed: ") + hipGetErrorString(e));
+        return MFE_EHIP;
+    }
+    return MFE_OK;
+}
+
 int build_bcrs13(mfe_problem *P) {
     mfe_ctx *ctx = P->ctx;
     hipStream_t s = ctx->stream;
@@ -199,9 +288,8 @@ int build_bcrs13(mfe_problem *P) {
                        (const int32_t *)P->col.ptr, (int32_t *)P->rowblocks.ptr, (int32_t *)slice_n.ptr);
     MFE_HIP_TRY(hipGetLastError());
     // slot rows per slice -> slot_base; the same counts x 1 give the total slot rows
-    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, nslices, (const int32_t *)slice_n.ptr,
-                       (int32_t *)P->slot_base.ptr, 1, (int64_t *)total.ptr);
-    MFE_HIP_TRY(hipGetLastError());
+    MFE_TRY(scan_counts(ctx, s, nslices, (const int32_t *)slice_n.ptr, (int32_t *)P->slot_base.ptr,
+                        (int64_t *)total.ptr));
     int64_t nslots = 0;
     MFE_HIP_TRY(hipMemcpyAsync(&nslots, total.ptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
@@ -218,17 +306,12 @@ int build_bcrs13(mfe_problem *P) {
                        (const int32_t *)P->col.ptr, (const double *)P->val64.ptr,
                        (const int32_t *)P->slot_base.ptr, (int32_t *)P->jas.ptr, (double *)P->bval64.ptr);
     MFE_HIP_TRY(hipGetLastError());
-    // number of real (unpadded) blocks: scan of the per-row counts
-    Buffer bptr;
-    MFE_TRY(dev_alloc(ctx, &bptr, (size_t)(m + 1) * sizeof(int32_t)));
-    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, m, (const int32_t *)P->rowblocks.ptr,
-                       (int32_t *)bptr.ptr, 1, (int64_t *)total.ptr + 1);
-    MFE_HIP_TRY(hipGetLastError());
+    // number of real (unpadded) blocks: the sum of the per-row counts
+    MFE_TRY(scan_counts(ctx, s, m, (const int32_t *)P->rowblocks.ptr, nullptr, (int64_t *)total.ptr + 1));
     int64_t nb = 0;
     MFE_HIP_TRY(hipMemcpyAsync(&nb, (int64_t *)total.ptr + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     P->nblocks = nb;
-    dev_free(ctx, &bptr);
     dev_free(ctx, &slice_n);
     dev_free(ctx, &total);
     return MFE_OK;
@@ -258,9 +341,7 @@ int export_bcrs13(const mfe_problem *P, int32_t *bptr_out, int32_t *bcol, double
     Buffer bptr, total;
     MFE_TRY(dev_alloc(ctx, &bptr, (size_t)(m + 1) * sizeof(int32_t)));
     MFE_TRY(dev_alloc(ctx, &total, sizeof(int64_t)));
-    hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, m, (const int32_t *)P->rowblocks.ptr,
-                       (int32_t *)bptr.ptr, 1, (int64_t *)total.ptr);
-    MFE_HIP_TRY(hipGetLastError());
+    MFE_TRY(scan_counts(ctx, s, m, (const int32_t *)P->rowblocks.ptr, (int32_t *)bptr.ptr, (int64_t *)total.ptr));
     const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_b13_export, dim3(grid), dim3(kBlock), 0, s, m, (const int32_t *)P->slot_base.ptr,
                        (const int32_t *)P->rowblocks.ptr, (const int32_t *)bptr.ptr,
