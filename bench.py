@@ -44,7 +44,7 @@ def spmv_bytes(fmt, m, nnz, nb, fp=8):
     return (3 * fp + 4) * nb + 4 * (m + 1) + 2 * fp * m
 
 
-def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30):
+def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30, warmup=5):
     """Mean duration of the fused SpMV + dot kernel from HIP event pairs
     recorded around each launch on the library's stream.  Before each launch
     flush_bytes of unrelated memory are written on the same stream, as the
@@ -56,15 +56,17 @@ def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30):
     pq = torch.zeros(1, dtype=torch.float64, device=x.device)
     flush = torch.empty(max(flush_bytes // 8, 1), dtype=torch.float64, device=x.device) if flush_bytes else None
     pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
-    P.spmv_dot(x, q, pq, fmt=fmt)  # warm-up
+    for _ in range(warmup):
+        P.spmv_dot(x, q, pq, fmt=fmt)
     for ev in pairs:
         if flush is not None:
             with torch.cuda.stream(P.ctx.stream):
                 flush.fill_(0.0)
         P.spmv_dot(x, q, pq, fmt=fmt, events=ev)
     P.ctx.stream.synchronize()
-    ms = [a.elapsed_time(b) for a, b in pairs]
-    return sum(ms) / len(ms), min(ms)
+    ms = sorted(a.elapsed_time(b) for a, b in pairs)
+    time_spmv_dot.median_ms = ms[len(ms) // 2]
+    return sum(ms) / len(ms), ms[0]
 
 
 def cpu_baseline(N, its=(2, 8)):
@@ -95,7 +97,7 @@ def main():
     ap.add_argument("--fmt", default="bcrs13", choices=["bcrs13", "csr"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--max-iter", type=int, default=20000)
-    ap.add_argument("--spmv-reps", type=int, default=20)
+    ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--learned-samples", type=int, default=50, help="held-out seeds in the learned section")
     ap.add_argument("--no-extras", action="store_true",
@@ -139,7 +141,8 @@ def main():
     for fmt in ("bcrs13", "csr"):
         mean_ms, min_ms = time_spmv_dot(P, fmt, args.spmv_reps, torch)
         by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks)
-        spmv[fmt] = dict(mean_ms=mean_ms, min_ms=min_ms, bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
+        spmv[fmt] = dict(mean_ms=mean_ms, median_ms=time_spmv_dot.median_ms, min_ms=min_ms, launches=args.spmv_reps,
+                         bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
                          frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
         log(f"[bench] spmv_dot {fmt}: {mean_ms:.4f} ms, {spmv[fmt]['GBps']:.0f} GB/s")
     dom = spmv[args.fmt]

@@ -93,7 +93,8 @@ int mfe_version(void);
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn,
                    void *alloc_user, mfe_ctx **out);
 /* Synchronises the stream and destroys the context together with every
- * problem still attached to it (their handles become invalid). */
+ * problem, batch and network still attached to it (their handles become
+ * invalid). */
 int mfe_ctx_destroy(mfe_ctx *ctx);
 
 /* Problem statement and assembly (Sec. 1; Fig 3.6 structure, Fig 3.7

@@ -186,6 +186,8 @@ int mfe_ctx_destroy(mfe_ctx *ctx) {
     if (!ctx) return MFE_OK;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    while (!ctx->nets.empty()) mfe_net_destroy(ctx->nets.back());
+    while (!ctx->batches.empty()) mfe_batch_destroy(ctx->batches.back());
     while (!ctx->problems.empty()) mfe_problem_destroy(ctx->problems.back());
     dev_free(ctx, &ctx->scratch);
     dev_free(ctx, &ctx->dot_state);
@@ -378,12 +380,7 @@ int mfe_problem_destroy(mfe_problem *p) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     free_problem_storage(p);
-    auto &v = ctx->problems;
-    for (size_t i = 0; i < v.size(); ++i)
-        if (v[i] == p) {
-            v.erase(v.begin() + (long)i);
-            break;
-        }
+    unregister(ctx->problems, p);
     delete p;
     return MFE_OK;
 }

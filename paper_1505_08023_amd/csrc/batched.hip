@@ -641,6 +641,7 @@ int mfe_batch_create(mfe_ctx *ctx, int nsys, const int32_t *sizes, const double 
         mfe_batch_destroy(B);
         return rc;
     }
+    ctx->batches.push_back(B);
     *out = B;
     return MFE_OK;
 }
@@ -659,6 +660,7 @@ int mfe_batch_destroy(mfe_batch *B) {
         delete B->P;
     }
     if (B->pinned) (void)hipHostFree(B->pinned);
+    unregister(ctx->batches, B);
     delete B;
     return MFE_OK;
 }

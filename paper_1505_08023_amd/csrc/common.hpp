@@ -106,7 +106,21 @@ struct mfe_ctx {
     mfe::Buffer dot_state;   // CgState used by mfe_dot
     mfe::Buffer spmv_dot_state;  // CgState used by mfe_spmv_dot
     std::vector<mfe_problem *> problems;  // live problems, destroyed with the context
+    std::vector<mfe_batch *> batches;     // live batches, likewise
+    std::vector<mfe_net *> nets;          // live networks, likewise
 };
+
+namespace mfe {
+// remove `item` from a context's registry (no-op if absent)
+template <typename T>
+void unregister(std::vector<T *> &v, T *item) {
+    for (size_t i = 0; i < v.size(); ++i)
+        if (v[i] == item) {
+            v.erase(v.begin() + (long)i);
+            return;
+        }
+}
+}  // namespace mfe
 
 namespace mfe {
 

@@ -1040,6 +1040,7 @@ int mfe_net_create(mfe_ctx *ctx, int G, int batch_max, mfe_net **out) {
         mfe_net_destroy(N);
         return rc;
     }
+    ctx->nets.push_back(N);
     *out = N;
     return MFE_OK;
 }
@@ -1055,6 +1056,7 @@ int mfe_net_destroy(mfe_net *N) {
         for (Buffer *b : {&l.act, &l.gact, &l.w, &l.wa, &l.wc}) dev_free(ctx, b);
     for (Buffer *b : {&N->p32, &N->g32, &N->m32, &N->v32, &N->in, &N->out32, &N->gpre, &N->part, &N->bpart, &N->lpart})
         dev_free(ctx, b);
+    unregister(ctx->nets, N);
     delete N;
     return MFE_OK;
 }

@@ -23,6 +23,9 @@
 #ifndef MFE_CSR_LANES
 #define MFE_CSR_LANES 32      // lanes per row of the CRS kernel
 #endif
+#ifndef MFE_CSR_STREAM
+#define MFE_CSR_STREAM 1      // CRS by LDS-staged wavefront tiles (0: MFE_CSR_LANES lanes per row)
+#endif
 #ifndef MFE_SPMV_Q_NT
 #define MFE_SPMV_Q_NT 0       // q store of the dot mode: 0 by vector size, 1 always non-temporal, 2 never
 #endif
@@ -123,6 +126,70 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
     store_partials<MODE>(d1, d2, partials);
 }
 
+// CRS by wavefront tiles staged in LDS: a wavefront takes kCsrsRows
+// consecutive rows, loads their (value, column) runs, contiguous in the CRS
+// arrays, with coalesced loads into LDS, then each row is summed by
+// 64 / kCsrsRows lanes (strided entries, combined by an xor butterfly)
+// reading LDS and gathering x.
+// A tile whose entries exceed the LDS capacity is summed straight from
+// global memory instead.
+#ifndef MFE_CSRS_ROWS
+#define MFE_CSRS_ROWS 16  // rows per wavefront tile (64 / rows lanes per row); 8, 16 and 32 measured
+#endif
+constexpr int kCsrsRows = MFE_CSRS_ROWS;       // rows per wavefront tile
+constexpr int kCsrsCap = kCsrsRows * 28;       // staged entries per wavefront tile
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *__restrict__ ptr,
+                                                      const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
+                                                      double *partials) {
+    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
+    __shared__ T sval[kBlock / 64][kCsrsCap];
+    __shared__ int32_t scol[kBlock / 64][kCsrsCap];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    constexpr int LPR = 64 / kCsrsRows;  // lanes per row
+    const int sub = lane % LPR, rl = lane / LPR;
+    T *sv = sval[wave];
+    int32_t *sc = scol[wave];
+    constexpr int R = (kBlock / 64) * kCsrsRows;  // rows per workgroup tile
+    const long ntiles = (m + R - 1) / R;
+    double d1 = 0.0, d2 = 0.0;
+    for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
+        const int64_t r0 = tr.t * R + (int64_t)wave * kCsrsRows;
+        if (r0 >= m) continue;  // wavefront-uniform
+        const int64_t r1 = r0 + kCsrsRows < m ? r0 + kCsrsRows : m;
+        const int32_t lo = ptr[r0], hi = ptr[r1];
+        const int64_t row = r0 + rl;
+        T sum = 0;
+        if (hi - lo <= kCsrsCap) {
+            for (int32_t j = lo + lane; j < hi; j += 64) {
+                sv[j - lo] = matrix_load(val + j);
+                sc[j - lo] = matrix_load(col + j);
+            }
+            wave_sync();
+            if (row < r1) {
+                const int32_t a = ptr[row] - lo, b = ptr[row + 1] - lo;
+                for (int32_t j = a + sub; j < b; j += LPR) sum += sv[j] * E.x[sc[j]];
+            }
+            wave_sync();
+        } else if (row < r1) {
+            for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += LPR)
+                sum += matrix_load(val + j) * E.x[matrix_load(col + j)];
+        }
+#pragma unroll
+        for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
+        if (sub == 0 && row < r1) finish_row<T, MODE>(E, row, sum, d1, d2);
+    }
+    store_partials<MODE>(d1, d2, partials);
+}
+
 // ---------------------------------------------------------------- 1x3 BCRS
 
 // One slice per wavefront per tile: slice bounds, column indices, values,
@@ -196,12 +263,17 @@ int grid_for(K kernel, long ntiles, int num_cu) {
 
 template <typename T, int MODE>
 int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
+    const T *val = std::is_same<T, double>::value ? (const T *)P->val64.ptr : (const T *)P->val32.ptr;
+#if MFE_CSR_STREAM
+    auto kern = k_spmv_csrs<T, MODE>;
+    const long ntiles = (P->m + (kBlock / 64) * kCsrsRows - 1) / ((kBlock / 64) * kCsrsRows);
+#else
     // L lanes per row: with 32, a row of the 27-point matrix (one contiguous
     // 216-byte run of values) is read by one half-wavefront.
     constexpr int L = MFE_CSR_LANES;
-    const T *val = std::is_same<T, double>::value ? (const T *)P->val64.ptr : (const T *)P->val32.ptr;
     auto kern = k_spmv_csr<T, L, MODE>;
     const long ntiles = (P->m + kBlock / L - 1) / (kBlock / L);
+#endif
     const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->ptr.ptr,
                        (const int32_t *)P->col.ptr, val, E, st, partials);

@@ -382,3 +382,20 @@ def test_cg_breakdown_on_indefinite_matrix(ctx):
     P = Problem.from_csr(ctx, ptr, col, val, b)
     x, st = P.cg(tol=1e-10, max_iter=10, fmt="csr", raise_on_breakdown=False)
     assert st["status"] == -4 and st["iterations"] == 0
+
+
+def test_context_destroy_releases_attached_objects():
+    """mfe_ctx_destroy destroys the problems, batches and networks still
+    attached to the context (C callers need not destroy them first)."""
+    import ctypes
+    from paper_1505_08023_amd import _lib
+    lib = _lib.load()
+    h = ctypes.c_void_p()
+    _lib.check(lib.mfe_ctx_create(0, None, _lib.mfe_alloc_fn(), _lib.mfe_free_fn(), None, ctypes.byref(h)),
+               "mfe_ctx_create")
+    p, b, n = ctypes.c_void_p(), ctypes.c_void_p(), ctypes.c_void_p()
+    _lib.check(lib.mfe_problem_create(h, 4, 4, 4, None, None, 3, 1, ctypes.byref(p)), "mfe_problem_create")
+    sizes = (ctypes.c_int32 * 6)(3, 4, 5, 4, 4, 4)
+    _lib.check(lib.mfe_batch_create(h, 2, sizes, None, 3, 1, ctypes.byref(b)), "mfe_batch_create")
+    _lib.check(lib.mfe_net_create(h, 9, 1, ctypes.byref(n)), "mfe_net_create")
+    assert lib.mfe_ctx_destroy(h) == 0
