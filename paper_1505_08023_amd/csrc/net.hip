@@ -188,6 +188,130 @@ __global__ __launch_bounds__(256) void k_conv_reduce(const float *__restrict__ p
     }
 }
 
+// ------------------------------------------------------------------ stride 1 through LDS
+
+// Stride-1 convolution for few input channels (the full-resolution levels):
+// a workgroup computes an output brick of kBx x kBy x kBz voxels and first
+// stages the input brick with its one-voxel halo, (kBx+2)(kBy+2)(kBz+2)
+// voxels x CIN channels, in LDS, zero outside the grid.  Every A operand of
+// the implicit GEMM is then a 16-byte LDS read instead of a global gather
+// (each input voxel is read from memory about (1 + 2/16)(1 + 2/4)^2 times
+// instead of 27).  M fragment = one x-row of 16 voxels; wave w owns rows
+// 4w .. 4w+3 of the 16 (y, z) rows.  W and the epilogue as in k_conv.
+constexpr int kBx = 16, kBy = 4, kBz = 4;
+constexpr int kHx = kBx + 2, kHy = kBy + 2, kHz = kBz + 2;
+
+template <int CIN, int NT>
+__global__ __launch_bounds__(256) void k_conv_s1_lds(const bf16 *__restrict__ in, int G, int batch,
+                                                     const bf16 *__restrict__ W, int Kpad, int Cout,
+                                                     const float *__restrict__ bias, const bf16 *add, int relu,
+                                                     bf16 *out, float *__restrict__ out32) {
+    constexpr int KP = (27 * CIN + 63) / 64 * 64;  // = Kpad
+    constexpr int WS = KP + 8;                      // LDS row stride of W (16-byte pad against bank conflicts)
+    __shared__ __attribute__((aligned(16))) bf16 tile[kHx * kHy * kHz * CIN];
+    __shared__ __attribute__((aligned(16))) bf16 wt[16 * NT * WS];
+    const int nbx = (G + kBx - 1) / kBx, nby = (G + kBy - 1) / kBy, nbz = (G + kBz - 1) / kBz;
+    int b = blockIdx.x;
+    const int bx = b % nbx;
+    b /= nbx;
+    const int by = b % nby;
+    b /= nby;
+    const int bz = b % nbz;
+    const int n = b / nbz;
+    const int x0 = bx * kBx, y0 = by * kBy, z0 = bz * kBz;
+    const int64_t V = (int64_t)G * G * G;
+    // stage the input brick with halo: 16-byte chunks of 8 channels; every
+    // load of a thread is issued before its first LDS store
+    constexpr int kChunks = kHx * kHy * kHz * (CIN / 8);
+    constexpr int kIters = (kChunks + 255) / 256;
+    bf16x8 v[kIters];
+#pragma unroll
+    for (int i = 0; i < kIters; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        const int hv = q / (CIN / 8), part = q % (CIN / 8);
+        const int hx = hv % kHx, hy = (hv / kHx) % kHy, hz = hv / (kHx * kHy);
+        const int gx = x0 - 1 + hx, gy = y0 - 1 + hy, gz = z0 - 1 + hz;
+        v[i] = zero8();
+        if (q < kChunks && gx >= 0 && gx < G && gy >= 0 && gy < G && gz >= 0 && gz < G)
+            v[i] = load8(in + ((int64_t)n * V + ((int64_t)gz * G + gy) * G + gx) * CIN + part * 8);
+    }
+    // the layer's weight rows, 16 NT x KP, also once per workgroup
+    constexpr int kWChunks = 16 * NT * (KP / 8);
+    constexpr int kWIters = (kWChunks + 255) / 256;
+    bf16x8 wv[kWIters];
+#pragma unroll
+    for (int i = 0; i < kWIters; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        wv[i] = q < kWChunks ? load8(W + (int64_t)(q / (KP / 8)) * Kpad + (q % (KP / 8)) * 8) : zero8();
+    }
+#pragma unroll
+    for (int i = 0; i < kIters; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        if (q < kChunks) *(bf16x8 *)(tile + q * 8) = v[i];  // q * 8 = hv * CIN + part * 8
+    }
+#pragma unroll
+    for (int i = 0; i < kWIters; ++i) {
+        const int q = threadIdx.x + 256 * i;
+        if (q < kWChunks) *(bf16x8 *)(wt + (q / (KP / 8)) * WS + (q % (KP / 8)) * 8) = wv[i];
+    }
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int row = lane & 15, kg = lane >> 4;
+    constexpr int Kreal = 27 * CIN;
+    f32x4 acc[4][NT];
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) acc[mt][nt] = (f32x4)(0.0f);
+    const bf16 *Wrow = wt + row * WS;
+    constexpr int nsteps = KP >> 5;
+    for (int st = 0; st < nsteps; ++st) {
+        const int k = st * 32 + 8 * kg;
+        bf16x8 b0[NT];
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt) b0[nt] = *(const bf16x8 *)(Wrow + nt * 16 * WS + k);
+        const int d = k / CIN, c0 = k % CIN;
+        const int dx = d % 3, dy = (d / 3) % 3, dz = d / 9;
+        bf16x8 a[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            const int f = wave * 4 + mt;  // x-row (vy, vz) of the brick
+            const int vy = f % kBy, vz = f / kBy;
+            const int hv = ((vz + dz) * kHy + (vy + dy)) * kHx + (row + dx);
+            a[mt] = k < Kreal ? *(const bf16x8 *)(tile + hv * CIN + c0) : zero8();
+        }
+#pragma unroll
+        for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+                acc[mt][nt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[mt], b0[nt], acc[mt][nt], 0, 0, 0);
+    }
+#pragma unroll
+    for (int mt = 0; mt < 4; ++mt) {
+        const int f = wave * 4 + mt;
+        const int gy = y0 + f % kBy, gz = z0 + f / kBy;
+        if (gy >= G || gz >= G) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int gx = x0 + 4 * kg + j;
+            if (gx >= G) continue;
+            const int64_t v = (int64_t)n * V + ((int64_t)gz * G + gy) * G + gx;
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const int o = nt * 16 + row;
+                if (o >= Cout) continue;
+                float val = acc[mt][nt][j];
+                const int64_t idx = v * Cout + o;
+                if (bias) val += bias[o];
+                if (add) val += (float)add[idx];
+                if (relu) val = fmaxf(val, 0.0f);
+                out[idx] = (bf16)val;
+                if (out32) out32[idx] = val;
+            }
+        }
+    }
+}
+
 // ------------------------------------------------------------------ transposed stride 2 by parity class
 
 // Along one axis an output p = 2j + q of the t2 pattern receives tap d = 1
@@ -693,9 +817,42 @@ int build_t2_classes(hipStream_t s, const bf16 *M, int rows, int Kpad, int Cin, 
 int64_t t2_class_elems(int Cin, int rows) { return t2_layout(Cin, rows).woff[8]; }
 
 // W: [rows][Kpad] weights; WC: their class matrices, needed for t2
+// stride 1 through LDS for Cin <= 32 and Cout <= 32
+int conv_s1_lds(hipStream_t s, const bf16 *in, int G, int Cin, const bf16 *W, int Kpad, int Cout, int batch,
+                const float *bias, const bf16 *add, int relu, bf16 *out, float *out32) {
+    const int64_t nbrick = (int64_t)batch * ((G + kBx - 1) / kBx) * ((G + kBy - 1) / kBy) * ((G + kBz - 1) / kBz);
+    const dim3 grid((unsigned)nbrick);
+    if (Kpad != pad64(27 * Cin)) {
+        set_error("internal: weight padding does not match the LDS stride-1 convolution");
+        return MFE_EINVAL;
+    }
+#define MFE_S1L_CASE(CI, NT_)                                                                               \
+    if (Cin == CI && (Cout + 15) / 16 == NT_) {                                                            \
+        hipLaunchKernelGGL((k_conv_s1_lds<CI, NT_>), grid, dim3(256), 0, s, in, G, batch, W, Kpad, Cout, bias, \
+                           add, relu, out, out32);                                                        \
+        MFE_HIP_TRY(hipGetLastError());                                                                    \
+        return MFE_OK;                                                                                     \
+    }
+    MFE_S1L_CASE(8, 1)
+    MFE_S1L_CASE(8, 2)
+    MFE_S1L_CASE(16, 1)
+    MFE_S1L_CASE(16, 2)
+    MFE_S1L_CASE(32, 1)
+    MFE_S1L_CASE(32, 2)
+#undef MFE_S1L_CASE
+    set_error("internal: no LDS stride-1 convolution for these channels");
+    return MFE_EINVAL;
+}
+
+#ifndef MFE_CONV_LDS
+#define MFE_CONV_LDS 1  // stride-1 convolutions with Cin, Cout <= 32 through LDS bricks
+#endif
+
 int conv(hipStream_t s, int mode, const bf16 *in, int Gi, int Cin, const bf16 *W, const bf16 *WC, int Kpad,
          int Cout, int Go, int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32,
          float *ws, int64_t ws_floats) {
+    if (MFE_CONV_LDS && mode == kS1 && Cin <= 32 && Cout <= 32)
+        return conv_s1_lds(s, in, Gi, Cin, W, Kpad, Cout, batch, bias, add, relu, out, out32);
     if (mode == kS1)
         return conv_mode<kS1>(s, in, Gi, Cin, W, Kpad, Cout, Go, batch, bias, add, relu, out, out32, ws, ws_floats);
     if (mode == kS2)
