@@ -246,6 +246,33 @@ def extras(args, ctx, P, x, line, torch):
     mixed["speedup"] = mixed["fp64_cg"]["seconds"] / mixed["fp32_inner_fp64_refine"]["seconds"]
     line["mixed_precision_1e-10"] = mixed
 
+    # inner tolerance of the FP32 solves, swept at 1e-10 (best first), and
+    # mixed against FP64 at the headline tolerance 1e-8
+    def timed(fn):
+        with torch.cuda.stream(ctx.stream):
+            x.zero_()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st
+    sweep = []
+    for itol in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
+        dt, st = timed(lambda: P.cg_mixed(x, tol=1e-10, inner_tol=itol, fmt=args.fmt)[1])
+        sweep.append(dict(inner_tol=itol, seconds=dt, inner_iterations=st["iterations"], outer=st["outer"],
+                          rel_res_true=st["rel_res_true"]))
+    sweep.sort(key=lambda r: r["seconds"])
+    line["mixed_inner_tol_sweep_1e-10"] = sweep
+    log(f"[bench] inner tolerance sweep: best {sweep[0]}")
+    m8 = {}
+    for name, fn in (("fp64_cg", lambda: P.cg(x, tol=1e-8, max_iter=args.max_iter, fmt=args.fmt)[1]),
+                     ("fp32_inner_fp64_refine", lambda: P.cg_mixed(x, tol=1e-8, inner_tol=1e-4, fmt=args.fmt)[1])):
+        dt, st = timed(fn)
+        m8[name] = dict(seconds=dt, iterations=st["iterations"], outer=st["outer"], rel_res_true=st["rel_res_true"])
+    m8["speedup"] = m8["fp64_cg"]["seconds"] / m8["fp32_inner_fp64_refine"]["seconds"]
+    line["mixed_precision_1e-8"] = m8
+    log(f"[bench] mixed at 1e-8: {m8}")
+
     # batched uneven solves: 64 meshes, Nx, Ny, Nz ~ U{16..96}, seed 0, to 1e-8 each
     sizes, faces = inputs.batched_meshes(nsys=64, lo=16, hi=96, seed=0)
     B = Batch(ctx, sizes, faces, precisions=("f64", "f32"))
