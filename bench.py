@@ -290,10 +290,19 @@ def extras(args, ctx, P, x, line, torch):
         t = time.perf_counter()
         st = fn()
         torch.cuda.synchronize()
+        dt = time.perf_counter() - t
         its = [s["iterations"] for s in st]
-        bat[name] = dict(seconds=time.perf_counter() - t, max_iterations=max(its), sum_iterations=sum(its),
+        bat[name] = dict(seconds=dt, max_iterations=max(its), sum_iterations=sum(its),
                          worst_rel_res_true=max(s["rel_res_true"] for s in st),
                          all_converged=all(s["status"] == 0 for s in st))
+        if name == "fp64":
+            # algorithmic bytes: each system's iterations x (1x3 BCRS SpMV + 64 m)
+            tot = 0
+            for (nx, ny, nz), k in zip(sizes.tolist(), its):
+                ms, nbs = (nx + 1) * (ny + 1) * (nz + 1), (nx + 1) * (3 * ny + 1) * (3 * nz + 1)
+                tot += k * (spmv_bytes("bcrs13", ms, 0, nbs) + 64 * ms)
+            bat[name]["algorithmic_bytes"] = tot
+            bat[name]["effective_GBps"] = tot / dt / 1e9
         log(f"[bench] batched {name}: {bat[name]}")
     line["batched_64_meshes_1e-8"] = bat
     B.close()
