@@ -38,21 +38,38 @@ __device__ __forceinline__ int row_blocks(const int32_t *col, const double *val,
     return nb;
 }
 
+// One 64-thread workgroup per slice.  The slice's CRS runs, contiguous in
+// the CRS arrays, are first copied to LDS with coalesced loads (a thread per
+// row then walks its row in LDS instead of issuing loads 27 entries apart
+// from its neighbours'); a slice with more than kConvCap entries reads
+// global memory directly.
+constexpr int kConvCap = 64 * 28;
+
 // Blocks per row, and per slice the maximum over its 64 rows.
-__global__ __launch_bounds__(kBlock) void k_b13_count(int64_t m, const int32_t *__restrict__ ptr,
-                                                      const int32_t *__restrict__ col,
-                                                      int32_t *__restrict__ rowblocks,
-                                                      int32_t *__restrict__ slice_n) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(64) void k_b13_count(int64_t m, const int32_t *__restrict__ ptr,
+                                                  const int32_t *__restrict__ col,
+                                                  int32_t *__restrict__ rowblocks,
+                                                  int32_t *__restrict__ slice_n) {
+    __shared__ int32_t sc[kConvCap];
+    const int64_t s = blockIdx.x;
+    const int64_t i = s * 64 + threadIdx.x;
+    const int64_t r1 = s * 64 + 64 < m ? s * 64 + 64 : m;
+    const int32_t tlo = ptr[s * 64], thi = ptr[r1];
+    const bool staged = thi - tlo <= kConvCap;
+    if (staged)
+        for (int32_t j = tlo + (int32_t)threadIdx.x; j < thi; j += 64) sc[j - tlo] = col[j];
+    __syncthreads();
     int nb = 0;
     if (i < m) {
-        nb = row_blocks(col, nullptr, ptr[i], ptr[i + 1], m, [](int, int32_t, const double *) {});
+        auto none = [](int, int32_t, const double *) {};
+        nb = staged ? row_blocks(sc, nullptr, ptr[i] - tlo, ptr[i + 1] - tlo, m, none)
+                    : row_blocks(col, nullptr, ptr[i], ptr[i + 1], m, none);
         rowblocks[i] = nb;
     }
     int mx = nb;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = max(mx, __shfl_xor(mx, off, 64));
-    if ((threadIdx.x & 63) == 0 && (i >> 6) * 64 < m) slice_n[i >> 6] = mx;
+    if (threadIdx.x == 0) slice_n[s] = mx;
 }
 
 // Exclusive prefix sum of n int32 counts into out[0..n] (out[n] = total),
@@ -155,25 +172,39 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_apply(int64_t n, const in
 // with zero blocks that point at the row's last block column (a valid index
 // whose x entries are already in cache).
 template <typename T>
-__global__ __launch_bounds__(kBlock) void k_b13_fill(int64_t m, const int32_t *__restrict__ ptr,
-                                                     const int32_t *__restrict__ col,
-                                                     const double *__restrict__ val,
-                                                     const int32_t *__restrict__ slot_base,
-                                                     int32_t *__restrict__ jas, T *__restrict__ bval) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int64_t s = i >> 6;
-    const int lane = (int)(i & 63);
-    if (s * 64 >= m) return;
+__global__ __launch_bounds__(64) void k_b13_fill(int64_t m, const int32_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ col,
+                                                 const double *__restrict__ val,
+                                                 const int32_t *__restrict__ slot_base,
+                                                 int32_t *__restrict__ jas, T *__restrict__ bval) {
+    __shared__ int32_t sc[kConvCap];
+    __shared__ double sv[kConvCap];
+    const int64_t s = blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const int64_t i = s * 64 + lane;
+    const int64_t r1 = s * 64 + 64 < m ? s * 64 + 64 : m;
+    const int32_t tlo = ptr[s * 64], thi = ptr[r1];
+    const bool staged = thi - tlo <= kConvCap;
+    if (staged)
+        for (int32_t j = tlo + lane; j < thi; j += 64) {
+            sc[j - tlo] = col[j];
+            sv[j - tlo] = val[j];
+        }
+    __syncthreads();
     const B13Slice sl = b13_slice(slot_base[s], slot_base[s + 1]);
     int32_t last_c = 0;
     int nb = 0;
     if (i < m) {
-        nb = row_blocks(col, val, ptr[i], ptr[i + 1], m, [&](int blk, int32_t c, const double *v) {
+        auto put = [&](int blk, int32_t c, const double *v) {
             jas[b13_jas(sl, blk, lane)] = c;
             for (int j = 0; j < 3; ++j) bval[b13_val(sl, blk, j, lane)] = (T)v[j];
             last_c = c;
-        });
+        };
+        nb = staged ? row_blocks(sc, sv, ptr[i] - tlo, ptr[i + 1] - tlo, m, put)
+                    : row_blocks(col, val, ptr[i], ptr[i + 1], m, put);
     }
+    // pad up to the slice's slot count with zero blocks that point at the
+    // row's last block column (a valid index whose x entries are in cache)
     for (int k = nb; k < sl.S; ++k) {
         jas[b13_jas(sl, k, lane)] = last_c;
         for (int j = 0; j < 3; ++j) bval[b13_val(sl, k, j, lane)] = (T)0;
@@ -283,8 +314,8 @@ int build_bcrs13(mfe_problem *P) {
     MFE_TRY(dev_alloc(ctx, &slice_n, (size_t)nslices * sizeof(int32_t)));
     MFE_TRY(dev_alloc(ctx, &P->slot_base, (size_t)(nslices + 1) * sizeof(int32_t)));
     MFE_TRY(dev_alloc(ctx, &total, 2 * sizeof(int64_t)));
-    const unsigned grid = (unsigned)((nslices * 64 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_b13_count, dim3(grid), dim3(kBlock), 0, s, m, (const int32_t *)P->ptr.ptr,
+    const unsigned grid = (unsigned)nslices;  // one 64-thread workgroup per slice
+    hipLaunchKernelGGL(k_b13_count, dim3(grid), dim3(64), 0, s, m, (const int32_t *)P->ptr.ptr,
                        (const int32_t *)P->col.ptr, (int32_t *)P->rowblocks.ptr, (int32_t *)slice_n.ptr);
     MFE_HIP_TRY(hipGetLastError());
     // slot rows per slice -> slot_base; the same counts x 1 give the total slot rows
@@ -302,7 +333,7 @@ int build_bcrs13(mfe_problem *P) {
     P->nslots = nslots;
     MFE_TRY(dev_alloc(ctx, &P->jas, (size_t)nslots * 64 * sizeof(int32_t)));
     MFE_TRY(dev_alloc(ctx, &P->bval64, (size_t)nslots * 64 * 3 * sizeof(double)));
-    hipLaunchKernelGGL(k_b13_fill<double>, dim3(grid), dim3(kBlock), 0, s, m, (const int32_t *)P->ptr.ptr,
+    hipLaunchKernelGGL(k_b13_fill<double>, dim3(grid), dim3(64), 0, s, m, (const int32_t *)P->ptr.ptr,
                        (const int32_t *)P->col.ptr, (const double *)P->val64.ptr,
                        (const int32_t *)P->slot_base.ptr, (int32_t *)P->jas.ptr, (double *)P->bval64.ptr);
     MFE_HIP_TRY(hipGetLastError());
