@@ -69,32 +69,49 @@ __device__ __forceinline__ int shared_elements(int i, int s, int N) {
     return (i > 0) + (i < N);
 }
 
-// One thread per row.  mode 0: structure + values + rhs; mode 1: rhs only.
-// The mesh's rows and entries are written at offsets row_off / nnz_off of
-// the arrays (column indices shifted by row_off), so several meshes can form
-// one block-diagonal matrix.
-__global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int64_t row_off, int64_t nnz_off,
-                                                     int32_t *__restrict__ ptr, int32_t *__restrict__ col,
-                                                     double *__restrict__ val, double *__restrict__ b,
-                                                     int rhs_only) {
+// One thread per row, one 64-thread workgroup per 64 consecutive rows.
+// mode 0: structure + values + rhs; mode 1: rhs only.  The rows of a
+// workgroup own one contiguous run of the CRS arrays: each thread writes its
+// row's entries into LDS at its offset in that run, then the workgroup copies
+// the run to memory with coalesced stores.  The mesh's rows and entries are
+// written at offsets row_off / nnz_off of the arrays (column indices shifted
+// by row_off), so several meshes can form one block-diagonal matrix.
+constexpr int kAsmRows = 64;
+__global__ __launch_bounds__(kAsmRows) void k_assemble(Mesh M, int64_t row_off, int64_t nnz_off,
+                                                       int32_t *__restrict__ ptr, int32_t *__restrict__ col,
+                                                       double *__restrict__ val, double *__restrict__ b,
+                                                       int rhs_only) {
+    __shared__ int32_t scol[kAsmRows * 27];
+    __shared__ double sval[kAsmRows * 27];
     const int64_t m = (int64_t)M.nx * M.ny * M.nz;
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (i >= m) return;
-    const int ix = (int)(i % M.nx);
-    const int iy = (int)((i / M.nx) % M.ny);
-    const int iz = (int)(i / ((int64_t)M.nx * M.ny));
+    const int64_t i0 = (int64_t)blockIdx.x * kAsmRows;
+    const int64_t i = i0 + threadIdx.x;
+    const bool live = i < m;
+    const int64_t ic = live ? i : m - 1;  // rows past the end compute row m-1 and discard it
+    const int ix = (int)(ic % M.nx);
+    const int iy = (int)((ic / M.nx) % M.ny);
+    const int iz = (int)(ic / ((int64_t)M.nx * M.ny));
 
     const int64_t SX = 3 * (int64_t)M.Nx + 1, SY = 3 * (int64_t)M.Ny + 1;
     const int cy = line_count(iy, M.Ny), cz = line_count(iz, M.Nz);
     const int64_t start = SX * SY * line_prefix(iz) + SX * line_prefix(iy) * cz +
                           line_prefix(ix) * (int64_t)cy * cz;
-    if (!rhs_only) {
+    const int64_t end = start + (int64_t)line_count(ix, M.Nx) * cy * cz;
+    if (!rhs_only && live) {
         ptr[row_off + i] = (int32_t)(nnz_off + start);
-        if (i == m - 1) ptr[row_off + m] = (int32_t)(nnz_off + start + (int64_t)line_count(ix, M.Nx) * cy * cz);
+        if (i == m - 1) ptr[row_off + m] = (int32_t)(nnz_off + end);
+    }
+    // the workgroup's run of entries: from its first row's start to its last live row's end
+    const int64_t run_lo = __shfl(start, 0, 64);
+    int64_t run_hi = live ? end : 0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        const int64_t o = __shfl_xor(run_hi, off, 64);
+        run_hi = o > run_hi ? o : run_hi;
     }
 
     double gi;
-    const bool dir_i = boundary_value(M, ix, iy, iz, i, gi);
+    const bool dir_i = boundary_value(M, ix, iy, iz, ic, gi);
     double bi = 0.0;  // zero source: element loads vanish
     int64_t k = start;
     for (int sz = -1; sz <= 1; ++sz) {
@@ -106,7 +123,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int64_t row_off, in
             for (int sx = -1; sx <= 1; ++sx) {
                 const int jx = ix + sx;
                 if (jx < 0 || jx > M.Nx) continue;
-                const int64_t j = i + sx + (int64_t)M.nx * (sy + (int64_t)M.ny * sz);
+                const int64_t j = ic + sx + (int64_t)M.nx * (sy + (int64_t)M.ny * sz);
                 // sum of the element entries over the shared elements
                 const int ne = shared_elements(ix, sx, M.Nx) * shared_elements(iy, sy, M.Ny) *
                                shared_elements(iz, sz, M.Nz);
@@ -115,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int64_t row_off, in
                 for (int e = 0; e < ne; ++e) raw += kij;
                 double v = raw;
                 if (dir_i) {
-                    v = (j == i) ? 1.0 : 0.0;
+                    v = (j == ic) ? 1.0 : 0.0;
                 } else {
                     double gj;
                     if (boundary_value(M, jx, jy, jz, j, gj)) {
@@ -123,15 +140,21 @@ __global__ __launch_bounds__(kBlock) void k_assemble(Mesh M, int64_t row_off, in
                         v = 0.0;
                     }
                 }
-                if (!rhs_only) {
-                    col[nnz_off + k] = (int32_t)(row_off + j);
-                    val[nnz_off + k] = v;
+                if (!rhs_only && live) {
+                    scol[k - run_lo] = (int32_t)(row_off + j);
+                    sval[k - run_lo] = v;
                 }
                 ++k;
             }
         }
     }
-    b[row_off + i] = dir_i ? gi : bi;
+    if (live) b[row_off + i] = dir_i ? gi : bi;
+    if (rhs_only) return;  // uniform over the workgroup
+    __syncthreads();
+    for (int64_t t = run_lo + threadIdx.x; t < run_hi; t += kAsmRows) {
+        col[nnz_off + t] = scol[t - run_lo];
+        val[nnz_off + t] = sval[t - run_lo];
+    }
 }
 
 }  // namespace
@@ -152,8 +175,8 @@ int launch_assemble_into(hipStream_t s, int Nx, int Ny, int Nz, const double *fa
     for (int i = 0; i < 6; ++i) M.face[i] = f[i];
     M.node_g = node_g;
     const int64_t m = (int64_t)M.nx * M.ny * M.nz;
-    const int64_t grid = (m + kBlock - 1) / kBlock;
-    hipLaunchKernelGGL(k_assemble, dim3((unsigned)grid), dim3(kBlock), 0, s, M, row_off, nnz_off, ptr, col, val, b,
+    const int64_t grid = (m + kAsmRows - 1) / kAsmRows;
+    hipLaunchKernelGGL(k_assemble, dim3((unsigned)grid), dim3(kAsmRows), 0, s, M, row_off, nnz_off, ptr, col, val, b,
                        rhs_only ? 1 : 0);
     MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
