@@ -44,14 +44,14 @@ def spmv_bytes(fmt, m, nnz, nb, fp=8):
     return (3 * fp + 4) * nb + 4 * (m + 1) + 2 * fp * m
 
 
-def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30, warmup=5):
+def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30, warmup=5, f32=False):
     """Mean duration of the fused SpMV + dot kernel from HIP event pairs
     recorded around each launch on the library's stream.  Before each launch
     flush_bytes of unrelated memory are written on the same stream, as the
     vector updates of a CG iteration do between two products, so that x is
     not left in the memory-side cache by the previous launch."""
     from paper_1505_08023_amd import inputs
-    x = torch.tensor(inputs.spmv_vector(P.m, seed=0), device=P.ctx.device)
+    x = torch.tensor(inputs.spmv_vector(P.m, seed=0, dtype="float32" if f32 else "float64"), device=P.ctx.device)
     q = torch.empty_like(x)
     pq = torch.zeros(1, dtype=torch.float64, device=x.device)
     flush = torch.empty(max(flush_bytes // 8, 1), dtype=torch.float64, device=x.device) if flush_bytes else None
@@ -145,6 +145,14 @@ def main():
                          bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
                          frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
         log(f"[bench] spmv_dot {fmt}: {mean_ms:.4f} ms, {spmv[fmt]['GBps']:.0f} GB/s")
+    # the FP32 product of the mixed-precision inner solves
+    for fmt in ("bcrs13", "csr"):
+        mean_ms, min_ms = time_spmv_dot(P, fmt, args.spmv_reps, torch, f32=True)
+        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, fp=4)
+        spmv[fmt + "_f32"] = dict(mean_ms=mean_ms, median_ms=time_spmv_dot.median_ms, min_ms=min_ms,
+                                  launches=args.spmv_reps, bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
+                                  frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
+        log(f"[bench] spmv_dot {fmt} FP32: {mean_ms:.4f} ms, {spmv[fmt + '_f32']['GBps']:.0f} GB/s")
     dom = spmv[args.fmt]
     vec_bytes = 64 * P.m
     it_bytes = dom["bytes"] + vec_bytes

@@ -157,6 +157,12 @@ int mfe_spmv_f32(const mfe_problem *p, int format, const float *x_dev, float *y_
 int mfe_spmv_dot(const mfe_problem *p, int format, const double *p_dev, double *q_dev, double *pq_dev,
                  void *ev_before, void *ev_after);
 
+/* The same fused product in FP32 (the kernel of the inner solves of
+ * mfe_cg_mixed): FP32 matrix values, p and q, FP32 row sums, p.q accumulated
+ * in FP64 into *pq_dev.  Needs MFE_F32 at create.  Does not synchronise. */
+int mfe_spmv_dot_f32(const mfe_problem *p, int format, const float *p_dev, float *q_dev, double *pq_dev,
+                     void *ev_before, void *ev_after);
+
 /* Dot product (Sec. 1, DOT) of two FP64 device vectors of length n >= 0
  * (x_dev, y_dev may be NULL when n = 0),
  * reduced in a fixed order (bitwise reproducible run to run).  The result is

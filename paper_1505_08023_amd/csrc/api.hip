@@ -434,6 +434,30 @@ int mfe_spmv_dot(const mfe_problem *p, int format, const double *p_dev, double *
     return launch_finalize(kFinDot, (const double *)ctx->scratch.ptr, n, st, ctx->stream);
 }
 
+int mfe_spmv_dot_f32(const mfe_problem *p, int format, const float *p_dev, float *q_dev, double *pq_dev,
+                     void *ev_before, void *ev_after) {
+    clear_error();
+    if (!p || !p_dev || !q_dev || !pq_dev) {
+        set_error("problem, p, q and pq must be non-NULL");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(check_format(p, format));
+    if (!(p->precisions & MFE_F32)) {
+        set_error("FP32 values were not built for this problem");
+        return MFE_EUNSUPPORTED;
+    }
+    MFE_TRY(set_device(p->ctx));
+    mfe_ctx *ctx = p->ctx;
+    CgState *st = (CgState *)ctx->spmv_dot_state.ptr;
+    MFE_TRY(launch_state_reset(st, pq_dev, ctx->stream));
+    if (ev_before) MFE_HIP_TRY(hipEventRecord((hipEvent_t)ev_before, ctx->stream));
+    SpmvArgs a{p_dev, q_dev, nullptr, nullptr, st, (double *)ctx->scratch.ptr};
+    int n = 0;
+    MFE_TRY(launch_spmv(p, format, true, kSpmvDot, a, ctx->stream, &n));
+    if (ev_after) MFE_HIP_TRY(hipEventRecord((hipEvent_t)ev_after, ctx->stream));
+    return launch_finalize(kFinDot, (const double *)ctx->scratch.ptr, n, st, ctx->stream);
+}
+
 int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, double *out_host) {
     clear_error();
     if (!ctx || !out_host || n < 0 || (n > 0 && (!x_dev || !y_dev))) {

@@ -221,8 +221,11 @@ class Problem:
         return y
 
     def spmv_dot(self, p, q=None, pq=None, fmt="bcrs13", events=None):
-        """q = A p and p.q (into the device scalar pq) by the fused CG kernel.
+        """q = A p and p.q (into the device scalar pq) by the fused CG kernel,
+        in FP64, or in FP32 (mfe_spmv_dot_f32) when p is a float32 tensor.
         events = (before, after) torch.cuda.Event pair recorded around the kernel."""
+        f32 = p.dtype == torch.float32
+        dt = torch.float32 if f32 else torch.float64
         if q is None:
             q = torch.empty_like(p)
         if pq is None:
@@ -233,10 +236,10 @@ class Problem:
                 if not e.cuda_event:
                     e.record(self.ctx.stream)
             ev = (ctypes.c_void_p(events[0].cuda_event), ctypes.c_void_p(events[1].cuda_event))
+        name = "mfe_spmv_dot_f32" if f32 else "mfe_spmv_dot"
         with _on(self.ctx):
-            check(self.ctx.lib.mfe_spmv_dot(self.handle, _fmt(fmt), _ptr(p, torch.float64, self.m, "p"),
-                                            _ptr(q, torch.float64, self.m, "q"), _ptr(pq, torch.float64, 1, "pq"),
-                                            ev[0], ev[1]), "mfe_spmv_dot")
+            check(getattr(self.ctx.lib, name)(self.handle, _fmt(fmt), _ptr(p, dt, self.m, "p"), _ptr(q, dt, self.m, "q"),
+                                              _ptr(pq, torch.float64, 1, "pq"), ev[0], ev[1]), name)
         return q, pq
 
     def cg(self, x=None, tol=1e-8, max_iter=200, fmt="bcrs13", history=False, raise_on_breakdown=True,

@@ -56,6 +56,29 @@ def test_spmv_f32(ctx, N, fmt):
 
 
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+@pytest.mark.parametrize("N", [(2, 3, 4), (33, 17, 9), (128, 128, 128)])
+def test_spmv_dot_f32(ctx, N, fmt):
+    """The fused FP32 product of the inner solves: q row by row as the FP32
+    SpMV bar, and p.q (FP64 accumulation) against the FP64 dot of the FP32
+    vectors within the rounding of the FP32 rows."""
+    from paper_1505_08023_amd.mfe import Problem
+    A = oracle.assemble(*N)
+    P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
+    x32 = inputs.spmv_vector(A.m, seed=5, dtype=np.float32)
+    a32 = A.val.astype(np.float32).astype(np.float64)
+    x64 = x32.astype(np.float64)
+    ref = np.add.reduceat(a32 * x64[A.col], A.ptr[:-1])
+    scale = np.add.reduceat(np.abs(a32) * np.abs(x64)[A.col], A.ptr[:-1])
+    q, pq = P.spmv_dot(torch.tensor(x32, device=ctx.device), fmt=fmt)
+    assert q.dtype == torch.float32
+    q = q.cpu().numpy().astype(np.float64)
+    assert np.all(np.abs(q - ref) <= 32 * EPS32 * scale + 1e-38)
+    dot_ref = float(x64 @ q)  # the GPU's own FP32 rows, dotted in FP64
+    assert abs(float(pq.cpu()) - dot_ref) <= 1e-12 * float(np.abs(x64) @ np.abs(q))
+    P.close()
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
 @pytest.mark.parametrize("N", [(20, 20, 20), (17, 9, 23)])
 def test_mixed_cg_matches_oracle(ctx, N, fmt):
     from paper_1505_08023_amd.mfe import Problem
