@@ -131,6 +131,22 @@ def test_batch_edge_cases(ctx):
     B.close()
 
 
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_batch_tiny_meshes(ctx, fmt):
+    """Meshes of 1 and 2 elements per axis next to a larger one: 64-row slices
+    of the 1x3 layout span several systems; each system still matches its own
+    oracle solve."""
+    from paper_1505_08023_amd.mfe import Batch
+    sizes = np.array([[1, 1, 1], [2, 1, 3], [1, 2, 1], [6, 5, 4], [2, 2, 2]], dtype=np.int32)
+    faces = np.random.default_rng(11).uniform(0, 1, (5, 6))
+    B = Batch(ctx, sizes, faces)
+    x, stats = B.cg(tol=1e-10, max_iter=500, fmt=fmt)
+    x = x.cpu().numpy()
+    for j, (N, fv) in enumerate(zip(sizes, faces)):
+        check_system(x, B.row_offsets, j, tuple(int(n) for n in N), fv, stats[j], 1e-10, its_tol=None)
+    B.close()
+
+
 def test_batch_full_config(ctx):
     """64 meshes with Nx, Ny, Nz ~ U{16..96} (seed 0), FP64 and mixed, to 1e-8."""
     from paper_1505_08023_amd.mfe import Batch
