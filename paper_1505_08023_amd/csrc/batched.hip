@@ -61,20 +61,8 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
         if (st[sys].status != kRunning) return;
     }
     const int64_t lo = M.wg_lo[w], hi = M.wg_hi[w];
-    constexpr int R = FMT == MFE_BCRS13 ? kBlock : kBlock / L;  // rows per pass
-    const int g = FMT == MFE_BCRS13 ? threadIdx.x : threadIdx.x / L;
-    const int sub = FMT == MFE_BCRS13 ? 0 : threadIdx.x % L;
     double d1 = 0.0, d2 = 0.0;
-    for (int64_t base = lo; base < hi; base += R) {
-        const int64_t row = base + g;
-        T sum;
-        if (FMT == MFE_BCRS13) {
-            if (row >= hi) continue;
-            sum = b13_row(slot_base, jas, bval, row, x);
-        } else {
-            sum = csr_row<T, L>(ptr, col, cval, row < hi ? row : -1, sub, x);
-            if (sub != 0 || row >= hi) continue;
-        }
+    auto emit = [&](int64_t row, T sum) {
         if (MODE == kSpmvDot) {
             y[row] = sum;
             d1 += (double)x[row] * (double)sum;
@@ -87,6 +75,44 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
         } else {  // kSpmvTrue
             const double r = b[row] - (double)sum;
             d1 += r * r;
+        }
+    };
+    if (FMT == MFE_BCRS13) {
+        // the 64-row slices overlapping [lo, hi) (system offsets are not
+        // slice aligned), one per wavefront per pass; rows outside [lo, hi)
+        // belong to the neighbouring workgroup.  The next pass's column
+        // indices are requested before this pass's values and gathers.
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+        const int64_t s_lo = lo >> 6, s_hi = (hi + 63) >> 6;
+        constexpr int SP = kBlock / 64;  // slices per pass
+        B13Idx cur, nxt;
+        auto fetch = [&](int64_t sb, B13Idx &r) {
+            const int64_t sl = sb + wave, row = sl * 64 + lane;
+            r.sl.S = 0;
+            if (sl >= s_hi) return;
+            r.sl = b13_slice(slot_base[sl], slot_base[sl + 1]);
+            if (row >= lo && row < hi) b13_load_idx(jas, lane, r);
+        };
+        if (s_lo < s_hi) fetch(s_lo, cur);
+        for (int64_t sb = s_lo; sb < s_hi; sb += SP) {
+            nxt.sl.S = 0;
+            if (sb + SP < s_hi) fetch(sb + SP, nxt);
+            const int64_t row = (sb + wave) * 64 + lane;
+            if (sb + wave < s_hi && row >= lo && row < hi) {
+                const T sum = cur.sl.S == 9 ? b13_row9_idx(cur.c, bval, cur.sl, lane, x)
+                                            : b13_row_generic(jas, bval, cur.sl, lane, x);
+                emit(row, sum);
+            }
+            cur = nxt;
+        }
+    } else {
+        constexpr int R = kBlock / L;  // rows per pass
+        const int g = threadIdx.x / L, sub = threadIdx.x % L;
+        for (int64_t base = lo; base < hi; base += R) {
+            const int64_t row = base + g;
+            const T sum = csr_row<T, L>(ptr, col, cval, row < hi ? row : -1, sub, x);
+            if (sub != 0 || row >= hi) continue;
+            emit(row, sum);
         }
     }
     d1 = block_sum(d1);
