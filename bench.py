@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # and WRITE_SIZE (x 1.0) counter runs, scaled by streaming kernels of known
 # size (profiles/spmv_b13_fp64_256cubed_hbm_counters.md).  Reset to None
 # whenever the kernel changes.
-MEASURED_TRAFFIC = {("bcrs13", 256): 4.588e9, ("csr", 256): None}
+MEASURED_TRAFFIC = {("bcrs13", 256): None, ("csr", 256): None}
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
 
 
@@ -35,13 +35,20 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def spmv_bytes(fmt, m, nnz, nb, fp=8):
+def spmv_bytes(fmt, m, nnz, nb, fp=8, layout=None):
     """Algorithmic bytes of one SpMV: matrix streamed once, x read once, y
     written once, int32 indices; for the fused dot p_i is the x entry already
-    read.  CRS: 12 nnz + 4 (m+1) + 16 m; 1x3 BCRS: 28 nb + 4 (m+1) + 16 m."""
+    read.  CRS: (fp + 4) nnz + 4 (m+1) + 2 fp m.  1x3 BCRS: 3 fp nb values,
+    4 bytes of column index per block outside the descriptor slices, 48 per
+    descriptor slice, 4 (slices + 1) of slice bounds, 2 fp m (layout: the
+    problem's b13_layout; None counts every slice as indexed)."""
     if fmt == "csr":
         return (fp + 4) * nnz + 4 * (m + 1) + 2 * fp * m
-    return (3 * fp + 4) * nb + 4 * (m + 1) + 2 * fp * m
+    slices = (m + 63) // 64
+    cs = cb = 0
+    if layout is not None:
+        slices, cs, cb = layout["slices"], layout["compressed_slices"], layout["compressed_blocks"]
+    return 3 * fp * nb + 4 * (nb - cb) + 48 * cs + 4 * (slices + 1) + 2 * fp * m
 
 
 def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30, warmup=5, f32=False):
@@ -140,7 +147,7 @@ def main():
     spmv = {}
     for fmt in ("bcrs13", "csr"):
         mean_ms, min_ms = time_spmv_dot(P, fmt, args.spmv_reps, torch)
-        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks)
+        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, layout=P.b13_layout)
         spmv[fmt] = dict(mean_ms=mean_ms, median_ms=time_spmv_dot.median_ms, min_ms=min_ms, launches=args.spmv_reps,
                          bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
                          frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -148,7 +155,7 @@ def main():
     # the FP32 product of the mixed-precision inner solves
     for fmt in ("bcrs13", "csr"):
         mean_ms, min_ms = time_spmv_dot(P, fmt, args.spmv_reps, torch, f32=True)
-        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, fp=4)
+        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, fp=4, layout=P.b13_layout)
         spmv[fmt + "_f32"] = dict(mean_ms=mean_ms, median_ms=time_spmv_dot.median_ms, min_ms=min_ms,
                                   launches=args.spmv_reps, bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
                                   frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -304,11 +311,14 @@ def extras(args, ctx, P, x, line, torch):
                          worst_rel_res_true=max(s["rel_res_true"] for s in st),
                          all_converged=all(s["status"] == 0 for s in st))
         if name == "fp64":
-            # algorithmic bytes: each system's iterations x (1x3 BCRS SpMV + 64 m)
+            # algorithmic bytes: each system's iterations x (its rows' share of
+            # the batch's 1x3 BCRS SpMV bytes + 64 m)
+            dims = [((nx + 1) * (ny + 1) * (nz + 1), (nx + 1) * (3 * ny + 1) * (3 * nz + 1))
+                    for nx, ny, nz in sizes.tolist()]
+            full = spmv_bytes("bcrs13", B.m, 0, sum(nbs for _, nbs in dims), layout=B.b13_layout)
             tot = 0
-            for (nx, ny, nz), k in zip(sizes.tolist(), its):
-                ms, nbs = (nx + 1) * (ny + 1) * (nz + 1), (nx + 1) * (3 * ny + 1) * (3 * nz + 1)
-                tot += k * (spmv_bytes("bcrs13", ms, 0, nbs) + 64 * ms)
+            for (ms, _), k in zip(dims, its):
+                tot += k * (full * ms / B.m + 64 * ms)
             bat[name]["algorithmic_bytes"] = tot
             bat[name]["effective_GBps"] = tot / dt / 1e9
         log(f"[bench] batched {name}: {bat[name]}")
@@ -360,7 +370,7 @@ def extras(args, ctx, P, x, line, torch):
             dt = time.perf_counter() - t
             best = dt if best is None else min(best, dt)
         assert st["iterations"] == 200
-        it_bytes = spmv_bytes(fmt, P2.m, P2.nnz, P2.nblocks) + 64 * P2.m
+        it_bytes = spmv_bytes(fmt, P2.m, P2.nnz, P2.nblocks, layout=P2.b13_layout) + 64 * P2.m
         c2[fmt] = dict(it_per_s=200 / best, seconds=best, effective_GBps=200 * it_bytes / best / 1e9)
         log(f"[bench] 128^3 CG x200 {fmt}: {c2[fmt]}")
     line["cg_128cubed_200_iterations"] = c2

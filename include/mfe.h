@@ -54,7 +54,8 @@ extern "C" {
 
 /* matrix formats (bit flags) */
 #define MFE_CSR 1      /* compressed row storage, Sec. 3.1 */
-#define MFE_BCRS13 2   /* fixed 1x3 blocks, zero padded, 64-row slice-major layout */
+#define MFE_BCRS13 2   /* fixed 1x3 blocks, zero padded, 64-row slice-major layout
+                          (see mfe_problem_bcrs13_layout) */
 
 /* precisions (bit flags) */
 #define MFE_F64 1
@@ -124,6 +125,16 @@ int mfe_problem_set_bc(mfe_problem *p, const double *face_vals, const double *no
 /* Sizes: rows, stored entries, 1x3 blocks (0 when BCRS13 was not built).
  * Any output pointer may be NULL. */
 int mfe_problem_info(const mfe_problem *p, int64_t *m, int64_t *nnz, int64_t *nblocks);
+
+/* Storage of the 1x3 BCRS (all zero when it was not built): 64-row slices;
+ * slot rows (slice s stores 64 x its slot count blocks, padding included);
+ * slices whose column indices the SpMV forms from a 48-byte per-slice
+ * descriptor instead of reading them (slices of 64 rows x 9 blocks in which
+ * the first column of block k of row i is i + e_i + d_k, e_i in {0, 1}: the
+ * interior of a box mesh), and the real blocks of those slices.  The
+ * indices of every slice stay stored.  Any output pointer may be NULL. */
+int mfe_problem_bcrs13_layout(const mfe_problem *p, int64_t *slices, int64_t *slots, int64_t *compressed_slices,
+                              int64_t *compressed_blocks);
 
 /* Copy the FP64 CRS matrix and b into caller device buffers
  * (ptr_dev[m+1], col_dev[nnz], val_dev[nnz], b_dev[m]; any may be NULL). */
@@ -268,6 +279,10 @@ int mfe_batch_info(const mfe_batch *b, int64_t *m_total, int64_t *nnz_total, int
  * system, boundary entries used) if non-NULL, else face_vals (host
  * double[6*nsys]) if non-NULL, else the paper's values. */
 int mfe_batch_set_bc(mfe_batch *b, const double *face_vals, const double *node_g_dev);
+/* 1x3 BCRS storage of the block-diagonal matrix (as mfe_problem_bcrs13_layout;
+ * slices are those of the concatenated rows, so a slice may span two systems). */
+int mfe_batch_bcrs13_layout(const mfe_batch *b, int64_t *slices, int64_t *slots, int64_t *compressed_slices,
+                            int64_t *compressed_blocks);
 /* FP64 CRS of the block-diagonal matrix and b (device buffers, as mfe_problem_export_csr). */
 int mfe_batch_export_csr(const mfe_batch *b, int32_t *ptr_dev, int32_t *col_dev, double *val_dev, double *b_dev);
 /* Times the batched SpMV for each candidate launch shape (CRS lanes per row

@@ -87,7 +87,7 @@ void free_problem_storage(mfe_problem *P) {
     mfe_ctx *ctx = P->ctx;
     release_graphs(P);
     Buffer *bufs[] = {&P->ptr, &P->col, &P->val64, &P->val32, &P->b, &P->slot_base, &P->jas, &P->bval64,
-                      &P->bval32, &P->rowblocks, &P->r, &P->p, &P->q, &P->state, &P->partials,
+                      &P->bval32, &P->rowblocks, &P->bdesc, &P->r, &P->p, &P->q, &P->state, &P->partials,
                       &P->r32, &P->p32, &P->q32, &P->d32, &P->ax, &P->s, &P->dinv};
     for (Buffer *b : bufs) dev_free(ctx, b);
 }
@@ -122,7 +122,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 2; }
+int mfe_version(void) { return 3; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -341,6 +341,21 @@ int mfe_problem_info(const mfe_problem *p, int64_t *m, int64_t *nnz, int64_t *nb
     if (m) *m = p->m;
     if (nnz) *nnz = p->nnz;
     if (nblocks) *nblocks = (p->formats & MFE_BCRS13) ? p->nblocks : 0;
+    return MFE_OK;
+}
+
+int mfe_problem_bcrs13_layout(const mfe_problem *p, int64_t *slices, int64_t *slots, int64_t *compressed_slices,
+                              int64_t *compressed_blocks) {
+    clear_error();
+    if (!p) {
+        set_error("problem is NULL");
+        return MFE_EINVAL;
+    }
+    const bool built = (p->formats & MFE_BCRS13) != 0;
+    if (slices) *slices = built ? (p->m + 63) / 64 : 0;
+    if (slots) *slots = built ? p->nslots : 0;
+    if (compressed_slices) *compressed_slices = built ? p->b13_cslices : 0;
+    if (compressed_blocks) *compressed_blocks = built ? p->b13_cblocks : 0;
     return MFE_OK;
 }
 

@@ -47,3 +47,23 @@ __host__ __device__ __forceinline__ int64_t b13_val(const B13Slice &sl, int k, i
 }
 
 }  // namespace mfe
+
+namespace mfe {
+
+// Column-index compression of a 9-slot slice.  When every block column of
+// the slice has the form
+//     jas(slot k, lane l) = 64 s + l + e_l + d[k],   e_l in {0, 1},
+// (a structured-mesh slice: one offset per slot, one 0/1 shift per row, the
+// shift being 1 for rows whose first stored column is the row itself) the
+// SpMV forms the columns from this descriptor and does not read the slice's
+// 576 column indices; the indices stay stored (export, other slices).  The
+// reconstruction is exact, so results do not depend on which path a slice
+// takes.  uniform = 0: read the indices.
+struct B13Desc {
+    int32_t d[9];
+    uint32_t e_lo, e_hi;  // e_l of lanes 0..31 and 32..63
+    int32_t uniform;
+};
+static_assert(sizeof(B13Desc) == 48, "B13Desc is 48 bytes");
+
+}  // namespace mfe

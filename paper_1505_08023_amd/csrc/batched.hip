@@ -50,7 +50,8 @@ __device__ __forceinline__ double sys_sum(const double *__restrict__ part, const
 template <typename T, int FMT, int L, int MODE>
 __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                                   const T *__restrict__ cval, const int32_t *__restrict__ slot_base,
-                                                  const int32_t *__restrict__ jas, const T *__restrict__ bval,
+                                                  const int32_t *__restrict__ jas,
+                                                  const B13Desc *__restrict__ desc, const T *__restrict__ bval,
                                                   const T *__restrict__ x, T *__restrict__ y, T *__restrict__ pout,
                                                   const double *__restrict__ b, CgState *st, Map M,
                                                   double *__restrict__ part, int nwg) {
@@ -91,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
             r.sl.S = 0;
             if (sl >= s_hi) return;
             r.sl = b13_slice(slot_base[sl], slot_base[sl + 1]);
-            if (row >= lo && row < hi) b13_load_idx(jas, lane, r);
+            if (row >= lo && row < hi) b13_cols(jas, desc, sl, lane, r);
         };
         if (s_lo < s_hi) fetch(s_lo, cur);
         for (int64_t sb = s_lo; sb < s_hi; sb += SP) {
@@ -379,7 +380,8 @@ void launch_b(const mfe_batch *B, const T *x, T *y, T *pout, const double *b, Cg
     const T *bval = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
     hipLaunchKernelGGL((k_bspmv<T, FMT, L, MODE>), dim3(B->nwg), dim3(kBlock), 0, s, (const int32_t *)P->ptr.ptr,
                        (const int32_t *)P->col.ptr, cval, (const int32_t *)P->slot_base.ptr,
-                       (const int32_t *)P->jas.ptr, bval, x, y, pout, b, st, map_of(B), part, B->nwg);
+                       (const int32_t *)P->jas.ptr, (const B13Desc *)P->bdesc.ptr, bval, x, y, pout, b, st,
+                       map_of(B), part, B->nwg);
 }
 
 template <typename T, int MODE>
@@ -702,6 +704,16 @@ int mfe_batch_info(const mfe_batch *B, int64_t *m_total, int64_t *nnz_total, int
     if (row_offsets)
         for (int j = 0; j <= B->nsys; ++j) row_offsets[j] = B->row0[j];
     return MFE_OK;
+}
+
+int mfe_batch_bcrs13_layout(const mfe_batch *B, int64_t *slices, int64_t *slots, int64_t *compressed_slices,
+                            int64_t *compressed_blocks) {
+    clear_error();
+    if (!B) {
+        set_error("batch is NULL");
+        return MFE_EINVAL;
+    }
+    return mfe_problem_bcrs13_layout(B->P, slices, slots, compressed_slices, compressed_blocks);
 }
 
 int mfe_batch_export_csr(const mfe_batch *B, int32_t *ptr_dev, int32_t *col_dev, double *val_dev, double *b_dev) {

@@ -136,11 +136,13 @@ struct mfe_problem {
     bool is_mesh = false;
     int Nx = 0, Ny = 0, Nz = 0;
     int64_t m = 0, nnz = 0, nblocks = 0, nslots = 0;
+    int64_t b13_cslices = 0, b13_cblocks = 0;  // slices with compressed column indices, their real blocks
     int formats = 0, precisions = 0;
     // CRS (always FP64; FP32 values when MFE_F32)
     mfe::Buffer ptr, col, val64, val32, b;
     // 1x3 BCRS
     mfe::Buffer slot_base, jas, bval64, bval32, rowblocks;
+    mfe::Buffer bdesc;  // B13Desc per slice
     // CG workspace (allocated on first solve)
     mfe::Buffer r, p, q, state, partials;
     mfe::Buffer r32, p32, q32, d32, ax;  // mixed precision workspace

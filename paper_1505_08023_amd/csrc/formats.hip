@@ -211,6 +211,68 @@ __global__ __launch_bounds__(64) void k_b13_fill(int64_t m, const int32_t *__res
     }
 }
 
+// Slice descriptors (B13Desc): one 64-thread workgroup per slice.  Only
+// full 9-slot slices are candidates.  d[0] is the smallest offset of slot 0
+// over the lanes, e_l a lane's excess over it; the slice is uniform when
+// every e_l is 0 or 1 and, for each slot, column - row - e_l is one value
+// over the lanes.  cnt[s] receives the slice's real blocks when uniform
+// (else 0) and flag[s] whether it is.
+__device__ __forceinline__ int32_t wave_min_i(int32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = min(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int32_t wave_max_i(int32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = max(v, __shfl_xor(v, off, 64));
+    return v;
+}
+__device__ __forceinline__ int32_t wave_sum_i(int32_t v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ __launch_bounds__(64) void k_b13_desc(int64_t m, const int32_t *__restrict__ slot_base,
+                                                 const int32_t *__restrict__ jas,
+                                                 const int32_t *__restrict__ rowblocks, B13Desc *__restrict__ desc,
+                                                 int32_t *__restrict__ cnt, int32_t *__restrict__ flag) {
+    const int64_t s = blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const B13Slice sl = b13_slice(slot_base[s], slot_base[s + 1]);
+    B13Desc D{};
+    int uniform = 0, blocks = 0;
+    if (sl.S == 9 && s * 64 + 64 <= m) {  // wavefront-uniform condition
+        const int64_t row = s * 64 + lane;
+        int32_t c[9];
+#pragma unroll
+        for (int k = 0; k < 9; ++k) c[k] = jas[b13_jas(sl, k, lane)];
+        const int32_t d0 = (int32_t)(c[0] - row);  // |column - row| < m < 2^31
+        const int32_t base = wave_min_i(d0);
+        const int32_t e = d0 - base;
+        bool ok = e == 0 || e == 1;
+        D.d[0] = base;
+#pragma unroll
+        for (int k = 1; k < 9; ++k) {
+            const int32_t t = (int32_t)(c[k] - row) - e;
+            const int32_t lo = wave_min_i(t), hi = wave_max_i(t);
+            ok = ok && lo == hi;
+            D.d[k] = lo;
+        }
+        uniform = __all(ok) ? 1 : 0;
+        const uint64_t bits = __ballot(e == 1);
+        D.e_lo = (uint32_t)bits;
+        D.e_hi = (uint32_t)(bits >> 32);
+        D.uniform = uniform;
+        blocks = wave_sum_i(rowblocks[row]);
+    }
+    if (lane == 0) {
+        desc[s] = D;
+        cnt[s] = uniform ? blocks : 0;
+        flag[s] = uniform;
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t n, const double *__restrict__ in,
                                                      float *__restrict__ out) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
@@ -343,6 +405,22 @@ int build_bcrs13(mfe_problem *P) {
     MFE_HIP_TRY(hipMemcpyAsync(&nb, (int64_t *)total.ptr + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     P->nblocks = nb;
+    // slice descriptors; slice_n is reused for the per-slice flags
+    MFE_TRY(dev_alloc(ctx, &P->bdesc, (size_t)nslices * sizeof(B13Desc)));
+    Buffer cnt;
+    MFE_TRY(dev_alloc(ctx, &cnt, (size_t)nslices * sizeof(int32_t)));
+    hipLaunchKernelGGL(k_b13_desc, dim3(grid), dim3(64), 0, s, m, (const int32_t *)P->slot_base.ptr,
+                       (const int32_t *)P->jas.ptr, (const int32_t *)P->rowblocks.ptr, (B13Desc *)P->bdesc.ptr,
+                       (int32_t *)cnt.ptr, (int32_t *)slice_n.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    MFE_TRY(scan_counts(ctx, s, nslices, (const int32_t *)slice_n.ptr, nullptr, (int64_t *)total.ptr));
+    MFE_TRY(scan_counts(ctx, s, nslices, (const int32_t *)cnt.ptr, nullptr, (int64_t *)total.ptr + 1));
+    int64_t counts[2] = {0, 0};
+    MFE_HIP_TRY(hipMemcpyAsync(counts, total.ptr, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    P->b13_cslices = counts[0];
+    P->b13_cblocks = counts[1];
+    dev_free(ctx, &cnt);
     dev_free(ctx, &slice_n);
     dev_free(ctx, &total);
     return MFE_OK;

@@ -35,6 +35,14 @@
 #ifndef MFE_SPMV_WG_PER_CU
 #define MFE_SPMV_WG_PER_CU 0  // resident workgroups per CU (0: as many as fit)
 #endif
+#ifndef MFE_B13_WAVES_PER_EU
+#define MFE_B13_WAVES_PER_EU 0  // minimum wavefronts per SIMD the 1x3 BCRS kernels are built for (0: compiler's choice)
+#endif
+#if MFE_B13_WAVES_PER_EU > 0
+#define MFE_B13_OCCUPANCY __attribute__((amdgpu_waves_per_eu(MFE_B13_WAVES_PER_EU, 8)))
+#else
+#define MFE_B13_OCCUPANCY
+#endif
 
 namespace mfe {
 namespace {
@@ -195,31 +203,36 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
 // One slice per wavefront per tile: slice bounds, column indices, values,
 // gathers, in that dependent order.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
+__global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
                                                      const int32_t *__restrict__ jas,
+                                                     const B13Desc *__restrict__ desc,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
                                                      double *partials) {
     if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double d1 = 0.0, d2 = 0.0;
     for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
-        const int64_t row = tr.t * kBlock + threadIdx.x;
+        const int64_t s = (int64_t)tr.t * (kBlock / 64) + wave;
+        const int64_t row = s * 64 + lane;
         if (row >= m) continue;
-        const T sum = b13_row(slot_base, jas, val, row, E.x);
+        const T sum = b13_row(slot_base, jas, desc, val, s, lane, E.x);
         finish_row<T, MODE>(E, row, sum, d1, d2);
     }
     store_partials<MODE>(d1, d2, partials);
 }
 
 // Software-pipelined walk for grids whose workgroups take several tiles: a
-// wavefront owns slice 4t + w of tile t.  The slice bounds come from scalar
-// loads (the slice index is wavefront-uniform) and the next tile's column
-// indices are requested before the current tile's values and gathers, so the
-// index -> gather dependency of one tile overlaps the streaming of the
-// previous one.  Arithmetic and summation order are those of k_spmv_b13.
+// wavefront owns slice 4t + w of tile t.  The slice bounds and descriptor
+// come from scalar loads (the slice index is wavefront-uniform) and the next
+// tile's column indices are formed or requested before the current tile's
+// values and gathers, so the index -> gather dependency of one tile overlaps
+// the streaming of the previous one.  Arithmetic and summation order are
+// those of k_spmv_b13.
 template <typename T, int MODE>
-__global__ __launch_bounds__(kBlock) void k_spmv_b13p(int64_t m, const int32_t *__restrict__ slot_base,
+__global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t m, const int32_t *__restrict__ slot_base,
                                                       const int32_t *__restrict__ jas,
+                                                      const B13Desc *__restrict__ desc,
                                                       const T *__restrict__ val, Epi<T> E, CgState *st,
                                                       double *partials) {
     if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
@@ -234,7 +247,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_b13p(int64_t m, const int32_t *
         r.sl.S = 0;
         if (s * 64 >= m) return;
         r.sl = b13_slice(slot_base[s], slot_base[s + 1]);
-        if (row < m) b13_load_idx(jas, lane, r);
+        if (row < m) b13_cols(jas, desc, s, lane, r);
     };
     if (tr.t < tr.end) fetch(tr.t, cur);
     for (; tr.t < tr.end; tr.t += tr.step) {
@@ -294,7 +307,7 @@ int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *parti
         grid = grid_for(kern, ntiles, P->ctx->num_cu);
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
-                       (const int32_t *)P->jas.ptr, val, E, st, partials);
+                       (const int32_t *)P->jas.ptr, (const B13Desc *)P->bdesc.ptr, val, E, st, partials);
     MFE_HIP_TRY(hipGetLastError());
     if (grid_out) *grid_out = grid;
     return MFE_OK;

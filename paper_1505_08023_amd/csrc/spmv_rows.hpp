@@ -42,35 +42,6 @@ __device__ __forceinline__ T b13_row_generic(const int32_t *jas, const T *val, c
     return sum;
 }
 
-// Slices of 9 blocks per row (3 y-lines x 3 z-planes: every row not on a
-// y or z face): 3 column-index loads and 14 value loads per row, then 27
-// gathers of x, the three of a block at consecutive columns.
-template <typename T>
-__device__ __forceinline__ T b13_row9(const int32_t *jas, const T *val, const B13Slice &sl, int lane,
-                                      const T *x) {
-    const int4_t q0 = matrix_load((const int4_t *)(jas + sl.jbase + lane * 4));
-    const int4_t q1 = matrix_load((const int4_t *)(jas + sl.jbase + 256 + lane * 4));
-    const int32_t c8 = matrix_load(jas + sl.jbase + 512 + lane);
-    const int32_t c[9] = {q0.x, q0.y, q0.z, q0.w, q1.x, q1.y, q1.z, q1.w, c8};
-    vec2_t<T> a[9], b[4];
-#pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = matrix_load((const vec2_t<T> *)(val + sl.vbase + k * 128 + lane * 2));
-#pragma unroll
-    for (int p = 0; p < 4; ++p)
-        b[p] = matrix_load((const vec2_t<T> *)(val + sl.vbase + 9 * 128 + p * 128 + lane * 2));
-    const T w8 = matrix_load(val + sl.vbase + 13 * 128 + lane);
-    const T v2[9] = {b[0].x, b[0].y, b[1].x, b[1].y, b[2].x, b[2].y, b[3].x, b[3].y, w8};
-    T sum = 0;
-#pragma unroll
-    for (int k = 0; k < 9; ++k) {
-        const T *xp = x + c[k];
-        sum += a[k].x * xp[0];
-        sum += a[k].y * xp[1];
-        sum += v2[k] * xp[2];
-    }
-    return sum;
-}
-
 // Column indices of one row of a 9-slot slice, loaded ahead of its values so
 // that the next row's index loads overlap the current row's gathers.
 struct B13Idx {
@@ -85,6 +56,23 @@ __device__ __forceinline__ void b13_load_idx(const int32_t *__restrict__ jas, in
     r.c[0] = q0.x, r.c[1] = q0.y, r.c[2] = q0.z, r.c[3] = q0.w;
     r.c[4] = q1.x, r.c[5] = q1.y, r.c[6] = q1.z, r.c[7] = q1.w;
     r.c[8] = matrix_load(jas + r.sl.jbase + 512 + lane);
+}
+
+// Column indices of one row of slice s (r.sl already set): formed from the
+// slice descriptor when the slice is uniform, else loaded.  s must be
+// wavefront-uniform (the descriptor is read with scalar loads).
+__device__ __forceinline__ void b13_cols(const int32_t *__restrict__ jas, const B13Desc *__restrict__ desc,
+                                         int64_t s, int lane, B13Idx &r) {
+    if (r.sl.S != 9) return;
+    const B13Desc &D = desc[s];
+    if (D.uniform) {
+        const uint32_t bits = lane < 32 ? D.e_lo : D.e_hi;
+        const int32_t base = (int32_t)(s * 64 + lane) + (int32_t)((bits >> (lane & 31)) & 1u);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) r.c[k] = base + D.d[k];
+    } else {
+        b13_load_idx(jas, lane, r);
+    }
 }
 
 // Values and gathers of a 9-slot row whose indices are already loaded.
@@ -110,14 +98,15 @@ __device__ __forceinline__ T b13_row9_idx(const int32_t *c, const T *val, const 
     return sum;
 }
 
-// 1x3 BCRS row `row` (one lane per row).
+// 1x3 BCRS row 64 s + lane (one lane per row; s wavefront-uniform).
 template <typename T>
 __device__ __forceinline__ T b13_row(const int32_t *__restrict__ slot_base, const int32_t *__restrict__ jas,
-                                     const T *__restrict__ val, int64_t row, const T *__restrict__ x) {
-    const int64_t s = row >> 6;
-    const int lane = (int)(row & 63);
-    const B13Slice sl = b13_slice(slot_base[s], slot_base[s + 1]);
-    return sl.S == 9 ? b13_row9(jas, val, sl, lane, x) : b13_row_generic(jas, val, sl, lane, x);
+                                     const B13Desc *__restrict__ desc, const T *__restrict__ val, int64_t s,
+                                     int lane, const T *__restrict__ x) {
+    B13Idx r;
+    r.sl = b13_slice(slot_base[s], slot_base[s + 1]);
+    b13_cols(jas, desc, s, lane, r);
+    return r.sl.S == 9 ? b13_row9_idx(r.c, val, r.sl, lane, x) : b13_row_generic(jas, val, r.sl, lane, x);
 }
 
 }  // namespace mfe

@@ -136,6 +136,12 @@ class Problem:
         check(ctx.lib.mfe_problem_info(handle, ctypes.byref(m), ctypes.byref(nnz), ctypes.byref(nb)),
               "mfe_problem_info")
         self.m, self.nnz, self.nblocks = m.value, nnz.value, nb.value
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(ctx.lib.mfe_problem_bcrs13_layout(handle, *[ctypes.byref(t) for t in v]), "mfe_problem_bcrs13_layout")
+        # 1x3 BCRS storage: slices, slot rows, slices with descriptor-formed
+        # column indices and their real blocks (zeros without 1x3 BCRS)
+        self.b13_layout = dict(zip(("slices", "slots", "compressed_slices", "compressed_blocks"),
+                                   (t.value for t in v)))
         ctx.problems.add(self)
         _LIVE.add(self)
 
@@ -337,6 +343,10 @@ class Batch:
         check(ctx.lib.mfe_batch_info(h, ctypes.byref(m), ctypes.byref(nnz), offs.ctypes.data_as(ctypes.c_void_p)),
               "mfe_batch_info")
         self.m, self.nnz, self.row_offsets = m.value, nnz.value, offs
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(ctx.lib.mfe_batch_bcrs13_layout(h, *[ctypes.byref(t) for t in v]), "mfe_batch_bcrs13_layout")
+        self.b13_layout = dict(zip(("slices", "slots", "compressed_slices", "compressed_blocks"),
+                                   (t.value for t in v)))
         ctx.problems.add(self)
         _LIVE.add(self)
 

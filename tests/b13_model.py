@@ -1,0 +1,51 @@
+"""Host models of the 1x3 BCRS slice descriptors (test helpers).
+
+The library forms the column indices of a 64-row slice from a descriptor
+when, for every block slot k and row i of the slice, the first column of the
+block is i + e_i + d_k with e_i in {0, 1}.  Two independent counts of such
+slices are kept here: a direct model over the oracle's 1x3 blocking, and a
+closed form for the box mesh.
+"""
+import numpy as np
+
+
+def descriptor_slices(bptr, bcol, m):
+    """Direct model from the oracle's blocking: a full slice whose longest row
+    has 9 blocks (shorter rows padded with their last block's column, as the
+    library pads them) in which column(k, row i) - i - e_i is one value per
+    slot k.  Returns (slices, their real blocks)."""
+    nblk = np.diff(bptr)
+    count = blocks = 0
+    for s in range(m // 64):
+        rows = np.arange(64 * s, 64 * s + 64)
+        if nblk[rows].max() != 9:
+            continue
+        c = np.zeros((64, 9), dtype=np.int64)
+        for l, i in enumerate(rows):
+            own = bcol[bptr[i]:bptr[i + 1]]
+            c[l, :len(own)] = own
+            c[l, len(own):] = own[-1] if len(own) else 0
+        d = c - rows[:, None]
+        e = d[:, 0] - d[:, 0].min()
+        if np.all((e == 0) | (e == 1)) and np.all(d - e[:, None] == (d - e[:, None])[0]):
+            count += 1
+            blocks += int(nblk[rows].sum())
+    return count, blocks
+
+
+def descriptor_slices_closed_form(Nx, Ny, Nz):
+    """Box mesh: a row i with 1 <= iy <= Ny-1 and 1 <= iz <= Nz-1 has the
+    full 9 blocks, block (dy, dz) starting at i - 1 + dy (Nx+1) + dz (Nx+1)(Ny+1)
+    (one column later when ix = 0: shift e = 1).  In plane iz these rows are
+    one contiguous range, and every full slice inside it qualifies except
+    one ending at the last interior row of the mesh, whose top block is
+    moved back by the end-of-matrix rule (a block starts at m - 3 at the
+    latest)."""
+    nx, nxny = Nx + 1, (Nx + 1) * (Ny + 1)
+    count = 0
+    for iz in range(1, Nz):
+        lo, hi = iz * nxny + nx, iz * nxny + Ny * nx
+        if iz == Nz - 1:
+            hi -= 1
+        count += max(0, hi // 64 - (lo + 63) // 64)
+    return count

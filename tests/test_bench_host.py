@@ -3,6 +3,7 @@ structure the oracle builds (nnz, 1x3 blocks) and the closed forms."""
 import numpy as np
 import pytest
 
+import b13_model
 import bench
 import oracle
 
@@ -11,7 +12,14 @@ def test_spmv_bytes_at_256_cubed():
     # closed forms at 256^3: m = 257^3, nnz = (3*257-2)^3, nb = 257 (3*257-2)^2
     m, nnz, nb = 257 ** 3, 769 ** 3, 257 * 769 ** 2
     assert bench.spmv_bytes("csr", m, nnz, nb) == 5_796_571_172
-    assert bench.spmv_bytes("bcrs13", m, nnz, nb) == 4_594_925_620
+    slices = (m + 63) // 64
+    assert bench.spmv_bytes("bcrs13", m, nnz, nb) == 28 * nb + 4 * (slices + 1) + 16 * m
+    cs = b13_model.descriptor_slices_closed_form(256, 256, 256)
+    assert cs == 260_865
+    lay = dict(slices=slices, compressed_slices=cs, compressed_blocks=576 * cs)
+    # the descriptor slices drop 576 x 4 index bytes for 48 descriptor bytes each
+    assert bench.spmv_bytes("bcrs13", m, nnz, nb, layout=lay) == 24 * nb + 4 * (nb - 576 * cs) + 48 * cs \
+        + 4 * (slices + 1) + 16 * m == 3_939_576_724
     assert oracle.num_rows(256, 256, 256) == m and oracle.count_nnz(256, 256, 256) == nnz
 
 
@@ -20,11 +28,26 @@ def test_block_count_matches_oracle_conversion(N):
     """The 1x3 block count used in the byte formula is the number of blocks
     the oracle's greedy conversion produces: n_x (3 n_y - 2)(3 n_z - 2)."""
     A = oracle.assemble(*N)
-    bptr, bcol, bval = oracle.bcrs13(A)
+    bptr, _, _ = oracle.bcrs13(A)
     nx, ny, nz = (n + 1 for n in N)
     assert bptr[-1] == nx * (3 * ny - 2) * (3 * nz - 2)
-    by = bench.spmv_bytes("bcrs13", A.m, A.nnz, int(bptr[-1]))
-    assert by == 28 * int(bptr[-1]) + 4 * (A.m + 1) + 16 * A.m
+
+
+def test_descriptor_slice_closed_form_matches_blocking():
+    """The closed-form count of descriptor slices (used for the 256^3 byte
+    count and its GPU check) against the direct model over the oracle's 1x3
+    blocking, on meshes with every alignment of lines and planes to the
+    64-row slices (including one where a slice ends on the last interior
+    row)."""
+    rng = np.random.default_rng(1)
+    meshes = [(63, 5, 5), (20, 20, 20), (33, 33, 33), (40, 9, 6), (1, 30, 30), (2, 25, 25), (64, 4, 9),
+              (7, 40, 3), (127, 3, 3)] + [tuple(int(v) for v in rng.integers(1, 40, 3)) for _ in range(20)]
+    for N in meshes:
+        A = oracle.assemble(*N)
+        bptr, bcol, _ = oracle.bcrs13(A)
+        count, blocks = b13_model.descriptor_slices(bptr, bcol, A.m)
+        assert count == b13_model.descriptor_slices_closed_form(*N), N
+        assert blocks == 576 * count
 
 
 def test_multi_gpu_request_is_refused(monkeypatch, capsys):

@@ -28,6 +28,7 @@ import numpy as np
 import pytest
 import torch
 
+import b13_model
 import oracle
 from paper_1505_08023_amd import inputs
 
@@ -101,6 +102,25 @@ def test_bcrs13_matches_oracle(ctx, N):
     P.close()
 
 
+@pytest.mark.parametrize("N", [(2, 3, 4), (5, 3, 7), (20, 20, 20), (33, 33, 33), (40, 9, 6)])
+def test_bcrs13_descriptor_slices(ctx, N):
+    """The per-slice descriptors cover exactly the slices the host model
+    finds (index work: bit-exact counts), and the products through them
+    match the oracle."""
+    A = oracle.assemble(*N)
+    bptr, bcol, _ = oracle.bcrs13(A)
+    want = b13_model.descriptor_slices(bptr, bcol, A.m)
+    P = mesh_problem(ctx, N)
+    lay = P.b13_layout
+    assert lay["slices"] == (A.m + 63) // 64
+    assert (lay["compressed_slices"], lay["compressed_blocks"]) == want, (lay, want)
+    if min(N) >= 20:
+        assert lay["compressed_slices"] >= 0.5 * lay["slices"]
+    x = inputs.spmv_vector(A.m, seed=3)
+    check_spmv(np_(P.spmv(torch.tensor(x, device=ctx.device), fmt="bcrs13")), A, x, oracle.csr_spmv(A, x))
+    P.close()
+
+
 def test_set_bc_matches_fresh_assembly(ctx):
     N = (9, 7, 8)
     fv = np.random.default_rng(5).uniform(0, 1, 6)
@@ -148,6 +168,9 @@ def test_spmv_full_size_sampled_rows(ctx, fmt):
     N = (256, 256, 256)
     P = mesh_problem(ctx, N, formats=(fmt,))
     m = P.m
+    if fmt == "bcrs13":
+        assert P.b13_layout["compressed_slices"] == b13_model.descriptor_slices_closed_form(*N)
+        assert P.b13_layout["compressed_blocks"] == 576 * P.b13_layout["compressed_slices"]
     x = inputs.spmv_vector(m, seed=0)
     y = np_(P.spmv(torch.tensor(x, device=ctx.device), fmt=fmt))
     rng = np.random.default_rng(7)
