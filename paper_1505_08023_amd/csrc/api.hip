@@ -43,6 +43,12 @@ void dev_free(mfe_ctx *ctx, Buffer *b) {
     b->bytes = 0;
 }
 
+TempBuffer::~TempBuffer() {
+    if (!b.ptr) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    dev_free(ctx, &b);
+}
+
 int resident_per_cu(const void *kernel) {
     static std::mutex mu;
     static std::unordered_map<const void *, int> cache;

@@ -45,6 +45,22 @@ constexpr int64_t kMallBytes = 256ll << 20;  // memory-side (Infinity) cache of 
 // touches exceed the memory-side cache.
 inline bool vectors_stream_nt(int64_t m) { return 40 * m > kMallBytes; }
 
+// Load a stored matrix (values and indices, `bytes` in all) non-temporally
+// when it is larger than MFE_MATRIX_NT_MIN_BYTES; a smaller one is loaded
+// normally and largely stays in the memory-side cache between products.
+// The default is the measured crossover on MI355X: cached loads were faster
+// up to a 296 MB matrix (up to 20 % per CG iteration), non-temporal ones
+// from 364 MB on.
+#ifndef MFE_MATRIX_NT
+#define MFE_MATRIX_NT 1  // non-temporal loads for matrices above MFE_MATRIX_NT_MIN_BYTES (0: never)
+#endif
+#ifndef MFE_MATRIX_NT_MIN_BYTES
+#define MFE_MATRIX_NT_MIN_BYTES (320ll << 20)
+#endif
+inline bool matrix_stream_nt(int64_t bytes) {
+    return MFE_MATRIX_NT != 0 && bytes > (int64_t)(MFE_MATRIX_NT_MIN_BYTES);
+}
+
 // ------------------------------------------------------------------ device solver state
 
 enum CgStatus : int { kRunning = 0, kConverged = 1, kCapped = 2, kBreakdown = -4 };
@@ -126,6 +142,20 @@ namespace mfe {
 
 int dev_alloc(mfe_ctx *ctx, Buffer *b, size_t bytes);
 void dev_free(mfe_ctx *ctx, Buffer *b);
+
+// Scratch device memory owned by one host function and released when it
+// returns, on every path.  The context's stream is synchronised before the
+// release, so work enqueued on it that still uses the memory has finished.
+struct TempBuffer {
+    mfe_ctx *ctx;
+    Buffer b;
+    explicit TempBuffer(mfe_ctx *c) : ctx(c) {}
+    TempBuffer(const TempBuffer &) = delete;
+    TempBuffer &operator=(const TempBuffer &) = delete;
+    ~TempBuffer();
+    int alloc(size_t bytes) { return dev_alloc(ctx, &b, bytes); }
+    void *ptr() const { return b.ptr; }
+};
 
 }  // namespace mfe
 

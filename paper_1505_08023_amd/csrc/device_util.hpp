@@ -9,9 +9,6 @@
 #ifndef MFE_XCD_REMAP
 #define MFE_XCD_REMAP 1  // XCD-contiguous tile ranges (see tile_range)
 #endif
-#ifndef MFE_MATRIX_NT
-#define MFE_MATRIX_NT 1  // non-temporal loads for matrix streams
-#endif
 
 namespace mfe {
 
@@ -99,15 +96,17 @@ __device__ __forceinline__ void stream_store(T v, T *p, bool nt) {
         *p = v;
 }
 
-// Matrix streams are read once per product: load them non-temporally so
-// they do not evict the x entries that the gathers reuse.
-template <typename T>
+// Matrix streams are read once per product.  A matrix larger than the
+// memory-side cache is loaded non-temporally (NT = true) so that it does not
+// evict the x entries that the gathers reuse; one that fits is loaded
+// normally and stays cached from one product to the next (the launchers
+// choose, see matrix_stream_nt).
+template <bool NT = (MFE_MATRIX_NT != 0), typename T>
 __device__ __forceinline__ T matrix_load(const T *p) {
-#if MFE_MATRIX_NT
-    return __builtin_nontemporal_load(p);
-#else
-    return *p;
-#endif
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
 }
 
 }  // namespace mfe

@@ -319,16 +319,15 @@ __global__ __launch_bounds__(kBlock) void k_validate_csr(int64_t m, int64_t nnz,
 }  // namespace
 
 int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const int32_t *col) {
-    Buffer bad;
-    MFE_TRY(dev_alloc(ctx, &bad, sizeof(int)));
-    MFE_HIP_TRY(hipMemsetAsync(bad.ptr, 0, sizeof(int), ctx->stream));
+    TempBuffer bad(ctx);
+    MFE_TRY(bad.alloc(sizeof(int)));
+    MFE_HIP_TRY(hipMemsetAsync(bad.ptr(), 0, sizeof(int), ctx->stream));
     hipLaunchKernelGGL(k_validate_csr, dim3((unsigned)((m + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                       ctx->stream, m, nnz, ptr, col, (int *)bad.ptr);
+                       ctx->stream, m, nnz, ptr, col, (int *)bad.ptr());
     MFE_HIP_TRY(hipGetLastError());
     int h = 0;
-    MFE_HIP_TRY(hipMemcpyAsync(&h, bad.ptr, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    MFE_HIP_TRY(hipMemcpyAsync(&h, bad.ptr(), sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     MFE_HIP_TRY(hipStreamSynchronize(ctx->stream));
-    dev_free(ctx, &bad);
     if (h) {
         set_error("CRS structure invalid: ptr must rise from 0 to nnz and columns ascend inside [0, m)");
         return MFE_EINVAL;
@@ -337,12 +336,14 @@ int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const
 }
 
 // Exclusive scan of n >= 1 counts into out[0..n] (out may be NULL: total
-// only); *total_dev (device int64) receives the sum.  The sum must fit int32.
-int scan_counts(mfe_ctx *ctx, hipStream_t s, int64_t n, const int32_t *in, int32_t *out, int64_t *total_dev) {
+// only) on the context's stream; *total_dev (device int64) receives the sum.
+// The sum must fit int32.
+int scan_counts(mfe_ctx *ctx, int64_t n, const int32_t *in, int32_t *out, int64_t *total_dev) {
+    hipStream_t s = ctx->stream;
     const int64_t nchunks = (n + kScanChunk - 1) / kScanChunk;
-    Buffer tmp;
-    MFE_TRY(dev_alloc(ctx, &tmp, (size_t)(2 * nchunks + 1) * sizeof(int32_t)));
-    int32_t *csum = (int32_t *)tmp.ptr, *coff = csum + nchunks;
+    TempBuffer tmp(ctx);
+    MFE_TRY(tmp.alloc((size_t)(2 * nchunks + 1) * sizeof(int32_t)));
+    int32_t *csum = (int32_t *)tmp.ptr(), *coff = csum + nchunks;
     hipLaunchKernelGGL(k_scan_chunks, dim3((unsigned)nchunks), dim3(kScanThreads), 0, s, n, in, csum);
     hipLaunchKernelGGL(k_scan1, dim3(1), dim3(1024), 0, s, nchunks, (const int32_t *)csum, coff, 1, total_dev);
     if (out) {
@@ -352,9 +353,7 @@ int scan_counts(mfe_ctx *ctx, hipStream_t s, int64_t n, const int32_t *in, int32
         MFE_HIP_TRY(hipMemcpyAsync(out + n, coff + nchunks, sizeof(int32_t), hipMemcpyDeviceToDevice, s));
     }
     const hipError_t e = hipGetLastError();
-    // the stream is ordered: freeing through the allocator after synchronising keeps tmp alive until used
     MFE_HIP_TRY(hipStreamSynchronize(s));
-    dev_free(ctx, &tmp);
     if (e != hipSuccess) {
         set_error(std::string("scan launch failed: ") + hipGetErrorString(e));
         return MFE_EHIP;
@@ -371,24 +370,23 @@ int build_bcrs13(mfe_problem *P) {
         return MFE_EUNSUPPORTED;
     }
     const int64_t nslices = (m + 63) / 64;
-    Buffer slice_n, total;
+    TempBuffer slice_buf(ctx), total_buf(ctx), cnt_buf(ctx);
     MFE_TRY(dev_alloc(ctx, &P->rowblocks, (size_t)m * sizeof(int32_t)));
-    MFE_TRY(dev_alloc(ctx, &slice_n, (size_t)nslices * sizeof(int32_t)));
+    MFE_TRY(slice_buf.alloc((size_t)nslices * sizeof(int32_t)));
     MFE_TRY(dev_alloc(ctx, &P->slot_base, (size_t)(nslices + 1) * sizeof(int32_t)));
-    MFE_TRY(dev_alloc(ctx, &total, 2 * sizeof(int64_t)));
+    MFE_TRY(total_buf.alloc(2 * sizeof(int64_t)));
+    int32_t *slice_n = (int32_t *)slice_buf.ptr();
+    int64_t *total = (int64_t *)total_buf.ptr();
     const unsigned grid = (unsigned)nslices;  // one 64-thread workgroup per slice
     hipLaunchKernelGGL(k_b13_count, dim3(grid), dim3(64), 0, s, m, (const int32_t *)P->ptr.ptr,
-                       (const int32_t *)P->col.ptr, (int32_t *)P->rowblocks.ptr, (int32_t *)slice_n.ptr);
+                       (const int32_t *)P->col.ptr, (int32_t *)P->rowblocks.ptr, slice_n);
     MFE_HIP_TRY(hipGetLastError());
     // slot rows per slice -> slot_base; the same counts x 1 give the total slot rows
-    MFE_TRY(scan_counts(ctx, s, nslices, (const int32_t *)slice_n.ptr, (int32_t *)P->slot_base.ptr,
-                        (int64_t *)total.ptr));
+    MFE_TRY(scan_counts(ctx, nslices, slice_n, (int32_t *)P->slot_base.ptr, total));
     int64_t nslots = 0;
-    MFE_HIP_TRY(hipMemcpyAsync(&nslots, total.ptr, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&nslots, total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     if (nslots * 64 * 3 >= ((int64_t)1 << 31)) {
-        dev_free(ctx, &slice_n);
-        dev_free(ctx, &total);
         set_error("1x3 BCRS slot count exceeds 32-bit indexing");
         return MFE_EUNSUPPORTED;
     }
@@ -400,29 +398,26 @@ int build_bcrs13(mfe_problem *P) {
                        (const int32_t *)P->slot_base.ptr, (int32_t *)P->jas.ptr, (double *)P->bval64.ptr);
     MFE_HIP_TRY(hipGetLastError());
     // number of real (unpadded) blocks: the sum of the per-row counts
-    MFE_TRY(scan_counts(ctx, s, m, (const int32_t *)P->rowblocks.ptr, nullptr, (int64_t *)total.ptr + 1));
+    MFE_TRY(scan_counts(ctx, m, (const int32_t *)P->rowblocks.ptr, nullptr, total + 1));
     int64_t nb = 0;
-    MFE_HIP_TRY(hipMemcpyAsync(&nb, (int64_t *)total.ptr + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipMemcpyAsync(&nb, total + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     P->nblocks = nb;
     // slice descriptors; slice_n is reused for the per-slice flags
     MFE_TRY(dev_alloc(ctx, &P->bdesc, (size_t)nslices * sizeof(B13Desc)));
-    Buffer cnt;
-    MFE_TRY(dev_alloc(ctx, &cnt, (size_t)nslices * sizeof(int32_t)));
+    MFE_TRY(cnt_buf.alloc((size_t)nslices * sizeof(int32_t)));
+    int32_t *cnt = (int32_t *)cnt_buf.ptr();
     hipLaunchKernelGGL(k_b13_desc, dim3(grid), dim3(64), 0, s, m, (const int32_t *)P->slot_base.ptr,
                        (const int32_t *)P->jas.ptr, (const int32_t *)P->rowblocks.ptr, (B13Desc *)P->bdesc.ptr,
-                       (int32_t *)cnt.ptr, (int32_t *)slice_n.ptr);
+                       cnt, slice_n);
     MFE_HIP_TRY(hipGetLastError());
-    MFE_TRY(scan_counts(ctx, s, nslices, (const int32_t *)slice_n.ptr, nullptr, (int64_t *)total.ptr));
-    MFE_TRY(scan_counts(ctx, s, nslices, (const int32_t *)cnt.ptr, nullptr, (int64_t *)total.ptr + 1));
+    MFE_TRY(scan_counts(ctx, nslices, slice_n, nullptr, total));
+    MFE_TRY(scan_counts(ctx, nslices, cnt, nullptr, total + 1));
     int64_t counts[2] = {0, 0};
-    MFE_HIP_TRY(hipMemcpyAsync(counts, total.ptr, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipMemcpyAsync(counts, total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     P->b13_cslices = counts[0];
     P->b13_cblocks = counts[1];
-    dev_free(ctx, &cnt);
-    dev_free(ctx, &slice_n);
-    dev_free(ctx, &total);
     return MFE_OK;
 }
 
@@ -447,21 +442,20 @@ int export_bcrs13(const mfe_problem *P, int32_t *bptr_out, int32_t *bcol, double
     mfe_ctx *ctx = P->ctx;
     hipStream_t s = ctx->stream;
     const int64_t m = P->m;
-    Buffer bptr, total;
-    MFE_TRY(dev_alloc(ctx, &bptr, (size_t)(m + 1) * sizeof(int32_t)));
-    MFE_TRY(dev_alloc(ctx, &total, sizeof(int64_t)));
-    MFE_TRY(scan_counts(ctx, s, m, (const int32_t *)P->rowblocks.ptr, (int32_t *)bptr.ptr, (int64_t *)total.ptr));
+    TempBuffer bptr_buf(ctx), total_buf(ctx);
+    MFE_TRY(bptr_buf.alloc((size_t)(m + 1) * sizeof(int32_t)));
+    MFE_TRY(total_buf.alloc(sizeof(int64_t)));
+    int32_t *bptr = (int32_t *)bptr_buf.ptr();
+    MFE_TRY(scan_counts(ctx, m, (const int32_t *)P->rowblocks.ptr, bptr, (int64_t *)total_buf.ptr()));
     const unsigned grid = (unsigned)((m + kBlock - 1) / kBlock);
     hipLaunchKernelGGL(k_b13_export, dim3(grid), dim3(kBlock), 0, s, m, (const int32_t *)P->slot_base.ptr,
-                       (const int32_t *)P->rowblocks.ptr, (const int32_t *)bptr.ptr,
+                       (const int32_t *)P->rowblocks.ptr, (const int32_t *)bptr,
                        (const int32_t *)P->jas.ptr, (const double *)P->bval64.ptr, bcol, bval);
     MFE_HIP_TRY(hipGetLastError());
     if (bptr_out)
-        MFE_HIP_TRY(hipMemcpyAsync(bptr_out, bptr.ptr, (size_t)(m + 1) * sizeof(int32_t),
+        MFE_HIP_TRY(hipMemcpyAsync(bptr_out, bptr, (size_t)(m + 1) * sizeof(int32_t),
                                    hipMemcpyDeviceToDevice, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
-    dev_free(ctx, &bptr);
-    dev_free(ctx, &total);
     return MFE_OK;
 }
 

@@ -1395,27 +1395,25 @@ int mfe_conv3d_wgrad_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, co
     const int Kpad = pad64(27 * cin), rows = (cout + 15) / 16 * 16;
     const int64_t total = (int64_t)batch * voxels(Go);
     const int nsplit = wgrad_splits(total, Kpad / 64);
-    Buffer part, sum;
-    MFE_TRY(dev_alloc(ctx, &part, (size_t)nsplit * rows * Kpad * sizeof(float)));
-    MFE_TRY(dev_alloc(ctx, &sum, (size_t)rows * Kpad * sizeof(float)));
+    TempBuffer part(ctx), sum(ctx);
+    MFE_TRY(part.alloc((size_t)nsplit * rows * Kpad * sizeof(float)));
+    MFE_TRY(sum.alloc((size_t)rows * Kpad * sizeof(float)));
     hipStream_t s = ctx->stream;
     int rc = wgrad(s, mode, (const bf16 *)gy_dev, Go, cout, (const bf16 *)x_dev, Gi, cin, Kpad, batch,
-                   (float *)part.ptr, nsplit);
+                   (float *)part.ptr(), nsplit);
     std::vector<float> h((size_t)rows * Kpad);
     if (rc == MFE_OK) {
         const int64_t n = (int64_t)rows * Kpad;
-        hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(n)), dim3(256), 0, s, (const float *)part.ptr, nsplit, n,
-                           (float *)sum.ptr);
+        hipLaunchKernelGGL(k_sum_splits, dim3(grid_of(n)), dim3(256), 0, s, (const float *)part.ptr(), nsplit, n,
+                           (float *)sum.ptr());
         if (hipGetLastError() != hipSuccess ||
-            hipMemcpyAsync(h.data(), sum.ptr, h.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
+            hipMemcpyAsync(h.data(), sum.ptr(), h.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
             rc = MFE_EHIP;
     }
     if (hipStreamSynchronize(s) != hipSuccess && rc == MFE_OK) rc = MFE_EHIP;
     if (rc == MFE_OK)
         for (int o = 0; o < cout; ++o)
             for (int k = 0; k < 27 * cin; ++k) dw_host[(size_t)o * 27 * cin + k] = h[(size_t)o * Kpad + k];
-    dev_free(ctx, &part);
-    dev_free(ctx, &sum);
     return rc;
 }
 

@@ -11,7 +11,8 @@
 //
 // Both kernels run a workgroup grid sized to stay resident and walk row tiles
 // in XCD-contiguous ranges, so each XCD's L2 holds the x entries of the mesh
-// planes its rows touch while the matrix streams past non-temporally.
+// planes its rows touch while the matrix streams past (non-temporally when it
+// is larger than the memory-side cache can usefully keep, matrix_stream_nt).
 #include <type_traits>
 
 #include "b13_layout.hpp"
@@ -116,7 +117,7 @@ __device__ __forceinline__ bool cg_gate(CgState *st) {
 
 // ---------------------------------------------------------------- CRS
 
-template <typename T, int L, int MODE>
+template <typename T, int L, int MODE, bool MNT>
 __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *__restrict__ ptr,
                                                      const int32_t *__restrict__ col,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
@@ -128,7 +129,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
     double d1 = 0.0, d2 = 0.0;
     for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
         const int64_t row = tr.t * R + g;
-        const T sum = csr_row<T, L>(ptr, col, val, row < m ? row : -1, sub, E.x);
+        const T sum = csr_row<T, L, MNT>(ptr, col, val, row < m ? row : -1, sub, E.x);
         if (sub == 0 && row < m) finish_row<T, MODE>(E, row, sum, d1, d2);
     }
     store_partials<MODE>(d1, d2, partials);
@@ -153,7 +154,7 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <typename T, int MODE>
+template <typename T, int MODE, bool MNT>
 __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
                                                       const T *__restrict__ val, Epi<T> E, CgState *st,
@@ -178,8 +179,8 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
         T sum = 0;
         if (hi - lo <= kCsrsCap) {
             for (int32_t j = lo + lane; j < hi; j += 64) {
-                sv[j - lo] = matrix_load(val + j);
-                sc[j - lo] = matrix_load(col + j);
+                sv[j - lo] = matrix_load<MNT>(val + j);
+                sc[j - lo] = matrix_load<MNT>(col + j);
             }
             wave_sync();
             if (row < r1) {
@@ -189,7 +190,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
             wave_sync();
         } else if (row < r1) {
             for (int32_t j = ptr[row] + sub; j < ptr[row + 1]; j += LPR)
-                sum += matrix_load(val + j) * E.x[matrix_load(col + j)];
+                sum += matrix_load<MNT>(val + j) * E.x[matrix_load<MNT>(col + j)];
         }
 #pragma unroll
         for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
@@ -202,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
 
 // One slice per wavefront per tile: slice bounds, column indices, values,
 // gathers, in that dependent order.
-template <typename T, int MODE>
+template <typename T, int MODE, bool MNT>
 __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
                                                      const int32_t *__restrict__ jas,
                                                      const B13Desc *__restrict__ desc,
@@ -216,7 +217,7 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13(int64_t m
         const int64_t s = (int64_t)tr.t * (kBlock / 64) + wave;
         const int64_t row = s * 64 + lane;
         if (row >= m) continue;
-        const T sum = b13_row(slot_base, jas, desc, val, s, lane, E.x);
+        const T sum = b13_row<T, MNT>(slot_base, jas, desc, val, s, lane, E.x);
         finish_row<T, MODE>(E, row, sum, d1, d2);
     }
     store_partials<MODE>(d1, d2, partials);
@@ -229,7 +230,7 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13(int64_t m
 // values and gathers, so the index -> gather dependency of one tile overlaps
 // the streaming of the previous one.  Arithmetic and summation order are
 // those of k_spmv_b13.
-template <typename T, int MODE>
+template <typename T, int MODE, bool MNT>
 __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t m, const int32_t *__restrict__ slot_base,
                                                       const int32_t *__restrict__ jas,
                                                       const B13Desc *__restrict__ desc,
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t 
         r.sl.S = 0;
         if (s * 64 >= m) return;
         r.sl = b13_slice(slot_base[s], slot_base[s + 1]);
-        if (row < m) b13_cols(jas, desc, s, lane, r);
+        if (row < m) b13_cols<MNT>(jas, desc, s, lane, r);
     };
     if (tr.t < tr.end) fetch(tr.t, cur);
     for (; tr.t < tr.end; tr.t += tr.step) {
@@ -256,8 +257,8 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t 
         if (tn < tr.end) fetch(tn, nxt);
         const int64_t row = tr.t * kBlock + threadIdx.x;
         if (row < m) {
-            const T sum = cur.sl.S == 9 ? b13_row9_idx(cur.c, val, cur.sl, lane, E.x)
-                                        : b13_row_generic(jas, val, cur.sl, lane, E.x);
+            const T sum = cur.sl.S == 9 ? b13_row9_idx<T, MNT>(cur.c, val, cur.sl, lane, E.x)
+                                        : b13_row_generic<T, MNT>(jas, val, cur.sl, lane, E.x);
             finish_row<T, MODE>(E, row, sum, d1, d2);
         }
         cur = nxt;
@@ -274,17 +275,28 @@ int grid_for(K kernel, long ntiles, int num_cu) {
     return resident_grid((long)num_cu * per_cu, ntiles);
 }
 
-template <typename T, int MODE>
-int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
+// Bytes of a stored matrix, for the non-temporal choice (matrix_stream_nt).
+template <typename T>
+int64_t csr_bytes(const mfe_problem *P) {
+    return P->nnz * (int64_t)(sizeof(T) + sizeof(int32_t)) + (P->m + 1) * (int64_t)sizeof(int32_t);
+}
+template <typename T>
+int64_t b13_bytes(const mfe_problem *P) {
+    return P->nslots * 64 * (int64_t)(3 * sizeof(T) + sizeof(int32_t));
+}
+
+template <typename T, int MODE, bool MNT>
+int launch_csr_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s,
+                  int *grid_out) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->val64.ptr : (const T *)P->val32.ptr;
 #if MFE_CSR_STREAM
-    auto kern = k_spmv_csrs<T, MODE>;
+    auto kern = k_spmv_csrs<T, MODE, MNT>;
     const long ntiles = (P->m + (kBlock / 64) * kCsrsRows - 1) / ((kBlock / 64) * kCsrsRows);
 #else
     // L lanes per row: with 32, a row of the 27-point matrix (one contiguous
     // 216-byte run of values) is read by one half-wavefront.
     constexpr int L = MFE_CSR_LANES;
-    auto kern = k_spmv_csr<T, L, MODE>;
+    auto kern = k_spmv_csr<T, L, MODE, MNT>;
     const long ntiles = (P->m + kBlock / L - 1) / (kBlock / L);
 #endif
     const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
@@ -296,14 +308,21 @@ int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *parti
 }
 
 template <typename T, int MODE>
-int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
+int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
+    return matrix_stream_nt(csr_bytes<T>(P)) ? launch_csr_as<T, MODE, true>(P, E, st, partials, s, grid_out)
+                                             : launch_csr_as<T, MODE, false>(P, E, st, partials, s, grid_out);
+}
+
+template <typename T, int MODE, bool MNT>
+int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s,
+                  int *grid_out) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
     const long ntiles = (P->m + kBlock - 1) / kBlock;
     // the pipelined walk pays off once each workgroup takes several tiles
-    auto kern = k_spmv_b13p<T, MODE>;
+    auto kern = k_spmv_b13p<T, MODE, MNT>;
     int grid = grid_for(kern, ntiles, P->ctx->num_cu);
     if (ntiles < (long)MFE_B13_PIPE_TILES * grid) {
-        kern = k_spmv_b13<T, MODE>;
+        kern = k_spmv_b13<T, MODE, MNT>;
         grid = grid_for(kern, ntiles, P->ctx->num_cu);
     }
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
@@ -311,6 +330,12 @@ int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *parti
     MFE_HIP_TRY(hipGetLastError());
     if (grid_out) *grid_out = grid;
     return MFE_OK;
+}
+
+template <typename T, int MODE>
+int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
+    return matrix_stream_nt(b13_bytes<T>(P)) ? launch_b13_as<T, MODE, true>(P, E, st, partials, s, grid_out)
+                                             : launch_b13_as<T, MODE, false>(P, E, st, partials, s, grid_out);
 }
 
 template <typename T, int MODE>

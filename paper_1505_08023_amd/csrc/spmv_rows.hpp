@@ -11,13 +11,13 @@ namespace mfe {
 // CRS row by L lanes (L a power of two dividing 64): lane `sub` takes
 // entries sub, sub+L, ...; the xor butterfly leaves the row sum in every lane
 // of the group.  row < 0: no row (the lanes still join the butterfly).
-template <typename T, int L>
+template <typename T, int L, bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ T csr_row(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
                                      const T *__restrict__ val, int64_t row, int sub, const T *__restrict__ x) {
     T sum = 0;
     if (row >= 0) {
         const int32_t lo = ptr[row], hi = ptr[row + 1];
-        for (int32_t j = lo + sub; j < hi; j += L) sum += matrix_load(val + j) * x[matrix_load(col + j)];
+        for (int32_t j = lo + sub; j < hi; j += L) sum += matrix_load<NT>(val + j) * x[matrix_load<NT>(col + j)];
     }
 #pragma unroll
     for (int off = L / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, L);
@@ -29,15 +29,15 @@ using vec2_t = T __attribute__((ext_vector_type(2)));
 typedef int32_t int4_t __attribute__((ext_vector_type(4)));
 
 // Any slice: one block at a time.
-template <typename T>
+template <typename T, bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ T b13_row_generic(const int32_t *jas, const T *val, const B13Slice &sl, int lane,
                                              const T *x) {
     T sum = 0;
     for (int k = 0; k < sl.S; ++k) {
-        const T *xp = x + matrix_load(jas + b13_jas(sl, k, lane));
-        sum += matrix_load(val + b13_val(sl, k, 0, lane)) * xp[0];
-        sum += matrix_load(val + b13_val(sl, k, 1, lane)) * xp[1];
-        sum += matrix_load(val + b13_val(sl, k, 2, lane)) * xp[2];
+        const T *xp = x + matrix_load<NT>(jas + b13_jas(sl, k, lane));
+        sum += matrix_load<NT>(val + b13_val(sl, k, 0, lane)) * xp[0];
+        sum += matrix_load<NT>(val + b13_val(sl, k, 1, lane)) * xp[1];
+        sum += matrix_load<NT>(val + b13_val(sl, k, 2, lane)) * xp[2];
     }
     return sum;
 }
@@ -49,18 +49,20 @@ struct B13Idx {
     int32_t c[9];
 };
 
+template <bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ void b13_load_idx(const int32_t *__restrict__ jas, int lane, B13Idx &r) {
     if (r.sl.S != 9) return;
-    const int4_t q0 = matrix_load((const int4_t *)(jas + r.sl.jbase + lane * 4));
-    const int4_t q1 = matrix_load((const int4_t *)(jas + r.sl.jbase + 256 + lane * 4));
+    const int4_t q0 = matrix_load<NT>((const int4_t *)(jas + r.sl.jbase + lane * 4));
+    const int4_t q1 = matrix_load<NT>((const int4_t *)(jas + r.sl.jbase + 256 + lane * 4));
     r.c[0] = q0.x, r.c[1] = q0.y, r.c[2] = q0.z, r.c[3] = q0.w;
     r.c[4] = q1.x, r.c[5] = q1.y, r.c[6] = q1.z, r.c[7] = q1.w;
-    r.c[8] = matrix_load(jas + r.sl.jbase + 512 + lane);
+    r.c[8] = matrix_load<NT>(jas + r.sl.jbase + 512 + lane);
 }
 
 // Column indices of one row of slice s (r.sl already set): formed from the
 // slice descriptor when the slice is uniform, else loaded.  s must be
 // wavefront-uniform (the descriptor is read with scalar loads).
+template <bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ void b13_cols(const int32_t *__restrict__ jas, const B13Desc *__restrict__ desc,
                                          int64_t s, int lane, B13Idx &r) {
     if (r.sl.S != 9) return;
@@ -71,21 +73,21 @@ __device__ __forceinline__ void b13_cols(const int32_t *__restrict__ jas, const 
 #pragma unroll
         for (int k = 0; k < 9; ++k) r.c[k] = base + D.d[k];
     } else {
-        b13_load_idx(jas, lane, r);
+        b13_load_idx<NT>(jas, lane, r);
     }
 }
 
 // Values and gathers of a 9-slot row whose indices are already loaded.
-template <typename T>
+template <typename T, bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ T b13_row9_idx(const int32_t *c, const T *val, const B13Slice &sl, int lane,
                                           const T *x) {
     vec2_t<T> a[9], b[4];
 #pragma unroll
-    for (int k = 0; k < 9; ++k) a[k] = matrix_load((const vec2_t<T> *)(val + sl.vbase + k * 128 + lane * 2));
+    for (int k = 0; k < 9; ++k) a[k] = matrix_load<NT>((const vec2_t<T> *)(val + sl.vbase + k * 128 + lane * 2));
 #pragma unroll
     for (int p = 0; p < 4; ++p)
-        b[p] = matrix_load((const vec2_t<T> *)(val + sl.vbase + 9 * 128 + p * 128 + lane * 2));
-    const T w8 = matrix_load(val + sl.vbase + 13 * 128 + lane);
+        b[p] = matrix_load<NT>((const vec2_t<T> *)(val + sl.vbase + 9 * 128 + p * 128 + lane * 2));
+    const T w8 = matrix_load<NT>(val + sl.vbase + 13 * 128 + lane);
     const T v2[9] = {b[0].x, b[0].y, b[1].x, b[1].y, b[2].x, b[2].y, b[3].x, b[3].y, w8};
     T sum = 0;
 #pragma unroll
@@ -99,14 +101,14 @@ __device__ __forceinline__ T b13_row9_idx(const int32_t *c, const T *val, const 
 }
 
 // 1x3 BCRS row 64 s + lane (one lane per row; s wavefront-uniform).
-template <typename T>
+template <typename T, bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ T b13_row(const int32_t *__restrict__ slot_base, const int32_t *__restrict__ jas,
                                      const B13Desc *__restrict__ desc, const T *__restrict__ val, int64_t s,
                                      int lane, const T *__restrict__ x) {
     B13Idx r;
     r.sl = b13_slice(slot_base[s], slot_base[s + 1]);
-    b13_cols(jas, desc, s, lane, r);
-    return r.sl.S == 9 ? b13_row9_idx(r.c, val, r.sl, lane, x) : b13_row_generic(jas, val, r.sl, lane, x);
+    b13_cols<NT>(jas, desc, s, lane, r);
+    return r.sl.S == 9 ? b13_row9_idx<T, NT>(r.c, val, r.sl, lane, x) : b13_row_generic<T, NT>(jas, val, r.sl, lane, x);
 }
 
 }  // namespace mfe
