@@ -46,6 +46,17 @@ __host__ __device__ __forceinline__ int64_t b13_val(const B13Slice &sl, int k, i
     return sl.vbase + (int64_t)sl.S * 128 + (int64_t)P * 128 + l;
 }
 
+// FP32 values of a 9-slot slice are stored packed instead, in the same
+// region: the 27 values of a row in block order v = 3 k + j, as
+// [q][lane][4] for q = 0..5 (v = 0..23) followed by [lane][3] (v = 24..26),
+// so that a wavefront loads them with six 16-byte loads and one 12-byte load
+// per lane rather than fourteen 8- or 4-byte ones.  Other slices keep the
+// layout of b13_val in FP32 too.
+__host__ __device__ __forceinline__ int64_t b13_val32_9(const B13Slice &sl, int v, int l) {
+    if (v < 24) return sl.vbase + (int64_t)(v / 4) * 256 + l * 4 + (v % 4);
+    return sl.vbase + 1536 + (int64_t)l * 3 + (v - 24);
+}
+
 }  // namespace mfe
 
 namespace mfe {

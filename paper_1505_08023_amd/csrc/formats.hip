@@ -273,6 +273,23 @@ __global__ __launch_bounds__(64) void k_b13_desc(int64_t m, const int32_t *__res
     }
 }
 
+// FP32 copy of the 1x3 BCRS values: 9-slot slices into the packed layout
+// (b13_val32_9), the others element by element.  One thread per (slice, lane).
+__global__ __launch_bounds__(kBlock) void k_b13_cast_f32(int64_t nslices, const int32_t *__restrict__ slot_base,
+                                                         const double *__restrict__ v64, float *__restrict__ v32) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t s = t >> 6;
+    const int lane = (int)(t & 63);
+    if (s >= nslices) return;
+    const B13Slice sl = b13_slice(slot_base[s], slot_base[s + 1]);
+    if (sl.S == 9) {
+        for (int v = 0; v < 27; ++v) v32[b13_val32_9(sl, v, lane)] = (float)v64[b13_val(sl, v / 3, v % 3, lane)];
+    } else {
+        for (int k = 0; k < sl.S; ++k)
+            for (int j = 0; j < 3; ++j) v32[b13_val(sl, k, j, lane)] = (float)v64[b13_val(sl, k, j, lane)];
+    }
+}
+
 __global__ __launch_bounds__(kBlock) void k_cast_f32(int64_t n, const double *__restrict__ in,
                                                      float *__restrict__ out) {
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kBlock)
@@ -431,7 +448,9 @@ int cast_values_f32(mfe_problem *P) {
     if (P->formats & MFE_BCRS13) {
         const int64_t n = P->nslots * 64 * 3;
         MFE_TRY(dev_alloc(ctx, &P->bval32, (size_t)n * sizeof(float)));
-        hipLaunchKernelGGL(k_cast_f32, dim3(4096), dim3(kBlock), 0, s, n, (const double *)P->bval64.ptr,
+        const int64_t nslices = (P->m + 63) / 64;
+        hipLaunchKernelGGL(k_b13_cast_f32, dim3((unsigned)((nslices * 64 + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                           nslices, (const int32_t *)P->slot_base.ptr, (const double *)P->bval64.ptr,
                            (float *)P->bval32.ptr);
         MFE_HIP_TRY(hipGetLastError());
     }

@@ -2,6 +2,8 @@
 // kernels (Sec. 3.1: CRS row of Fig 3.1; 1x3 segments of Figs 3.2/3.3).
 #pragma once
 
+#include <type_traits>
+
 #include "b13_layout.hpp"
 #include "common.hpp"
 #include "device_util.hpp"
@@ -77,10 +79,33 @@ __device__ __forceinline__ void b13_cols(const int32_t *__restrict__ jas, const 
     }
 }
 
-// Values and gathers of a 9-slot row whose indices are already loaded.
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+// Values and gathers of a 9-slot row whose indices are already loaded.  FP32
+// values come from the packed layout (b13_val32_9); the products are summed
+// in the same order in both precisions.
 template <typename T, bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ T b13_row9_idx(const int32_t *c, const T *val, const B13Slice &sl, int lane,
                                           const T *x) {
+    if constexpr (std::is_same<T, float>::value) {
+        float v[27];
+#pragma unroll
+        for (int q = 0; q < 6; ++q) {
+            const float4_t t = matrix_load<NT>((const float4_t *)(val + sl.vbase + q * 256 + lane * 4));
+            v[4 * q] = t.x, v[4 * q + 1] = t.y, v[4 * q + 2] = t.z, v[4 * q + 3] = t.w;
+        }
+#pragma unroll
+        for (int j = 0; j < 3; ++j) v[24 + j] = matrix_load<NT>(val + sl.vbase + 1536 + lane * 3 + j);
+        float sum = 0;
+#pragma unroll
+        for (int k = 0; k < 9; ++k) {
+            const float *xp = x + c[k];
+            sum += v[3 * k] * xp[0];
+            sum += v[3 * k + 1] * xp[1];
+            sum += v[3 * k + 2] * xp[2];
+        }
+        return sum;
+    }
     vec2_t<T> a[9], b[4];
 #pragma unroll
     for (int k = 0; k < 9; ++k) a[k] = matrix_load<NT>((const vec2_t<T> *)(val + sl.vbase + k * 128 + lane * 2));
