@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # and WRITE_SIZE (x 1.0) counter runs, scaled by streaming kernels of known
 # size (profiles/spmv_b13_fp64_256cubed_hbm_counters.md).  Reset to None
 # whenever the kernel changes.
-MEASURED_TRAFFIC = {("bcrs13", 256): 4.007e9, ("csr", 256): 6.808e9}
+MEASURED_TRAFFIC = {("bcrs13", 256): 4.007e9, ("csr", 256): None}
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
 
 
@@ -38,12 +38,18 @@ def log(*a):
 def spmv_bytes(fmt, m, nnz, nb, fp=8, layout=None):
     """Algorithmic bytes of one SpMV: matrix streamed once, x read once, y
     written once, int32 indices; for the fused dot p_i is the x entry already
-    read.  CRS: (fp + 4) nnz + 4 (m+1) + 2 fp m.  1x3 BCRS: 3 fp nb values,
-    4 bytes of column index per block outside the descriptor slices, 48 per
-    descriptor slice, 4 (slices + 1) of slice bounds, 2 fp m (layout: the
-    problem's b13_layout; None counts every slice as indexed)."""
+    read.  CRS (layout: the problem's csr_layout): fp nnz values, 4 bytes of
+    column index per entry outside the descriptor tiles, 112 per descriptor
+    tile, 4 (tiles + 1) of tile bounds plus 4 per row of the other tiles,
+    2 fp m.  1x3 BCRS (layout: b13_layout): 3 fp nb values, 4 bytes of column
+    index per block outside the descriptor slices, 48 per descriptor slice,
+    4 (slices + 1) of slice bounds, 2 fp m.  layout None counts every tile or
+    slice as indexed (CRS then 4 (m+1) of row pointers)."""
     if fmt == "csr":
-        return (fp + 4) * nnz + 4 * (m + 1) + 2 * fp * m
+        if layout is None:
+            return (fp + 4) * nnz + 4 * (m + 1) + 2 * fp * m
+        R, tiles, ct = layout["tile_rows"], layout["tiles"], layout["compressed_tiles"]
+        return fp * nnz + 4 * (nnz - 27 * R * ct) + 112 * ct + 4 * (tiles + 1) + 4 * (m - R * ct) + 2 * fp * m
     slices = (m + 63) // 64
     cs = cb = 0
     if layout is not None:
@@ -147,7 +153,7 @@ def main():
     spmv = {}
     for fmt in ("bcrs13", "csr"):
         mean_ms, min_ms = time_spmv_dot(P, fmt, args.spmv_reps, torch)
-        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, layout=P.b13_layout)
+        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, layout=P.csr_layout if fmt == "csr" else P.b13_layout)
         spmv[fmt] = dict(mean_ms=mean_ms, median_ms=time_spmv_dot.median_ms, min_ms=min_ms, launches=args.spmv_reps,
                          bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
                          frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -155,7 +161,7 @@ def main():
     # the FP32 product of the mixed-precision inner solves
     for fmt in ("bcrs13", "csr"):
         mean_ms, min_ms = time_spmv_dot(P, fmt, args.spmv_reps, torch, f32=True)
-        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, fp=4, layout=P.b13_layout)
+        by = spmv_bytes(fmt, P.m, P.nnz, P.nblocks, fp=4, layout=P.csr_layout if fmt == "csr" else P.b13_layout)
         spmv[fmt + "_f32"] = dict(mean_ms=mean_ms, median_ms=time_spmv_dot.median_ms, min_ms=min_ms,
                                   launches=args.spmv_reps, bytes=by, GBps=by / (mean_ms * 1e-3) / 1e9,
                                   frac_hbm=by / (mean_ms * 1e-3) / 1e9 / HBM_PEAK_GBS)
@@ -370,7 +376,8 @@ def extras(args, ctx, P, x, line, torch):
             dt = time.perf_counter() - t
             best = dt if best is None else min(best, dt)
         assert st["iterations"] == 200
-        it_bytes = spmv_bytes(fmt, P2.m, P2.nnz, P2.nblocks, layout=P2.b13_layout) + 64 * P2.m
+        it_bytes = spmv_bytes(fmt, P2.m, P2.nnz, P2.nblocks,
+                              layout=P2.csr_layout if fmt == "csr" else P2.b13_layout) + 64 * P2.m
         c2[fmt] = dict(it_per_s=200 / best, seconds=best, effective_GBps=200 * it_bytes / best / 1e9)
         log(f"[bench] 128^3 CG x200 {fmt}: {c2[fmt]}")
     line["cg_128cubed_200_iterations"] = c2

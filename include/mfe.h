@@ -126,6 +126,14 @@ int mfe_problem_set_bc(mfe_problem *p, const double *face_vals, const double *no
  * Any output pointer may be NULL. */
 int mfe_problem_info(const mfe_problem *p, int64_t *m, int64_t *nnz, int64_t *nblocks);
 
+/* Storage of the CRS as the CRS product walks it: wavefront tiles of
+ * *tile_rows consecutive rows (*tiles of them), and the tiles whose column
+ * indices the product forms from a 112-byte per-tile descriptor instead of
+ * reading them (full tiles whose rows all hold 27 entries with column
+ * i + off_k for entry k of row i: the interior of a box mesh).  The indices
+ * stay stored.  Any output pointer may be NULL. */
+int mfe_problem_csr_layout(const mfe_problem *p, int64_t *tile_rows, int64_t *tiles, int64_t *compressed_tiles);
+
 /* Storage of the 1x3 BCRS (all zero when it was not built): 64-row slices;
  * slot rows (slice s stores 64 x its slot count blocks, padding included);
  * slices whose column indices the SpMV forms from a 48-byte per-slice

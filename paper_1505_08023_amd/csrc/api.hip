@@ -93,13 +93,14 @@ void free_problem_storage(mfe_problem *P) {
     mfe_ctx *ctx = P->ctx;
     release_graphs(P);
     Buffer *bufs[] = {&P->ptr, &P->col, &P->val64, &P->val32, &P->b, &P->slot_base, &P->jas, &P->bval64,
-                      &P->bval32, &P->rowblocks, &P->bdesc, &P->r, &P->p, &P->q, &P->state, &P->partials,
+                      &P->bval32, &P->rowblocks, &P->bdesc, &P->cdesc, &P->r, &P->p, &P->q, &P->state, &P->partials,
                       &P->r32, &P->p32, &P->q32, &P->d32, &P->ax, &P->s, &P->dinv};
     for (Buffer *b : bufs) dev_free(ctx, b);
 }
 
 // Derived formats and precisions after the FP64 CRS exists.
 int finish_problem(mfe_problem *P) {
+    MFE_TRY(build_csr_tiles(P));
     if (P->formats & MFE_BCRS13) MFE_TRY(build_bcrs13(P));
     if (P->precisions & MFE_F32) MFE_TRY(cast_values_f32(P));
     MFE_HIP_TRY(hipStreamSynchronize(P->ctx->stream));
@@ -128,7 +129,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 3; }
+int mfe_version(void) { return 4; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -347,6 +348,18 @@ int mfe_problem_info(const mfe_problem *p, int64_t *m, int64_t *nnz, int64_t *nb
     if (m) *m = p->m;
     if (nnz) *nnz = p->nnz;
     if (nblocks) *nblocks = (p->formats & MFE_BCRS13) ? p->nblocks : 0;
+    return MFE_OK;
+}
+
+int mfe_problem_csr_layout(const mfe_problem *p, int64_t *tile_rows, int64_t *tiles, int64_t *compressed_tiles) {
+    clear_error();
+    if (!p) {
+        set_error("problem is NULL");
+        return MFE_EINVAL;
+    }
+    if (tile_rows) *tile_rows = kCsrsRows;
+    if (tiles) *tiles = (p->m + kCsrsRows - 1) / kCsrsRows;
+    if (compressed_tiles) *compressed_tiles = p->csr_ctiles;
     return MFE_OK;
 }
 

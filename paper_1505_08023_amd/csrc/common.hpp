@@ -99,6 +99,22 @@ struct CgState {
 
 // (the 1x3 BCRS slice layout is described in b13_layout.hpp)
 
+// CRS wavefront tiles: the CRS product gives each wavefront kCsrsRows
+// consecutive rows.  A tile whose rows all hold 27 entries with
+// column(row i, entry k) = i + off[k] (the interior of a box mesh) has
+// uniform = 1 in its descriptor, and the product forms its columns from the
+// 27 offsets instead of loading its 27 kCsrsRows column indices (which stay
+// stored).  The reconstruction is exact: products are bitwise the same.
+#ifndef MFE_CSRS_ROWS
+#define MFE_CSRS_ROWS 16  // rows per wavefront tile (64 / rows lanes per row); 8, 16 and 32 measured
+#endif
+constexpr int kCsrsRows = MFE_CSRS_ROWS;
+struct CsrDesc {
+    int32_t off[27];
+    int32_t uniform;
+};
+static_assert(sizeof(CsrDesc) == 112, "CsrDesc is 112 bytes");
+
 // ------------------------------------------------------------------ context / problem
 
 struct Buffer {
@@ -167,9 +183,11 @@ struct mfe_problem {
     int Nx = 0, Ny = 0, Nz = 0;
     int64_t m = 0, nnz = 0, nblocks = 0, nslots = 0;
     int64_t b13_cslices = 0, b13_cblocks = 0;  // slices with compressed column indices, their real blocks
+    int64_t csr_ctiles = 0;                     // CRS wavefront tiles with a uniform descriptor
     int formats = 0, precisions = 0;
     // CRS (always FP64; FP32 values when MFE_F32)
     mfe::Buffer ptr, col, val64, val32, b;
+    mfe::Buffer cdesc;  // CsrDesc per CRS wavefront tile
     // 1x3 BCRS
     mfe::Buffer slot_base, jas, bval64, bval32, rowblocks;
     mfe::Buffer bdesc;  // B13Desc per slice
@@ -193,6 +211,7 @@ int launch_assemble_into(hipStream_t s, int Nx, int Ny, int Nz, const double *fa
                          bool rhs_only);
 
 // formats (formats.hip)
+int build_csr_tiles(mfe_problem *P);
 int build_bcrs13(mfe_problem *P);
 int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const int32_t *col);
 int cast_values_f32(mfe_problem *P);

@@ -273,6 +273,40 @@ __global__ __launch_bounds__(64) void k_b13_desc(int64_t m, const int32_t *__res
     }
 }
 
+// CRS tile descriptors (CsrDesc): one 64-thread workgroup per wavefront
+// tile of kCsrsRows rows.  A full tile is uniform when each of its rows holds
+// 27 entries and every column minus its row equals that of the tile's first
+// row at the same entry.  flag[t] receives whether it is.
+__global__ __launch_bounds__(64) void k_csr_desc(int64_t m, const int32_t *__restrict__ ptr,
+                                                 const int32_t *__restrict__ col, CsrDesc *__restrict__ desc,
+                                                 int32_t *__restrict__ flag) {
+    const int64_t t = blockIdx.x;
+    const int lane = (int)threadIdx.x;
+    const int64_t r0 = t * kCsrsRows;
+    // workgroup-uniform: a full tile of 27 kCsrsRows entries (checked before
+    // any column is read, so the reads stay inside the tile's run)
+    bool ok = r0 + kCsrsRows <= m;
+    int32_t lo = 0;
+    if (ok) {
+        lo = ptr[r0];
+        ok = ptr[r0 + kCsrsRows] - lo == 27 * kCsrsRows;
+    }
+    if (ok) {
+        bool mine = true;
+        if (lane < kCsrsRows) mine = ptr[r0 + lane + 1] - ptr[r0 + lane] == 27;
+        for (int j = lane; j < 27 * kCsrsRows; j += 64) {
+            const int64_t row = r0 + j / 27;
+            mine = mine && (int64_t)col[lo + j] - row == (int64_t)col[lo + j % 27] - r0;
+        }
+        ok = __all(mine);
+    }
+    if (ok && lane < 27) desc[t].off[lane] = (int32_t)(col[lo + lane] - r0);
+    if (lane == 0) {
+        desc[t].uniform = ok ? 1 : 0;
+        flag[t] = ok ? 1 : 0;
+    }
+}
+
 // FP32 copy of the 1x3 BCRS values: 9-slot slices into the packed layout
 // (b13_val32_9), the others element by element.  One thread per (slice, lane).
 __global__ __launch_bounds__(kBlock) void k_b13_cast_f32(int64_t nslices, const int32_t *__restrict__ slot_base,
@@ -375,6 +409,26 @@ int scan_counts(mfe_ctx *ctx, int64_t n, const int32_t *in, int32_t *out, int64_
         set_error(std::string("scan launch failed: ") + hipGetErrorString(e));
         return MFE_EHIP;
     }
+    return MFE_OK;
+}
+
+int build_csr_tiles(mfe_problem *P) {
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t ntiles = (P->m + kCsrsRows - 1) / kCsrsRows;
+    if (ntiles == 0) return MFE_OK;
+    TempBuffer flag(ctx), total(ctx);
+    MFE_TRY(dev_alloc(ctx, &P->cdesc, (size_t)ntiles * sizeof(CsrDesc)));
+    MFE_TRY(flag.alloc((size_t)ntiles * sizeof(int32_t)));
+    MFE_TRY(total.alloc(sizeof(int64_t)));
+    hipLaunchKernelGGL(k_csr_desc, dim3((unsigned)ntiles), dim3(64), 0, s, P->m, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, (CsrDesc *)P->cdesc.ptr, (int32_t *)flag.ptr());
+    MFE_HIP_TRY(hipGetLastError());
+    MFE_TRY(scan_counts(ctx, ntiles, (const int32_t *)flag.ptr(), nullptr, (int64_t *)total.ptr()));
+    int64_t n = 0;
+    MFE_HIP_TRY(hipMemcpyAsync(&n, total.ptr(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    P->csr_ctiles = n;
     return MFE_OK;
 }
 

@@ -139,14 +139,11 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
 // consecutive rows, loads their (value, column) runs, contiguous in the CRS
 // arrays, with coalesced loads into LDS, then each row is summed by
 // 64 / kCsrsRows lanes (strided entries, combined by an xor butterfly)
-// reading LDS and gathering x.
-// A tile whose entries exceed the LDS capacity is summed straight from
-// global memory instead.
-#ifndef MFE_CSRS_ROWS
-#define MFE_CSRS_ROWS 16  // rows per wavefront tile (64 / rows lanes per row); 8, 16 and 32 measured
-#endif
-constexpr int kCsrsRows = MFE_CSRS_ROWS;       // rows per wavefront tile
-constexpr int kCsrsCap = kCsrsRows * 28;       // staged entries per wavefront tile
+// reading LDS and gathering x.  A tile with a uniform descriptor (CsrDesc)
+// stages only its values and forms the columns from the 27 offsets, in the
+// same summation order.  A tile whose entries exceed the LDS capacity is
+// summed straight from global memory instead.
+constexpr int kCsrsCap = kCsrsRows * 28;       // staged entries per wavefront tile (kCsrsRows: common.hpp)
 
 __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -157,6 +154,7 @@ __device__ __forceinline__ void wave_sync() {
 template <typename T, int MODE, bool MNT>
 __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *__restrict__ ptr,
                                                       const int32_t *__restrict__ col,
+                                                      const CsrDesc *__restrict__ cdesc,
                                                       const T *__restrict__ val, Epi<T> E, CgState *st,
                                                       double *partials) {
     if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
@@ -176,8 +174,17 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
         const int64_t r1 = r0 + kCsrsRows < m ? r0 + kCsrsRows : m;
         const int32_t lo = ptr[r0], hi = ptr[r1];
         const int64_t row = r0 + rl;
+        const CsrDesc &D = cdesc[tr.t * (kBlock / 64) + wave];  // this wavefront's tile
         T sum = 0;
-        if (hi - lo <= kCsrsCap) {
+        if (D.uniform) {
+            // 27 entries per row, columns row + off[k]: stage the values only
+            for (int j = lane; j < 27 * kCsrsRows; j += 64) sv[j] = matrix_load<MNT>(val + lo + j);
+            if (lane < 27) sc[lane] = D.off[lane];
+            wave_sync();
+            const int a = rl * 27;
+            for (int j = sub; j < 27; j += LPR) sum += sv[a + j] * E.x[row + sc[j]];
+            wave_sync();
+        } else if (hi - lo <= kCsrsCap) {
             for (int32_t j = lo + lane; j < hi; j += 64) {
                 sv[j - lo] = matrix_load<MNT>(val + j);
                 sc[j - lo] = matrix_load<MNT>(col + j);
@@ -300,8 +307,13 @@ int launch_csr_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
     const long ntiles = (P->m + kBlock / L - 1) / (kBlock / L);
 #endif
     const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
+#if MFE_CSR_STREAM
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, (const CsrDesc *)P->cdesc.ptr, val, E, st, partials);
+#else
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->ptr.ptr,
                        (const int32_t *)P->col.ptr, val, E, st, partials);
+#endif
     MFE_HIP_TRY(hipGetLastError());
     if (grid_out) *grid_out = grid;
     return MFE_OK;

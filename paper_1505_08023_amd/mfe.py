@@ -142,6 +142,10 @@ class Problem:
         # column indices and their real blocks (zeros without 1x3 BCRS)
         self.b13_layout = dict(zip(("slices", "slots", "compressed_slices", "compressed_blocks"),
                                    (t.value for t in v)))
+        v = [ctypes.c_int64() for _ in range(3)]
+        check(ctx.lib.mfe_problem_csr_layout(handle, *[ctypes.byref(t) for t in v]), "mfe_problem_csr_layout")
+        # CRS wavefront tiles: rows per tile, tiles, tiles with descriptor-formed column indices
+        self.csr_layout = dict(zip(("tile_rows", "tiles", "compressed_tiles"), (t.value for t in v)))
         ctx.problems.add(self)
         _LIVE.add(self)
 

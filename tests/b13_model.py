@@ -49,3 +49,33 @@ def descriptor_slices_closed_form(Nx, Ny, Nz):
             hi -= 1
         count += max(0, hi // 64 - (lo + 63) // 64)
     return count
+
+
+def csr_descriptor_tiles(ptr, col, m, R=16):
+    """CRS wavefront tiles of R rows whose columns the library may form from a
+    descriptor, modelled directly on the oracle's CRS: a full tile whose rows
+    each hold 27 entries, with column - row per entry the same in every row."""
+    count = 0
+    for t in range(m // R):
+        r0 = t * R
+        lo, hi = ptr[r0], ptr[r0 + R]
+        if hi - lo != 27 * R or np.any(np.diff(ptr[r0:r0 + R + 1]) != 27):
+            continue
+        d = col[lo:hi].astype(np.int64).reshape(R, 27) - np.arange(r0, r0 + R)[:, None]
+        if np.all(d == d[0]):
+            count += 1
+    return count
+
+
+def csr_descriptor_tiles_closed_form(Nx, Ny, Nz, R=16):
+    """Box mesh: the rows with all 27 neighbours (1 <= ix <= Nx-1 and the same
+    for y and z) form one run of Nx-1 consecutive rows per interior x-line;
+    every R-row tile inside such a run qualifies and no other tile does."""
+    nx, nxny = Nx + 1, (Nx + 1) * (Ny + 1)
+    count = 0
+    for iz in range(1, Nz):
+        for iy in range(1, Ny):
+            lo = iz * nxny + iy * nx + 1
+            hi = lo + Nx - 1
+            count += max(0, hi // R - (lo + R - 1) // R)
+    return count

@@ -33,6 +33,30 @@ def test_block_count_matches_oracle_conversion(N):
     assert bptr[-1] == nx * (3 * ny - 2) * (3 * nz - 2)
 
 
+def test_csr_bytes_with_tile_descriptors_at_256_cubed():
+    m, nnz = 257 ** 3, 769 ** 3
+    tiles = (m + 15) // 16
+    ct = b13_model.csr_descriptor_tiles_closed_form(256, 256, 256)
+    assert ct == 975_375
+    lay = dict(tile_rows=16, tiles=tiles, compressed_tiles=ct)
+    by = bench.spmv_bytes("csr", m, nnz, 0, layout=lay)
+    # values; indices of the 85,538 indexed tiles; descriptors; bounds; x, y
+    assert by == 8 * nnz + 4 * (nnz - 432 * ct) + 112 * ct + 4 * (tiles + 1) + 4 * (m - 16 * ct) + 16 * m
+    assert by < bench.spmv_bytes("csr", m, nnz, 0)
+
+
+def test_csr_tile_closed_form_matches_assembly():
+    """The closed-form count of CRS descriptor tiles against the direct model
+    over the oracle's CRS, on meshes with every alignment of x-lines to the
+    16-row tiles."""
+    rng = np.random.default_rng(3)
+    meshes = [(20, 20, 20), (33, 33, 33), (40, 9, 6), (63, 5, 5), (17, 17, 17), (2, 3, 4)] + \
+        [tuple(int(v) for v in rng.integers(1, 40, 3)) for _ in range(12)]
+    for N in meshes:
+        A = oracle.assemble(*N)
+        assert b13_model.csr_descriptor_tiles(A.ptr, A.col, A.m) == b13_model.csr_descriptor_tiles_closed_form(*N), N
+
+
 def test_descriptor_slice_closed_form_matches_blocking():
     """The closed-form count of descriptor slices (used for the 256^3 byte
     count and its GPU check) against the direct model over the oracle's 1x3

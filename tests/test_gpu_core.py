@@ -104,9 +104,9 @@ def test_bcrs13_matches_oracle(ctx, N):
 
 @pytest.mark.parametrize("N", [(2, 3, 4), (5, 3, 7), (20, 20, 20), (33, 33, 33), (40, 9, 6)])
 def test_bcrs13_descriptor_slices(ctx, N):
-    """The per-slice descriptors cover exactly the slices the host model
-    finds (index work: bit-exact counts), and the products through them
-    match the oracle."""
+    """The per-slice (1x3 BCRS) and per-tile (CRS) descriptors cover exactly
+    the slices and tiles the host models find (index work: bit-exact counts),
+    and the products through them match the oracle."""
     A = oracle.assemble(*N)
     bptr, bcol, _ = oracle.bcrs13(A)
     want = b13_model.descriptor_slices(bptr, bcol, A.m)
@@ -116,8 +116,13 @@ def test_bcrs13_descriptor_slices(ctx, N):
     assert (lay["compressed_slices"], lay["compressed_blocks"]) == want, (lay, want)
     if min(N) >= 20:
         assert lay["compressed_slices"] >= 0.5 * lay["slices"]
+    # CRS wavefront tiles with descriptors
+    cl = P.csr_layout
+    assert cl["tiles"] == (A.m + cl["tile_rows"] - 1) // cl["tile_rows"]
+    assert cl["compressed_tiles"] == b13_model.csr_descriptor_tiles(A.ptr, A.col, A.m, cl["tile_rows"])
     x = inputs.spmv_vector(A.m, seed=3)
-    check_spmv(np_(P.spmv(torch.tensor(x, device=ctx.device), fmt="bcrs13")), A, x, oracle.csr_spmv(A, x))
+    for fmt in ("bcrs13", "csr"):
+        check_spmv(np_(P.spmv(torch.tensor(x, device=ctx.device), fmt=fmt)), A, x, oracle.csr_spmv(A, x))
     P.close()
 
 
@@ -171,6 +176,9 @@ def test_spmv_full_size_sampled_rows(ctx, fmt):
     if fmt == "bcrs13":
         assert P.b13_layout["compressed_slices"] == b13_model.descriptor_slices_closed_form(*N)
         assert P.b13_layout["compressed_blocks"] == 576 * P.b13_layout["compressed_slices"]
+    else:
+        R = P.csr_layout["tile_rows"]
+        assert P.csr_layout["compressed_tiles"] == b13_model.csr_descriptor_tiles_closed_form(*N, R=R)
     x = inputs.spmv_vector(m, seed=0)
     y = np_(P.spmv(torch.tensor(x, device=ctx.device), fmt=fmt))
     rng = np.random.default_rng(7)
