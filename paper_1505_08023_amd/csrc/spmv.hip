@@ -2,12 +2,16 @@
 // epilogues (the DOT that follows MATVEC in CG, Sec. 3.1 discussion of
 // Fig 3.5, and the residual at CG start/exit).
 //
-//   CRS (Fig 3.1):  L lanes per row stream the row's (val, col) pairs
-//                   contiguously, gather x, and combine by an xor butterfly.
+//   CRS (Fig 3.1):  16-row wavefront tiles staged in LDS, 4 lanes per row
+//                   over the row's (val, col) pairs, gathers of x, an xor
+//                   butterfly per row.
 //   1x3 BCRS:       one lane per row; per block one column index and three
 //                   values, all coalesced across the wavefront's 64 rows,
 //                   and three consecutive x entries (the implicit column
 //                   increment of Fig 3.2, unrolled as in Fig 3.3).
+//   In both, tiles or slices whose column indices follow one offset per
+//   entry (CsrDesc, B13Desc) form them from a small descriptor instead of
+//   loading them; the sums are the same.
 //
 // Both kernels run a workgroup grid sized to stay resident and walk row tiles
 // in XCD-contiguous ranges, so each XCD's L2 holds the x entries of the mesh
