@@ -126,6 +126,57 @@ def test_bcrs13_descriptor_slices(ctx, N):
     P.close()
 
 
+def shifted_pattern_csr(m, e, offsets, edge, seed):
+    """Rows edge..m-edge-1: 9 runs of 3 columns at i + e_i + offsets[k]
+    (e_i in {0, 1}); the other rows: their diagonal only.  Random values."""
+    rng = np.random.default_rng(seed)
+    cols = []
+    for i in range(m):
+        if edge <= i < m - edge:
+            cols.append(np.concatenate([i + e[i] + d + np.arange(3) for d in offsets]))
+        else:
+            cols.append(np.array([i]))
+    ptr = np.concatenate([[0], np.cumsum([len(c) for c in cols])]).astype(np.int64)
+    col = np.concatenate(cols).astype(np.int32)
+    return oracle.CSR(ptr, col, rng.uniform(-1, 1, len(col)), np.zeros(m))
+
+
+def test_descriptors_on_a_generic_matrix_with_random_row_shifts(ctx):
+    """A CRS matrix (not a mesh) whose middle rows hold 9 runs of 3 columns at
+    row + e_row + d_k with random 0/1 shifts e: every full 64-row slice there
+    gets a 1x3 BCRS descriptor whatever its shift bits; CRS tiles get one
+    only where e is constant over the tile.  Coverage against the host
+    models, products against the oracle in both formats and precisions."""
+    from paper_1505_08023_amd.mfe import Problem
+    m, edge = 64 * 40 + 23, 700
+    offsets = [-640, -333, -200, -3, 0, 3, 150, 321, 640]
+    rng = np.random.default_rng(9)
+    e = rng.integers(0, 2, m)
+    e[64 * 20:64 * 22] = 0  # two slices without shifts
+    e[64 * 24:64 * 26] = 1  # and two with every row shifted
+    A = shifted_pattern_csr(m, e, offsets, edge, seed=10)
+    bptr, bcol, _ = oracle.bcrs13(A)
+    d = ctx.device
+    P = Problem.from_csr(ctx, torch.tensor(A.ptr.astype(np.int32), device=d), torch.tensor(A.col, device=d),
+                         torch.tensor(A.val, device=d), formats=("csr", "bcrs13"), precisions=("f64", "f32"))
+    want = b13_model.descriptor_slices(bptr, bcol, A.m)
+    assert want[0] > 0 and want[0] == sum(1 for s in range(m // 64) if 64 * s >= edge and 64 * s + 64 <= m - edge)
+    assert (P.b13_layout["compressed_slices"], P.b13_layout["compressed_blocks"]) == want
+    R = P.csr_layout["tile_rows"]
+    assert P.csr_layout["compressed_tiles"] == b13_model.csr_descriptor_tiles(A.ptr, A.col, A.m, R) > 0
+    x = inputs.spmv_vector(A.m, seed=11)
+    y_ref = oracle.csr_spmv(A, x)
+    for fmt in ("csr", "bcrs13"):
+        check_spmv(np_(P.spmv(torch.tensor(x, device=d), fmt=fmt)), A, x, y_ref)
+        x32 = x.astype(np.float32)
+        a32 = A.val.astype(np.float32).astype(np.float64)
+        ref32 = np.add.reduceat(a32 * x32.astype(np.float64)[A.col], A.ptr[:-1])
+        scale32 = np.add.reduceat(np.abs(a32) * np.abs(x32.astype(np.float64))[A.col], A.ptr[:-1])
+        y32 = np_(P.spmv(torch.tensor(x32, device=d), fmt=fmt)).astype(np.float64)
+        assert np.all(np.abs(y32 - ref32) <= 32 * np.finfo(np.float32).eps * scale32 + 1e-38)
+    P.close()
+
+
 def test_set_bc_matches_fresh_assembly(ctx):
     N = (9, 7, 8)
     fv = np.random.default_rng(5).uniform(0, 1, 6)
