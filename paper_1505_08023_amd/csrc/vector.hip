@@ -17,6 +17,14 @@
 namespace mfe {
 namespace {
 
+// 16-byte vector of T with only T's alignment (caller vectors need not be
+// 16-byte aligned; gfx950 serves such accesses with one load or store).
+template <typename T>
+struct Vec16 {
+    static constexpr int W = 16 / (int)sizeof(T);
+    typedef T t __attribute__((ext_vector_type(16 / sizeof(T)), aligned(sizeof(T))));
+};
+
 template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ r, const T *__restrict__ q,
                                                      CgState *st, const double *__restrict__ pq_part, int n_pq,
@@ -41,7 +49,24 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ 
     const T a = (T)alpha;
     double d = 0.0;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // 16 bytes per vector access (the pointers need only element alignment),
+    // then the < W trailing elements (69.1 -> 64.9 us at 256^3)
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t mv = m / W;
+    for (int64_t i = gid; i < mv; i += stride) {
+        typename V::t rv = ((const typename V::t *)r)[i];
+        const typename V::t qv = stream_load((const typename V::t *)q + i, NT);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const T ri = rv[j] - a * qv[j];
+            rv[j] = ri;
+            d += (double)ri * (double)ri;
+        }
+        ((typename V::t *)r)[i] = rv;
+    }
+    for (int64_t i = mv * W + gid; i < m; i += stride) {
         const T ri = r[i] - a * stream_load(q + i, NT);
         r[i] = ri;
         d += (double)ri * (double)ri;
@@ -70,6 +95,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__
     }
     // p is updated even on the last iteration: the update is not needed then,
     // but deciding it would need the stopping test in every workgroup
+    // (16-byte vector accesses were measured no faster here: 114.7 against
+    // 113.4 us at 256^3)
     const T a = (T)alpha, be = (T)beta;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
     for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
