@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # and WRITE_SIZE (x 1.0) counter runs, scaled by streaming kernels of known
 # size (profiles/spmv_b13_fp64_256cubed_hbm_counters.md).  Reset to None
 # whenever the kernel changes.
-MEASURED_TRAFFIC = {("bcrs13", 256): 4.007e9, ("csr", 256): None}
+MEASURED_TRAFFIC = {("bcrs13", 256): 4.007e9, ("csr", 256): 4.824e9}
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
 
 
@@ -213,8 +213,8 @@ def main():
 
 def assembly_and_conversion(ctx, n, torch, reps=3):
     """Best-of-reps wall time of creating the n^3 problem in CRS only
-    (mesh, structure, element sums, Dirichlet elimination) and the extra time
-    when the 1x3 BCRS is built too."""
+    (mesh, structure, element sums, Dirichlet elimination, CRS tile
+    descriptors) and the extra time when the 1x3 BCRS is built too."""
     from paper_1505_08023_amd.mfe import Problem
     best = {}
     for fmts in (("csr",), ("csr", "bcrs13")):
