@@ -188,7 +188,7 @@ def main():
                    "tol": args.tol, "x0": "zero", "step": "one CG solve to tol"},
         "roofline": {"bound": "hbm", "achieved": dom["GBps"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["GBps"] / HBM_PEAK_GBS, "traffic": MEASURED_TRAFFIC.get((args.fmt, N)),
-                     "kernel": "k_spmv_b13p<double, dot>" if args.fmt == "bcrs13" else "k_spmv_csr<double, 32, dot>",
+                     "kernel": "k_spmv_b13p<double, dot>" if args.fmt == "bcrs13" else "k_spmv_csrs<double, dot>",
                      "timing": "HIP events around each launch on the library stream, 1 GiB of other memory "
                                "written before each, as between two products of a CG iteration",
                      "bytes_per_launch": dom["bytes"], "mean_launch_ms": dom["mean_ms"]},
@@ -202,6 +202,11 @@ def main():
     # known-size kernel that scales the HBM byte counters of a profiler run
     line["copy_probe"] = copy_probe(torch, ctx.device)
     log(f"[bench] copy probe: {line['copy_probe']['GBps']:.0f} GB/s")
+    # the library's own streaming probes (16-byte non-temporal accesses): the
+    # bandwidth a plain stream reaches on this machine, next to the 8 TB/s peak
+    line["stream_probe"] = stream_probe(ctx, torch)
+    line["roofline"]["frac_of_stream_read"] = dom["GBps"] / line["stream_probe"]["read_GBps"]
+    log(f"[bench] stream probe: {line['stream_probe']}")
     if not args.no_extras:
         extras(args, ctx, P, x, line, torch)
     if not args.no_cpu_baseline:
@@ -242,6 +247,31 @@ def copy_probe(torch, device, nbytes=1 << 30):
     torch.cuda.synchronize()
     ms = e0.elapsed_time(e1) / 10
     return dict(bytes_moved=2 * nbytes, ms=ms, GBps=2 * nbytes / (ms * 1e-3) / 1e9)
+
+
+def stream_probe(ctx, torch, nbytes=2 << 30, reps=10):
+    """Median bandwidth of the library's streaming read and copy probes over
+    nbytes of source (HIP events around each launch)."""
+    n = nbytes // 8
+    src = torch.ones(n, dtype=torch.float64, device=ctx.device)
+    out = {}
+    for kind, dst, moved in (("read", torch.empty(4096, dtype=torch.float64, device=ctx.device), nbytes),
+                             ("copy", torch.empty(n // 2, dtype=torch.float64, device=ctx.device), nbytes)):
+        m = n if kind == "read" else n // 2  # the copy moves nbytes in all (half read, half written)
+        src_k = src if kind == "read" else src[:m]
+        torch.cuda.synchronize()
+        for _ in range(3):
+            ctx.stream_probe(kind, src_k, dst)
+        pairs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(reps)]
+        for ev in pairs:
+            ctx.stream_probe(kind, src_k, dst, events=ev)
+        ctx.stream.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in pairs)[reps // 2]
+        out[f"{kind}_GBps"] = moved / (ms * 1e-3) / 1e9
+        out[f"{kind}_ms"] = ms
+    out["bytes_moved"] = nbytes
+    del src
+    return out
 
 
 def extras(args, ctx, P, x, line, torch):

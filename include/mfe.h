@@ -188,6 +188,16 @@ int mfe_spmv_dot_f32(const mfe_problem *p, int format, const float *p_dev, float
  * written to *out_host (the stream is synchronised). */
 int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, double *out_host);
 
+/* Streaming bandwidth probe, a measurement reference for the kernels above
+ * (not part of the method): kind 0 copies n doubles from src_dev to dst_dev,
+ * kind 1 reads n doubles from src_dev and writes one partial sum per
+ * workgroup to dst_dev (room for 4096 doubles), both with grid-stride
+ * 16-byte non-temporal accesses on a resident grid.  src_dev and dst_dev
+ * must not overlap.  ev_before / ev_after as in mfe_spmv_dot.  Does not
+ * synchronise. */
+int mfe_stream_probe(mfe_ctx *ctx, int kind, int64_t n, const double *src_dev, double *dst_dev, void *ev_before,
+                     void *ev_after);
+
 /* Unpreconditioned CG (Sec. 1 CG module) on A x = b in FP64, with the
  * SpMV of `format` (MFE_CSR or MFE_BCRS13, which must have been built).
  * x_dev holds x0 on entry and the solution on exit.  r0 = b - A x0; the loop

@@ -129,7 +129,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 4; }
+int mfe_version(void) { return 5; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -508,6 +508,21 @@ int mfe_dot(mfe_ctx *ctx, int64_t n, const double *x_dev, const double *y_dev, d
     MFE_HIP_TRY(hipMemcpyAsync(&pin[3], st, sizeof(CgState), hipMemcpyDeviceToHost, ctx->stream));
     MFE_HIP_TRY(hipStreamSynchronize(ctx->stream));
     *out_host = pin[3].pq;
+    return MFE_OK;
+}
+
+int mfe_stream_probe(mfe_ctx *ctx, int kind, int64_t n, const double *src_dev, double *dst_dev, void *ev_before,
+                     void *ev_after) {
+    clear_error();
+    if (!ctx || (kind != 0 && kind != 1) || n < 0 || (n > 0 && (!src_dev || !dst_dev))) {
+        set_error("ctx, kind 0 or 1, n >= 0 and (when n > 0) src and dst must be given");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(set_device(ctx));
+    if (n == 0) return MFE_OK;
+    if (ev_before) MFE_HIP_TRY(hipEventRecord((hipEvent_t)ev_before, ctx->stream));
+    MFE_TRY(launch_stream_probe(ctx, kind, n, src_dev, dst_dev));
+    if (ev_after) MFE_HIP_TRY(hipEventRecord((hipEvent_t)ev_after, ctx->stream));
     return MFE_OK;
 }
 

@@ -289,6 +289,8 @@ int launch_zero_if(int64_t m, double *x, double *r, double *p, const double *b, 
                    hipStream_t s);
 int launch_dot(mfe_ctx *ctx, int64_t n, const double *x, const double *y, double *partials, hipStream_t s,
                int *grid);
+// bandwidth probes: kind 0 copies src to dst, kind 1 reads src into per-workgroup partials at dst
+int launch_stream_probe(mfe_ctx *ctx, int kind, int64_t n, const double *src, double *dst);
 
 // Grid sizing shared by the launchers.  resident_per_cu: workgroups of
 // kBlock threads of `kernel` that fit on one CU (cached per kernel).

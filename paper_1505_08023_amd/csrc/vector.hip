@@ -356,7 +356,47 @@ int vec_grid(const void *kern, int64_t m, int num_cu) {
     return resident_grid((long)num_cu * resident_per_cu(kern), (long)((m + kBlock - 1) / kBlock));
 }
 
+// Streaming bandwidth probes (a reference for the bandwidth the kernels above
+// reach): grid-stride 16-byte non-temporal accesses over n doubles.
+__global__ __launch_bounds__(kBlock) void k_stream_copy(int64_t n, const double *__restrict__ src,
+                                                        double *__restrict__ dst) {
+    using V = Vec16<double>;
+    const int64_t nv = n / 2, stride = (int64_t)gridDim.x * kBlock;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    for (int64_t i = gid; i < nv; i += stride)
+        __builtin_nontemporal_store(__builtin_nontemporal_load((const V::t *)src + i), (V::t *)dst + i);
+    if (gid == 0 && (n & 1)) dst[n - 1] = src[n - 1];
+}
+
+// Reads n doubles and writes one partial sum per workgroup (so that no load
+// can be dropped).
+__global__ __launch_bounds__(kBlock) void k_stream_read(int64_t n, const double *__restrict__ src,
+                                                        double *__restrict__ part) {
+    using V = Vec16<double>;
+    const int64_t nv = n / 2, stride = (int64_t)gridDim.x * kBlock;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double s = 0.0;
+    for (int64_t i = gid; i < nv; i += stride) {
+        const V::t v = __builtin_nontemporal_load((const V::t *)src + i);
+        s += v[0] + v[1];
+    }
+    if (gid == 0 && (n & 1)) s += src[n - 1];
+    s = block_sum(s);
+    if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
 }  // namespace
+
+int launch_stream_probe(mfe_ctx *ctx, int kind, int64_t n, const double *src, double *dst) {
+    const void *kern = kind == 0 ? (const void *)k_stream_copy : (const void *)k_stream_read;
+    const int g = vec_grid(kern, (n + 1) / 2, ctx->num_cu);  // at most kMaxPartials workgroups
+    if (kind == 0)
+        hipLaunchKernelGGL(k_stream_copy, dim3(g), dim3(kBlock), 0, ctx->stream, n, src, dst);
+    else
+        hipLaunchKernelGGL(k_stream_read, dim3(g), dim3(kBlock), 0, ctx->stream, n, src, dst);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
 
 template <typename T, bool NT>
 int update_r_as(const mfe_problem *P, void *r, const void *q, CgState *st, const double *pq_partials, int n_pq,

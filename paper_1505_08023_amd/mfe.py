@@ -110,6 +110,26 @@ class Context:
                                    _ptr(y, torch.float64, n, "y"), ctypes.byref(out)), "mfe_dot")
         return out.value
 
+    def stream_probe(self, kind, src, dst, events=None):
+        """Bandwidth probe (mfe_stream_probe): kind "copy" writes src into dst,
+        kind "read" reads src and writes per-workgroup sums to dst (>= 4096
+        doubles).  events = (before, after) torch.cuda.Event pair recorded
+        around the kernel on the library's stream."""
+        n = src.numel()
+        k = {"copy": 0, "read": 1}[kind]
+        ev = (None, None)
+        if events is not None:
+            for e in events:  # materialise the HIP event handles on this stream
+                if not e.cuda_event:
+                    e.record(self.stream)
+            ev = (ctypes.c_void_p(events[0].cuda_event), ctypes.c_void_p(events[1].cuda_event))
+        if dst.numel() < (n if k == 0 else 4096):
+            raise ValueError("dst too small for the probe")
+        with _on(self):
+            check(self.lib.mfe_stream_probe(self.handle, k, n, _ptr(src, torch.float64, n, "src"),
+                                            _ptr(dst, torch.float64, None, "dst"), ev[0], ev[1]),
+                  "mfe_stream_probe")
+
     def close(self):
         if self.handle:
             for p in list(self.problems):

@@ -278,6 +278,23 @@ def test_from_csr_rejects_bad_structure(ctx):
                              torch.ones(3, dtype=torch.float64, device=d))
 
 
+def test_stream_probe(ctx):
+    """The bandwidth probes do what they time: the copy is exact, the read's
+    per-workgroup partials sum to the sum of the input (ones: exact)."""
+    d = ctx.device
+    for n in (0, 1, 7, 1000, 2_000_003):
+        src = torch.arange(n, dtype=torch.float64, device=d)
+        dst = torch.full((n,), -1.0, dtype=torch.float64, device=d)
+        ctx.stream_probe("copy", src, dst)
+        ctx.stream.synchronize()
+        assert torch.equal(dst, src)
+        ones = torch.ones(n, dtype=torch.float64, device=d)
+        part = torch.zeros(4096, dtype=torch.float64, device=d)
+        ctx.stream_probe("read", ones, part)
+        ctx.stream.synchronize()
+        assert float(part.sum()) == float(n)
+
+
 def test_dot_matches_oracle_and_is_reproducible(ctx):
     for n in (0, 1, 63, 1000, 2_000_003):
         x = inputs.spmv_vector(n, seed=1)
