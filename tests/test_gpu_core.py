@@ -201,7 +201,9 @@ def check_spmv(y_gpu, A, x, y_ref):
     assert np.linalg.norm(y_gpu - y_ref) <= 1e-12 * np.linalg.norm(y_ref)
 
 
-@pytest.mark.parametrize("N", MESHES + [(64, 64, 64), (128, 128, 128)])
+# 64^3: matrices loaded through the caches; 112^3: non-temporal loads with the
+# plain 1x3 BCRS walk; 128^3: non-temporal loads with the pipelined walk
+@pytest.mark.parametrize("N", MESHES + [(64, 64, 64), (112, 112, 112), (128, 128, 128)])
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
 def test_spmv_matches_oracle(ctx, N, fmt):
     print("spmv", N, fmt, flush=True)
@@ -242,6 +244,31 @@ def test_spmv_full_size_sampled_rows(ctx, fmt):
             ref += vv * x[cc]
         scale = float(np.sum(np.abs(v) * np.abs(x[c])))
         assert abs(y[r] - ref) <= 1e-12 * scale + 1e-300, (r, y[r], ref)
+    P.close()
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_spmv_f32_full_size_sampled_rows(ctx, fmt):
+    """256^3 FP32 product (the inner product of the mixed-precision solve, in
+    its launch configuration: packed FP32 values, non-temporal loads); rows
+    sampled and rebuilt by the oracle, bar as in the FP32 SpMV tests: per row
+    |d| <= 32 eps32 sum_j |A32_ij x32_j| against the FP64 product of the
+    FP32-rounded matrix and vector."""
+    N = (256, 256, 256)
+    P = mesh_problem(ctx, N, formats=(fmt,), precisions=("f64", "f32"))
+    m = P.m
+    x32 = inputs.spmv_vector(m, seed=6, dtype=np.float32)
+    y = np_(P.spmv(torch.tensor(x32, device=ctx.device), fmt=fmt)).astype(np.float64)
+    rng = np.random.default_rng(8)
+    rows = np.unique(np.concatenate([rng.integers(0, m, 3000), np.arange(0, 200), np.arange(m - 200, m)]))
+    got, _ = oracle.assemble_rows(*N, rows)
+    x64 = x32.astype(np.float64)
+    eps32 = float(np.finfo(np.float32).eps)
+    for r, (c, v) in zip(rows, got):
+        a32 = np.asarray(v, np.float32).astype(np.float64)
+        ref = float(np.sum(a32 * x64[c]))
+        scale = float(np.sum(np.abs(a32) * np.abs(x64[c])))
+        assert abs(y[r] - ref) <= 32 * eps32 * scale + 1e-38, (r, y[r], ref)
     P.close()
 
 
