@@ -461,7 +461,6 @@ def extras(args, ctx, P, x, line, torch):
         net = Net(ctx, 65, 1)
         net.set_params(params)
         seeds = list(range(learned.HELD_OUT_BASE, learned.HELD_OUT_BASE + args.learned_samples))
-        learned.evaluate(ctx, net, 64, seeds[:2])  # warm-up (graph capture)
         ev = learned.evaluate(ctx, net, 64, seeds)
         ev.pop("rows")
         ev["weights"] = os.path.relpath(wpath, ROOT)

@@ -272,6 +272,14 @@ int mfe_verify_series(const mfe_problem *p, const double *x_dev, double x_max, d
 int mfe_cg_mixed(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol,
                  int max_outer, int max_inner, mfe_cg_stats *stats);
 
+/* mfe_cg_mixed from an initial guess that may be poor (the learned
+ * prediction with mixed precision): if the first FP64 residual has
+ * ||b - A x0||_2 >= ||b||_2 the solve starts from x0 = 0 instead, decided on
+ * the device as in mfe_cg_warm; stats->guess_rejected reports it.
+ * Arguments and return values as mfe_cg_mixed. */
+int mfe_cg_mixed_warm(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol,
+                      int max_outer, int max_inner, mfe_cg_stats *stats);
+
 /* ---------------------------------------------------------------------
  * Batched solves: many box meshes of uneven size solved together (the
  * batched extension of the Sec. 1 CG module).  Each system follows exactly

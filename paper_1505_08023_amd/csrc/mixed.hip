@@ -83,11 +83,12 @@ int outer_residual(mfe_problem *P, int format, double *x, CgState *outer, CgStat
     return MFE_OK;
 }
 
-int set_state(mfe_ctx *ctx, CgState *dev, double tol, int max_iter) {
+int set_state(mfe_ctx *ctx, CgState *dev, double tol, int max_iter, bool warm = false) {
     CgState h{};
     h.tol = tol;
     h.max_iter = max_iter;
     h.status = kRunning;
+    h.warm = warm ? 1 : 0;
     CgState *pin = (CgState *)ctx->pinned;
     pin[2] = h;
     MFE_HIP_TRY(hipMemcpyAsync(dev, &pin[2], sizeof(CgState), hipMemcpyHostToDevice, ctx->stream));
@@ -98,7 +99,7 @@ int set_state(mfe_ctx *ctx, CgState *dev, double tol, int max_iter) {
 }  // namespace
 
 int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inner_tol, int max_outer,
-                   int max_inner, mfe_cg_stats *stats) {
+                   int max_inner, mfe_cg_stats *stats, bool warm) {
     const auto t0 = std::chrono::steady_clock::now();
     mfe_ctx *ctx = P->ctx;
     hipStream_t s = ctx->stream;
@@ -110,15 +111,20 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
     float *r32 = (float *)P->r32.ptr, *p32 = (float *)P->p32.ptr, *q32 = (float *)P->q32.ptr,
           *d32 = (float *)P->d32.ptr;
 
-    // outer tolerance test uses the start finalizer: max_iter 1 keeps it "running"
-    MFE_TRY(set_state(ctx, outer, tol, 1));
+    // outer tolerance test uses the start finalizer: max_iter 1 keeps it
+    // "running"; with warm, a guess with ||b - A x0|| >= ||b|| is replaced by
+    // x0 = 0 (r = b) on the device, as in the FP64 warm start
+    MFE_TRY(set_state(ctx, outer, tol, 1, warm));
     CgState o;
     MFE_TRY(outer_residual(P, format, x, outer, &o));
     const double bnorm = o.bnorm;
     int nouter = 0, inner_its = 0, spmvs = 1, rc = MFE_OK;
     bool fallback = false;
+    const bool rejected = o.zero_x == 2;
     double prev = o.bnorm > 0 ? std::sqrt(o.rho) : 0.0;
-    if (o.zero_x) MFE_TRY(launch_zero_if(P->m, x, nullptr, nullptr, nullptr, outer, ctx->num_cu, s));
+    if (o.zero_x)
+        MFE_TRY(launch_zero_if(P->m, x, (double *)P->r.ptr, (double *)P->p.ptr, (const double *)P->b.ptr, outer,
+                               ctx->num_cu, s));
     while (o.status == kRunning) {
         if (nouter >= max_outer) {
             rc = MFE_NOT_CONVERGED;
@@ -178,7 +184,7 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
         stats->rel_res_recurrence = rel_true;
         stats->rel_res_true = rel_true;
         stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-        stats->guess_rejected = 0;
+        stats->guess_rejected = rejected ? 1 : 0;
         stats->reserved_ = 0;
     }
     return rc;

@@ -109,48 +109,75 @@ def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0):
     return history
 
 
-def evaluate(ctx, net, n, seeds, tol=1e-8):
-    """Per held-out seed: plain CG from x0 = 0 against CG from the network's
-    guess (inference included in its time; the solver falls back to the zero
-    start when the guess's residual is not below ||b||).  Times are host wall
-    clock, GPU-synchronised."""
+def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True):
+    """Per held-out seed: plain FP64 CG from x0 = 0 against CG from the
+    network's guess (inference included in its time; the solver falls back to
+    the zero start when the guess's residual is not below ||b||), and, with
+    mixed, the FP32-inner / FP64-refinement solve from zero and from the guess
+    (the learned + mixed-precision form).  All solves stop at the same
+    tolerance on ||b - A x|| / ||b||.  Every variant runs once on the first
+    seed before timing (graph capture).  Times are host wall clock,
+    GPU-synchronised."""
     V = (n + 1) ** 3
-    P = Problem.mesh(ctx, n, n, n, formats=("bcrs13",))
+    P = Problem.mesh(ctx, n, n, n, formats=("bcrs13",), precisions=("f64", "f32") if mixed else ("f64",))
     x = torch.zeros(V, dtype=torch.float64, device=ctx.device)
     x0 = torch.zeros(V, dtype=torch.float64, device=ctx.device)
-    rows = []
-    for s in seeds:
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        st = fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t, st
+
+    def one(s):
         g = torch.tensor(inputs.node_field(n, n, n, inputs.smooth_faces(int(s))), device=ctx.device)
         P.set_bc(node_g=g)
-        # plain
+        r = dict(seed=int(s))
         x.zero_()
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        _, st0 = P.cg(x, tol=tol, max_iter=20000)
-        torch.cuda.synchronize()
-        t_plain = time.perf_counter() - t
-        # learned: inference, then CG from the guess (rejected on the device
-        # in favour of x0 = 0 when its residual is not below ||b||)
-        torch.cuda.synchronize()
-        t = time.perf_counter()
-        net.predict_x0(g, x0)
-        _, st1 = P.cg(x0, tol=tol, max_iter=20000, warm=True)
-        torch.cuda.synchronize()
-        t_learned = time.perf_counter() - t
+        r["t_plain"], st0 = timed(lambda: P.cg(x, tol=tol, max_iter=20000)[1])
+
+        def learned_fp64():
+            net.predict_x0(g, x0)
+            return P.cg(x0, tol=tol, max_iter=20000, warm=True)[1]
+        r["t_learned"], st1 = timed(learned_fp64)
+        r.update(its_plain=st0["iterations"], its_learned=st1["iterations"], used=not st1["guess_rejected"],
+                 res_plain=st0["rel_res_true"], res_learned=st1["rel_res_true"])
+        if mixed:
+            x.zero_()
+            r["t_mixed"], st2 = timed(lambda: P.cg_mixed(x, tol=tol)[1])
+
+            def learned_mixed():
+                net.predict_x0(g, x0)
+                return P.cg_mixed(x0, tol=tol, warm=True)[1]
+            r["t_learned_mixed"], st3 = timed(learned_mixed)
+            r.update(its_mixed=st2["iterations"], its_learned_mixed=st3["iterations"],
+                     res_mixed=st2["rel_res_true"], res_learned_mixed=st3["rel_res_true"],
+                     used_mixed=not st3["guess_rejected"])
         # the guess's own residual, outside the timed region
         net.predict_x0(g, x0)
         _, chk = P.cg(x0, tol=tol, max_iter=0)
-        rows.append(dict(seed=int(s), its_plain=st0["iterations"], its_learned=st1["iterations"],
-                         t_plain=t_plain, t_learned=t_learned, guess_rel_res=chk["rel_res_true"],
-                         used=not st1["guess_rejected"], res_plain=st0["rel_res_true"],
-                         res_learned=st1["rel_res_true"]))
+        r["guess_rel_res"] = chk["rel_res_true"]
+        return r
+
+    one(seeds[0])  # warm-up
+    rows = [one(s) for s in seeds]
     P.close()
     a = lambda k: float(np.mean([r[k] for r in rows]))
-    return dict(samples=len(rows), mean_its_plain=a("its_plain"), mean_its_learned=a("its_learned"),
-                mean_time_plain_s=a("t_plain"), mean_time_learned_s=a("t_learned"),
-                mean_guess_rel_res=a("guess_rel_res"), guesses_used=int(sum(r["used"] for r in rows)),
-                worst_res_learned=max(r["res_learned"] for r in rows),
-                speedup_time=a("t_plain") / a("t_learned"), rows=rows)
+    out = dict(samples=len(rows), mean_its_plain=a("its_plain"), mean_its_learned=a("its_learned"),
+               mean_time_plain_s=a("t_plain"), mean_time_learned_s=a("t_learned"),
+               mean_guess_rel_res=a("guess_rel_res"), guesses_used=int(sum(r["used"] for r in rows)),
+               worst_res_learned=max(r["res_learned"] for r in rows),
+               speedup_time=a("t_plain") / a("t_learned"))
+    if mixed:
+        out.update(mean_its_mixed=a("its_mixed"), mean_its_learned_mixed=a("its_learned_mixed"),
+                   mean_time_mixed_s=a("t_mixed"), mean_time_learned_mixed_s=a("t_learned_mixed"),
+                   worst_res_learned_mixed=max(r["res_learned_mixed"] for r in rows),
+                   guesses_used_mixed=int(sum(r["used_mixed"] for r in rows)),
+                   speedup_time_mixed=a("t_plain") / a("t_mixed"),
+                   speedup_time_learned_mixed=a("t_plain") / a("t_learned_mixed"))
+    out["rows"] = rows
+    return out
 
 
 def save(path, params, meta):

@@ -320,17 +320,21 @@ class Problem:
             out["u"] = u
         return out
 
-    def cg_mixed(self, x=None, tol=1e-10, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13"):
-        """FP32-inner CG inside FP64 iterative refinement.  Returns (x, stats dict)."""
+    def cg_mixed(self, x=None, tol=1e-10, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13",
+                 warm=False):
+        """FP32-inner CG inside FP64 iterative refinement from x (zero if
+        None); warm=True rejects a guess no closer than zero
+        (mfe_cg_mixed_warm).  Returns (x, stats dict)."""
         d = self.ctx.device
         if x is None:
             with _on(self.ctx):
                 x = torch.zeros(self.m, dtype=torch.float64, device=d)
         st = mfe_cg_stats()
+        name = "mfe_cg_mixed_warm" if warm else "mfe_cg_mixed"
         with _on(self.ctx):
-            rc = self.ctx.lib.mfe_cg_mixed(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"), float(tol),
-                                           float(inner_tol), int(max_outer), int(max_inner), ctypes.byref(st))
-        check(rc, "mfe_cg_mixed", (MFE_OK, MFE_NOT_CONVERGED))
+            rc = getattr(self.ctx.lib, name)(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"), float(tol),
+                                             float(inner_tol), int(max_outer), int(max_inner), ctypes.byref(st))
+        check(rc, name, (MFE_OK, MFE_NOT_CONVERGED))
         return x, st.as_dict()
 
     def close(self):

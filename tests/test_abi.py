@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_string():
     lib = _lib.load()
-    assert lib.mfe_version() == 5
+    assert lib.mfe_version() == 6
     assert isinstance(lib.mfe_last_error(), bytes)
 
 

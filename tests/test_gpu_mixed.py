@@ -126,3 +126,33 @@ def test_mixed_zero_rhs_and_bad_args(ctx):
     Q = Problem.mesh(ctx, 6, 6, 6)  # no FP32 values built
     with pytest.raises(MfeError, match="EUNSUPPORTED"):
         Q.cg_mixed(tol=1e-10)
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_mixed_warm_start(ctx, fmt):
+    """mfe_cg_mixed_warm keeps a guess closer than x0 = 0 (fewer inner
+    iterations, same accuracy) and otherwise solves from zero, bitwise as the
+    mixed solve from zero; mfe_cg_mixed never rejects."""
+    from paper_1505_08023_amd.mfe import Problem
+    N = (20, 20, 20)
+    A = oracle.assemble(*N)
+    ref = oracle.cg(A, tol=1e-12, max_iter=1000)
+    P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
+    x_zero, st_zero = P.cg_mixed(tol=1e-8, fmt=fmt)
+    rng = np.random.default_rng(12)
+    guess = ref["x"] + 1e-4 * rng.standard_normal(P.m)
+    dirichlet = oracle.boundary(*N)[0] != 0
+    guess[dirichlet] = ref["x"][dirichlet]
+    x, st = P.cg_mixed(x=torch.tensor(guess, device=ctx.device), tol=1e-8, fmt=fmt, warm=True)
+    assert st["guess_rejected"] == 0 and st["status"] == 0 and st["rel_res_true"] <= 1e-8
+    assert st["iterations"] < st_zero["iterations"]
+    bnorm = np.linalg.norm(A.b)
+    gap = np.linalg.norm(x.cpu().numpy() - ref["x"])
+    assert gap <= (st["rel_res_true"] + ref["rel_res_true"]) * bnorm / lam_min(N) + 1e-12
+    bad = torch.tensor(10.0 * rng.standard_normal(P.m), device=ctx.device)
+    x, st = P.cg_mixed(x=bad, tol=1e-8, fmt=fmt, warm=True)
+    assert st["guess_rejected"] == 1 and st["iterations"] == st_zero["iterations"]
+    assert torch.equal(x, x_zero)
+    x, st = P.cg_mixed(x=torch.tensor(10.0 * rng.standard_normal(P.m), device=ctx.device), tol=1e-8, fmt=fmt)
+    assert st["guess_rejected"] == 0 and st["status"] == 0 and st["rel_res_true"] <= 1e-8
+    P.close()

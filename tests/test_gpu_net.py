@@ -191,3 +191,26 @@ def test_network_training_reduces_loss(ctx):
     m = boundary_mask(G)
     assert np.array_equal(x0[m], g[0][m])
     net.close()
+
+
+def test_trained_network_reduces_cg_iterations(ctx):
+    """The shipped 64^3 network against the method without it, on held-out
+    boundary data: CG (FP64, and FP32-inner / FP64-refinement) from the
+    network's guess reaches the same 1e-8 tolerance in fewer iterations than
+    from x0 = 0, and every guess is kept (its residual is below ||b||)."""
+    import os
+    from paper_1505_08023_amd import learned
+    from paper_1505_08023_amd.mfe import Net
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    params, meta = learned.load(os.path.join(root, "paper_1505_08023_amd", "weights", "net64.npz"))
+    net = Net(ctx, 65, 1)
+    net.set_params(params)
+    seeds = list(range(learned.HELD_OUT_BASE + 900, learned.HELD_OUT_BASE + 904))
+    ev = learned.evaluate(ctx, net, 64, seeds)
+    print({k: v for k, v in ev.items() if k != "rows"})
+    assert ev["guesses_used"] == len(seeds) and ev["guesses_used_mixed"] == len(seeds)
+    assert ev["worst_res_learned"] <= 1e-8 and ev["worst_res_learned_mixed"] <= 1e-8
+    assert ev["mean_its_learned"] <= 0.85 * ev["mean_its_plain"]
+    assert ev["mean_its_learned_mixed"] < ev["mean_its_mixed"]
+    assert ev["mean_guess_rel_res"] < 1e-2
+    net.close()
