@@ -83,16 +83,20 @@ int outer_residual(mfe_problem *P, int format, double *x, CgState *outer, CgStat
     return MFE_OK;
 }
 
-int set_state(mfe_ctx *ctx, CgState *dev, double tol, int max_iter, bool warm = false) {
+// A fresh solver state (tolerance, cap, running), written on the device so
+// that no host round trip separates the refinement steps.
+__global__ void k_state_init(CgState *st, double tol, int max_iter, int warm) {
     CgState h{};
     h.tol = tol;
     h.max_iter = max_iter;
     h.status = kRunning;
-    h.warm = warm ? 1 : 0;
-    CgState *pin = (CgState *)ctx->pinned;
-    pin[2] = h;
-    MFE_HIP_TRY(hipMemcpyAsync(dev, &pin[2], sizeof(CgState), hipMemcpyHostToDevice, ctx->stream));
-    MFE_HIP_TRY(hipStreamSynchronize(ctx->stream));
+    h.warm = warm;
+    *st = h;
+}
+
+int set_state(mfe_ctx *ctx, CgState *dev, double tol, int max_iter, bool warm = false) {
+    hipLaunchKernelGGL(k_state_init, dim3(1), dim3(1), 0, ctx->stream, dev, tol, max_iter, warm ? 1 : 0);
+    MFE_HIP_TRY(hipGetLastError());
     return MFE_OK;
 }
 
