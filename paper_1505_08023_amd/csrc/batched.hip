@@ -443,6 +443,8 @@ int capture_iterations(mfe_batch *B, int format, const Tuning &t, T *x, T *r, T 
     return MFE_OK;
 }
 
+constexpr int kMaxBatchGraphs = 16;
+
 template <typename T>
 int graph_for_batch(mfe_batch *B, int format, const Tuning &t, bool f32, T *x, T *r, T *p, T *q, CgState *st, int k,
                     hipGraphExec_t *out) {
@@ -454,6 +456,18 @@ int graph_for_batch(mfe_batch *B, int format, const Tuning &t, bool f32, T *x, T
         }
     hipGraphExec_t ex = nullptr;
     MFE_TRY(capture_iterations<T>(B, format, t, x, r, p, q, st, k, &ex));
+    // bounded cache, as for single problems: drop the oldest graph once no
+    // work of the context uses it
+    if (B->graphs.size() >= (size_t)kMaxBatchGraphs) {
+        const hipError_t e = hipStreamSynchronize(B->ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(ex);
+            set_error(std::string("hipStreamSynchronize failed: ") + hipGetErrorString(e));
+            return MFE_EHIP;
+        }
+        (void)hipGraphExecDestroy(B->graphs.front().exec);
+        B->graphs.erase(B->graphs.begin());
+    }
     B->graphs.push_back({format, t.lanes, t.factor, k, f32, x, st, ex});
     *out = ex;
     return MFE_OK;

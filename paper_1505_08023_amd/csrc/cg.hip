@@ -17,6 +17,10 @@
 
 #include "common.hpp"
 
+// Iteration graphs kept per problem, keyed by solver kind, format, precision,
+// solution buffer, graph length and state slot.
+constexpr int kMaxGraphs = 16;
+
 struct mfe_graph_cache {
     struct Entry {
         int kind;  // 0: CG, 1: single-reduction CG, 2: Jacobi-preconditioned CG
@@ -117,7 +121,20 @@ int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, v
         }
     hipGraphExec_t ex = nullptr;
     MFE_TRY(capture(P, kind, format, f32, x, r, p, q, st, k, &ex));
-    P->graphs->entries.push_back({kind, format, f32, x, k, st, ex});
+    // bounded cache (callers that pass a new x buffer per solve would grow it
+    // without end): drop the oldest graph once no work of the context uses it
+    auto &v = P->graphs->entries;
+    if (v.size() >= (size_t)kMaxGraphs) {
+        const hipError_t e = hipStreamSynchronize(P->ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipGraphExecDestroy(ex);
+            set_error(std::string("hipStreamSynchronize failed: ") + hipGetErrorString(e));
+            return MFE_EHIP;
+        }
+        (void)hipGraphExecDestroy(v.front().exec);
+        v.erase(v.begin());
+    }
+    v.push_back({kind, format, f32, x, k, st, ex});
     *out = ex;
     return MFE_OK;
 }

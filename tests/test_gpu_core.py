@@ -497,6 +497,21 @@ def test_cg_warm_start(ctx, fmt):
     P.close()
 
 
+def test_cg_many_solution_buffers(ctx):
+    """Solves into 20 different x buffers (more than the per-problem graph
+    cache keeps): every solve is right, the old graphs are dropped safely."""
+    N = (12, 12, 12)
+    P = mesh_problem(ctx, N)
+    xs = [torch.full((P.m,), float(i), dtype=torch.float64, device=ctx.device) for i in range(20)]
+    x_ref, st_ref = P.cg(tol=1e-8, max_iter=500)
+    for x in xs + xs[:3]:
+        x.zero_()
+        _, st = P.cg(x, tol=1e-8, max_iter=500)
+        assert st["status"] == 0 and st["iterations"] == st_ref["iterations"]
+        assert torch.equal(x, x_ref)
+    P.close()
+
+
 def test_cg_breakdown_on_indefinite_matrix(ctx):
     from paper_1505_08023_amd.mfe import Problem
     d = ctx.device
