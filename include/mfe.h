@@ -25,6 +25,10 @@
  *   - Work is enqueued on the context's stream.  Calls that return results
  *     on the host (stats, info, dot values) synchronise that stream first;
  *     the others return without synchronising.
+ *   - A context and everything attached to it are used by one host thread at
+ *     a time: calls on one context must not overlap (they share the stream,
+ *     pinned host slots and reduction scratch).  Different contexts are
+ *     independent.
  *   - Mesh numbering: node (ix, iy, iz), 0 <= ix <= Nx, ..., has id
  *     ix + (Nx+1)*(iy + (Ny+1)*iz) (x fastest) and coordinates
  *     (ix/Nx, iy/Ny, iz/Nz).  Matrix rows are nodes, all of them: Dirichlet
