@@ -82,7 +82,7 @@ def time_spmv_dot(P, fmt, reps, torch, flush_bytes=1 << 30, warmup=5, f32=False)
     return sum(ms) / len(ms), ms[0]
 
 
-def cpu_baseline(N, its=(2, 8)):
+def cpu_baseline(N, its=(2, 42)):
     """Oracle CG on the host: iterations its[1]-its[0] timed as the
     difference of two capped runs (assembly untimed)."""
     import oracle
