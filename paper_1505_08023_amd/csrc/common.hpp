@@ -104,7 +104,9 @@ struct CgState {
 // column(row i, entry k) = i + off[k] (the interior of a box mesh) has
 // uniform = 1 in its descriptor, and the product forms its columns from the
 // 27 offsets instead of loading its 27 kCsrsRows column indices (which stay
-// stored).  The reconstruction is exact: products are bitwise the same.
+// stored); uniform = 2 when, besides, the offsets come in 9 runs of three
+// consecutive columns, which the product then takes a run at a time (three
+// adjacent x entries per gather pair, as a 1x3 block).
 #ifndef MFE_CSRS_ROWS
 #define MFE_CSRS_ROWS 16  // rows per wavefront tile (64 / rows lanes per row); 8, 16 and 32 measured
 #endif

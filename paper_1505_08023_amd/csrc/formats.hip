@@ -302,7 +302,10 @@ __global__ __launch_bounds__(64) void k_csr_desc(int64_t m, const int32_t *__res
     }
     if (ok && lane < 27) desc[t].off[lane] = (int32_t)(col[lo + lane] - r0);
     if (lane == 0) {
-        desc[t].uniform = ok ? 1 : 0;
+        bool runs3 = ok;
+        for (int i = 0; runs3 && i < 9; ++i)
+            runs3 = col[lo + 3 * i + 1] == col[lo + 3 * i] + 1 && col[lo + 3 * i + 2] == col[lo + 3 * i] + 2;
+        desc[t].uniform = ok ? (runs3 ? 2 : 1) : 0;
         flag[t] = ok ? 1 : 0;
     }
 }

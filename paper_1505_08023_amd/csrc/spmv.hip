@@ -145,7 +145,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
 // 64 / kCsrsRows lanes (strided entries, combined by an xor butterfly)
 // reading LDS and gathering x.  A tile with a uniform descriptor (CsrDesc)
 // stages only its values and forms the columns from the 27 offsets, in the
-// same summation order.  A tile whose entries exceed the LDS capacity is
+// same summation order, or, when the offsets form 9 runs of three
+// consecutive columns, sums a run per step (a different order, the same
+// products).  A tile whose entries exceed the LDS capacity is
 // summed straight from global memory instead.
 constexpr int kCsrsCap = kCsrsRows * 28;       // staged entries per wavefront tile (kCsrsRows: common.hpp)
 
@@ -180,7 +182,27 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
         const int64_t row = r0 + rl;
         const CsrDesc &D = cdesc[tr.t * (kBlock / 64) + wave];  // this wavefront's tile
         T sum = 0;
-        if (D.uniform) {
+        if (D.uniform == 2) {
+            // 27 entries per row in 9 runs of three consecutive columns: stage
+            // the values and the 9 run starts.  With LPR = 4 lanes per row,
+            // lane `sub` takes runs sub and sub + 4 (each a 1x3 block: one
+            // 16-byte and one 8-byte gather) and lanes 1..3 one entry each of
+            // run 8, so no lane does more than 7 products; other lane counts
+            // take runs sub, sub + LPR, ...
+            for (int j = lane; j < 27 * kCsrsRows; j += 64) sv[j] = matrix_load<MNT>(val + lo + j);
+            if (lane < 9) sc[lane] = D.off[3 * lane];
+            wave_sync();
+            const int a = rl * 27;
+            constexpr int nfull = LPR == 4 ? 8 : 9;
+            for (int i = sub; i < nfull; i += LPR) {
+                const T *xp = E.x + row + sc[i];
+                sum += sv[a + 3 * i] * xp[0];
+                sum += sv[a + 3 * i + 1] * xp[1];
+                sum += sv[a + 3 * i + 2] * xp[2];
+            }
+            if (LPR == 4 && sub > 0) sum += sv[a + 23 + sub] * E.x[row + sc[8] + sub - 1];
+            wave_sync();
+        } else if (D.uniform) {
             // 27 entries per row, columns row + off[k]: stage the values only
             for (int j = lane; j < 27 * kCsrsRows; j += 64) sv[j] = matrix_load<MNT>(val + lo + j);
             if (lane < 27) sc[lane] = D.off[lane];
