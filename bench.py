@@ -27,7 +27,7 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # and WRITE_SIZE (x 1.0) counter runs, scaled by streaming kernels of known
 # size (profiles/spmv_b13_fp64_256cubed_hbm_counters.md).  Reset to None
 # whenever the kernel changes.
-MEASURED_TRAFFIC = {("bcrs13", 256): 4.007e9, ("csr", 256): None}
+MEASURED_TRAFFIC = {("bcrs13", 256): 4.007e9, ("csr", 256): 4.772e9}
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
 
 
