@@ -361,7 +361,18 @@ int mfe_net_forward(mfe_net *net, int batch, const double *g_dev, float *pred_de
  * be NULL. */
 int mfe_net_loss_grad(mfe_net *net, int batch, const double *g_dev, const double *target_dev, double *loss_host,
                       float *grad_host);
-/* One Adam update with the gradient of the last mfe_net_loss_grad. */
+/* As mfe_net_loss_grad with the energy norm of the error in place of its
+ * square: e = prediction - target on interior nodes (0 on boundary nodes),
+ * loss = e^T A e / (batch (G-2)^3), output gradient 2 A e / (batch (G-2)^3),
+ * A the stiffness matrix of `problem` (the (G-1)^3 element box mesh of the
+ * network's grid, built with `format`; its product runs on the GPU).  CG
+ * minimises this norm of the error over its Krylov space (the CG module of
+ * Sec. 1; the property is the textbook one), so it measures how far a guess is
+ * from the solution in the solver's own terms.  Allocates two FP64 work
+ * vectors of batch_max G^3 entries on first use (freed with the net). */
+int mfe_net_loss_grad_energy(mfe_net *net, const mfe_problem *problem, int format, int batch, const double *g_dev,
+                             const double *target_dev, double *loss_host, float *grad_host);
+/* One Adam update with the gradient of the last mfe_net_loss_grad(_energy). */
 int mfe_net_adam_step(mfe_net *net, float lr, float beta1, float beta2, float eps);
 /* x0_dev (FP64 [G^3]) = g on boundary nodes, the network's prediction inside. */
 int mfe_net_predict_x0(mfe_net *net, const double *g_dev, double *x0_dev);

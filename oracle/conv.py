@@ -149,22 +149,37 @@ def net_forward(params, x, round_bf16=False):
     return acts
 
 
-def net_loss(params, x, target, interior, round_bf16=False):
-    """Mean squared error of channel 0 over interior nodes."""
+def _a_times(diff, interior, apply_a):
+    """A e per sample (node order x fastest, as the grid's C order), kept on
+    interior nodes."""
+    return np.stack([apply_a(d.ravel()).reshape(d.shape) for d in diff]) * interior
+
+
+def net_loss(params, x, target, interior, round_bf16=False, apply_a=None):
+    """Mean squared error of channel 0 over interior nodes; with apply_a (a
+    function returning A v for a node vector v) the energy norm e^T A e of the
+    interior error e instead, per interior node."""
     acts = net_forward(params, x, round_bf16)
     pred = acts[-1][..., 0]
     diff = (pred - target) * interior
-    return float(np.sum(diff ** 2) / np.sum(interior)), acts
+    if apply_a is None:
+        return float(np.sum(diff ** 2) / np.sum(interior)), acts
+    return float(np.sum(diff * _a_times(diff, interior, apply_a)) / np.sum(interior)), acts
 
 
-def net_grads(params, x, target, interior):
+def net_grads(params, x, target, interior, apply_a=None, scales=False):
     """Gradient of net_loss (FP64) by the chain rule through conv3d_input_grad /
-    conv3d_weight_grad; returns [(dw, db)] per layer."""
+    conv3d_weight_grad; returns [(dw, db)] per layer.  For the energy norm the
+    output gradient is 2 A e (A symmetric).  With scales, also returns per
+    layer the sums of absolute terms behind each entry, (sum |gy| |x|, sum |gy|),
+    the scale that rounding errors of the summed terms are relative to."""
     acts = net_forward(params, x)
     count = float(np.sum(interior))
     g_out = np.zeros_like(acts[-1])
-    g_out[..., 0] = 2.0 * (acts[-1][..., 0] - target) * interior / count
+    diff = (acts[-1][..., 0] - target) * interior
+    g_out[..., 0] = 2.0 * (diff if apply_a is None else _a_times(diff, interior, apply_a)) / count
     grads = [None] * len(LAYERS)
+    sc = [None] * len(LAYERS)
     g_act = {len(LAYERS) - 1: g_out}
     for li in range(len(LAYERS) - 1, -1, -1):
         cin, cout, mode, relu, skip = LAYERS[li]
@@ -174,8 +189,10 @@ def net_grads(params, x, target, interior):
         h_in = acts[li - 1] if li > 0 else x
         w, _ = params[li]
         grads[li] = (conv3d_weight_grad(gy, h_in, mode), gy.reshape(-1, cout).sum(axis=0))
+        if scales:
+            sc[li] = (conv3d_weight_grad(np.abs(gy), np.abs(h_in), mode), np.abs(gy).reshape(-1, cout).sum(axis=0))
         if skip is not None:
             g_act[skip] = g_act.get(skip, 0.0) + gy
         if li > 0:
             g_act[li - 1] = g_act.get(li - 1, 0.0) + conv3d_input_grad(gy, w, mode, h_in.shape[1])
-    return grads
+    return (grads, sc) if scales else grads

@@ -623,6 +623,30 @@ __global__ __launch_bounds__(256) void k_mse(int64_t total, int G, const float *
     if (threadIdx.x == 0) part[blockIdx.x] = acc;
 }
 
+// e = prediction - target on interior nodes, 0 on boundary nodes (FP64)
+__global__ __launch_bounds__(256) void k_err(int64_t total, int G, const float *__restrict__ pred,
+                                             const double *__restrict__ target, double *__restrict__ e) {
+    const int64_t V = (int64_t)G * G * G;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
+        e[i] = on_boundary(i % V, G) ? 0.0 : (double)pred[i * 8] - target[i];
+}
+
+// energy norm of the error: partials of e.Ae, and the output gradient 2 (Ae) / count on interior nodes
+__global__ __launch_bounds__(256) void k_energy(int64_t total, int G, const double *__restrict__ e,
+                                                const double *__restrict__ ae, double inv_count, bf16 *__restrict__ g,
+                                                double *__restrict__ part) {
+    const int64_t V = (int64_t)G * G * G;
+    double acc = 0.0;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
+        const double q = on_boundary(i % V, G) ? 0.0 : ae[i];
+        acc += e[i] * q;
+        g[i * 8] = (bf16)(2.0 * q * inv_count);
+        for (int c = 1; c < 8; ++c) g[i * 8 + c] = (bf16)0.0f;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) part[blockIdx.x] = acc;
+}
+
 // prediction (channel 0) out of the stride-8 output, FP32
 __global__ __launch_bounds__(256) void k_pred(int64_t total, const float *__restrict__ out32, float *__restrict__ pred) {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256)
@@ -948,6 +972,7 @@ struct mfe_net {
     int64_t nparam_dev = 0;  // padded device layout
     int64_t nparam = 0;      // natural layout [o][27][c] + b per layer
     Buffer p32, g32, m32, v32, in, out32, gpre, part, bpart, lpart;
+    Buffer err, aerr;  // energy-norm loss: e and A e, FP64 [batch_max][G^3] (allocated on first use)
     int64_t part_floats = 0, bpart_floats = 0;
     int64_t step = 0;
     std::vector<std::pair<int, hipGraphExec_t>> fwd_graphs, bwd_graphs;  // per batch size
@@ -1211,7 +1236,8 @@ int mfe_net_destroy(mfe_net *N) {
         for (auto &e : *c) (void)hipGraphExecDestroy(e.second);
     for (auto &l : N->L)
         for (Buffer *b : {&l.act, &l.gact, &l.w, &l.wa, &l.wc}) dev_free(ctx, b);
-    for (Buffer *b : {&N->p32, &N->g32, &N->m32, &N->v32, &N->in, &N->out32, &N->gpre, &N->part, &N->bpart, &N->lpart})
+    for (Buffer *b : {&N->p32, &N->g32, &N->m32, &N->v32, &N->in, &N->out32, &N->gpre, &N->part, &N->bpart, &N->lpart,
+                      &N->err, &N->aerr})
         dev_free(ctx, b);
     unregister(ctx->nets, N);
     delete N;
@@ -1279,6 +1305,32 @@ int mfe_net_forward(mfe_net *N, int batch, const double *g_dev, float *pred_dev)
     return MFE_OK;
 }
 
+namespace {
+
+// Backward pass from the output gradient the loss kernel left in the last layer's gact, then the loss
+// (sum of lg block partials / count) and the parameter gradient back to the host when asked for.
+int finish_loss_grad(mfe_net *N, int batch, int lg, double count, double *loss_host, float *grad_host) {
+    hipStream_t s = N->ctx->stream;
+    MFE_TRY(run_net_graph(N, true, batch));
+    if (loss_host) {
+        std::vector<double> lp(lg);
+        MFE_HIP_TRY(hipMemcpyAsync(lp.data(), N->lpart.ptr, lg * sizeof(double), hipMemcpyDeviceToHost, s));
+        MFE_HIP_TRY(hipStreamSynchronize(s));
+        double acc = 0.0;
+        for (double v : lp) acc += v;
+        *loss_host = acc / count;
+    }
+    if (grad_host) {
+        std::vector<float> dev(N->nparam_dev);
+        MFE_HIP_TRY(hipMemcpyAsync(dev.data(), N->g32.ptr, dev.size() * sizeof(float), hipMemcpyDeviceToHost, s));
+        MFE_HIP_TRY(hipStreamSynchronize(s));
+        dev_to_natural(N, dev, grad_host);
+    }
+    return MFE_OK;
+}
+
+}  // namespace
+
 int mfe_net_loss_grad(mfe_net *N, int batch, const double *g_dev, const double *target_dev, double *loss_host,
                       float *grad_host) {
     clear_error();
@@ -1296,22 +1348,47 @@ int mfe_net_loss_grad(mfe_net *N, int batch, const double *g_dev, const double *
     hipLaunchKernelGGL(k_mse, dim3(lg), dim3(256), 0, s, total, N->G, (const float *)N->out32.ptr, target_dev,
                        1.0 / ((double)batch * inner), (bf16 *)N->L[kNumLayers - 1].gact.ptr, (double *)N->lpart.ptr);
     MFE_HIP_TRY(hipGetLastError());
-    MFE_TRY(run_net_graph(N, true, batch));
-    if (loss_host) {
-        std::vector<double> lp(lg);
-        MFE_HIP_TRY(hipMemcpyAsync(lp.data(), N->lpart.ptr, lg * sizeof(double), hipMemcpyDeviceToHost, s));
-        MFE_HIP_TRY(hipStreamSynchronize(s));
-        double acc = 0.0;
-        for (double v : lp) acc += v;
-        *loss_host = acc / ((double)batch * inner);
+    return finish_loss_grad(N, batch, lg, (double)batch * inner, loss_host, grad_host);
+}
+
+int mfe_net_loss_grad_energy(mfe_net *N, const mfe_problem *A, int format, int batch, const double *g_dev,
+                             const double *target_dev, double *loss_host, float *grad_host) {
+    clear_error();
+    MFE_TRY(check_net(N, batch));
+    if (!A || !g_dev || !target_dev) {
+        set_error("problem, g and target must be non-NULL");
+        return MFE_EINVAL;
     }
-    if (grad_host) {
-        std::vector<float> dev(N->nparam_dev);
-        MFE_HIP_TRY(hipMemcpyAsync(dev.data(), N->g32.ptr, dev.size() * sizeof(float), hipMemcpyDeviceToHost, s));
-        MFE_HIP_TRY(hipStreamSynchronize(s));
-        dev_to_natural(N, dev, grad_host);
+    if (A->ctx != N->ctx || !A->is_mesh || A->Nx != N->G - 1 || A->Ny != N->G - 1 || A->Nz != N->G - 1) {
+        set_error("the problem must be the (G-1)^3 element box mesh of the network's grid, on its context");
+        return MFE_EINVAL;
     }
-    return MFE_OK;
+    if ((format != MFE_CSR && format != MFE_BCRS13) || !(A->formats & format)) {
+        set_error("format must be MFE_CSR or MFE_BCRS13 and built for the problem");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(N->ctx->device) != hipSuccess) return MFE_EHIP;
+    hipStream_t s = N->ctx->stream;
+    const int64_t V = voxels(N->G);
+    const size_t bytes = (size_t)N->bmax * V * sizeof(double);
+    if (!N->err.ptr) MFE_TRY(dev_alloc(N->ctx, &N->err, bytes));
+    if (!N->aerr.ptr) MFE_TRY(dev_alloc(N->ctx, &N->aerr, bytes));
+    MFE_TRY(forward(N, batch, g_dev));
+    const int64_t total = (int64_t)batch * V;
+    const int64_t inner = (int64_t)(N->G - 2) * (N->G - 2) * (N->G - 2);
+    double *e = (double *)N->err.ptr, *ae = (double *)N->aerr.ptr;
+    hipLaunchKernelGGL(k_err, dim3(grid_of(total)), dim3(256), 0, s, total, N->G, (const float *)N->out32.ptr,
+                       target_dev, e);
+    MFE_HIP_TRY(hipGetLastError());
+    for (int b = 0; b < batch; ++b) {
+        SpmvArgs a{e + (int64_t)b * V, ae + (int64_t)b * V, nullptr, nullptr, nullptr, nullptr};
+        MFE_TRY(launch_spmv(A, format, false, kSpmvPlain, a, s));
+    }
+    const int lg = std::min(1024, grid_of(total));
+    hipLaunchKernelGGL(k_energy, dim3(lg), dim3(256), 0, s, total, N->G, (const double *)e, (const double *)ae,
+                       1.0 / ((double)batch * inner), (bf16 *)N->L[kNumLayers - 1].gact.ptr, (double *)N->lpart.ptr);
+    MFE_HIP_TRY(hipGetLastError());
+    return finish_loss_grad(N, batch, lg, (double)batch * inner, loss_host, grad_host);
 }
 
 int mfe_net_adam_step(mfe_net *N, float lr, float beta1, float beta2, float eps) {

@@ -82,7 +82,10 @@ def generate(ctx, n, seeds, chunk=32, tol=1e-8):
     return g_all, u_all
 
 
-def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0):
+def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0, energy=None):
+    """Adam with cosine decay over the fields (g, u).  energy: None for the
+    mean squared error of the interior prediction, or the mesh's Problem for
+    the energy norm e^T A e of the interior error (the norm CG minimises)."""
     S = g.shape[0]
     rng = np.random.default_rng(seed)
     steps_per_epoch = S // batch
@@ -96,7 +99,7 @@ def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0):
             idx = perm[i * batch:(i + 1) * batch]
             gb = g.index_select(0, idx).reshape(-1)
             ub = u.index_select(0, idx).reshape(-1)
-            loss = net.loss_grad(gb, ub)
+            loss = net.loss_grad(gb, ub, energy=energy)
             cur = lr * 0.5 * (1 + math.cos(math.pi * step / total))  # cosine decay
             net.adam_step(cur)
             run += loss
@@ -198,6 +201,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--eval", type=int, default=1000)
     ap.add_argument("--init", default=None, help="start from these weights (.npz)")
+    ap.add_argument("--loss", choices=("mse", "energy"), default="mse",
+                    help="training loss: squared error or energy norm of the interior error")
     ap.add_argument("--out", default=None)
     args = ap.parse_args(argv)
     ctx = Context(0)
@@ -214,13 +219,16 @@ def main(argv=None):
         g, u = generate(ctx, n, np.arange(args.train))
         result["generate_s"] = time.time() - t
         t = time.time()
-        result["loss_history"] = train(net, g, u, args.epochs, args.batch, args.lr)
+        prob = Problem.mesh(ctx, n, n, n, formats=("bcrs13",)) if args.loss == "energy" else None
+        result["loss_history"] = train(net, g, u, args.epochs, args.batch, args.lr, energy=prob)
+        if prob is not None:
+            prob.close()
         result["train_s"] = time.time() - t
         del g, u
         torch.cuda.empty_cache()
         if args.out:
             save(args.out, net.get_params(), dict(n=n, train=args.train, epochs=args.epochs, batch=args.batch,
-                                                  lr=args.lr, init=args.init or "he_init(0)",
+                                                  lr=args.lr, init=args.init or "he_init(0)", loss=args.loss,
                                                   loss_history=result["loss_history"]))
     if args.eval > 0:
         ev = evaluate(ctx, net, n, np.arange(HELD_OUT_BASE, HELD_OUT_BASE + args.eval))

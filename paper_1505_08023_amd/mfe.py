@@ -530,16 +530,25 @@ class Net:
                   "mfe_net_forward")
         return pred
 
-    def loss_grad(self, g, target, want_grad=False):
+    def loss_grad(self, g, target, want_grad=False, energy=None, fmt="bcrs13"):
+        """Forward, loss and backward (the gradient is kept for adam_step).
+        energy=None: mean squared error over interior nodes; energy=a Problem
+        (the (G-1)^3 mesh): the error's energy norm e^T A e per interior node."""
         import numpy as np
         b = g.numel() // self.G ** 3
         loss = ctypes.c_double()
         grad = np.zeros(self.nparams, dtype=np.float32) if want_grad else None
+        gp = grad.ctypes.data_as(ctypes.c_void_p) if want_grad else None
         with _on(self.ctx):
-            check(self.ctx.lib.mfe_net_loss_grad(self.handle, b, _ptr(g, torch.float64), _ptr(target, torch.float64),
-                                                 ctypes.byref(loss),
-                                                 grad.ctypes.data_as(ctypes.c_void_p) if want_grad else None),
-                  "mfe_net_loss_grad")
+            if energy is None:
+                check(self.ctx.lib.mfe_net_loss_grad(self.handle, b, _ptr(g, torch.float64),
+                                                     _ptr(target, torch.float64), ctypes.byref(loss), gp),
+                      "mfe_net_loss_grad")
+            else:
+                check(self.ctx.lib.mfe_net_loss_grad_energy(self.handle, energy.handle, FORMATS[fmt], b,
+                                                            _ptr(g, torch.float64), _ptr(target, torch.float64),
+                                                            ctypes.byref(loss), gp),
+                      "mfe_net_loss_grad_energy")
         return (loss.value, grad) if want_grad else loss.value
 
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -119,6 +119,47 @@ def test_network_gradient_against_finite_differences():
         assert abs(fd - grads[li][1][o]) <= 1e-6 * max(1e-3, abs(fd))
 
 
+def test_energy_loss_gradient_against_finite_differences():
+    """The energy-norm loss e^T A e (A the assembled 8^3 stiffness matrix of
+    the oracle) through the whole network: its chain-rule gradient, whose
+    output term 2 A e rests on the symmetry of A, against central differences."""
+    import oracle
+    rng = np.random.default_rng(4)
+    G = 9
+    A = oracle.assemble(G - 1, G - 1, G - 1)
+    apply_a = lambda v: oracle.csr_spmv(A, v)
+    params = small_params(rng, scale=1.0)
+    mask = np.zeros((G, G, G), bool)
+    mask[0], mask[-1], mask[:, 0], mask[:, -1], mask[:, :, 0], mask[:, :, -1] = (True,) * 6
+    g = rng.uniform(0, 1, (G, G, G))
+    x = conv.net_input(g, mask)[None]
+    target = rng.uniform(0, 1, (1, G, G, G))
+    interior = (~mask)[None].astype(float)
+    loss = conv.net_loss(params, x, target, interior, apply_a=apply_a)[0]
+    assert loss > 0.0
+    grads = conv.net_grads(params, x, target, interior, apply_a=apply_a)
+    eps = 1e-6
+    for li in (0, 8, 13):
+        w, b = params[li]
+        for _ in range(2):
+            idx = tuple(rng.integers(0, s) for s in w.shape)
+            wp = [(ww.copy(), bb) for ww, bb in params]
+            wm = [(ww.copy(), bb) for ww, bb in params]
+            wp[li][0][idx] += eps
+            wm[li][0][idx] -= eps
+            fd = (conv.net_loss(wp, x, target, interior, apply_a=apply_a)[0]
+                  - conv.net_loss(wm, x, target, interior, apply_a=apply_a)[0]) / (2 * eps)
+            assert abs(fd - grads[li][0][idx]) <= 1e-6 * max(1e-3, abs(fd)), (li, idx)
+        o = int(rng.integers(0, b.shape[0]))
+        bp = [(ww, bb.copy()) for ww, bb in params]
+        bm = [(ww, bb.copy()) for ww, bb in params]
+        bp[li][1][o] += eps
+        bm[li][1][o] -= eps
+        fd = (conv.net_loss(bp, x, target, interior, apply_a=apply_a)[0]
+              - conv.net_loss(bm, x, target, interior, apply_a=apply_a)[0]) / (2 * eps)
+        assert abs(fd - grads[li][1][o]) <= 1e-6 * max(1e-3, abs(fd))
+
+
 def test_bf16_rounding():
     # spacing 2^-7 at 1: 1 + 2^-8 is a tie (to the even 1.0), 1 + 3 2^-8 a tie (to the even 1 + 2^-6)
     v = np.array([1.0, 1.00390625, 1.001953125, -3.14159, 1e-20, 65504.0, 1.01171875])

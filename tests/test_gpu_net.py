@@ -143,6 +143,62 @@ def test_network_forward_and_gradient(ctx):
     net.close()
 
 
+def test_network_energy_loss_gradient(ctx):
+    """The energy-norm loss e^T A e / count (A the 16^3 stiffness matrix,
+    applied by the library's SpMV) and the gradient through the network,
+    against the FP64 oracle on the same bf16 parameters, with both formats.
+    The output gradient 2 A e is a second difference of the error, and its
+    products with the smooth activations cancel more than those of the
+    squared error's 2 e do (the sums come out 1.3-2.5 times smaller against
+    the sums of their absolute terms), so each layer's error is bounded
+    against those absolute sums: ||dw - ref|| <= 0.1 ||sum |gy| |x| || (the
+    squared-error test's 10 % taken against the scale of the terms rather than
+    of their sum), with the same cosine >= 0.99.  A dropped factor 2 errs by
+    0.12-0.27 of that scale and a sign or operand mistake fails the cosine."""
+    import oracle
+    from paper_1505_08023_amd.mfe import Net, Problem
+    G, B = 17, 2
+    rng = np.random.default_rng(7)
+    params = unflatten(flatten(he_params(rng)))
+    pb = [(conv.bf16(w), b) for w, b in params]
+    mask = boundary_mask(G)
+    g = rng.uniform(0, 1, (B, G, G, G))
+    target = rng.uniform(0, 1, (B, G, G, G))
+    x = np.stack([conv.net_input(g[i], mask) for i in range(B)])
+    interior = np.broadcast_to(~mask, (B, G, G, G)).astype(float)
+    A = oracle.assemble(G - 1, G - 1, G - 1)
+    apply_a = lambda v: oracle.csr_spmv(A, v)
+    prob = Problem.mesh(ctx, G - 1, G - 1, G - 1)
+    net = Net(ctx, G, B)
+    net.set_params(flatten(params))
+    gt = torch.tensor(g.reshape(-1), device=ctx.device)
+    tt = torch.tensor(target.reshape(-1), device=ctx.device)
+    ref_loss, _ = conv.net_loss(pb, x, target, interior, round_bf16=True, apply_a=apply_a)
+    ref_grads, ref_scales = conv.net_grads(pb, x, target, interior, apply_a=apply_a, scales=True)
+    losses = {}
+    for fmt in ("bcrs13", "csr"):
+        loss, grad = net.loss_grad(gt, tt, want_grad=True, energy=prob, fmt=fmt)
+        losses[fmt] = loss
+        assert abs(loss - ref_loss) <= 0.02 * ref_loss, (fmt, loss, ref_loss)
+        for li, ((gw, gb), (rw, rb), (sw, sb)) in enumerate(zip(unflatten(grad), ref_grads, ref_scales)):
+            a = np.concatenate([gw.ravel(), gb])
+            r = np.concatenate([rw.ravel(), rb])
+            sc = np.concatenate([sw.ravel(), sb])
+            err = np.linalg.norm(a - r) / np.linalg.norm(sc)
+            cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+            print(fmt, "layer", li, "error / absolute sums", err, "rel err", np.linalg.norm(a - r) / np.linalg.norm(r),
+                  "cos", cos)
+            assert err <= 0.1 and cos >= 0.99, (fmt, li, err, cos)
+    assert abs(losses["csr"] - losses["bcrs13"]) <= 1e-12 * losses["csr"]
+    # the mesh must be the network's grid
+    other = Problem.mesh(ctx, 8, 8, 8)
+    with pytest.raises(RuntimeError):
+        net.loss_grad(gt, tt, energy=other)
+    other.close()
+    prob.close()
+    net.close()
+
+
 def test_network_graph_replays(ctx):
     """The forward and backward passes replay captured graphs: alternating
     inputs, with other device work in between, reproduce every result
