@@ -464,7 +464,7 @@ def extras(args, ctx, P, x, line, torch):
         ev = learned.evaluate(ctx, net, 64, seeds)
         ev.pop("rows")
         ev["weights"] = os.path.relpath(wpath, ROOT)
-        ev["trained_on"] = {k: meta[k] for k in ("train", "epochs", "batch", "lr") if k in meta}
+        ev["trained_on"] = {k: meta[k] for k in ("train", "epochs", "batch", "lr", "schedule") if k in meta}
         line["learned_warm_start_64cubed_1e-8"] = ev
         log(f"[bench] learned vs plain: {ev}")
         net.close()
