@@ -603,6 +603,98 @@ out:
     return status;
 }
 
+/* Rounding of the inner solve of orc_cg_mixed_keep: to FP32 when f32 != 0,
+ * none otherwise.  Each FP32 operation there is the FP64 operation on FP32
+ * operands followed by this rounding; for +, - and x that double rounding is
+ * innocuous (FP64 carries more than 2 x 24 + 2 significand bits), so the
+ * result is the FP32 operation's own. */
+static double rnd(int f32, double v) { return f32 ? (double)(float)v : v; }
+
+/* Refinement that keeps the inner CG's search direction from one step to
+ * the next instead of restarting it: the inner residual is replaced by the
+ * FP64 residual of the refinement step (a reliable update of the residual,
+ * after Sleijpen and van der Vorst, 1996), and the inner recurrence goes on.
+ * As orc_cg_mixed, except after an inner solve that met its tolerance: with
+ * s_old and s the norms of the previous and the new FP64 residual r, beta
+ * and P the last inner step's beta = rho_new / rho and direction,
+ *     r_inner = fl(r / s),   p = r_inner + fl(beta s_old / s) P,
+ * i.e. the CG step P_next = R + beta P in the new scale, with the FP64
+ * residual for R.  After a capped inner solve, or with keep = 0, the inner
+ * CG restarts from p = r_inner.
+ * f32 = 1: the inner solve in FP32 as in orc_cg_mixed (with keep = 0 this
+ * computes what orc_cg_mixed computes); f32 = 0: the same steps in FP64 with
+ * the FP64 matrix.  In exact arithmetic the FP64 residual equals the
+ * recursive one, so keep = 1 then takes the iterates of plain CG.
+ * Returns as orc_cg_mixed. */
+int orc_cg_mixed_keep(int64_t m, const int64_t *ptr, const int32_t *col, const double *val,
+                      const double *b, double *x, double tol, double inner_tol, int max_outer,
+                      int max_inner, int keep, int f32, int *outer, int *inner_total, double *res_true)
+{
+    int64_t nnz = ptr[m];
+    double *vi = (double *)malloc((size_t)nnz * sizeof(double));
+    double *r = (double *)malloc((size_t)m * sizeof(double));
+    double *ax = (double *)malloc((size_t)m * sizeof(double));
+    double *ri = (double *)malloc((size_t)m * sizeof(double));
+    double *d = (double *)malloc((size_t)m * sizeof(double));
+    double *p = (double *)malloc((size_t)m * sizeof(double));
+    double *q = (double *)malloc((size_t)m * sizeof(double));
+    int status = ORC_NOT_CONVERGED;
+    if (!vi || !r || !ax || !ri || !d || !p || !q) { status = ORC_ENOMEM; goto out; }
+    for (int64_t k = 0; k < nnz; ++k) vi[k] = rnd(f32, val[k]);
+    double bnorm = sqrt(dot(m, b, b));
+    *outer = 0; *inner_total = 0;
+    if (bnorm == 0.0) {
+        for (int64_t i = 0; i < m; ++i) x[i] = 0.0;
+        *res_true = 0.0; status = ORC_OK; goto out;
+    }
+    int have_dir = 0;
+    double beta = 0.0, s_old = 0.0;
+    for (;;) {
+        orc_csr_spmv(m, ptr, col, val, x, ax);
+        for (int64_t i = 0; i < m; ++i) r[i] = b[i] - ax[i];
+        double s = sqrt(dot(m, r, r));
+        *res_true = s / bnorm;
+        if (s / bnorm <= tol) { status = ORC_OK; break; }
+        if (*outer >= max_outer) { status = ORC_NOT_CONVERGED; break; }
+        const double c = rnd(f32, beta * (s_old / s));
+        for (int64_t i = 0; i < m; ++i) {
+            ri[i] = rnd(f32, r[i] / s);
+            d[i] = 0.0;
+            p[i] = (keep && have_dir) ? rnd(f32, ri[i] + rnd(f32, c * p[i])) : ri[i];
+        }
+        double rho = dot(m, ri, ri), rho0 = rho;
+        int k = 0;
+        have_dir = 0;
+        while (k < max_inner) {
+            for (int64_t i = 0; i < m; ++i) {
+                double acc = 0.0;
+                for (int64_t j = ptr[i]; j < ptr[i + 1]; ++j) acc = rnd(f32, acc + rnd(f32, vi[j] * p[col[j]]));
+                q[i] = acc;
+            }
+            double pq = dot(m, p, q);
+            if (!(pq > 0.0) || !isfinite(pq)) { status = ORC_BREAKDOWN; break; }
+            double a = rnd(f32, rho / pq);
+            for (int64_t i = 0; i < m; ++i) d[i] = rnd(f32, d[i] + rnd(f32, a * p[i]));
+            for (int64_t i = 0; i < m; ++i) ri[i] = rnd(f32, ri[i] - rnd(f32, a * q[i]));
+            double rho_new = dot(m, ri, ri);
+            ++k;
+            double be = rho_new / rho;
+            if (sqrt(rho_new / rho0) <= inner_tol) { beta = be; have_dir = 1; break; }
+            double bf = rnd(f32, be);
+            for (int64_t i = 0; i < m; ++i) p[i] = rnd(f32, ri[i] + rnd(f32, bf * p[i]));
+            rho = rho_new;
+        }
+        *inner_total += k;
+        *outer += 1;
+        if (status == ORC_BREAKDOWN) break;
+        for (int64_t i = 0; i < m; ++i) x[i] += s * d[i];
+        s_old = s;
+    }
+out:
+    free(vi); free(r); free(ax); free(ri); free(d); free(p); free(q);
+    return status;
+}
+
 /* ------------------------------------------------------------------ */
 /* Single-reduction CG (Chronopoulos and Gear, 1989)                    */
 /* ------------------------------------------------------------------ */

@@ -397,6 +397,50 @@ def test_fe_converges_to_series():
 
 # ---------------------------------------------------------------- mixed precision extension
 
+def test_mixed_keep_direction_fp64_inner_is_cg():
+    """Keeping the inner direction across refinement steps, with the inner
+    steps in FP64, is one uninterrupted CG in exact arithmetic (the FP64
+    residual equals the recursive one).  So after K inner iterations in all
+    its iterate is CG's K-th iterate, up to rounding, while the restarting
+    form needs more iterations to the same tolerance; a wrong carry of the
+    direction (scale s/s_old instead of s_old/s, beta dropped) breaks the
+    equality."""
+    N = 16
+    A = oracle.assemble(N, N, N)
+    for inner_tol in (1e-1, 1e-2):
+        keep = oracle.cg_mixed(A, tol=1e-10, inner_tol=inner_tol, keep_direction=True, inner_f32=False)
+        assert keep["status"] == oracle.OK and keep["outer"] >= 5
+        K = keep["inner_iterations"]
+        cgk = oracle.cg(A, tol=0.0, max_iter=K)
+        assert cgk["iterations"] == K
+        scale = np.linalg.norm(cgk["x"])
+        assert np.linalg.norm(keep["x"] - cgk["x"]) <= 1e-9 * scale
+        restart = oracle.cg_mixed(A, tol=1e-10, inner_tol=inner_tol, inner_f32=False)
+        assert restart["status"] == oracle.OK and restart["inner_iterations"] > K
+
+
+def test_mixed_emulated_fp32_matches_native():
+    """orc_cg_mixed_keep's FP32 emulation (FP64 operations on FP32 values,
+    each rounded to FP32) gives, with keep_direction off, bitwise the
+    restarting solve computed in native FP32."""
+    for N in ((8, 8, 8), (9, 5, 7)):
+        A = oracle.assemble(*N)
+        a = oracle.cg_mixed(A, tol=1e-10)
+        b = oracle.cg_mixed(A, tol=1e-10, emulated=True)
+        assert np.array_equal(a["x"], b["x"]) and a["inner_iterations"] == b["inner_iterations"]
+
+
+def test_mixed_keep_direction_fp32_reaches_tolerance_in_fewer_iterations():
+    N = 24
+    A = oracle.assemble(N, N, N)
+    ref = oracle.cg(A, tol=1e-13, max_iter=2000)["x"]
+    keep = oracle.cg_mixed(A, tol=1e-10, inner_tol=1e-2, keep_direction=True)
+    restart = oracle.cg_mixed(A, tol=1e-10, inner_tol=1e-2)
+    assert keep["status"] == oracle.OK and keep["rel_res_true"] <= 1e-10
+    assert keep["inner_iterations"] < restart["inner_iterations"]
+    assert np.linalg.norm(keep["x"] - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
 def test_mixed_precision_reaches_fp64_accuracy():
     N = 16
     A = oracle.assemble(N, N, N)
