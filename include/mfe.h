@@ -284,6 +284,23 @@ int mfe_cg_mixed(const mfe_problem *p, int format, double *x_dev, double tol, do
 int mfe_cg_mixed_warm(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol,
                       int max_outer, int max_inner, mfe_cg_stats *stats);
 
+/* Flags of mfe_cg_mixed_ex. */
+#define MFE_MIXED_WARM 1           /* start from x_dev as mfe_cg_mixed_warm does */
+#define MFE_MIXED_KEEP_DIRECTION 2 /* keep the inner CG's direction across refinement steps */
+/* mfe_cg_mixed (flags 0) and mfe_cg_mixed_warm (MFE_MIXED_WARM) with
+ * options.  MFE_MIXED_KEEP_DIRECTION: after an inner solve that met its
+ * tolerance the next one is not restarted from d = 0, p = r; its recursive
+ * residual is replaced by the new FP64 residual (a reliable update of the
+ * residual, after Sleijpen and van der Vorst) and its recurrence goes on:
+ * with s_old and s the previous and the new ||r||, r32 = fl32(r / s) and
+ * p32 = r32 + (s_old / s)(p32 - r32_old), the CG step P_next = R + beta P in
+ * the new scale with the FP64 residual for R (in exact arithmetic the inner
+ * iterations are then those of one uninterrupted CG).  After a capped inner
+ * solve the next one restarts.  Other flag bits: MFE_EINVAL.  Arguments,
+ * stats and return values as mfe_cg_mixed. */
+int mfe_cg_mixed_ex(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol, int max_outer,
+                    int max_inner, int flags, mfe_cg_stats *stats);
+
 /* ---------------------------------------------------------------------
  * Batched solves: many box meshes of uneven size solved together (the
  * batched extension of the Sec. 1 CG module).  Each system follows exactly

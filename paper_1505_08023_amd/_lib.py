@@ -12,6 +12,7 @@ MFE_OK, MFE_NOT_CONVERGED = 0, 1
 MFE_EINVAL, MFE_ENOMEM, MFE_EHIP, MFE_EBREAKDOWN, MFE_EUNSUPPORTED = -1, -2, -3, -4, -5
 MFE_CSR, MFE_BCRS13 = 1, 2
 MFE_F64, MFE_F32 = 1, 2
+MFE_MIXED_WARM, MFE_MIXED_KEEP_DIRECTION = 1, 2
 
 STATUS_NAMES = {0: "MFE_OK", 1: "MFE_NOT_CONVERGED", -1: "MFE_EINVAL", -2: "MFE_ENOMEM",
                 -3: "MFE_EHIP", -4: "MFE_EBREAKDOWN", -5: "MFE_EUNSUPPORTED"}
@@ -55,6 +56,7 @@ SIGNATURES = {
     "mfe_spmv_dot": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp]),
     "mfe_dot": (c_int, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(c_dbl)]),
     "mfe_cg_mixed_warm": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
+    "mfe_cg_mixed_ex": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_stream_probe": (c_int, [c_vp, c_int, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "mfe_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_spmv_dot_f32": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp]),

@@ -129,7 +129,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 7; }
+int mfe_version(void) { return 8; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -630,6 +630,31 @@ int mfe_cg_mixed_warm(const mfe_problem *p, int format, double *x_dev, double to
     MFE_TRY(set_device(p->ctx));
     return cg_mixed_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, inner_tol, max_outer, max_inner,
                           stats, true);
+}
+
+int mfe_cg_mixed_ex(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol, int max_outer,
+                    int max_inner, int flags, mfe_cg_stats *stats) {
+    clear_error();
+    if (!p || !x_dev) {
+        set_error("problem and x must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (!(tol >= 0.0) || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1 || max_inner < 1) {
+        set_error("need tol >= 0, 0 < inner_tol < 1, max_outer >= 1, max_inner >= 1");
+        return MFE_EINVAL;
+    }
+    if (flags & ~(MFE_MIXED_WARM | MFE_MIXED_KEEP_DIRECTION)) {
+        set_error("unknown flags");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(check_format(p, format));
+    if (!(p->precisions & MFE_F32)) {
+        set_error("FP32 values were not built for this problem");
+        return MFE_EUNSUPPORTED;
+    }
+    MFE_TRY(set_device(p->ctx));
+    return cg_mixed_solve(const_cast<mfe_problem *>(p), format, x_dev, tol, inner_tol, max_outer, max_inner,
+                          stats, (flags & MFE_MIXED_WARM) != 0, (flags & MFE_MIXED_KEEP_DIRECTION) != 0);
 }
 
 }  // extern "C"

@@ -273,7 +273,7 @@ void release_graphs(mfe_problem *P);
 
 // mixed precision (mixed.hip)
 int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inner_tol, int max_outer,
-                   int max_inner, mfe_cg_stats *st, bool warm = false);
+                   int max_inner, mfe_cg_stats *st, bool warm = false, bool keep_direction = false);
 
 // vector kernels (vector.hip).  update_r consumes the n_pq partials of p.q
 // at pq_partials and writes its r.r partials to rr_partials (*grid of them);

@@ -13,6 +13,18 @@
 // The inner solve streams half the matrix bytes of an FP64 iteration; the
 // FP64 residual keeps the final accuracy independent of FP32 rounding.  A
 // refinement step that does not halve the residual switches to FP64 CG.
+//
+// With keep_direction, an inner solve that met its tolerance is not
+// restarted at the next step: its recursive residual is replaced by the new
+// FP64 residual (a reliable update of the residual, after Sleijpen and van
+// der Vorst) and its recurrence goes on from the last direction, carried to
+// the new scale.  At exit the inner CG has already formed p = r + beta P
+// (P the last direction, r its recursive residual), so with s_old, s the
+// previous and the new residual norms
+//     r32 = fl32(r / s),   p32 = r32 + (s_old / s) (p32 - r32_old),
+// the CG step P_next = R + beta P in the new scale with the FP64 residual
+// for R.  In exact arithmetic the two residuals agree and the inner
+// iterations are those of one uninterrupted CG.
 #include <chrono>
 #include <cmath>
 
@@ -35,6 +47,30 @@ __global__ __launch_bounds__(kBlock) void k_mixed_start(int64_t m, const double 
         const float v = (float)(r[i] / s);
         r32[i] = v;
         p32[i] = v;
+        d32[i] = 0.0f;
+        acc += (double)v * (double)v;
+    }
+    acc = block_sum(acc);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = acc;
+        part[kMaxPartials + blockIdx.x] = acc;
+    }
+}
+
+// Continued inner solve: r32 = fl32(r / s), p32 = r32 + fl32(s_old / s) (p32 - r32_old), d32 = 0;
+// partials of r32.r32 in both slots, as k_mixed_start.
+__global__ __launch_bounds__(kBlock) void k_mixed_continue(int64_t m, const double *__restrict__ r,
+                                                           const CgState *outer, double s_old,
+                                                           float *__restrict__ r32, float *__restrict__ p32,
+                                                           float *__restrict__ d32, double *__restrict__ part) {
+    const double s = sqrt(outer->rho);
+    const float c = (float)(s_old / s);
+    double acc = 0.0;
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+        const float v = (float)(r[i] / s);
+        p32[i] = v + c * (p32[i] - r32[i]);
+        r32[i] = v;
         d32[i] = 0.0f;
         acc += (double)v * (double)v;
     }
@@ -103,7 +139,7 @@ int set_state(mfe_ctx *ctx, CgState *dev, double tol, int max_iter, bool warm = 
 }  // namespace
 
 int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inner_tol, int max_outer,
-                   int max_inner, mfe_cg_stats *stats, bool warm) {
+                   int max_inner, mfe_cg_stats *stats, bool warm, bool keep_direction) {
     const auto t0 = std::chrono::steady_clock::now();
     mfe_ctx *ctx = P->ctx;
     hipStream_t s = ctx->stream;
@@ -126,6 +162,8 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
     bool fallback = false;
     const bool rejected = o.zero_x == 2;
     double prev = o.bnorm > 0 ? std::sqrt(o.rho) : 0.0;
+    bool have_dir = false;  // the last inner solve met its tolerance: its direction can go on
+    double s_old = 0.0;
     if (o.zero_x)
         MFE_TRY(launch_zero_if(P->m, x, (double *)P->r.ptr, (double *)P->p.ptr, (const double *)P->b.ptr, outer,
                                ctx->num_cu, s));
@@ -142,8 +180,12 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
         if (need > eff) eff = need < 0.5 ? need : 0.5;
         MFE_TRY(set_state(ctx, inner, eff, max_inner));
         const int g = vgrid((const void *)k_mixed_start, P->m, ctx->num_cu);
-        hipLaunchKernelGGL(k_mixed_start, dim3(g), dim3(kBlock), 0, s, P->m, (const double *)P->r.ptr, outer,
-                           r32, p32, d32, partials);
+        if (keep_direction && have_dir)
+            hipLaunchKernelGGL(k_mixed_continue, dim3(g), dim3(kBlock), 0, s, P->m, (const double *)P->r.ptr,
+                               outer, s_old, r32, p32, d32, partials);
+        else
+            hipLaunchKernelGGL(k_mixed_start, dim3(g), dim3(kBlock), 0, s, P->m, (const double *)P->r.ptr, outer,
+                               r32, p32, d32, partials);
         MFE_HIP_TRY(hipGetLastError());
         MFE_TRY(launch_finalize(kFinStart, partials, g, inner, s));
         CgState in{};
@@ -158,6 +200,8 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
             fallback = true;
             break;
         }
+        have_dir = in.status == kConverged;
+        s_old = prev;
         const int gu = vgrid((const void *)k_mixed_update, P->m, ctx->num_cu);
         hipLaunchKernelGGL(k_mixed_update, dim3(gu), dim3(kBlock), 0, s, P->m, x, (const float *)d32, outer);
         MFE_HIP_TRY(hipGetLastError());

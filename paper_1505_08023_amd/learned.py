@@ -112,12 +112,13 @@ def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0, energy=None):
     return history
 
 
-def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True):
+def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_direction=False):
     """Per held-out seed: plain FP64 CG from x0 = 0 against CG from the
     network's guess (inference included in its time; the solver falls back to
     the zero start when the guess's residual is not below ||b||), and, with
     mixed, the FP32-inner / FP64-refinement solve from zero and from the guess
-    (the learned + mixed-precision form).  All solves stop at the same
+    (the learned + mixed-precision form; inner_tol and keep_direction as in
+    Problem.cg_mixed).  All solves stop at the same
     tolerance on ||b - A x|| / ||b||.  Every variant runs once on the first
     seed before timing (graph capture).  Times are host wall clock,
     GPU-synchronised."""
@@ -148,11 +149,12 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True):
                  res_plain=st0["rel_res_true"], res_learned=st1["rel_res_true"])
         if mixed:
             x.zero_()
-            r["t_mixed"], st2 = timed(lambda: P.cg_mixed(x, tol=tol)[1])
+            r["t_mixed"], st2 = timed(lambda: P.cg_mixed(x, tol=tol, inner_tol=inner_tol,
+                                                         keep_direction=keep_direction)[1])
 
             def learned_mixed():
                 net.predict_x0(g, x0)
-                return P.cg_mixed(x0, tol=tol, warm=True)[1]
+                return P.cg_mixed(x0, tol=tol, inner_tol=inner_tol, warm=True, keep_direction=keep_direction)[1]
             r["t_learned_mixed"], st3 = timed(learned_mixed)
             r.update(its_mixed=st2["iterations"], its_learned_mixed=st3["iterations"],
                      res_mixed=st2["rel_res_true"], res_learned_mixed=st3["rel_res_true"],

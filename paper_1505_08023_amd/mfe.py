@@ -321,19 +321,28 @@ class Problem:
         return out
 
     def cg_mixed(self, x=None, tol=1e-10, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13",
-                 warm=False):
+                 warm=False, keep_direction=False):
         """FP32-inner CG inside FP64 iterative refinement from x (zero if
         None); warm=True rejects a guess no closer than zero
-        (mfe_cg_mixed_warm).  Returns (x, stats dict)."""
+        (mfe_cg_mixed_warm); keep_direction=True lets the inner CG go on
+        from its last direction after each refinement step
+        (mfe_cg_mixed_ex).  Returns (x, stats dict)."""
         d = self.ctx.device
         if x is None:
             with _on(self.ctx):
                 x = torch.zeros(self.m, dtype=torch.float64, device=d)
         st = mfe_cg_stats()
-        name = "mfe_cg_mixed_warm" if warm else "mfe_cg_mixed"
+        xp = _ptr(x, torch.float64, self.m, "x")
         with _on(self.ctx):
-            rc = getattr(self.ctx.lib, name)(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"), float(tol),
-                                             float(inner_tol), int(max_outer), int(max_inner), ctypes.byref(st))
+            if keep_direction:
+                name = "mfe_cg_mixed_ex"
+                flags = (_lib.MFE_MIXED_WARM if warm else 0) | _lib.MFE_MIXED_KEEP_DIRECTION
+                rc = self.ctx.lib.mfe_cg_mixed_ex(self.handle, _fmt(fmt), xp, float(tol), float(inner_tol),
+                                                  int(max_outer), int(max_inner), flags, ctypes.byref(st))
+            else:
+                name = "mfe_cg_mixed_warm" if warm else "mfe_cg_mixed"
+                rc = getattr(self.ctx.lib, name)(self.handle, _fmt(fmt), xp, float(tol), float(inner_tol),
+                                                 int(max_outer), int(max_inner), ctypes.byref(st))
         check(rc, name, (MFE_OK, MFE_NOT_CONVERGED))
         return x, st.as_dict()
 

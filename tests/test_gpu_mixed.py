@@ -99,6 +99,66 @@ def test_mixed_cg_matches_oracle(ctx, N, fmt):
     P.close()
 
 
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+@pytest.mark.parametrize("N", [(20, 20, 20), (17, 9, 23)])
+def test_mixed_keep_direction_matches_oracle(ctx, N, fmt):
+    """The refinement that keeps the inner direction (mfe_cg_mixed_ex):
+    reaches 1e-10 as the oracle's form of it does, within the residual bound
+    of the FP64 solution, with no more inner iterations than the oracle's
+    (up to rounding: the library also loosens the last inner solve to what
+    the outer tolerance needs, the oracle keeps inner_tol) and fewer than
+    the restarting solve's."""
+    from paper_1505_08023_amd.mfe import Problem
+    tol = 1e-10
+    A = oracle.assemble(*N)
+    ref64 = oracle.cg(A, tol=1e-13, max_iter=5000)
+    refk = oracle.cg_mixed(A, tol=tol, inner_tol=1e-2, keep_direction=True)
+    assert refk["status"] == oracle.OK and refk["rel_res_true"] <= tol
+    P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
+    x, st = P.cg_mixed(tol=tol, inner_tol=1e-2, fmt=fmt, keep_direction=True)
+    _, sr = P.cg_mixed(tol=tol, inner_tol=1e-2, fmt=fmt)
+    print("keep", N, fmt, st, "oracle outer/inner", refk["outer"], refk["inner_iterations"], "restart", sr)
+    assert st["status"] == 0 and st["rel_res_true"] <= tol and st["outer"] >= 2
+    assert st["iterations"] <= refk["inner_iterations"] + max(4, 0.1 * refk["inner_iterations"])
+    assert st["iterations"] < sr["iterations"]
+    bnorm = np.linalg.norm(A.b)
+    gap = np.linalg.norm(x.cpu().numpy() - ref64["x"])
+    bound = (st["rel_res_true"] + ref64["rel_res_true"]) * bnorm / lam_min(N) + 1e-12
+    assert gap <= bound, (gap, bound)
+    P.close()
+
+
+def test_mixed_keep_direction_warm_and_flags(ctx):
+    """MFE_MIXED_WARM with the kept direction: a guess closer than zero is
+    kept and saves inner iterations; a poor one is rejected and the solve is
+    bitwise the zero-start one; unknown flag bits are refused."""
+    import ctypes
+    from paper_1505_08023_amd._lib import MFE_EINVAL, mfe_cg_stats
+    from paper_1505_08023_amd.mfe import Problem, _ptr
+    N = (24, 24, 24)
+    P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
+    x_zero, st_zero = P.cg_mixed(tol=1e-8, inner_tol=1e-2, keep_direction=True)
+    ref = oracle.cg(oracle.assemble(*N), tol=1e-12, max_iter=1000)["x"]
+    rng = np.random.default_rng(11)
+    guess = ref + 1e-4 * rng.standard_normal(P.m)
+    dirichlet = oracle.boundary(*N)[0] != 0
+    guess[dirichlet] = ref[dirichlet]
+    x, st = P.cg_mixed(x=torch.tensor(guess, device=ctx.device), tol=1e-8, inner_tol=1e-2, warm=True,
+                       keep_direction=True)
+    assert st["guess_rejected"] == 0 and st["rel_res_true"] <= 1e-8
+    assert st["iterations"] < st_zero["iterations"]
+    bad = torch.tensor(1e3 * rng.standard_normal(P.m), device=ctx.device)
+    x, st = P.cg_mixed(x=bad, tol=1e-8, inner_tol=1e-2, warm=True, keep_direction=True)
+    assert st["guess_rejected"] == 1 and st["iterations"] == st_zero["iterations"]
+    assert torch.equal(x, x_zero)
+    xs = torch.zeros(P.m, dtype=torch.float64, device=ctx.device)
+    stt = mfe_cg_stats()
+    rc = ctx.lib.mfe_cg_mixed_ex(P.handle, 2, _ptr(xs, torch.float64, P.m, "x"), 1e-8, 1e-2, 10, 100, 4,
+                                 ctypes.byref(stt))
+    assert rc == MFE_EINVAL
+    P.close()
+
+
 def test_mixed_cg_128_against_fp64(ctx):
     """128^3: mixed to 1e-10 and FP64 CG to 1e-10 reach the same solution."""
     from paper_1505_08023_amd.mfe import Problem
