@@ -29,6 +29,9 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # whenever the kernel changes.
 MEASURED_TRAFFIC = {("bcrs13", 256): 4.007e9, ("csr", 256): 4.772e9}
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
+# inner tolerance of the mixed-precision refinement that keeps the inner CG
+# direction (the fastest of 1e-1 ... 1e-4 at 256^3, to 1e-10 and to 1e-8)
+KEEP_INNER_TOL = 1e-2
 
 
 def log(*a):
@@ -281,7 +284,9 @@ def extras(args, ctx, P, x, line, torch):
     # mixed precision against FP64 CG at equal accuracy (1e-10)
     mixed = {}
     for name, fn in (("fp64_cg", lambda: P.cg(x, tol=1e-10, max_iter=args.max_iter, fmt=args.fmt)[1]),
-                     ("fp32_inner_fp64_refine", lambda: P.cg_mixed(x, tol=1e-10, inner_tol=1e-4, fmt=args.fmt)[1])):
+                     ("fp32_inner_fp64_refine", lambda: P.cg_mixed(x, tol=1e-10, inner_tol=1e-4, fmt=args.fmt)[1]),
+                     ("fp32_inner_fp64_refine_keep_direction",
+                      lambda: P.cg_mixed(x, tol=1e-10, inner_tol=KEEP_INNER_TOL, fmt=args.fmt, keep_direction=True)[1])):
         with torch.cuda.stream(ctx.stream):
             x.zero_()
         fn()  # warm-up (graph capture)
@@ -295,6 +300,8 @@ def extras(args, ctx, P, x, line, torch):
                            rel_res_true=st["rel_res_true"])
         log(f"[bench] {name} to 1e-10: {mixed[name]}")
     mixed["speedup"] = mixed["fp64_cg"]["seconds"] / mixed["fp32_inner_fp64_refine"]["seconds"]
+    mixed["speedup_keep_direction"] = (mixed["fp64_cg"]["seconds"]
+                                       / mixed["fp32_inner_fp64_refine_keep_direction"]["seconds"])
     line["mixed_precision_1e-10"] = mixed
 
     # inner tolerance of the FP32 solves, swept at 1e-10 (best first), and
@@ -308,19 +315,23 @@ def extras(args, ctx, P, x, line, torch):
         torch.cuda.synchronize()
         return time.perf_counter() - t, st
     sweep = []
-    for itol in (1e-2, 1e-3, 1e-4, 1e-5, 1e-6):
-        dt, st = timed(lambda: P.cg_mixed(x, tol=1e-10, inner_tol=itol, fmt=args.fmt)[1])
-        sweep.append(dict(inner_tol=itol, seconds=dt, inner_iterations=st["iterations"], outer=st["outer"],
-                          rel_res_true=st["rel_res_true"]))
+    for keep, itols in ((False, (1e-2, 1e-3, 1e-4, 1e-5, 1e-6)), (True, (1e-1, 1e-2, 1e-3, 1e-4))):
+        for itol in itols:
+            dt, st = timed(lambda: P.cg_mixed(x, tol=1e-10, inner_tol=itol, fmt=args.fmt, keep_direction=keep)[1])
+            sweep.append(dict(inner_tol=itol, keep_direction=keep, seconds=dt, inner_iterations=st["iterations"],
+                              outer=st["outer"], rel_res_true=st["rel_res_true"]))
     sweep.sort(key=lambda r: r["seconds"])
     line["mixed_inner_tol_sweep_1e-10"] = sweep
     log(f"[bench] inner tolerance sweep: best {sweep[0]}")
     m8 = {}
     for name, fn in (("fp64_cg", lambda: P.cg(x, tol=1e-8, max_iter=args.max_iter, fmt=args.fmt)[1]),
-                     ("fp32_inner_fp64_refine", lambda: P.cg_mixed(x, tol=1e-8, inner_tol=1e-4, fmt=args.fmt)[1])):
+                     ("fp32_inner_fp64_refine", lambda: P.cg_mixed(x, tol=1e-8, inner_tol=1e-4, fmt=args.fmt)[1]),
+                     ("fp32_inner_fp64_refine_keep_direction",
+                      lambda: P.cg_mixed(x, tol=1e-8, inner_tol=KEEP_INNER_TOL, fmt=args.fmt, keep_direction=True)[1])):
         dt, st = timed(fn)
         m8[name] = dict(seconds=dt, iterations=st["iterations"], outer=st["outer"], rel_res_true=st["rel_res_true"])
     m8["speedup"] = m8["fp64_cg"]["seconds"] / m8["fp32_inner_fp64_refine"]["seconds"]
+    m8["speedup_keep_direction"] = m8["fp64_cg"]["seconds"] / m8["fp32_inner_fp64_refine_keep_direction"]["seconds"]
     line["mixed_precision_1e-8"] = m8
     log(f"[bench] mixed at 1e-8: {m8}")
 
@@ -467,6 +478,15 @@ def extras(args, ctx, P, x, line, torch):
         ev["trained_on"] = {k: meta[k] for k in ("train", "epochs", "batch", "lr", "schedule") if k in meta}
         line["learned_warm_start_64cubed_1e-8"] = ev
         log(f"[bench] learned vs plain: {ev}")
+        # the same with the mixed solves keeping their inner direction (inner
+        # tolerance 1e-4, the fastest at 64^3)
+        evk = learned.evaluate(ctx, net, 64, seeds, inner_tol=1e-4, keep_direction=True)
+        evk.pop("rows")
+        line["learned_warm_start_64cubed_1e-8_keep_direction"] = {
+            k: evk[k] for k in ("samples", "mean_its_plain", "mean_time_plain_s", "mean_its_mixed", "mean_time_mixed_s",
+                                "mean_its_learned_mixed", "mean_time_learned_mixed_s", "worst_res_learned_mixed",
+                                "guesses_used_mixed", "speedup_time_mixed", "speedup_time_learned_mixed")}
+        log(f"[bench] learned + mixed, direction kept: {line['learned_warm_start_64cubed_1e-8_keep_direction']}")
         net.close()
 
 
