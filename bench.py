@@ -342,7 +342,9 @@ def extras(args, ctx, P, x, line, torch):
     bat = {"systems": 64, "rows": B.m, "nnz": B.nnz, "autotune": {"lanes_per_row": lanes, "grid_factor": factor}}
     xb = torch.zeros(B.m, dtype=torch.float64, device=ctx.device)
     for name, fn in (("fp64", lambda: B.cg(xb, tol=1e-8, fmt=args.fmt)[1]),
-                     ("fp32_inner_fp64_refine", lambda: B.cg_mixed(xb, tol=1e-8, fmt=args.fmt)[1])):
+                     ("fp32_inner_fp64_refine", lambda: B.cg_mixed(xb, tol=1e-8, fmt=args.fmt)[1]),
+                     ("fp32_inner_fp64_refine_keep_direction",
+                      lambda: B.cg_mixed(xb, tol=1e-8, inner_tol=1e-4, fmt=args.fmt, keep_direction=True)[1])):
         with torch.cuda.stream(ctx.stream):
             xb.zero_()
         fn()

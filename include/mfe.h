@@ -346,6 +346,12 @@ int mfe_batch_cg(mfe_batch *b, int format, double *x_dev, double tol, int max_it
  * together; needs MFE_F32 at create. */
 int mfe_batch_cg_mixed(mfe_batch *b, int format, double *x_dev, double tol, double inner_tol, int max_outer,
                        int max_inner, mfe_cg_stats *stats);
+/* mfe_batch_cg_mixed with flags: MFE_MIXED_KEEP_DIRECTION keeps each
+ * system's inner direction across refinement steps as mfe_cg_mixed_ex does
+ * (per system: after an inner solve that met its tolerance); other bits
+ * (MFE_MIXED_WARM included): MFE_EINVAL. */
+int mfe_batch_cg_mixed_ex(mfe_batch *b, int format, double *x_dev, double tol, double inner_tol, int max_outer,
+                          int max_inner, int flags, mfe_cg_stats *stats);
 
 /* ---------------------------------------------------------------------
  * Learned initial guess (extension of the CG module): a 3-D convolutional

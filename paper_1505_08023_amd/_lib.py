@@ -74,6 +74,7 @@ SIGNATURES = {
     "mfe_batch_autotune": (c_int, [c_vp, c_int, ctypes.POINTER(c_int), ctypes.POINTER(c_int)]),
     "mfe_batch_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp]),
     "mfe_batch_cg_mixed": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, c_vp]),
+    "mfe_batch_cg_mixed_ex": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, c_int, c_vp]),
     "mfe_net_create": (c_int, [c_vp, c_int, c_int, PP]),
     "mfe_net_destroy": (c_int, [c_vp]),
     "mfe_net_num_params": (c_int, [c_vp, ctypes.POINTER(c_i64)]),

@@ -235,19 +235,24 @@ __global__ __launch_bounds__(kBlock) void k_bzero_if(double *__restrict__ x, con
     for (int64_t i = M.wg_lo[w] + threadIdx.x; i < M.wg_hi[w]; i += kBlock) x[i] = 0.0;
 }
 
-// mixed precision: r32 = fl32(r / s_sys), p32 = r32, d32 = 0 for running systems
-__global__ __launch_bounds__(kBlock) void k_bmixed_start(const double *__restrict__ r, const CgState *outer, Map M,
-                                                         float *__restrict__ r32, float *__restrict__ p32,
-                                                         float *__restrict__ d32, double *__restrict__ part, int nwg) {
+// mixed precision: r32 = fl32(r / s_sys), p32 = r32, d32 = 0 for running systems; a system whose inner
+// state carries scale = s_old > 0 keeps its inner direction instead (as the single-system refinement
+// does): p32 = r32 + fl32(s_old / s_sys) (p32 - r32_old)
+__global__ __launch_bounds__(kBlock) void k_bmixed_start(const double *__restrict__ r, const CgState *outer,
+                                                         const CgState *inner, Map M, float *__restrict__ r32,
+                                                         float *__restrict__ p32, float *__restrict__ d32,
+                                                         double *__restrict__ part, int nwg) {
     const int w = blockIdx.x;
     const int sys = M.wg_sys[w];
     double acc = 0.0;
     if (outer[sys].status == kRunning) {
         const double s = sqrt(outer[sys].rho);
+        const double s_old = inner[sys].scale;
+        const float c = s_old > 0.0 ? (float)(s_old / s) : 0.0f;
         for (int64_t i = M.wg_lo[w] + threadIdx.x; i < M.wg_hi[w]; i += kBlock) {
             const float v = (float)(r[i] / s);
+            p32[i] = s_old > 0.0 ? v + c * (p32[i] - r32[i]) : v;
             r32[i] = v;
-            p32[i] = v;
             d32[i] = 0.0f;
             acc += (double)v * (double)v;
         }
@@ -483,7 +488,8 @@ int read_states(mfe_batch *B, const CgState *st, std::vector<CgState> &out) {
     return MFE_OK;
 }
 
-int set_states(mfe_batch *B, CgState *st, double tol, int max_iter, const std::vector<double> *tols = nullptr) {
+int set_states(mfe_batch *B, CgState *st, double tol, int max_iter, const std::vector<double> *tols = nullptr,
+               const std::vector<double> *scales = nullptr) {
     std::vector<CgState> h(B->nsys);
     for (int j = 0; j < B->nsys; ++j) {
         CgState &x = h[j];
@@ -491,6 +497,7 @@ int set_states(mfe_batch *B, CgState *st, double tol, int max_iter, const std::v
         x.tol = tols ? (*tols)[j] : tol;
         x.max_iter = max_iter;
         x.status = kRunning;
+        x.scale = scales ? (*scales)[j] : 0.0;
     }
     CgState *pin = (CgState *)B->pinned;
     std::copy(h.begin(), h.end(), pin);
@@ -826,12 +833,22 @@ int mfe_batch_cg(mfe_batch *B, int format, double *x_dev, double tol, int max_it
 
 int mfe_batch_cg_mixed(mfe_batch *B, int format, double *x_dev, double tol, double inner_tol, int max_outer,
                        int max_inner, mfe_cg_stats *stats) {
+    return mfe_batch_cg_mixed_ex(B, format, x_dev, tol, inner_tol, max_outer, max_inner, 0, stats);
+}
+
+int mfe_batch_cg_mixed_ex(mfe_batch *B, int format, double *x_dev, double tol, double inner_tol, int max_outer,
+                          int max_inner, int flags, mfe_cg_stats *stats) {
     clear_error();
     if (!B || !x_dev || !(tol >= 0.0) || !(inner_tol > 0.0 && inner_tol < 1.0) || max_outer < 1 || max_inner < 1 ||
         (format != MFE_CSR && format != MFE_BCRS13) || !(B->P->formats & format)) {
         set_error("need batch, x, tol >= 0, 0 < inner_tol < 1, max_outer, max_inner >= 1 and a built format");
         return MFE_EINVAL;
     }
+    if (flags & ~MFE_MIXED_KEEP_DIRECTION) {
+        set_error("flags: only MFE_MIXED_KEEP_DIRECTION applies to a batch");
+        return MFE_EINVAL;
+    }
+    const bool keep = (flags & MFE_MIXED_KEEP_DIRECTION) != 0;
     if (!(B->P->precisions & MFE_F32)) {
         set_error("FP32 values were not built for this batch");
         return MFE_EUNSUPPORTED;
@@ -850,7 +867,7 @@ int mfe_batch_cg_mixed(mfe_batch *B, int format, double *x_dev, double tol, doub
     const Map M = map_of(B);
     std::vector<int> outer_steps(ns, 0), inner_its(ns, 0);
     std::vector<CgState> o, in;
-    std::vector<double> bnorm(ns), prev(ns);
+    std::vector<double> bnorm(ns), prev(ns), scales(ns, 0.0);
     auto outer_residual = [&]() -> int {
         MFE_TRY(set_states(B, outer, tol, 1));
         MFE_TRY(bspmv<double, kSpmvResid>(B, format, t, x_dev, P->r.ptr, P->p.ptr, (const double *)P->b.ptr, outer,
@@ -873,10 +890,10 @@ int mfe_batch_cg_mixed(mfe_batch *B, int format, double *x_dev, double tol, doub
         for (int j = 0; j < ns; ++j)
             if (o[j].status == kRunning && prev[j] > 0)
                 eff[j] = std::min(0.5, std::max(inner_tol, 0.5 * tol * bnorm[j] / prev[j]));
-        MFE_TRY(set_states(B, inner, inner_tol, max_inner, &eff));
+        MFE_TRY(set_states(B, inner, inner_tol, max_inner, &eff, &scales));
         hipLaunchKernelGGL(k_bmixed_start, dim3(B->nwg), dim3(kBlock), 0, s, (const double *)P->r.ptr,
-                           (const CgState *)outer, M, (float *)B->r32.ptr, (float *)B->p32.ptr, (float *)B->d32.ptr, pa,
-                           B->nwg);
+                           (const CgState *)outer, (const CgState *)inner, M, (float *)B->r32.ptr,
+                           (float *)B->p32.ptr, (float *)B->d32.ptr, pa, B->nwg);
         MFE_HIP_TRY(hipGetLastError());
         MFE_TRY(bfinalize(B, kFinStart, pa, inner, outer, s));
         const int k = std::min(kGraphIters, max_inner);
@@ -885,12 +902,15 @@ int mfe_batch_cg_mixed(mfe_batch *B, int format, double *x_dev, double tol, doub
                                        (float *)B->p32.ptr, (float *)B->q32.ptr, inner, k, &exec));
         MFE_TRY(run_batch(B, exec, inner, k, max_inner, in));
         bool breakdown = false;
-        for (int j = 0; j < ns; ++j)
+        for (int j = 0; j < ns; ++j) {
+            // the next step keeps the direction of an inner solve that met its tolerance (scale = its s)
+            scales[j] = keep && o[j].status == kRunning && in[j].status == kConverged ? prev[j] : 0.0;
             if (o[j].status == kRunning) {
                 inner_its[j] += in[j].iters;
                 outer_steps[j] += 1;
                 breakdown = breakdown || in[j].status == kBreakdown;
             }
+        }
         hipLaunchKernelGGL(k_bmixed_update, dim3(B->nwg), dim3(kBlock), 0, s, x_dev, (const float *)B->d32.ptr,
                            (const CgState *)outer, M);
         MFE_HIP_TRY(hipGetLastError());

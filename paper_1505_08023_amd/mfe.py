@@ -428,16 +428,18 @@ class Batch:
         check(rc, "mfe_batch_cg", (MFE_OK, MFE_NOT_CONVERGED))
         return x, [s.as_dict() for s in st]
 
-    def cg_mixed(self, x=None, tol=1e-8, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13"):
+    def cg_mixed(self, x=None, tol=1e-8, inner_tol=1e-4, max_outer=50, max_inner=2000, fmt="bcrs13",
+                 keep_direction=False):
         if x is None:
             with _on(self.ctx):
                 x = torch.zeros(self.m, dtype=torch.float64, device=self.ctx.device)
         st = self._stats()
+        flags = _lib.MFE_MIXED_KEEP_DIRECTION if keep_direction else 0
         with _on(self.ctx):
-            rc = self.ctx.lib.mfe_batch_cg_mixed(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"),
-                                                 float(tol), float(inner_tol), int(max_outer), int(max_inner),
-                                                 ctypes.cast(st, ctypes.c_void_p))
-        check(rc, "mfe_batch_cg_mixed", (MFE_OK, MFE_NOT_CONVERGED))
+            rc = self.ctx.lib.mfe_batch_cg_mixed_ex(self.handle, _fmt(fmt), _ptr(x, torch.float64, self.m, "x"),
+                                                    float(tol), float(inner_tol), int(max_outer), int(max_inner),
+                                                    flags, ctypes.cast(st, ctypes.c_void_p))
+        check(rc, "mfe_batch_cg_mixed_ex", (MFE_OK, MFE_NOT_CONVERGED))
         return x, [s.as_dict() for s in st]
 
     def close(self):

@@ -64,6 +64,7 @@ def test_argument_checks_before_any_device_call():
     assert lib.mfe_problem_export_csr(None, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_net_loss_grad_energy(None, None, 1, 1, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_cg_mixed_ex(None, 1, None, 1e-8, 1e-4, 10, 10, 0, None) == _lib.MFE_EINVAL
+    assert lib.mfe_batch_cg_mixed_ex(None, 1, None, 1e-8, 1e-4, 10, 10, 0, None) == _lib.MFE_EINVAL
     assert lib.mfe_problem_destroy(None) == _lib.MFE_OK
     assert lib.mfe_ctx_destroy(None) == _lib.MFE_OK
 

@@ -114,6 +114,31 @@ def test_batch_mixed(ctx):
     B.close()
 
 
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_batch_mixed_keep_direction(ctx, fmt):
+    """Each system of the batched refinement that keeps the inner direction
+    reaches 1e-10 against its own oracle solve, needs no more inner
+    iterations than the restarting form, and takes about those of a
+    one-system batch of the same mesh (systems do not interact; the
+    per-system sums may be split over different workgroups, so rounding can
+    move a count by one or two)."""
+    from paper_1505_08023_amd.mfe import Batch
+    sizes, faces = small_batch(seed=6, nsys=6, lo=8, hi=24)
+    B = Batch(ctx, sizes, faces, precisions=("f64", "f32"))
+    x, stats = B.cg_mixed(tol=1e-10, inner_tol=1e-2, fmt=fmt, keep_direction=True)
+    _, rstats = B.cg_mixed(tol=1e-10, inner_tol=1e-2, fmt=fmt)
+    x = x.cpu().numpy()
+    for j, (N, fv) in enumerate(zip(sizes, faces)):
+        assert stats[j]["outer"] >= 2
+        check_system(x, B.row_offsets, j, tuple(N), fv, stats[j], 1e-10, its_tol=None)
+    assert sum(s["iterations"] for s in stats) < sum(s["iterations"] for s in rstats)
+    one = Batch(ctx, sizes[2:3], faces[2:3], precisions=("f64", "f32"))
+    _, s1 = one.cg_mixed(tol=1e-10, inner_tol=1e-2, fmt=fmt, keep_direction=True)
+    assert abs(s1[0]["iterations"] - stats[2]["iterations"]) <= 3 and s1[0]["rel_res_true"] <= 1e-10
+    one.close()
+    B.close()
+
+
 def test_batch_edge_cases(ctx):
     from paper_1505_08023_amd.mfe import Batch
     # a single system equals the single-mesh solve; an all-zero system is solved by x = 0
