@@ -159,6 +159,20 @@ def test_mixed_keep_direction_warm_and_flags(ctx):
     P.close()
 
 
+def test_mixed_keep_direction_after_capped_inner_solves(ctx):
+    """An inner solve that stops at max_inner is restarted, not continued:
+    with every inner solve capped the direction-keeping refinement is bitwise
+    the restarting one."""
+    from paper_1505_08023_amd.mfe import Problem
+    P = Problem.mesh(ctx, 16, 16, 16, precisions=("f64", "f32"))
+    # 8 inner iterations gain about two decades here, short of 1e-6: every inner solve is capped
+    xa, sa = P.cg_mixed(tol=1e-8, inner_tol=1e-6, max_inner=8, max_outer=200)
+    xb, sb = P.cg_mixed(tol=1e-8, inner_tol=1e-6, max_inner=8, max_outer=200, keep_direction=True)
+    assert sa["outer"] == sb["outer"] >= 2 and sa["iterations"] == sb["iterations"]
+    assert torch.equal(xa, xb)
+    P.close()
+
+
 def test_mixed_cg_128_against_fp64(ctx):
     """128^3: mixed to 1e-10 and FP64 CG to 1e-10 reach the same solution."""
     from paper_1505_08023_amd.mfe import Problem
