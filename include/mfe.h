@@ -186,6 +186,21 @@ int mfe_spmv_dot(const mfe_problem *p, int format, const double *p_dev, double *
 int mfe_spmv_dot_f32(const mfe_problem *p, int format, const float *p_dev, float *q_dev, double *pq_dev,
                      void *ev_before, void *ev_after);
 
+/* mfe_spmv_dot for callers that cannot allocate device memory (code under
+ * HIP graph capture, allocation-free serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and results (q and p.q bitwise those of
+ * mfe_spmv_dot), but the reduction partials and the solver state live in a
+ * static device array of the library, 33,024 bytes per GPU (partials of up
+ * to 4096 workgroups, which no launch of the product exceeds; one that would
+ * is refused with MFE_EUNSUPPORTED before any work is enqueued), held from
+ * the first mfe_ctx_create on that GPU until the process ends.  The call
+ * allocates nothing and does not synchronise; it enqueues three kernels on
+ * the context's stream.  Every call on one GPU shares that array, whatever
+ * its context or stream: calls that overlap on one GPU race (the caller
+ * orders them, for instance on one stream).  Each call sets all of the
+ * array's contents it reads.  FP64, formats as mfe_spmv_dot. */
+int mfe_spmv_dot_noalloc(const mfe_problem *p, int format, const double *p_dev, double *q_dev, double *pq_dev);
+
 /* Dot product (Sec. 1, DOT) of two FP64 device vectors of length n >= 0
  * (x_dev, y_dev may be NULL when n = 0),
  * reduced in a fixed order (bitwise reproducible run to run).  The result is

@@ -54,6 +54,7 @@ SIGNATURES = {
     "mfe_spmv": (c_int, [c_vp, c_int, c_vp, c_vp]),
     "mfe_spmv_f32": (c_int, [c_vp, c_int, c_vp, c_vp]),
     "mfe_spmv_dot": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "mfe_spmv_dot_noalloc": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp]),
     "mfe_dot": (c_int, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(c_dbl)]),
     "mfe_cg_mixed_warm": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_cg_mixed_ex": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),

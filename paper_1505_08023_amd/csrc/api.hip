@@ -129,7 +129,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 8; }
+int mfe_version(void) { return 9; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -170,6 +170,7 @@ int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn fre
         set_error(std::string("context setup failed: ") + hipGetErrorString(hipGetLastError()));
         rc = MFE_EHIP;
     }
+    if (rc == MFE_OK) rc = noalloc_init(device);
     if (rc == MFE_OK) {
         c->num_cu = prop.multiProcessorCount;
         rc = dev_alloc(c, &c->scratch, kMaxPartials * sizeof(double));

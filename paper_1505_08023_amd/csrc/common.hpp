@@ -237,11 +237,16 @@ struct SpmvArgs {
     const double *b; // resid/true
     CgState *st;
     double *partials;
+    int max_partials = 0;  // > 0: refuse a launch whose grid would write more partials
 };
 
 // *grid (optional) receives the number of workgroups, i.e. of partials written.
 int launch_spmv(const mfe_problem *P, int format, bool f32, SpmvMode mode, const SpmvArgs &a,
                 hipStream_t s, int *grid = nullptr);
+
+// static scratch of the allocation-free entry point (noalloc.hip): looks up
+// this device's address of it; called by mfe_ctx_create with the device current
+int noalloc_init(int device);
 
 // problem storage (api.hip)
 void free_problem_storage(mfe_problem *P);

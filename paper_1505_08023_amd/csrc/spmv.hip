@@ -318,9 +318,20 @@ int64_t b13_bytes(const mfe_problem *P) {
     return P->nslots * 64 * (int64_t)(3 * sizeof(T) + sizeof(int32_t));
 }
 
+// A launch whose grid would write more partials than `cap` (when cap > 0)
+// is refused before it starts.
+int check_cap(int grid, int cap) {
+    if (cap > 0 && grid > cap) {
+        set_error("the product's grid (" + std::to_string(grid) + " workgroups) exceeds its partials buffer (" +
+                  std::to_string(cap) + ")");
+        return MFE_EUNSUPPORTED;
+    }
+    return MFE_OK;
+}
+
 template <typename T, int MODE, bool MNT>
 int launch_csr_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s,
-                  int *grid_out) {
+                  int *grid_out, int cap) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->val64.ptr : (const T *)P->val32.ptr;
 #if MFE_CSR_STREAM
     auto kern = k_spmv_csrs<T, MODE, MNT>;
@@ -333,6 +344,7 @@ int launch_csr_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
     const long ntiles = (P->m + kBlock / L - 1) / (kBlock / L);
 #endif
     const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
+    MFE_TRY(check_cap(grid, cap));
 #if MFE_CSR_STREAM
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->ptr.ptr,
                        (const int32_t *)P->col.ptr, (const CsrDesc *)P->cdesc.ptr, val, E, st, partials);
@@ -346,14 +358,15 @@ int launch_csr_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
 }
 
 template <typename T, int MODE>
-int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
-    return matrix_stream_nt(csr_bytes<T>(P)) ? launch_csr_as<T, MODE, true>(P, E, st, partials, s, grid_out)
-                                             : launch_csr_as<T, MODE, false>(P, E, st, partials, s, grid_out);
+int launch_csr(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out,
+               int cap) {
+    return matrix_stream_nt(csr_bytes<T>(P)) ? launch_csr_as<T, MODE, true>(P, E, st, partials, s, grid_out, cap)
+                                             : launch_csr_as<T, MODE, false>(P, E, st, partials, s, grid_out, cap);
 }
 
 template <typename T, int MODE, bool MNT>
 int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s,
-                  int *grid_out) {
+                  int *grid_out, int cap) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
     const long ntiles = (P->m + kBlock - 1) / kBlock;
     // the pipelined walk pays off once each workgroup takes several tiles
@@ -363,6 +376,7 @@ int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
         kern = k_spmv_b13<T, MODE, MNT>;
         grid = grid_for(kern, ntiles, P->ctx->num_cu);
     }
+    MFE_TRY(check_cap(grid, cap));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
                        (const int32_t *)P->jas.ptr, (const B13Desc *)P->bdesc.ptr, val, E, st, partials);
     MFE_HIP_TRY(hipGetLastError());
@@ -371,16 +385,17 @@ int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
 }
 
 template <typename T, int MODE>
-int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out) {
-    return matrix_stream_nt(b13_bytes<T>(P)) ? launch_b13_as<T, MODE, true>(P, E, st, partials, s, grid_out)
-                                             : launch_b13_as<T, MODE, false>(P, E, st, partials, s, grid_out);
+int launch_b13(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s, int *grid_out,
+               int cap) {
+    return matrix_stream_nt(b13_bytes<T>(P)) ? launch_b13_as<T, MODE, true>(P, E, st, partials, s, grid_out, cap)
+                                             : launch_b13_as<T, MODE, false>(P, E, st, partials, s, grid_out, cap);
 }
 
 template <typename T, int MODE>
 int launch_mode(const mfe_problem *P, int format, const SpmvArgs &a, hipStream_t s, int *grid) {
     Epi<T> E{(const T *)a.x, (T *)a.y, (T *)a.p_out, a.b, vectors_stream_nt(P->m)};
-    if (format == MFE_CSR) return launch_csr<T, MODE>(P, E, a.st, a.partials, s, grid);
-    return launch_b13<T, MODE>(P, E, a.st, a.partials, s, grid);
+    if (format == MFE_CSR) return launch_csr<T, MODE>(P, E, a.st, a.partials, s, grid, a.max_partials);
+    return launch_b13<T, MODE>(P, E, a.st, a.partials, s, grid, a.max_partials);
 }
 
 }  // namespace

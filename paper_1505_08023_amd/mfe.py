@@ -272,6 +272,16 @@ class Problem:
                                               _ptr(pq, torch.float64, 1, "pq"), ev[0], ev[1]), name)
         return q, pq
 
+    def spmv_dot_noalloc(self, p, q, pq, fmt="bcrs13"):
+        """q = A p and p.q into the device scalar pq (FP64) through
+        mfe_spmv_dot_noalloc, which allocates no device memory: the caller
+        passes every output."""
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_spmv_dot_noalloc(self.handle, _fmt(fmt), _ptr(p, torch.float64, self.m, "p"),
+                                                    _ptr(q, torch.float64, self.m, "q"),
+                                                    _ptr(pq, torch.float64, 1, "pq")), "mfe_spmv_dot_noalloc")
+        return q, pq
+
     def cg(self, x=None, tol=1e-8, max_iter=200, fmt="bcrs13", history=False, raise_on_breakdown=True,
            warm=False, variant="cg"):
         """Unpreconditioned CG from x (zero if None).  warm=True: x is a guess

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_string():
     lib = _lib.load()
-    assert lib.mfe_version() == 8
+    assert lib.mfe_version() == 9
     assert isinstance(lib.mfe_last_error(), bytes)
 
 
@@ -55,6 +55,7 @@ def test_argument_checks_before_any_device_call():
     assert lib.mfe_spmv_f32(None, 1, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_cg(None, 1, None, 1e-8, 10, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_dot(None, 1, None, None, None) == _lib.MFE_EINVAL
+    assert lib.mfe_spmv_dot_noalloc(None, 1, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_stream_probe(None, 0, 1, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_problem_set_bc(None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_problem_info(None, None, None, None) == _lib.MFE_EINVAL
