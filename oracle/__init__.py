@@ -75,8 +75,8 @@ def lib():
                                    ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl)]
         L.orc_cg_mixed_keep.restype = _c_int
         L.orc_cg_mixed_keep.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_dbl,
-                                        _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
-                                        ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl)]
+                                        _c_int, _c_int, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
+                                        ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl)]
         L.orc_analytic_u.restype = _c_dbl
         L.orc_analytic_u.argtypes = [_c_dbl, _c_dbl, _c_dbl, _c_int]
         _LIB = L
@@ -274,24 +274,27 @@ def cg_jacobi(A, b=None, x0=None, tol=1e-8, max_iter=200, history=False):
 
 
 def cg_mixed(A, b=None, x0=None, tol=1e-10, inner_tol=1e-4, max_outer=50, max_inner=500,
-             keep_direction=False, inner_f32=True, emulated=False):
+             keep_direction=False, inner_f32=True, emulated=False, safeguards=False):
     """FP32-inner CG inside FP64 iterative refinement (mixed-precision
     extension).  keep_direction: the inner CG goes on from its last direction
     after each refinement step (orc_cg_mixed_keep); inner_f32=False runs the
     inner steps in FP64; emulated forces orc_cg_mixed_keep (FP32 emulated in
-    FP64 arithmetic) for the restarting form too."""
+    FP64 arithmetic) for the restarting form too; safeguards adds the
+    last-step inner tolerance and the FP64 CG fallback on stagnation
+    (orc_cg_mixed_keep's adaptive and fallback)."""
     b = A.b if b is None else np.ascontiguousarray(b, np.float64)
     x = np.zeros(A.m) if x0 is None else np.array(x0, np.float64, copy=True)
-    outer, inner, rt = _c_int(0), _c_int(0), _c_dbl(0)
-    if keep_direction or not inner_f32 or emulated:
+    outer, inner, fb, rt = _c_int(0), _c_int(0), _c_int(0), _c_dbl(0)
+    if keep_direction or not inner_f32 or emulated or safeguards:
+        sg = int(bool(safeguards))
         st = lib().orc_cg_mixed_keep(A.m, A.ptr, A.col, A.val, b, x, tol, inner_tol, max_outer, max_inner,
-                                     int(bool(keep_direction)), int(bool(inner_f32)),
-                                     ctypes.byref(outer), ctypes.byref(inner), ctypes.byref(rt))
+                                     int(bool(keep_direction)), int(bool(inner_f32)), sg, sg,
+                                     ctypes.byref(outer), ctypes.byref(inner), ctypes.byref(fb), ctypes.byref(rt))
     else:
         st = lib().orc_cg_mixed(A.m, A.ptr, A.col, A.val, b, x, tol, inner_tol, max_outer, max_inner,
                                 ctypes.byref(outer), ctypes.byref(inner), ctypes.byref(rt))
     return dict(x=x, status=st, outer=outer.value, inner_iterations=inner.value,
-                rel_res_true=rt.value)
+                fallback_iterations=fb.value, rel_res_true=rt.value)
 
 
 def analytic_u(x, y, z, max_pq=4001):

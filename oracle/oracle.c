@@ -625,10 +625,24 @@ static double rnd(int f32, double v) { return f32 ? (double)(float)v : v; }
  * computes what orc_cg_mixed computes); f32 = 0: the same steps in FP64 with
  * the FP64 matrix.  In exact arithmetic the FP64 residual equals the
  * recursive one, so keep = 1 then takes the iterates of plain CG.
+ *
+ * Two safeguards of the refinement (a reading: the method fixes neither):
+ *   adaptive = 1: an inner solve need not reduce its residual further than
+ *     the outer target asks.  With s the norm of the residual it starts
+ *     from, its relative tolerance is max(inner_tol, min(0.5, tol ||b|| /
+ *     (2 s))): on the last refinement step usually much looser than
+ *     inner_tol.
+ *   fallback = 1: a refinement step whose new FP64 residual is not at most
+ *     half the previous one (while the outer tolerance is not met), or an
+ *     inner breakdown, ends the refinement; plain FP64 CG (orc_cg) then
+ *     continues from the current x to tol, capped at max_inner * max_outer
+ *     iterations, and its status is the result.  *fallback_its receives its
+ *     iteration count (0 when it did not run); *res_true its true residual.
  * Returns as orc_cg_mixed. */
 int orc_cg_mixed_keep(int64_t m, const int64_t *ptr, const int32_t *col, const double *val,
                       const double *b, double *x, double tol, double inner_tol, int max_outer,
-                      int max_inner, int keep, int f32, int *outer, int *inner_total, double *res_true)
+                      int max_inner, int keep, int f32, int adaptive, int fallback,
+                      int *outer, int *inner_total, int *fallback_its, double *res_true)
 {
     int64_t nnz = ptr[m];
     double *vi = (double *)malloc((size_t)nnz * sizeof(double));
@@ -647,15 +661,23 @@ int orc_cg_mixed_keep(int64_t m, const int64_t *ptr, const int32_t *col, const d
         for (int64_t i = 0; i < m; ++i) x[i] = 0.0;
         *res_true = 0.0; status = ORC_OK; goto out;
     }
-    int have_dir = 0;
-    double beta = 0.0, s_old = 0.0;
+    int have_dir = 0, go_fp64 = 0;
+    double beta = 0.0, s_old = 0.0, s_prev = -1.0;
+    *fallback_its = 0;
     for (;;) {
         orc_csr_spmv(m, ptr, col, val, x, ax);
         for (int64_t i = 0; i < m; ++i) r[i] = b[i] - ax[i];
         double s = sqrt(dot(m, r, r));
         *res_true = s / bnorm;
         if (s / bnorm <= tol) { status = ORC_OK; break; }
+        if (fallback && s_prev >= 0.0 && !(s <= 0.5 * s_prev)) { go_fp64 = 1; break; }
         if (*outer >= max_outer) { status = ORC_NOT_CONVERGED; break; }
+        s_prev = s;
+        double itol = inner_tol;
+        if (adaptive) {
+            double need = tol * bnorm / (2.0 * s);
+            if (need > itol) itol = need < 0.5 ? need : 0.5;
+        }
         const double c = rnd(f32, beta * (s_old / s));
         for (int64_t i = 0; i < m; ++i) {
             ri[i] = rnd(f32, r[i] / s);
@@ -679,16 +701,26 @@ int orc_cg_mixed_keep(int64_t m, const int64_t *ptr, const int32_t *col, const d
             double rho_new = dot(m, ri, ri);
             ++k;
             double be = rho_new / rho;
-            if (sqrt(rho_new / rho0) <= inner_tol) { beta = be; have_dir = 1; break; }
+            if (sqrt(rho_new / rho0) <= itol) { beta = be; have_dir = 1; break; }
             double bf = rnd(f32, be);
             for (int64_t i = 0; i < m; ++i) p[i] = rnd(f32, ri[i] + rnd(f32, bf * p[i]));
             rho = rho_new;
         }
         *inner_total += k;
         *outer += 1;
-        if (status == ORC_BREAKDOWN) break;
+        if (status == ORC_BREAKDOWN) {
+            if (fallback) go_fp64 = 1;
+            break;
+        }
         for (int64_t i = 0; i < m; ++i) x[i] += s * d[i];
         s_old = s;
+    }
+    if (go_fp64) {
+        int its = 0;
+        double rec = 0.0;
+        int cap = max_inner * (max_outer > 1 ? max_outer : 1);
+        status = orc_cg(m, ptr, col, val, b, x, tol, cap, &its, &rec, res_true, NULL);
+        *fallback_its = its;
     }
 out:
     free(vi); free(r); free(ax); free(ri); free(d); free(p); free(q);

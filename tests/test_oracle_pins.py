@@ -449,3 +449,66 @@ def test_mixed_precision_reaches_fp64_accuracy():
     assert r["status"] == oracle.OK and r["rel_res_true"] <= 1e-10
     assert r["outer"] >= 2  # FP32 alone cannot reach 1e-10
     assert np.linalg.norm(r["x"] - ref) <= 1e-8 * np.linalg.norm(ref)
+
+
+def test_mixed_safeguard_last_inner_tolerance_reduces_to_cg():
+    """The last-step inner tolerance: with the inner steps in FP64, a zero
+    start (s = ||b||) and an inner tolerance tighter than the target, the
+    first inner solve only has to reach tol ||b|| / (2 s) = tol / 2, so it
+    is plain CG on b / ||b|| to tol / 2: one refinement step of exactly CG's
+    iteration count to tol / 2.  On these meshes CG to tol stops one
+    iteration earlier, so a target off by the factor 2 fails the count; no
+    residual of the history lies within rounding of tol / 2.  Without the
+    safeguard the inner solve goes on to the tighter inner tolerance."""
+    for N in ((12, 12, 12), (9, 14, 7)):
+        A = oracle.assemble(*N)
+        tol = 1e-8
+        r = oracle.cg_mixed(A, tol=tol, inner_tol=1e-13, inner_f32=False, safeguards=True)
+        plain = oracle.cg(A, tol=tol / 2, max_iter=2000, history=True)
+        assert oracle.cg(A, tol=tol, max_iter=2000)["iterations"] < plain["iterations"]
+        assert np.all(np.abs(plain["history"] / (tol / 2) - 1) > 1e-6)
+        assert r["status"] == oracle.OK and r["outer"] == 1 and r["fallback_iterations"] == 0
+        assert r["inner_iterations"] == plain["iterations"], (r["inner_iterations"], plain["iterations"])
+        assert r["rel_res_true"] <= tol
+        tight = oracle.cg_mixed(A, tol=tol, inner_tol=1e-13, inner_f32=False)
+        assert tight["inner_iterations"] > r["inner_iterations"] + 5
+
+
+def test_mixed_safeguard_fallback_is_fp64_cg_from_the_refined_iterate():
+    """The FP64 fallback: with one inner iteration per refinement step and
+    FP64 inner steps, each step is one steepest-descent step on A x = b
+    (x += (r.r / r.Ar) r from the current residual r).  At 14^3 the first
+    such step cuts the residual to 5 % of ||b|| and the second leaves 59 % of
+    it (ratios computed here independently, both far from the halving
+    threshold), so the refinement hands over after two steps, and the rest is
+    plain CG from the second steepest-descent iterate: the same iteration
+    count within 1 and the same solution within the tolerance bound.  With
+    the default inner tolerance the fallback does not run."""
+    N = (14, 14, 14)
+    A = oracle.assemble(*N)
+    M = A.dense()
+    b = A.b
+    x = np.zeros(A.m)
+    ratios = []
+    for _ in range(2):
+        r = b - M @ x
+        x = x + (r @ r) / (r @ (M @ r)) * r
+        ratios.append(np.linalg.norm(b - M @ x) / np.linalg.norm(r))
+    assert ratios[0] < 0.4 and ratios[1] > 0.55, ratios
+    tol = 1e-8
+    res = oracle.cg_mixed(A, tol=tol, inner_tol=1e-4, max_outer=50, max_inner=1, inner_f32=False, safeguards=True)
+    assert res["outer"] == 2 and res["inner_iterations"] == 2 and res["fallback_iterations"] > 0
+    ref = oracle.cg(A, x0=x, tol=tol, max_iter=50)
+    assert res["status"] == ref["status"] == oracle.OK
+    assert abs(res["fallback_iterations"] - ref["iterations"]) <= 1
+    assert res["rel_res_true"] <= tol
+    assert np.linalg.norm(res["x"] - ref["x"]) <= 4 * tol * np.linalg.norm(b) / min(np.linalg.eigvalsh(M))
+    # the same with FP32 inner steps hands over at the same step and still meets the tolerance
+    r32 = oracle.cg_mixed(A, tol=tol, inner_tol=1e-4, max_inner=1, safeguards=True)
+    assert r32["outer"] == 2 and r32["fallback_iterations"] > 0 and r32["rel_res_true"] <= tol
+    # the cap of the fallback is max_inner * max_outer
+    capped = oracle.cg_mixed(A, tol=tol, max_outer=3, max_inner=1, inner_f32=False, safeguards=True)
+    assert capped["status"] == oracle.NOT_CONVERGED and capped["fallback_iterations"] == 3
+    # the default inner tolerance halves the residual at every step: no fallback
+    d = oracle.cg_mixed(A, tol=1e-10, safeguards=True)
+    assert d["status"] == oracle.OK and d["fallback_iterations"] == 0 and d["outer"] >= 2
