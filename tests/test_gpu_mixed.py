@@ -4,9 +4,15 @@
               (the exact-input reference for an FP32 kernel): per row
               |d_i| <= 32 eps32 sum_j |A32_ij x32_j| (27 rounded FMAs).
   mixed CG    final FP64 true residual <= tol (1e-10), the oracle's mixed
-              solve reaches the same, and the solution is within the
-              residual bound of the oracle's FP64 CG solution:
-              ||x - x_ref|| <= (||r|| + ||r_ref||) / lambda_min(A).
+              solve (with the same two safeguards: the last inner solve only
+              to what the outer tolerance needs, FP64 CG after a step that
+              does not halve the residual) reaches the same with the same
+              number of refinement steps and inner iterations within the
+              FP32 rounding of the inner recurrences (3, or 5 %), and the
+              solution is within the residual bound of the oracle's FP64 CG
+              solution: ||x - x_ref|| <= (||r|| + ||r_ref||) / lambda_min(A).
+              At 128^3 and 256^3 (the mixed-precision benchmark size) the
+              residual is also rebuilt on sampled rows by the oracle.
 """
 import math
 
@@ -73,25 +79,32 @@ def test_spmv_dot_f32(ctx, N, fmt):
     assert q.dtype == torch.float32
     q = q.cpu().numpy().astype(np.float64)
     assert np.all(np.abs(q - ref) <= 32 * EPS32 * scale + 1e-38)
-    dot_ref = float(x64 @ q)  # the GPU's own FP32 rows, dotted in FP64
-    assert abs(float(pq.cpu()) - dot_ref) <= 1e-12 * float(np.abs(x64) @ np.abs(q))
+    # p.q against the FP64 dot of p with the exact-input product: the rows may
+    # differ by their FP32 rounding (the bar above), the FP64 sum by its own
+    dot_ref = float(x64 @ ref)
+    bound = 32 * EPS32 * float(np.abs(x64) @ scale) + 1e-12 * float(np.abs(x64) @ np.abs(ref))
+    assert abs(float(pq.cpu()) - dot_ref) <= bound
     P.close()
 
 
+@pytest.mark.parametrize("start", ["zero", "boundary"])
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
 @pytest.mark.parametrize("N", [(20, 20, 20), (17, 9, 23)])
-def test_mixed_cg_matches_oracle(ctx, N, fmt):
+def test_mixed_cg_matches_oracle(ctx, N, fmt, start):
     from paper_1505_08023_amd.mfe import Problem
     tol = 1e-10
     A = oracle.assemble(*N)
+    d, g = oracle.boundary(*N)
+    x0 = np.where(d, g, 0.0) if start == "boundary" else np.zeros(A.m)
     ref64 = oracle.cg(A, tol=1e-13, max_iter=5000)
-    refmx = oracle.cg_mixed(A, tol=tol, inner_tol=1e-4)
-    assert refmx["status"] == oracle.OK and refmx["rel_res_true"] <= tol
+    refmx = oracle.cg_mixed(A, x0=x0, tol=tol, inner_tol=1e-4, max_inner=2000, safeguards=True)
+    assert refmx["status"] == oracle.OK and refmx["rel_res_true"] <= tol and refmx["fallback_iterations"] == 0
     P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
-    x, st = P.cg_mixed(tol=tol, inner_tol=1e-4, fmt=fmt)
-    print("mixed", N, fmt, st, "oracle outer/inner", refmx["outer"], refmx["inner_iterations"])
+    x, st = P.cg_mixed(x=torch.tensor(x0, device=ctx.device), tol=tol, inner_tol=1e-4, fmt=fmt)
+    print("mixed", start, N, fmt, st, "oracle outer/inner", refmx["outer"], refmx["inner_iterations"])
     assert st["status"] == 0 and st["rel_res_true"] <= tol
-    assert st["outer"] >= 2
+    assert st["outer"] >= 2 and st["outer"] == refmx["outer"]
+    assert abs(st["iterations"] - refmx["inner_iterations"]) <= max(3, 0.05 * refmx["inner_iterations"])
     bnorm = np.linalg.norm(A.b)
     gap = np.linalg.norm(x.cpu().numpy() - ref64["x"])
     bound = (st["rel_res_true"] + ref64["rel_res_true"]) * bnorm / lam_min(N) + 1e-12
@@ -99,27 +112,36 @@ def test_mixed_cg_matches_oracle(ctx, N, fmt):
     P.close()
 
 
+@pytest.mark.parametrize("start", ["zero", "boundary"])
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
 @pytest.mark.parametrize("N", [(20, 20, 20), (17, 9, 23)])
-def test_mixed_keep_direction_matches_oracle(ctx, N, fmt):
+def test_mixed_keep_direction_matches_oracle(ctx, N, fmt, start):
     """The refinement that keeps the inner direction (mfe_cg_mixed_ex):
-    reaches 1e-10 as the oracle's form of it does, within the residual bound
-    of the FP64 solution, with no more inner iterations than the oracle's
-    (up to rounding: the library also loosens the last inner solve to what
-    the outer tolerance needs, the oracle keeps inner_tol) and fewer than
-    the restarting solve's."""
+    reaches 1e-10 as the oracle's form of it (with the same safeguards) does,
+    with refinement steps within 1 and inner iterations within FP32
+    rounding, within the residual bound of the FP64 solution, and in fewer
+    inner iterations than the restarting solve.  The inner count of this
+    form follows the FP32 rounding of the carried direction closely: the
+    GPU's two formats, which differ only in the order of each row's sum,
+    part by 4 of 45 inner iterations at 20^3 from x0 = g, and the GPU's
+    fused multiply-adds against the oracle's separate roundings by up to
+    12 %; so the bar is 15 % (the restarting form, which discards the
+    direction, stays within 5 %)."""
     from paper_1505_08023_amd.mfe import Problem
     tol = 1e-10
     A = oracle.assemble(*N)
+    d, g = oracle.boundary(*N)
+    x0 = np.where(d, g, 0.0) if start == "boundary" else np.zeros(A.m)
     ref64 = oracle.cg(A, tol=1e-13, max_iter=5000)
-    refk = oracle.cg_mixed(A, tol=tol, inner_tol=1e-2, keep_direction=True)
-    assert refk["status"] == oracle.OK and refk["rel_res_true"] <= tol
+    refk = oracle.cg_mixed(A, x0=x0, tol=tol, inner_tol=1e-2, max_inner=2000, keep_direction=True, safeguards=True)
+    assert refk["status"] == oracle.OK and refk["rel_res_true"] <= tol and refk["fallback_iterations"] == 0
     P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
-    x, st = P.cg_mixed(tol=tol, inner_tol=1e-2, fmt=fmt, keep_direction=True)
-    _, sr = P.cg_mixed(tol=tol, inner_tol=1e-2, fmt=fmt)
-    print("keep", N, fmt, st, "oracle outer/inner", refk["outer"], refk["inner_iterations"], "restart", sr)
+    x, st = P.cg_mixed(x=torch.tensor(x0, device=ctx.device), tol=tol, inner_tol=1e-2, fmt=fmt, keep_direction=True)
+    _, sr = P.cg_mixed(x=torch.tensor(x0, device=ctx.device), tol=tol, inner_tol=1e-2, fmt=fmt)
+    print("keep", start, N, fmt, st, "oracle outer/inner", refk["outer"], refk["inner_iterations"], "restart", sr)
     assert st["status"] == 0 and st["rel_res_true"] <= tol and st["outer"] >= 2
-    assert st["iterations"] <= refk["inner_iterations"] + max(4, 0.1 * refk["inner_iterations"])
+    assert abs(st["outer"] - refk["outer"]) <= 1
+    assert abs(st["iterations"] - refk["inner_iterations"]) <= max(3, 0.15 * refk["inner_iterations"])
     assert st["iterations"] < sr["iterations"]
     bnorm = np.linalg.norm(A.b)
     gap = np.linalg.norm(x.cpu().numpy() - ref64["x"])
@@ -173,18 +195,99 @@ def test_mixed_keep_direction_after_capped_inner_solves(ctx):
     P.close()
 
 
-def test_mixed_cg_128_against_fp64(ctx):
-    """128^3: mixed to 1e-10 and FP64 CG to 1e-10 reach the same solution."""
+def check_sampled_rows(N, x, tol, nrows=2000, seed=9):
+    """||b - A x|| <= tol ||b|| rebuilt by the oracle on sampled rows: every
+    sampled |r_i| is at most tol ||b||, and their mean square, scaled to m
+    rows, at most (tol ||b||)^2 times a sampling margin of 4."""
+    m = oracle.num_rows(*N)
+    rows = np.random.default_rng(seed).integers(0, m, nrows)
+    got, b = oracle.assemble_rows(*N, rows)
+    # ||b||: 1 on the (N+1)^2 nodes of x = 1, h on the (N-1)^2 free nodes next to it
+    n = N[0]
+    bn = math.sqrt((n + 1) ** 2 + (n - 1) ** 2 / n ** 2)
+    r = np.array([bi - float(vals @ x[cols]) for (cols, vals), bi in zip(got, b)])
+    assert np.all(np.abs(r) <= tol * bn), float(np.abs(r).max() / bn)
+    assert float(np.mean(r ** 2)) * m <= 4 * (tol * bn) ** 2
+    return float(np.abs(r).max() / bn)
+
+
+def test_mixed_cg_128_against_oracle(ctx):
+    """128^3, both forms, to 1e-10: the solution within the residual bound of
+    the oracle's FP64 CG solution (from x0 = g, to 1e-11), the residual
+    rebuilt by the oracle on sampled rows, and the error against the FP64
+    solution reported."""
     from paper_1505_08023_amd.mfe import Problem
     N = (128, 128, 128)
+    A = oracle.assemble(*N)
+    d, g = oracle.boundary(*N)
+    ref = oracle.cg(A, x0=np.where(d, g, 0.0), tol=1e-11, max_iter=2000)
+    assert ref["status"] == oracle.OK
     P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
-    xm, sm = P.cg_mixed(tol=1e-10, inner_tol=1e-4)
+    bnorm = float(np.linalg.norm(A.b))
+    for keep, inner_tol in ((False, 1e-4), (True, 1e-2)):
+        print("128^3 mixed keep", keep, flush=True)
+        xm, sm = P.cg_mixed(tol=1e-10, inner_tol=inner_tol, keep_direction=keep)
+        assert sm["status"] == 0 and sm["rel_res_true"] <= 1e-10
+        xs = xm.cpu().numpy()
+        gap = float(np.linalg.norm(xs - ref["x"]))
+        assert gap <= (sm["rel_res_true"] + ref["rel_res_true"]) * bnorm / lam_min(N)
+        worst = check_sampled_rows(N, xs, 1e-10)
+        print("128^3 mixed", keep, sm, "error against FP64", gap / np.linalg.norm(ref["x"]), "worst row", worst)
+    P.close()
+
+
+@pytest.mark.parametrize("keep", [False, True])
+def test_mixed_cg_256_benchmark_configuration(ctx, keep):
+    """256^3 to 1e-10 in the benchmark's configuration (1x3 BCRS, inner
+    tolerance 1e-4 restarting, 1e-2 keeping the direction): the FP64 true
+    residual, the residual rebuilt by the oracle on sampled rows, the
+    maximum principle, the centre value against the series solution, and
+    the error against the FP64 CG solution within the residual bound."""
+    from paper_1505_08023_amd.mfe import Problem
+    N = (256, 256, 256)
+    P = Problem.mesh(ctx, *N, formats=("bcrs13",), precisions=("f64", "f32"))
+    xm, sm = P.cg_mixed(tol=1e-10, inner_tol=1e-2 if keep else 1e-4, keep_direction=keep)
+    print("256^3 mixed keep", keep, sm, flush=True)
+    assert sm["status"] == 0 and sm["rel_res_true"] <= 1e-10 and sm["outer"] >= 2
+    u = xm.view(257, 257, 257)
+    assert float(u.min()) >= -1e-6 and float(u.max()) <= 1 + 1e-6
+    assert abs(float(u[128, 128, 128]) - oracle.analytic_u(0.5, 0.5, 0.5)) <= 1e-4
+    check_sampled_rows(N, xm.cpu().numpy(), 1e-10)
     xd, sd = P.cg(tol=1e-10, max_iter=20000)
-    print("128^3 mixed", sm, "fp64", sd)
-    assert sm["status"] == 0 and sm["rel_res_true"] <= 1e-10 and sd["rel_res_true"] <= 1e-10
-    bnorm = math.sqrt(129 ** 2 + 127 ** 2 / 128 ** 2)  # ones on x = 1, h next to it
+    bnorm = math.sqrt(257 ** 2 + 255 ** 2 / 256 ** 2)
     gap = float(torch.linalg.norm(xm - xd))
     assert gap <= (sm["rel_res_true"] + sd["rel_res_true"]) * bnorm / lam_min(N)
+    print("256^3 error against FP64", gap / float(torch.linalg.norm(xd)))
+    P.close()
+
+
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_mixed_fp64_fallback(ctx, fmt):
+    """The FP64 fallback of the refinement: with one inner iteration per step
+    the second step of 14^3 leaves 59 % of the residual (see the oracle pin),
+    so the solve hands over to FP64 CG after two steps, as the oracle's
+    safeguarded solve does; the handed-over solve reaches the tolerance in
+    the oracle's count within 2 (it starts from an FP32-rounded iterate) and
+    lands within the residual bound of the oracle's solution.  A fallback
+    capped by max_inner * max_outer reports MFE_NOT_CONVERGED."""
+    from paper_1505_08023_amd.mfe import Problem
+    N = (14, 14, 14)
+    A = oracle.assemble(*N)
+    ref = oracle.cg_mixed(A, tol=1e-8, inner_tol=1e-4, max_outer=50, max_inner=1, safeguards=True)
+    assert ref["outer"] == 2 and ref["fallback_iterations"] > 0 and ref["status"] == oracle.OK
+    P = Problem.mesh(ctx, *N, precisions=("f64", "f32"))
+    x, st = P.cg_mixed(tol=1e-8, inner_tol=1e-4, max_outer=50, max_inner=1, fmt=fmt)
+    print("fallback", fmt, st, "oracle", {k: v for k, v in ref.items() if k != "x"})
+    assert st["status"] == 0 and st["rel_res_true"] <= 1e-8 and st["outer"] == 2
+    fallback_its = st["iterations"] - 2
+    assert abs(fallback_its - ref["fallback_iterations"]) <= 2, (fallback_its, ref["fallback_iterations"])
+    bnorm = np.linalg.norm(A.b)
+    gap = np.linalg.norm(x.cpu().numpy() - ref["x"])
+    assert gap <= (st["rel_res_true"] + ref["rel_res_true"]) * bnorm / lam_min(N) + 1e-12
+    capped_ref = oracle.cg_mixed(A, tol=1e-8, max_outer=3, max_inner=1, safeguards=True)
+    x, st = P.cg_mixed(tol=1e-8, max_outer=3, max_inner=1, fmt=fmt)
+    assert capped_ref["status"] == oracle.NOT_CONVERGED and st["status"] == 1
+    assert st["iterations"] == 2 + 3 and st["outer"] == 2
     P.close()
 
 
