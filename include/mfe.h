@@ -410,7 +410,17 @@ int mfe_net_loss_grad(mfe_net *net, int batch, const double *g_dev, const double
  * vectors of batch_max G^3 entries on first use (freed with the net). */
 int mfe_net_loss_grad_energy(mfe_net *net, const mfe_problem *problem, int format, int batch, const double *g_dev,
                              const double *target_dev, double *loss_host, float *grad_host);
-/* One Adam update with the gradient of the last mfe_net_loss_grad(_energy). */
+/* Replace the gradient that the next mfe_net_adam_step applies (host FP32,
+ * natural layout), for instance one averaged over devices or computed
+ * elsewhere.  The next mfe_net_loss_grad(_energy) overwrites it. */
+int mfe_net_set_grad(mfe_net *net, const float *grad_host);
+/* One Adam update (Kingma and Ba) with the gradient of the last
+ * mfe_net_loss_grad(_energy) or mfe_net_set_grad, in FP32 on the master
+ * weights, t counting the steps since mfe_net_set_params:
+ *   m = beta1 m + (1 - beta1) g,  v = beta2 v + (1 - beta2) g^2,
+ *   p -= lr (m / (1 - beta1^t)) / (sqrt(v / (1 - beta2^t)) + eps);
+ * then the bf16 copies of the weights are rebuilt.  lr >= 0,
+ * 0 <= beta1, beta2 < 1, eps > 0. */
 int mfe_net_adam_step(mfe_net *net, float lr, float beta1, float beta2, float eps);
 /* x0_dev (FP64 [G^3]) = g on boundary nodes, the network's prediction inside. */
 int mfe_net_predict_x0(mfe_net *net, const double *g_dev, double *x0_dev);
@@ -423,6 +433,20 @@ int mfe_net_predict_x0(mfe_net *net, const double *g_dev, double *x0_dev);
  * 8, 16, 32, 64 or 128.  Synchronises. */
 int mfe_conv3d_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *in_dev, int cout,
                     const float *w_host, const float *bias_host, int relu, void *out_dev, float *out32_dev);
+/* Input gradient of that convolution (the backward pass's building block):
+ * gx[q][c] = sum over output voxels v and taps d with src(v, d) = q of
+ * w[o][d][c] gy[v][o], gy bf16 [batch][Go^3][cout] on the output grid
+ * Go of `mode` applied to Gi, gx bf16 [batch][Gi^3][cin].  It runs as the
+ * network's backward pass does: the adjoint convolution (s1 with mirrored
+ * taps for s1, the transposed stride-2 form for s2, stride 2 for t2) with
+ * the (o, c)-transposed weights, rounded to bf16 from w_host (FP32
+ * [cout][27][cin]), on the matrix cores with FP32 accumulation.
+ * accumulate = 1: gx += that (the sum rounded once to bf16), as the network
+ * accumulates gradients from several layers; 0: gx = that.  gx32_dev (FP32,
+ * may be NULL) gets the unrounded sum.  Gi must be odd for mode 1 (the
+ * adjoint maps back onto Gi).  Synchronises. */
+int mfe_conv3d_dgrad_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *gy_dev, int cout,
+                          const float *w_host, int accumulate, void *gx_dev, float *gx32_dev);
 /* Weight gradient of that convolution: dw_host[o][27][c] = sum over samples
  * and output voxels of gy[v][o] x[src(v, d)][c].  Synchronises. */
 int mfe_conv3d_wgrad_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *x_dev, int cout,

@@ -80,18 +80,35 @@ def conv3d_weight_grad(gy, x, mode):
 
 def conv3d_input_grad(gy, w, mode, G_in):
     """dL/dx[n, q, c] = sum over (p, d) with src(p, d) = q of w[o, d, c] gy[n, p, o],
-    accumulated by scattering every tap's contribution back to its source."""
+    accumulated by scattering every tap's contribution back to its source
+    (taps in order; one scatter of all valid output points per tap)."""
     n, G_out = gy.shape[0], gy.shape[1]
     gx = np.zeros((n, G_in, G_in, G_in, w.shape[2]))
     P = np.arange(G_out)
     for d, (dz, dy, dx) in taps():
         contrib = gy @ w[:, d, :]  # [n, p, c]
         (iz, oz), (iy, oy), (ix, ox) = (_src_index(P, dd, G_in, mode) for dd in (dz, dy, dx))
-        for a in np.nonzero(oz)[0]:
-            for b in np.nonzero(oy)[0]:
-                cols = np.nonzero(ox)[0]
-                np.add.at(gx, (slice(None), iz[a], iy[b], ix[cols]), contrib[:, a, b, cols, :])
+        a, b, c = np.nonzero(oz)[0], np.nonzero(oy)[0], np.nonzero(ox)[0]
+        src = np.ix_(iz[a], iy[b], ix[c])
+        np.add.at(gx, (slice(None),) + src, contrib[:, a][:, :, b][:, :, :, c])
     return gx
+
+
+def adam_step(p, m, v, g, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, 2015, Algorithm 1), all in FP32:
+    m = beta1 m + (1 - beta1) g; v = beta2 v + (1 - beta2) g^2;
+    m_hat = m / (1 - beta1^t); v_hat = v / (1 - beta2^t);
+    p = p - lr m_hat / (sqrt(v_hat) + eps), t = 1, 2, ... the step number.
+    Returns the new (p, m, v)."""
+    f = np.float32
+    p, m, v, g = (np.asarray(a, dtype=np.float32) for a in (p, m, v, g))
+    b1, b2 = f(beta1), f(beta2)
+    m = b1 * m + (f(1) - b1) * g
+    v = b2 * v + (f(1) - b2) * (g * g)
+    m_hat = m / (f(1) - b1 ** t)
+    v_hat = v / (f(1) - b2 ** t)
+    p = p - f(lr) * m_hat / (np.sqrt(v_hat) + f(eps))
+    return p, m, v
 
 
 def bf16(a):
@@ -165,6 +182,42 @@ def net_loss(params, x, target, interior, round_bf16=False, apply_a=None):
     if apply_a is None:
         return float(np.sum(diff ** 2) / np.sum(interior)), acts
     return float(np.sum(diff * _a_times(diff, interior, apply_a)) / np.sum(interior)), acts
+
+
+def net_grads_bf16(params, x, target, interior, apply_a=None, rounded=True):
+    """The gradient of net_loss as a bfloat16 network computes it: weights,
+    input and stored activations in bfloat16 (net_forward with round_bf16),
+    the output gradient 2 e / count (or 2 A e / count) rounded to bfloat16,
+    every layer's output gradient stored in bfloat16 (a skip connection's
+    share added first, then the input gradient of the next layer, the sum
+    rounded once), sums taken exactly (FP64 standing in for FP32
+    accumulation).  The ReLU masks come from the stored activations.
+    rounded=False drops every rounding, which leaves the FP64 chain rule.
+    Returns ([(dw, db)], [(sum |gy| |x|, sum |gy|)]) per layer: the
+    gradient and the sums of absolute terms behind each entry."""
+    R = bf16 if rounded else (lambda a: a)
+    pb = [(R(w), b) for w, b in params]
+    xb = R(x)
+    acts = net_forward(pb, xb, round_bf16=rounded)
+    count = float(np.sum(interior))
+    diff = (acts[-1][..., 0] - target) * interior
+    g_out = np.zeros_like(acts[-1])
+    g_out[..., 0] = R(2.0 * (diff if apply_a is None else _a_times(diff, interior, apply_a)) / count)
+    grads, sc = [None] * len(LAYERS), [None] * len(LAYERS)
+    g_act = {len(LAYERS) - 1: g_out}
+    for li in range(len(LAYERS) - 1, -1, -1):
+        cin, cout, mode, relu, skip = LAYERS[li]
+        gy = g_act.pop(li)
+        if relu:
+            gy = gy * (acts[li] > 0)
+        h_in = acts[li - 1] if li > 0 else xb
+        grads[li] = (conv3d_weight_grad(gy, h_in, mode), gy.reshape(-1, cout).sum(axis=0))
+        sc[li] = (conv3d_weight_grad(np.abs(gy), np.abs(h_in), mode), np.abs(gy).reshape(-1, cout).sum(axis=0))
+        if skip is not None:
+            g_act[skip] = R(g_act.get(skip, 0.0) + gy)
+        if li > 0:
+            g_act[li - 1] = R(conv3d_input_grad(gy, pb[li][0], mode, h_in.shape[1]) + g_act.get(li - 1, 0.0))
+    return grads, sc
 
 
 def net_grads(params, x, target, interior, apply_a=None, scales=False):

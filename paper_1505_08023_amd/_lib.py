@@ -84,9 +84,11 @@ SIGNATURES = {
     "mfe_net_forward": (c_int, [c_vp, c_int, c_vp, c_vp]),
     "mfe_net_loss_grad": (c_int, [c_vp, c_int, c_vp, c_vp, ctypes.POINTER(c_dbl), c_vp]),
     "mfe_net_loss_grad_energy": (c_int, [c_vp, c_vp, c_int, c_int, c_vp, c_vp, ctypes.POINTER(c_dbl), c_vp]),
+    "mfe_net_set_grad": (c_int, [c_vp, c_vp]),
     "mfe_net_adam_step": (c_int, [c_vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
     "mfe_net_predict_x0": (c_int, [c_vp, c_vp, c_vp]),
     "mfe_conv3d_bf16": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_vp, c_int, c_vp, c_vp]),
+    "mfe_conv3d_dgrad_bf16": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_int, c_vp, c_vp]),
     "mfe_conv3d_wgrad_bf16": (c_int, [c_vp, c_int, c_int, c_int, c_int, c_vp, c_int, c_vp, c_vp]),
 }
 

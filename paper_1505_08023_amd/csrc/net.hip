@@ -1391,6 +1391,21 @@ int mfe_net_loss_grad_energy(mfe_net *N, const mfe_problem *A, int format, int b
     return finish_loss_grad(N, batch, lg, (double)batch * inner, loss_host, grad_host);
 }
 
+int mfe_net_set_grad(mfe_net *N, const float *grad_host) {
+    clear_error();
+    if (!N || !grad_host) {
+        set_error("net and grad must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(N->ctx->device) != hipSuccess) return MFE_EHIP;
+    std::vector<float> dev;
+    natural_to_dev(N, grad_host, dev);
+    hipStream_t s = N->ctx->stream;
+    MFE_HIP_TRY(hipMemcpyAsync(N->g32.ptr, dev.data(), dev.size() * sizeof(float), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    return MFE_OK;
+}
+
 int mfe_net_adam_step(mfe_net *N, float lr, float beta1, float beta2, float eps) {
     clear_error();
     if (!N || !(lr >= 0.0f) || !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f)) {
@@ -1456,6 +1471,55 @@ int mfe_conv3d_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const vo
     dev_free(ctx, &bb);
     dev_free(ctx, &ws);
     dev_free(ctx, &wc);
+    return rc;
+}
+
+int mfe_conv3d_dgrad_bf16(mfe_ctx *ctx, int mode, int batch, int Gi, int cin, const void *gy_dev, int cout,
+                          const float *w_host, int accumulate, void *gx_dev, float *gx32_dev) {
+    clear_error();
+    if (!ctx || !gy_dev || !w_host || !gx_dev || batch < 1 || Gi < 2 || mode < 0 || mode > 2 ||
+        !valid_channels(cin) || !valid_channels(cout) || (accumulate != 0 && accumulate != 1)) {
+        set_error("need ctx, gy, w, gx, batch >= 1, Gi >= 2, mode 0..2, channels in {8, 16, 32, 64, 128}, "
+                  "accumulate 0 or 1");
+        return MFE_EINVAL;
+    }
+    const int Go = out_size(Gi, mode);
+    if (out_size(Go, adjoint_mode(mode)) != Gi) {
+        set_error("the adjoint of a stride-2 convolution maps back onto the input grid only for odd Gi");
+        return MFE_EINVAL;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) return MFE_EHIP;
+    // the network's own weight preparation: FP32 master [rows][Kpad] -> bf16
+    // W and the (o, c)-transposed, tap-permuted Wa, and for s2 the class
+    // matrices of Wa (its adjoint is a transposed stride-2 convolution)
+    const int Kpad = pad64(27 * cin), rows = (cout + 15) / 16 * 16;
+    const int KpadA = pad64(27 * cout), rowsA = (cin + 15) / 16 * 16;
+    std::vector<float> w32((size_t)rows * Kpad, 0.0f);
+    for (int o = 0; o < cout; ++o)
+        for (int k = 0; k < 27 * cin; ++k) w32[(size_t)o * Kpad + k] = w_host[(size_t)o * 27 * cin + k];
+    Buffer wm, wb, wab, ws, wc;
+    int rc = dev_alloc(ctx, &wm, w32.size() * sizeof(float));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &wb, (size_t)rows * Kpad * sizeof(bf16));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &wab, (size_t)rowsA * KpadA * sizeof(bf16));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &ws, kConvWsFloats * sizeof(float));
+    if (rc == MFE_OK && mode == kS2) rc = dev_alloc(ctx, &wc, t2_class_elems(cout, rowsA) * sizeof(bf16));
+    hipStream_t s = ctx->stream;
+    if (rc == MFE_OK && hipMemcpyAsync(wm.ptr, w32.data(), w32.size() * sizeof(float), hipMemcpyHostToDevice, s) !=
+                            hipSuccess)
+        rc = MFE_EHIP;
+    if (rc == MFE_OK) {
+        const int64_t n = std::max((int64_t)rows * Kpad, (int64_t)rowsA * KpadA);
+        hipLaunchKernelGGL(k_layer_weights, dim3(grid_of(n)), dim3(256), 0, s, (const float *)wm.ptr, cin, cout, Kpad,
+                           KpadA, rowsA, mode == kS1 ? 1 : 0, (bf16 *)wb.ptr, (bf16 *)wab.ptr);
+        if (hipGetLastError() != hipSuccess) rc = MFE_EHIP;
+    }
+    if (rc == MFE_OK && mode == kS2) rc = build_t2_classes(s, (const bf16 *)wab.ptr, rowsA, KpadA, cout, (bf16 *)wc.ptr);
+    if (rc == MFE_OK)
+        rc = conv(s, adjoint_mode(mode), (const bf16 *)gy_dev, Go, cout, (const bf16 *)wab.ptr, (const bf16 *)wc.ptr,
+                  KpadA, cin, Gi, batch, nullptr, accumulate ? (const bf16 *)gx_dev : nullptr, 0, (bf16 *)gx_dev,
+                  gx32_dev, (float *)ws.ptr, kConvWsFloats);
+    if (hipStreamSynchronize(s) != hipSuccess && rc == MFE_OK) rc = MFE_EHIP;
+    for (Buffer *b : {&wm, &wb, &wab, &ws, &wc}) dev_free(ctx, b);
     return rc;
 }
 

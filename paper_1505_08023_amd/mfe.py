@@ -499,6 +499,32 @@ def conv3d(ctx, mode, x, w, bias=None, relu=False, out32=False):
     return (y, y32) if out32 else y
 
 
+def conv3d_dgrad(ctx, mode, gy, w, G_in, gx=None, accumulate=False, out32=False):
+    """Input gradient of conv3d(mode) on a G_in grid for output gradient gy
+    (bf16 [batch, Go, Go, Go, cout]); w: FP32 [cout, 27, cin].  Returns gx
+    (bf16 [batch, G_in, G_in, G_in, cin]; with accumulate, gx += the
+    gradient) and, when asked, the FP32 sum before rounding."""
+    import numpy as np
+    if gy.dtype != torch.bfloat16 or not gy.is_contiguous() or gy.dim() != 5:
+        raise ValueError("gy must be a contiguous bf16 tensor [batch, Go, Go, Go, cout]")
+    w = np.ascontiguousarray(w, dtype=np.float32)
+    b, cout, cin = gy.shape[0], gy.shape[4], w.shape[2]
+    if gx is None:
+        if accumulate:
+            raise ValueError("accumulate needs gx")
+        gx = torch.empty((b, G_in, G_in, G_in, cin), dtype=torch.bfloat16, device=gy.device)
+    elif tuple(gx.shape) != (b, G_in, G_in, G_in, cin) or gx.dtype != torch.bfloat16 or not gx.is_contiguous():
+        raise ValueError("gx must be a contiguous bf16 tensor [batch, G_in, G_in, G_in, cin]")
+    gx32 = torch.empty((b, G_in, G_in, G_in, cin), dtype=torch.float32, device=gy.device) if out32 else None
+    with _on(ctx):
+        check(ctx.lib.mfe_conv3d_dgrad_bf16(ctx.handle, CONV_MODES[mode], b, G_in, cin, ctypes.c_void_p(gy.data_ptr()),
+                                            cout, w.ctypes.data_as(ctypes.c_void_p), int(bool(accumulate)),
+                                            ctypes.c_void_p(gx.data_ptr()),
+                                            ctypes.c_void_p(gx32.data_ptr()) if gx32 is not None else None),
+              "mfe_conv3d_dgrad_bf16")
+    return (gx, gx32) if out32 else gx
+
+
 def conv3d_wgrad(ctx, mode, x, gy):
     """Weight gradient [cout, 27, cin] (numpy FP32) of conv3d(mode, x) for output gradient gy."""
     import numpy as np
@@ -572,16 +598,26 @@ class Net:
                       "mfe_net_loss_grad_energy")
         return (loss.value, grad) if want_grad else loss.value
 
+    def set_grad(self, flat):
+        """Replace the gradient the next adam_step applies (FP32, natural layout)."""
+        import numpy as np
+        g = np.ascontiguousarray(flat, dtype=np.float32)
+        if g.size != self.nparams:
+            raise ValueError(f"expected {self.nparams} gradient entries, got {g.size}")
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_net_set_grad(self.handle, g.ctypes.data_as(ctypes.c_void_p)), "mfe_net_set_grad")
+
     def adam_step(self, lr, beta1=0.9, beta2=0.999, eps=1e-8):
         with _on(self.ctx):
             check(self.ctx.lib.mfe_net_adam_step(self.handle, lr, beta1, beta2, eps), "mfe_net_adam_step")
 
     def predict_x0(self, g, x0=None):
+        n = self.G ** 3
         if x0 is None:
             x0 = torch.empty_like(g)
         with _on(self.ctx):
-            check(self.ctx.lib.mfe_net_predict_x0(self.handle, _ptr(g, torch.float64), _ptr(x0, torch.float64)),
-                  "mfe_net_predict_x0")
+            check(self.ctx.lib.mfe_net_predict_x0(self.handle, _ptr(g, torch.float64, n, "g"),
+                                                  _ptr(x0, torch.float64, n, "x0")), "mfe_net_predict_x0")
         return x0
 
     def close(self):

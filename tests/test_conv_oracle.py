@@ -167,3 +167,77 @@ def test_bf16_rounding():
     assert r[0] == 1.0 and r[1] == 1.0 and r[2] == 1.0 and r[6] == 1.015625
     assert abs(r[3] + 3.140625) < 1e-12
     assert np.all(np.abs(r - v) <= np.abs(v) * 2 ** -8 + 1e-38)
+
+
+def test_adam_constant_gradient_closed_form():
+    """Adam from m = v = 0 with a constant gradient g: m_t = (1 - beta1^t) g
+    and v_t = (1 - beta2^t) g^2, so the bias-corrected moments are g and g^2
+    and every step moves p by -lr g / (|g| + eps), exactly in real
+    arithmetic.  A large eps (0.5) separates eps outside the square root
+    from eps inside it; a missing bias correction, swapped betas or a wrong
+    sign change the step."""
+    rng = np.random.default_rng(3)
+    g = rng.standard_normal(1000).astype(np.float32)
+    p0 = rng.standard_normal(1000).astype(np.float32)
+    lr, eps = 0.01, 0.5
+    p, m, v = p0, np.zeros(1000, np.float32), np.zeros(1000, np.float32)
+    for t in range(1, 6):
+        p, m, v = conv.adam_step(p, m, v, g, t, lr, 0.9, 0.999, eps)
+        expect = p0.astype(np.float64) - t * lr * g / (np.abs(g) + eps)
+        assert np.all(np.abs(p - expect) <= 1e-6 * (np.abs(expect) + t * lr)), t
+    assert p.dtype == np.float32
+
+
+def test_adam_without_moment_memory_is_a_scaled_sign_step():
+    """With beta1 = beta2 = 0 nothing is remembered: each step moves p by
+    -lr g_t / (|g_t| + eps) for that step's own gradient."""
+    rng = np.random.default_rng(4)
+    p = rng.standard_normal(500).astype(np.float32)
+    m, v = np.zeros(500, np.float32), np.zeros(500, np.float32)
+    lr, eps = 0.1, 0.25
+    for t in range(1, 4):
+        g = rng.standard_normal(500).astype(np.float32)
+        expect = p.astype(np.float64) - lr * g / (np.abs(g) + eps)
+        p, m, v = conv.adam_step(p, m, v, g, t, lr, 0.0, 0.0, eps)
+        assert np.all(np.abs(p - expect) <= 1e-6 * (np.abs(expect) + lr))
+
+
+@pytest.mark.parametrize("energy", [False, True])
+def test_bf16_network_gradient_structure_and_closeness(energy):
+    """The bfloat16-emulated network gradient (net_grads_bf16): with its
+    roundings dropped it is the FP64 chain rule (net_grads, pinned by finite
+    differences above) to rounding, so its skip shares, ReLU masks and
+    accumulation order are those of the definition; with them it stays
+    within 15 % relative L2 and cosine 0.99 of the FP64 gradient on the same
+    bf16 weights (bfloat16 activations move some ReLU masks), and every
+    entry is bounded by its sum of absolute terms."""
+    import oracle
+    rng = np.random.default_rng(6)
+    G = 9
+    params = [(rng.standard_normal((co, 27, ci)) * np.sqrt(2.0 / (27 * ci)), rng.standard_normal(co) * 0.01)
+              for ci, co, *_ in conv.LAYERS]
+    pb = [(conv.bf16(w), b) for w, b in params]
+    mask = np.zeros((G, G, G), bool)
+    mask[0], mask[-1], mask[:, 0], mask[:, -1], mask[:, :, 0], mask[:, :, -1] = (True,) * 6
+    g = rng.uniform(0, 1, (2, G, G, G))
+    target = rng.uniform(0, 1, (2, G, G, G))
+    x = np.stack([conv.net_input(g[i], mask) for i in range(2)])
+    interior = np.broadcast_to(~mask, (2, G, G, G)).astype(float)
+    apply_a = None
+    if energy:
+        A = oracle.assemble(G - 1, G - 1, G - 1)
+        apply_a = lambda v: oracle.csr_spmv(A, v)
+    exact = conv.net_grads(params, x, target, interior, apply_a=apply_a)
+    plain, _ = conv.net_grads_bf16(params, x, target, interior, apply_a=apply_a, rounded=False)
+    for (gw, gb), (rw, rb) in zip(plain, exact):
+        assert np.allclose(gw, rw, rtol=1e-12, atol=1e-14 * np.abs(rw).max())
+        assert np.allclose(gb, rb, rtol=1e-12, atol=1e-14 * np.abs(rb).max())
+    ref = conv.net_grads(pb, x, target, interior, apply_a=apply_a)
+    got, scales = conv.net_grads_bf16(params, x, target, interior, apply_a=apply_a)
+    for li, ((gw, gb), (rw, rb)) in enumerate(zip(got, ref)):
+        a, r = np.concatenate([gw.ravel(), gb]), np.concatenate([rw.ravel(), rb])
+        err = np.linalg.norm(a - r) / np.linalg.norm(r)
+        cos = float(a @ r / (np.linalg.norm(a) * np.linalg.norm(r)))
+        assert err <= 0.15 and cos >= 0.99, (li, err, cos)
+    for (gw, gb), (sw, sb) in zip(got, scales):
+        assert np.all(np.abs(gw) <= sw * (1 + 1e-12)) and np.all(np.abs(gb) <= sb * (1 + 1e-12))
