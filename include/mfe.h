@@ -121,6 +121,14 @@ int mfe_problem_from_csr(mfe_ctx *ctx, int64_t m, const int32_t *ptr_dev, const 
                          const double *val_dev, const double *b_dev, int formats, int precisions,
                          mfe_problem **out);
 
+/* mfe_problem_from_csr from host arrays (the CRS arrays of Sec. 3.1 as a
+ * caller holds them in host memory): ptr[m+1] (ptr[0] = 0), col[ptr[m]],
+ * val[ptr[m]], b[m] (may be NULL: b = 0) are copied to the device before
+ * the call returns; the caller may reuse them at once.  Same checks, results
+ * and errors as mfe_problem_from_csr. */
+int mfe_problem_from_csr_host(mfe_ctx *ctx, int64_t m, const int32_t *ptr, const int32_t *col, const double *val,
+                              const double *b, int formats, int precisions, mfe_problem **out);
+
 /* Re-impose new Dirichlet data on a mesh problem without re-assembling:
  * recomputes b (same rules as mfe_problem_create).  MFE_EINVAL for a problem
  * made by mfe_problem_from_csr. */
@@ -152,6 +160,15 @@ int mfe_problem_bcrs13_layout(const mfe_problem *p, int64_t *slices, int64_t *sl
  * (ptr_dev[m+1], col_dev[nnz], val_dev[nnz], b_dev[m]; any may be NULL). */
 int mfe_problem_export_csr(const mfe_problem *p, int32_t *ptr_dev, int32_t *col_dev,
                            double *val_dev, double *b_dev);
+
+/* mfe_problem_export_csr into host arrays (ptr[m+1], col[nnz], val[nnz],
+ * b[m]; any may be NULL).  Synchronises the stream. */
+int mfe_problem_export_csr_host(const mfe_problem *p, int32_t *ptr, int32_t *col, double *val, double *b);
+
+/* The right-hand side b of A x = b (Sec. 1: the assembled load vector after
+ * the Dirichlet values are imposed; for a CRS problem the b it was given)
+ * into b_dev[m].  Does not synchronise. */
+int mfe_rhs(const mfe_problem *p, double *b_dev);
 
 /* Copy the 1x3 BCRS as per-row block lists: bptr_dev[m+1] (first block of
  * each row, bptr[m] = nblocks), bcol_dev[nblocks] (first column of each
@@ -333,6 +350,15 @@ typedef struct mfe_batch mfe_batch;
  * Destroy a batch before its context. */
 int mfe_batch_create(mfe_ctx *ctx, int nsys, const int32_t *sizes, const double *face_vals, int formats,
                      int precisions, mfe_batch **out);
+/* A batch of existing problems (mesh or CRS, all of context ctx, copied: the
+ * problems stay usable and may be destroyed afterwards): the block-diagonal
+ * matrix of their FP64 CRS and b, system j at rows row_offsets[j].. in the
+ * order given, with `formats` and `precisions` built for it as at
+ * mfe_problem_create.  mfe_batch_set_bc applies only when every system is a
+ * mesh problem (else MFE_EINVAL).  MFE_EUNSUPPORTED when the total nnz >=
+ * 2^31. */
+int mfe_batch_from_problems(mfe_ctx *ctx, int nsys, mfe_problem *const *sys, int formats, int precisions,
+                            mfe_batch **out);
 int mfe_batch_destroy(mfe_batch *b);
 /* Total rows, total stored entries, row_offsets (host int64[nsys+1]); any may be NULL. */
 int mfe_batch_info(const mfe_batch *b, int64_t *m_total, int64_t *nnz_total, int64_t *row_offsets);
@@ -367,6 +393,19 @@ int mfe_batch_cg_mixed(mfe_batch *b, int format, double *x_dev, double tol, doub
  * (MFE_MIXED_WARM included): MFE_EINVAL. */
 int mfe_batch_cg_mixed_ex(mfe_batch *b, int format, double *x_dev, double tol, double inner_tol, int max_outer,
                           int max_inner, int flags, mfe_cg_stats *stats);
+
+/* One batched solve of existing problems in a single call: builds the batch
+ * of mfe_batch_from_problems in `format`, copies each x_dev[j] (length m_j:
+ * x0 in, the solution out) in, runs mfe_batch_cg (mixed = 0) or
+ * mfe_batch_cg_mixed with inner tolerance 1e-4, 50 refinement steps and
+ * max_iter inner iterations (mixed = 1; FP32 values are built), copies the
+ * results (the last iterates after a breakdown) back and releases the batch.
+ * Every system follows the single-system recurrence with its own stopping
+ * test.  stats: host array of nsys (may be NULL).  Returns as mfe_batch_cg.
+ * The batch is rebuilt on every call; repeated solves of the same systems
+ * should keep a batch of mfe_batch_from_problems instead. */
+int mfe_cg_batched(mfe_ctx *ctx, int nsys, mfe_problem *const *sys, int format, double *const *x_dev, double tol,
+                   int max_iter, int mixed, mfe_cg_stats *stats);
 
 /* ---------------------------------------------------------------------
  * Learned initial guess (extension of the CG module): a 3-D convolutional

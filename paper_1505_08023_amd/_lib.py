@@ -43,6 +43,9 @@ SIGNATURES = {
     "mfe_ctx_destroy": (c_int, [c_vp]),
     "mfe_problem_create": (c_int, [c_vp, c_int, c_int, c_int, c_vp, c_vp, c_int, c_int, PP]),
     "mfe_problem_from_csr": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_int, c_int, PP]),
+    "mfe_problem_from_csr_host": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp, c_vp, c_int, c_int, PP]),
+    "mfe_problem_export_csr_host": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
+    "mfe_rhs": (c_int, [c_vp, c_vp]),
     "mfe_problem_set_bc": (c_int, [c_vp, c_vp, c_vp]),
     "mfe_problem_info": (c_int, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     "mfe_problem_csr_layout": (c_int, [c_vp] + [ctypes.POINTER(c_i64)] * 3),
@@ -69,6 +72,8 @@ SIGNATURES = {
     "mfe_cg_mixed": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_batch_create": (c_int, [c_vp, c_int, c_vp, c_vp, c_int, c_int, PP]),
     "mfe_batch_destroy": (c_int, [c_vp]),
+    "mfe_batch_from_problems": (c_int, [c_vp, c_int, c_vp, c_int, c_int, PP]),
+    "mfe_cg_batched": (c_int, [c_vp, c_int, c_vp, c_int, c_vp, c_dbl, c_int, c_int, c_vp]),
     "mfe_batch_info": (c_int, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), c_vp]),
     "mfe_batch_export_csr": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),
     "mfe_batch_set_bc": (c_int, [c_vp, c_vp, c_vp]),

@@ -129,7 +129,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 10; }
+int mfe_version(void) { return 11; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -326,6 +326,38 @@ int mfe_problem_from_csr(mfe_ctx *ctx, int64_t m, const int32_t *ptr_dev, const 
     return MFE_OK;
 }
 
+int mfe_problem_from_csr_host(mfe_ctx *ctx, int64_t m, const int32_t *ptr, const int32_t *col, const double *val,
+                              const double *b, int formats, int precisions, mfe_problem **out) {
+    clear_error();
+    if (!ctx || !out || !ptr || !col || !val) {
+        set_error("ctx, out, ptr, col and val must be non-NULL");
+        return MFE_EINVAL;
+    }
+    if (m < 1 || !fits_int32(m) || ptr[0] != 0 || ptr[m] < 0) {
+        set_error("m must be in [1, 2^31-1), ptr[0] = 0 and ptr[m] >= 0");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(set_device(ctx));
+    const int64_t nnz = ptr[m];
+    hipStream_t s = ctx->stream;
+    TempBuffer dp(ctx), dc(ctx), dv(ctx), db(ctx);
+    MFE_TRY(dp.alloc((size_t)(m + 1) * sizeof(int32_t)));
+    MFE_TRY(dc.alloc((size_t)nnz * sizeof(int32_t)));
+    MFE_TRY(dv.alloc((size_t)nnz * sizeof(double)));
+    if (b) MFE_TRY(db.alloc((size_t)m * sizeof(double)));
+    MFE_HIP_TRY(hipMemcpyAsync(dp.ptr(), ptr, (m + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (nnz > 0) {
+        MFE_HIP_TRY(hipMemcpyAsync(dc.ptr(), col, nnz * sizeof(int32_t), hipMemcpyHostToDevice, s));
+        MFE_HIP_TRY(hipMemcpyAsync(dv.ptr(), val, nnz * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    if (b) MFE_HIP_TRY(hipMemcpyAsync(db.ptr(), b, m * sizeof(double), hipMemcpyHostToDevice, s));
+    // the host arrays must stay valid until the copies have run
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    return mfe_problem_from_csr(ctx, m, (const int32_t *)dp.ptr(), (const int32_t *)dc.ptr(),
+                                (const double *)dv.ptr(), b ? (const double *)db.ptr() : nullptr, formats, precisions,
+                                out);
+}
+
 int mfe_problem_set_bc(mfe_problem *p, const double *face_vals, const double *node_g_dev) {
     clear_error();
     if (!p) {
@@ -395,6 +427,33 @@ int mfe_problem_export_csr(const mfe_problem *p, int32_t *ptr_dev, int32_t *col_
     if (val_dev)
         MFE_HIP_TRY(hipMemcpyAsync(val_dev, p->val64.ptr, p->nnz * sizeof(double), hipMemcpyDeviceToDevice, s));
     if (b_dev) MFE_HIP_TRY(hipMemcpyAsync(b_dev, p->b.ptr, p->m * sizeof(double), hipMemcpyDeviceToDevice, s));
+    return MFE_OK;
+}
+
+int mfe_problem_export_csr_host(const mfe_problem *p, int32_t *ptr, int32_t *col, double *val, double *b) {
+    clear_error();
+    if (!p) {
+        set_error("problem is NULL");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(set_device(p->ctx));
+    hipStream_t s = p->ctx->stream;
+    if (ptr) MFE_HIP_TRY(hipMemcpyAsync(ptr, p->ptr.ptr, (p->m + 1) * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (col) MFE_HIP_TRY(hipMemcpyAsync(col, p->col.ptr, p->nnz * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    if (val) MFE_HIP_TRY(hipMemcpyAsync(val, p->val64.ptr, p->nnz * sizeof(double), hipMemcpyDeviceToHost, s));
+    if (b) MFE_HIP_TRY(hipMemcpyAsync(b, p->b.ptr, p->m * sizeof(double), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    return MFE_OK;
+}
+
+int mfe_rhs(const mfe_problem *p, double *b_dev) {
+    clear_error();
+    if (!p || !b_dev) {
+        set_error("problem and b must be non-NULL");
+        return MFE_EINVAL;
+    }
+    MFE_TRY(set_device(p->ctx));
+    MFE_HIP_TRY(hipMemcpyAsync(b_dev, p->b.ptr, p->m * sizeof(double), hipMemcpyDeviceToDevice, p->ctx->stream));
     return MFE_OK;
 }
 

@@ -621,6 +621,84 @@ int tuning_for(mfe_batch *B, int format, Tuning *t) {
 }  // namespace
 }  // namespace mfe
 
+namespace {
+
+// A batch object with the block-diagonal CRS storage allocated (rows row0,
+// entries nnz0 per system), not yet filled.
+int alloc_batch(mfe_ctx *ctx, int nsys, const std::vector<int64_t> &row0, const std::vector<int64_t> &nnz0,
+                int formats, int precisions, mfe_batch **out) {
+    if (nnz0[nsys] >= ((int64_t)1 << 31) - 1 || row0[nsys] >= ((int64_t)1 << 31) - 1) {
+        set_error("batch too large for 32-bit row pointers");
+        return MFE_EUNSUPPORTED;
+    }
+    if (hipSetDevice(ctx->device) != hipSuccess) {
+        set_error("hipSetDevice failed");
+        return MFE_EHIP;
+    }
+    mfe_batch *B = new (std::nothrow) mfe_batch();
+    mfe_problem *P = new (std::nothrow) mfe_problem();
+    if (!B || !P) {
+        delete B;
+        delete P;
+        set_error("host allocation failed");
+        return MFE_ENOMEM;
+    }
+    B->ctx = ctx;
+    B->nsys = nsys;
+    B->N.assign(3 * (size_t)nsys, 0);
+    B->row0 = row0;
+    B->P = P;
+    P->ctx = ctx;
+    P->m = row0[nsys];
+    P->nnz = nnz0[nsys];
+    P->formats = formats | MFE_CSR;
+    P->precisions = precisions | MFE_F64;
+    int rc = dev_alloc(ctx, &P->ptr, (size_t)(P->m + 1) * sizeof(int32_t));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->col, (size_t)P->nnz * sizeof(int32_t));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->val64, (size_t)P->nnz * sizeof(double));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->b, (size_t)P->m * sizeof(double));
+    if (rc == MFE_OK) rc = dev_alloc(ctx, &B->sys_wg, (nsys + 1) * sizeof(int32_t));
+    if (rc != MFE_OK) {
+        mfe_batch_destroy(B);
+        return rc;
+    }
+    *out = B;
+    return MFE_OK;
+}
+
+// Derived formats of the filled CRS and the pinned state slots; registers the batch.
+int finish_batch(mfe_batch *B, mfe_batch **out) {
+    int rc = finish_problem(B->P);
+    if (rc == MFE_OK && hipHostMalloc(&B->pinned, B->nsys * sizeof(CgState), hipHostMallocDefault) != hipSuccess) {
+        set_error("hipHostMalloc failed");
+        rc = MFE_EHIP;
+    }
+    if (rc != MFE_OK) {
+        mfe_batch_destroy(B);
+        return rc;
+    }
+    B->ctx->batches.push_back(B);
+    *out = B;
+    return MFE_OK;
+}
+
+// dst[i] = src[i] + add (column indices and row pointers moved into the block-diagonal matrix)
+__global__ __launch_bounds__(256) void k_shift_copy(int64_t n, const int32_t *__restrict__ src, int32_t add,
+                                                    int32_t *__restrict__ dst) {
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+        dst[i] = src[i] + add;
+}
+
+int shift_copy(hipStream_t s, int64_t n, const int32_t *src, int64_t add, int32_t *dst) {
+    if (n <= 0) return MFE_OK;
+    const int grid = (int)std::min<int64_t>(4096, (n + 255) / 256);
+    hipLaunchKernelGGL(k_shift_copy, dim3(grid), dim3(256), 0, s, n, src, (int32_t)add, dst);
+    MFE_HIP_TRY(hipGetLastError());
+    return MFE_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 int mfe_batch_create(mfe_ctx *ctx, int nsys, const int32_t *sizes, const double *face_vals, int formats,
@@ -645,54 +723,74 @@ int mfe_batch_create(mfe_ctx *ctx, int nsys, const int32_t *sizes, const double 
         row0[j + 1] = row0[j] + (int64_t)(Nx + 1) * (Ny + 1) * (Nz + 1);
         nnz0[j + 1] = nnz0[j] + (3 * (int64_t)Nx + 1) * (3 * (int64_t)Ny + 1) * (3 * (int64_t)Nz + 1);
     }
-    if (nnz0[nsys] >= ((int64_t)1 << 31) - 1 || row0[nsys] >= ((int64_t)1 << 31) - 1) {
-        set_error("batch too large for 32-bit row pointers");
-        return MFE_EUNSUPPORTED;
-    }
-    if (hipSetDevice(ctx->device) != hipSuccess) {
-        set_error("hipSetDevice failed");
-        return MFE_EHIP;
-    }
-    mfe_batch *B = new (std::nothrow) mfe_batch();
-    mfe_problem *P = new (std::nothrow) mfe_problem();
-    if (!B || !P) {
-        delete B;
-        delete P;
-        set_error("host allocation failed");
-        return MFE_ENOMEM;
-    }
-    B->ctx = ctx;
-    B->nsys = nsys;
+    mfe_batch *B = nullptr;
+    MFE_TRY(alloc_batch(ctx, nsys, row0, nnz0, formats, precisions, &B));
     B->N.assign(sizes, sizes + 3 * nsys);
-    B->row0 = row0;
-    B->P = P;
-    P->ctx = ctx;
-    P->m = row0[nsys];
-    P->nnz = nnz0[nsys];
-    P->formats = formats | MFE_CSR;
-    P->precisions = precisions | MFE_F64;
-    int rc = dev_alloc(ctx, &P->ptr, (size_t)(P->m + 1) * sizeof(int32_t));
-    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->col, (size_t)P->nnz * sizeof(int32_t));
-    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->val64, (size_t)P->nnz * sizeof(double));
-    if (rc == MFE_OK) rc = dev_alloc(ctx, &P->b, (size_t)P->m * sizeof(double));
-    if (rc == MFE_OK) rc = dev_alloc(ctx, &B->sys_wg, (nsys + 1) * sizeof(int32_t));
+    mfe_problem *P = B->P;
+    int rc = MFE_OK;
     for (int j = 0; j < nsys && rc == MFE_OK; ++j)
         rc = launch_assemble_into(ctx->stream, sizes[3 * j], sizes[3 * j + 1], sizes[3 * j + 2],
                                   face_vals ? face_vals + 6 * j : nullptr, nullptr, row0[j], nnz0[j],
                                   (int32_t *)P->ptr.ptr, (int32_t *)P->col.ptr, (double *)P->val64.ptr,
                                   (double *)P->b.ptr, false);
-    if (rc == MFE_OK) rc = finish_problem(P);
-    if (rc == MFE_OK && hipHostMalloc(&B->pinned, nsys * sizeof(CgState), hipHostMallocDefault) != hipSuccess) {
-        set_error("hipHostMalloc failed");
-        rc = MFE_EHIP;
+    if (rc != MFE_OK) {
+        mfe_batch_destroy(B);
+        return rc;
+    }
+    return finish_batch(B, out);
+}
+
+int mfe_batch_from_problems(mfe_ctx *ctx, int nsys, mfe_problem *const *sys, int formats, int precisions,
+                            mfe_batch **out) {
+    clear_error();
+    if (!ctx || !out || !sys || nsys < 1) {
+        set_error("ctx, sys and out must be non-NULL and nsys >= 1");
+        return MFE_EINVAL;
+    }
+    *out = nullptr;
+    if ((formats & ~(MFE_CSR | MFE_BCRS13)) || (precisions & ~(MFE_F64 | MFE_F32))) {
+        set_error("unknown format or precision flag");
+        return MFE_EINVAL;
+    }
+    std::vector<int64_t> row0(nsys + 1, 0), nnz0(nsys + 1, 0);
+    for (int j = 0; j < nsys; ++j) {
+        if (!sys[j] || sys[j]->ctx != ctx) {
+            set_error("every system must be a problem of this context");
+            return MFE_EINVAL;
+        }
+        row0[j + 1] = row0[j] + sys[j]->m;
+        nnz0[j + 1] = nnz0[j] + sys[j]->nnz;
+    }
+    mfe_batch *B = nullptr;
+    MFE_TRY(alloc_batch(ctx, nsys, row0, nnz0, formats, precisions, &B));
+    mfe_problem *P = B->P;
+    hipStream_t s = ctx->stream;
+    int rc = MFE_OK;
+    for (int j = 0; j < nsys && rc == MFE_OK; ++j) {
+        const mfe_problem *Q = sys[j];
+        if (Q->is_mesh) {
+            B->N[3 * j] = Q->Nx;
+            B->N[3 * j + 1] = Q->Ny;
+            B->N[3 * j + 2] = Q->Nz;
+        }
+        // rows 0..m-1 of system j; ptr[m] of the last system closes the matrix
+        rc = shift_copy(s, Q->m + (j == nsys - 1 ? 1 : 0), (const int32_t *)Q->ptr.ptr, nnz0[j],
+                        (int32_t *)P->ptr.ptr + row0[j]);
+        if (rc == MFE_OK) rc = shift_copy(s, Q->nnz, (const int32_t *)Q->col.ptr, row0[j], (int32_t *)P->col.ptr + nnz0[j]);
+        if (rc == MFE_OK &&
+            (hipMemcpyAsync((double *)P->val64.ptr + nnz0[j], Q->val64.ptr, Q->nnz * sizeof(double),
+                            hipMemcpyDeviceToDevice, s) != hipSuccess ||
+             hipMemcpyAsync((double *)P->b.ptr + row0[j], Q->b.ptr, Q->m * sizeof(double), hipMemcpyDeviceToDevice,
+                            s) != hipSuccess)) {
+            set_error("copy of a system's CRS arrays failed");
+            rc = MFE_EHIP;
+        }
     }
     if (rc != MFE_OK) {
         mfe_batch_destroy(B);
         return rc;
     }
-    ctx->batches.push_back(B);
-    *out = B;
-    return MFE_OK;
+    return finish_batch(B, out);
 }
 
 int mfe_batch_destroy(mfe_batch *B) {
@@ -752,6 +850,11 @@ int mfe_batch_set_bc(mfe_batch *B, const double *face_vals, const double *node_g
         set_error("batch is NULL");
         return MFE_EINVAL;
     }
+    for (int j = 0; j < B->nsys; ++j)
+        if (B->N[3 * j] < 1) {
+            set_error("boundary data can only be re-imposed when every system is a mesh");
+            return MFE_EINVAL;
+        }
     if (hipSetDevice(B->ctx->device) != hipSuccess) return MFE_EHIP;
     mfe_problem *P = B->P;
     for (int j = 0; j < B->nsys; ++j)
@@ -958,6 +1061,54 @@ int mfe_batch_cg_mixed_ex(mfe_batch *B, int format, double *x_dev, double tol, d
             stats[j].reserved_ = 0;
         }
     }
+    return rc;
+}
+
+int mfe_cg_batched(mfe_ctx *ctx, int nsys, mfe_problem *const *sys, int format, double *const *x_dev, double tol,
+                   int max_iter, int mixed, mfe_cg_stats *stats) {
+    clear_error();
+    if (!ctx || !sys || !x_dev || nsys < 1 || !(tol >= 0.0) || max_iter < 0 || (mixed != 0 && mixed != 1) ||
+        (format != MFE_CSR && format != MFE_BCRS13)) {
+        set_error("need ctx, sys, x, nsys >= 1, tol >= 0, max_iter >= 0, mixed 0 or 1, format CSR or BCRS13");
+        return MFE_EINVAL;
+    }
+    for (int j = 0; j < nsys; ++j)
+        if (!x_dev[j]) {
+            set_error("every system needs its x");
+            return MFE_EINVAL;
+        }
+    if (mixed && max_iter < 1) {
+        set_error("the mixed-precision solve needs max_iter >= 1");
+        return MFE_EINVAL;
+    }
+    mfe_batch *B = nullptr;
+    MFE_TRY(mfe_batch_from_problems(ctx, nsys, sys, format, mixed ? (MFE_F64 | MFE_F32) : MFE_F64, &B));
+    hipStream_t s = ctx->stream;
+    int rc = MFE_OK;
+    {
+        TempBuffer x(ctx);
+        rc = x.alloc((size_t)B->P->m * sizeof(double));
+        double *xb = (double *)x.ptr();
+        for (int j = 0; j < nsys && rc == MFE_OK; ++j)
+            if (hipMemcpyAsync(xb + B->row0[j], x_dev[j], sys[j]->m * sizeof(double), hipMemcpyDeviceToDevice, s) !=
+                hipSuccess) {
+                set_error("gather of the initial guesses failed");
+                rc = MFE_EHIP;
+            }
+        if (rc == MFE_OK)
+            rc = mixed ? mfe_batch_cg_mixed(B, format, xb, tol, 1e-4, 50, max_iter, stats)
+                       : mfe_batch_cg(B, format, xb, tol, max_iter, stats);
+        // results (the last iterates after a breakdown) back to each system's x
+        if (rc == MFE_OK || rc == MFE_NOT_CONVERGED || rc == MFE_EBREAKDOWN)
+            for (int j = 0; j < nsys; ++j)
+                if (hipMemcpyAsync(x_dev[j], xb + B->row0[j], sys[j]->m * sizeof(double), hipMemcpyDeviceToDevice,
+                                   s) != hipSuccess) {
+                    set_error("scatter of the solutions failed");
+                    rc = MFE_EHIP;
+                    break;
+                }
+    }
+    mfe_batch_destroy(B);
     return rc;
 }
 

@@ -206,6 +206,55 @@ class Problem:
                   "mfe_problem_from_csr")
         return cls(ctx, h)
 
+    @classmethod
+    def from_csr_host(cls, ctx, ptr, col, val, b=None, formats=("csr",), precisions=("f64",)):
+        """A generic CRS problem from host (numpy) arrays (mfe_problem_from_csr_host)."""
+        import numpy as np
+        fl = 0
+        for f in formats:
+            fl |= _fmt(f)
+        pr = 0
+        for p in precisions:
+            pr |= {"f64": MFE_F64, "f32": MFE_F32}[p]
+        ptr = np.ascontiguousarray(ptr, dtype=np.int32)
+        m = ptr.size - 1
+        col = np.ascontiguousarray(col, dtype=np.int32)
+        val = np.ascontiguousarray(val, dtype=np.float64)
+        if col.size < ptr[-1] or val.size < ptr[-1]:
+            raise ValueError("col and val must hold ptr[m] entries")
+        bb = None if b is None else np.ascontiguousarray(b, dtype=np.float64)
+        if bb is not None and bb.size != m:
+            raise ValueError(f"b must have {m} entries")
+        h = ctypes.c_void_p()
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        with _on(ctx):
+            check(ctx.lib.mfe_problem_from_csr_host(ctx.handle, m, vp(ptr), vp(col), vp(val),
+                                                    vp(bb) if bb is not None else None, fl, pr, ctypes.byref(h)),
+                  "mfe_problem_from_csr_host")
+        return cls(ctx, h)
+
+    def export_csr_host(self):
+        """(ptr, col, val, b) as numpy arrays (mfe_problem_export_csr_host)."""
+        import numpy as np
+        ptr = np.empty(self.m + 1, np.int32)
+        col = np.empty(self.nnz, np.int32)
+        val = np.empty(self.nnz, np.float64)
+        b = np.empty(self.m, np.float64)
+        vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_problem_export_csr_host(self.handle, vp(ptr), vp(col), vp(val), vp(b)),
+                  "mfe_problem_export_csr_host")
+        return ptr, col, val, b
+
+    def rhs(self, b=None):
+        """The right-hand side b (mfe_rhs) into a device tensor."""
+        if b is None:
+            with _on(self.ctx):
+                b = torch.empty(self.m, dtype=torch.float64, device=self.ctx.device)
+        with _on(self.ctx):
+            check(self.ctx.lib.mfe_rhs(self.handle, _ptr(b, torch.float64, self.m, "b")), "mfe_rhs")
+        return b
+
     # -- data out -------------------------------------------------------------------------
     def export_csr(self):
         d = self.ctx.device
@@ -384,6 +433,31 @@ class Batch:
             check(ctx.lib.mfe_batch_create(ctx.handle, self.nsys, sizes.ctypes.data_as(ctypes.c_void_p),
                                            fv.ctypes.data_as(ctypes.c_void_p) if fv is not None else None,
                                            fl, pr, ctypes.byref(h)), "mfe_batch_create")
+        self._attach(h)
+
+    @classmethod
+    def from_problems(cls, ctx, problems, formats=("csr", "bcrs13"), precisions=("f64",)):
+        """A batch of existing problems, copied (mfe_batch_from_problems)."""
+        self = cls.__new__(cls)
+        self.ctx = ctx
+        self.nsys = len(problems)
+        fl = 0
+        for f in formats:
+            fl |= _fmt(f)
+        pr = 0
+        for p in precisions:
+            pr |= {"f64": MFE_F64, "f32": MFE_F32}[p]
+        arr = (ctypes.c_void_p * self.nsys)(*[p.handle.value for p in problems])
+        h = ctypes.c_void_p()
+        with _on(ctx):
+            check(ctx.lib.mfe_batch_from_problems(ctx.handle, self.nsys, ctypes.cast(arr, ctypes.c_void_p), fl, pr,
+                                                  ctypes.byref(h)), "mfe_batch_from_problems")
+        self._attach(h)
+        return self
+
+    def _attach(self, h):
+        import numpy as np
+        ctx = self.ctx
         self.handle = h
         m, nnz = ctypes.c_int64(), ctypes.c_int64()
         offs = np.zeros(self.nsys + 1, dtype=np.int64)
@@ -472,6 +546,25 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+def cg_batched(ctx, problems, xs=None, tol=1e-8, max_iter=5000, fmt="bcrs13", mixed=False):
+    """One batched solve of existing problems (mfe_cg_batched): xs is a list
+    of FP64 device vectors (x0 in, solution out; zeros if None).  Returns
+    (xs, list of stats dicts)."""
+    n = len(problems)
+    if xs is None:
+        with _on(ctx):
+            xs = [torch.zeros(p.m, dtype=torch.float64, device=ctx.device) for p in problems]
+    ptrs = (ctypes.c_void_p * n)(*[_ptr(x, torch.float64, p.m, "x").value for x, p in zip(xs, problems)])
+    hs = (ctypes.c_void_p * n)(*[p.handle.value for p in problems])
+    st = (mfe_cg_stats * n)()
+    with _on(ctx):
+        rc = ctx.lib.mfe_cg_batched(ctx.handle, n, ctypes.cast(hs, ctypes.c_void_p), _fmt(fmt),
+                                    ctypes.cast(ptrs, ctypes.c_void_p), float(tol), int(max_iter), int(bool(mixed)),
+                                    ctypes.cast(st, ctypes.c_void_p))
+    check(rc, "mfe_cg_batched", (MFE_OK, MFE_NOT_CONVERGED))
+    return xs, [s.as_dict() for s in st]
 
 
 CONV_MODES = {"s1": 0, "s2": 1, "t2": 2}

@@ -1,0 +1,186 @@
+"""The boundary calls of the problem statement (Sec. 1; the CRS arrays of
+Sec. 3.1) that take or give host arrays, the right-hand side, and batched
+solves of existing problems, through the C ABI against the oracle.
+
+  mfe_rhs                      b of the assembled system, within 64 eps max(|b|, h) of the oracle's
+  from_csr_host / export_csr_host   host arrays in and out bit-exactly (ragged rows, empty rows);
+                               the product of the imported matrix meets the SpMV bar of test_gpu_core
+  mfe_batch_from_problems      mesh problems batched equal, bitwise, the batch assembled from the
+                               same sizes; mixed mesh and generic SPD CRS systems each solve as an
+                               independent oracle solve (counts within 2, the lambda_min solution bound)
+  mfe_cg_batched               the same in one call, FP64 and FP32-inner / FP64-refinement
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_1505_08023_amd import inputs
+from test_gpu_core import check_solution_gap, check_spmv, np_
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(np.float64).eps
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_1505_08023_amd.mfe import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def spd_csr(m, seed, density=6):
+    """A sparse symmetric diagonally dominant matrix with positive diagonal
+    (SPD), ascending distinct columns per row, and b uniform in [-1, 1)."""
+    rng = np.random.default_rng(seed)
+    pairs = {(int(i), int(j)) for i, j in rng.integers(0, m, (density * m, 2)) if i != j}
+    rows = [dict() for _ in range(m)]
+    for i, j in pairs:
+        v = -rng.uniform(0.1, 1.0)
+        rows[i][j] = v
+        rows[j][i] = v
+    for i in range(m):
+        rows[i][i] = sum(abs(v) for v in rows[i].values()) + rng.uniform(0.5, 2.0)
+    ptr = np.zeros(m + 1, np.int64)
+    col, val = [], []
+    for i in range(m):
+        cs = sorted(rows[i])
+        col += cs
+        val += [rows[i][c] for c in cs]
+        ptr[i + 1] = len(col)
+    return oracle.CSR(ptr, np.array(col, np.int32), np.array(val), rng.uniform(-1, 1, m))
+
+
+def test_rhs_matches_oracle(ctx):
+    from paper_1505_08023_amd.mfe import Problem
+    for N, fv in (((12, 7, 9), None), ((5, 5, 5), np.random.default_rng(3).uniform(0, 1, 6))):
+        A = oracle.assemble(*N, face_vals=fv)
+        P = Problem.mesh(ctx, *N, face_vals=fv)
+        b = np_(P.rhs())
+        assert np.abs(b - A.b).max() <= 64 * EPS * max(np.abs(A.b).max(), 1.0 / max(N))
+        P.close()
+    G = spd_csr(300, 1)
+    P = Problem.from_csr_host(ctx, G.ptr, G.col, G.val, G.b)
+    assert np.array_equal(np_(P.rhs()), G.b)
+    P.close()
+
+
+def test_host_array_import_and_export(ctx):
+    """A ragged CRS (rows of 0..60 entries, every 17th empty) from host arrays:
+    exported bit-exactly through both export forms, products in both formats
+    against the oracle; b = NULL gives b = 0."""
+    from paper_1505_08023_amd.mfe import Problem
+    rng = np.random.default_rng(2)
+    m = 1000 + 37
+    lens = rng.integers(0, 61, m)
+    lens[::17] = 0
+    ptr = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    col = np.concatenate([np.sort(rng.choice(m, l, replace=False)) for l in lens]).astype(np.int32)
+    val = rng.uniform(-1, 1, ptr[-1])
+    b = rng.uniform(-1, 1, m)
+    A = oracle.CSR(ptr, col, val, b)
+    P = Problem.from_csr_host(ctx, ptr, col, val, b, formats=("csr", "bcrs13"))
+    p2, c2, v2, b2 = P.export_csr_host()
+    assert np.array_equal(p2, ptr.astype(np.int32)) and np.array_equal(c2, col)
+    assert np.array_equal(v2, val) and np.array_equal(b2, b)
+    p3, c3, v3, b3 = (np_(t) for t in P.export_csr())
+    assert np.array_equal(p3, p2) and np.array_equal(c3, c2) and np.array_equal(v3, v2) and np.array_equal(b3, b2)
+    x = inputs.spmv_vector(m, seed=4)
+    y_ref = oracle.csr_spmv(A, x)
+    xg = torch.tensor(x, device=ctx.device)
+    for fmt in ("csr", "bcrs13"):
+        check_spmv(np_(P.spmv(xg, fmt=fmt)), A, x, y_ref)
+    P.close()
+    Z = Problem.from_csr_host(ctx, ptr, col, val)
+    assert not np.any(Z.export_csr_host()[3])
+    Z.close()
+
+
+def test_host_array_import_rejects_bad_structure(ctx):
+    from paper_1505_08023_amd._lib import MfeError
+    from paper_1505_08023_amd.mfe import Problem
+    for ptr, col in (([0, 2, 3], [1, 0, 1]), ([0, 2, 3], [0, 5, 1]), ([1, 2, 3], [0, 1, 1])):
+        with pytest.raises(MfeError, match="EINVAL"):
+            Problem.from_csr_host(ctx, np.array(ptr), np.array(col), np.ones(3))
+
+
+def test_batch_of_mesh_problems_equals_assembled_batch(ctx):
+    """mfe_batch_from_problems over mesh problems concatenates exactly what
+    mfe_batch_create assembles for the same sizes and face values: same CRS,
+    b, and bitwise the same batched solve."""
+    from paper_1505_08023_amd.mfe import Batch, Problem
+    sizes, faces = inputs.batched_meshes(nsys=6, lo=3, hi=16, seed=8)
+    probs = [Problem.mesh(ctx, *map(int, N), face_vals=fv) for N, fv in zip(sizes, faces)]
+    A = Batch(ctx, sizes, faces)
+    B = Batch.from_problems(ctx, probs)
+    for t, u in zip(A.export_csr(), B.export_csr()):
+        assert torch.equal(t, u)
+    assert np.array_equal(A.row_offsets, B.row_offsets)
+    for fmt in ("csr", "bcrs13"):
+        xa, sa = A.cg(tol=1e-8, fmt=fmt)
+        xb, sb = B.cg(tol=1e-8, fmt=fmt)
+        assert torch.equal(xa, xb) and [s["iterations"] for s in sa] == [s["iterations"] for s in sb]
+    # boundary data can be re-imposed: every system is a mesh
+    B.set_bc(face_vals=np.ones((6, 6)))
+    for p in probs:
+        p.close()
+    A.close()
+    B.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
+def test_cg_batched_mixed_systems_match_independent_oracle_solves(ctx, fmt, mixed):
+    """Mesh problems and generic SPD CRS problems solved together in one call
+    (mfe_cg_batched), each against its own oracle CG: tolerance met, counts
+    within 2 (FP64) and the solution within ||A^-1|| (||r|| + ||r_ref||)."""
+    from paper_1505_08023_amd.mfe import Problem, cg_batched
+    tol = 1e-8
+    meshes = [((9, 6, 11), (0.2, 1.0, 0.0, 0.5, 0.3, 0.9)), ((14, 14, 14), None), ((3, 4, 2), (1, 0, 1, 0, 1, 0))]
+    systems = []
+    for N, fv in meshes:
+        A = oracle.assemble(*N, face_vals=fv)
+        systems.append((Problem.mesh(ctx, *N, face_vals=fv), A, None))
+    for m, seed in ((400, 11), (1234, 12)):
+        G = spd_csr(m, seed)
+        lam = float(np.linalg.eigvalsh(G.dense())[0])
+        systems.append((Problem.from_csr_host(ctx, G.ptr, G.col, G.val, G.b), G, lam))
+    rng = np.random.default_rng(5)
+    x0 = [rng.uniform(-1, 1, A.m) for _, A, _ in systems]
+    xs, stats = cg_batched(ctx, [P for P, _, _ in systems], [torch.tensor(x, device=ctx.device) for x in x0],
+                           tol=tol, max_iter=3000, fmt=fmt, mixed=mixed)
+    for j, ((P, A, lam), x, st) in enumerate(zip(systems, xs, stats)):
+        ref = oracle.cg(A, x0=x0[j], tol=tol, max_iter=3000)
+        assert ref["status"] == oracle.OK
+        assert st["status"] == 0 and st["rel_res_true"] <= tol, (j, st)
+        if not mixed:
+            assert abs(st["iterations"] - ref["iterations"]) <= 2, (j, st["iterations"], ref["iterations"])
+        if lam is None:
+            check_solution_gap(np_(x), ref, st, meshes[j][0], A)
+        else:
+            bn = np.linalg.norm(A.b)
+            gap = np.linalg.norm(np_(x) - ref["x"])
+            assert gap <= (st["rel_res_true"] + ref["rel_res_true"]) * bn / lam * (1 + 1e-6) + 1e-12, (j, gap)
+    for P, _, _ in systems:
+        P.close()
+
+
+def test_batch_from_crs_problems_rejects_set_bc_and_foreign_problems(ctx):
+    from paper_1505_08023_amd._lib import MfeError
+    from paper_1505_08023_amd.mfe import Batch, Context, Problem
+    G = spd_csr(200, 3)
+    P = Problem.from_csr_host(ctx, G.ptr, G.col, G.val, G.b)
+    M = Problem.mesh(ctx, 4, 4, 4)
+    B = Batch.from_problems(ctx, [M, P])
+    with pytest.raises(MfeError, match="EINVAL"):
+        B.set_bc(face_vals=np.ones((2, 6)))
+    B.close()
+    other = Context(0)
+    Q = Problem.mesh(other, 3, 3, 3)
+    with pytest.raises(MfeError, match="EINVAL"):
+        Batch.from_problems(ctx, [M, Q])
+    Q.close()
+    other.close()
+    P.close()
+    M.close()
