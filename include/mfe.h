@@ -333,6 +333,17 @@ int mfe_cg_mixed_warm(const mfe_problem *p, int format, double *x_dev, double to
 int mfe_cg_mixed_ex(const mfe_problem *p, int format, double *x_dev, double tol, double inner_tol, int max_outer,
                     int max_inner, int flags, mfe_cg_stats *stats);
 
+/* Trilinear prolongation (an initial guess on a refined mesh): xc_dev holds
+ * nodal values of the Nx x Ny x Nz element box mesh (node numbering as
+ * above), xf_dev receives the interpolant of the coarse trilinear elements
+ * (Sec. 1 element space) at the nodes of the (factor Nx) x (factor Ny) x
+ * (factor Nz) mesh; with bnd_dev (length of the fine mesh, may be NULL) the
+ * fine boundary nodes take bnd_dev's values instead, for instance the fine
+ * problem's b (its Dirichlet values: its boundary rows are identity rows).
+ * factor >= 1.  Does not synchronise. */
+int mfe_prolong_trilinear(mfe_ctx *ctx, int Nx, int Ny, int Nz, const double *xc_dev, int factor,
+                          const double *bnd_dev, double *xf_dev);
+
 /* ---------------------------------------------------------------------
  * Batched solves: many box meshes of uneven size solved together (the
  * batched extension of the Sec. 1 CG module).  Each system follows exactly

@@ -32,55 +32,67 @@ def lib():
         path = os.path.join(_HERE, "liboracle.so")
         if not os.path.exists(path):
             _build.build()
-        L = ctypes.CDLL(path)
-        L.orc_num_rows.restype = _c_i64
-        L.orc_num_rows.argtypes = [_c_int] * 3
-        L.orc_count_nnz.restype = _c_i64
-        L.orc_count_nnz.argtypes = [_c_int] * 3
-        L.orc_boundary.restype = None
-        L.orc_boundary.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _u8p, _f64p]
-        L.orc_element_matrix.restype = None
-        L.orc_element_matrix.argtypes = [_c_dbl] * 3 + [_f64p]
-        L.orc_assemble.restype = _c_int
-        L.orc_assemble.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _c_int,
-                                                  _i64p, _i32p, _f64p, _f64p]
-        L.orc_assemble_rows.restype = _c_int
-        L.orc_assemble_rows.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _c_i64, _i64p,
-                                                       _i32p, _f64p, _i32p, _f64p]
-        L.orc_csr_spmv.restype = None
-        L.orc_csr_spmv.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p]
-        L.orc_bcrsvar_count.restype = _c_i64
-        L.orc_bcrsvar_count.argtypes = [_c_i64, _i64p, _i32p]
-        L.orc_bcrsvar_build.restype = None
-        L.orc_bcrsvar_build.argtypes = [_c_i64, _i64p, _i32p, _i32p, _i64p, _i64p]
-        for fn in (L.orc_bcrsvar_spmv, L.orc_bcrsvar_spmv_switch):
-            fn.restype = None
-            fn.argtypes = [_c_i64, _i64p, _i32p, _i64p, _f64p, _f64p, _f64p]
-        L.orc_bcrs13_build.restype = _c_i64
-        L.orc_bcrs13_build.argtypes = [_c_i64, _i64p, _i32p, ctypes.c_void_p,
-                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
-        L.orc_bcrs13_spmv.restype = None
-        L.orc_bcrs13_spmv.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p]
-        L.orc_cg.restype = _c_int
-        L.orc_cg.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_int,
-                             ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl),
-                             ctypes.POINTER(_c_dbl), ctypes.c_void_p]
-        L.orc_cg_single_reduction.restype = _c_int
-        L.orc_cg_single_reduction.argtypes = L.orc_cg.argtypes
-        L.orc_cg_jacobi.restype = _c_int
-        L.orc_cg_jacobi.argtypes = L.orc_cg.argtypes
-        L.orc_cg_mixed.restype = _c_int
-        L.orc_cg_mixed.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_dbl,
-                                   _c_int, _c_int, ctypes.POINTER(_c_int),
-                                   ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl)]
-        L.orc_cg_mixed_keep.restype = _c_int
-        L.orc_cg_mixed_keep.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_dbl,
-                                        _c_int, _c_int, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
-                                        ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl)]
-        L.orc_analytic_u.restype = _c_dbl
-        L.orc_analytic_u.argtypes = [_c_dbl, _c_dbl, _c_dbl, _c_int]
-        _LIB = L
+        _LIB = _configure(ctypes.CDLL(path))
     return _LIB
+
+
+def load_timing_build(path):
+    """A timing build of the oracle (oracle/build.py build_timing), for the
+    benchmark's CPU baseline: the same functions, passed as `library=`."""
+    return _configure(ctypes.CDLL(path))
+
+
+def _configure(L):
+    """Declare the C signatures on a loaded build of oracle.c."""
+    L.orc_num_threads.restype = _c_int
+    L.orc_num_threads.argtypes = []
+    L.orc_num_rows.restype = _c_i64
+    L.orc_num_rows.argtypes = [_c_int] * 3
+    L.orc_count_nnz.restype = _c_i64
+    L.orc_count_nnz.argtypes = [_c_int] * 3
+    L.orc_boundary.restype = None
+    L.orc_boundary.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _u8p, _f64p]
+    L.orc_element_matrix.restype = None
+    L.orc_element_matrix.argtypes = [_c_dbl] * 3 + [_f64p]
+    L.orc_assemble.restype = _c_int
+    L.orc_assemble.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _c_int,
+                                              _i64p, _i32p, _f64p, _f64p]
+    L.orc_assemble_rows.restype = _c_int
+    L.orc_assemble_rows.argtypes = [_c_int] * 3 + [ctypes.c_void_p, ctypes.c_void_p, _c_i64, _i64p,
+                                                   _i32p, _f64p, _i32p, _f64p]
+    L.orc_csr_spmv.restype = None
+    L.orc_csr_spmv.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p]
+    L.orc_bcrsvar_count.restype = _c_i64
+    L.orc_bcrsvar_count.argtypes = [_c_i64, _i64p, _i32p]
+    L.orc_bcrsvar_build.restype = None
+    L.orc_bcrsvar_build.argtypes = [_c_i64, _i64p, _i32p, _i32p, _i64p, _i64p]
+    for fn in (L.orc_bcrsvar_spmv, L.orc_bcrsvar_spmv_switch):
+        fn.restype = None
+        fn.argtypes = [_c_i64, _i64p, _i32p, _i64p, _f64p, _f64p, _f64p]
+    L.orc_bcrs13_build.restype = _c_i64
+    L.orc_bcrs13_build.argtypes = [_c_i64, _i64p, _i32p, ctypes.c_void_p,
+                                   ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    L.orc_bcrs13_spmv.restype = None
+    L.orc_bcrs13_spmv.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p]
+    L.orc_cg.restype = _c_int
+    L.orc_cg.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_int,
+                         ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl),
+                         ctypes.POINTER(_c_dbl), ctypes.c_void_p]
+    L.orc_cg_single_reduction.restype = _c_int
+    L.orc_cg_single_reduction.argtypes = L.orc_cg.argtypes
+    L.orc_cg_jacobi.restype = _c_int
+    L.orc_cg_jacobi.argtypes = L.orc_cg.argtypes
+    L.orc_cg_mixed.restype = _c_int
+    L.orc_cg_mixed.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_dbl,
+                               _c_int, _c_int, ctypes.POINTER(_c_int),
+                               ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl)]
+    L.orc_cg_mixed_keep.restype = _c_int
+    L.orc_cg_mixed_keep.argtypes = [_c_i64, _i64p, _i32p, _f64p, _f64p, _f64p, _c_dbl, _c_dbl,
+                                    _c_int, _c_int, _c_int, _c_int, _c_int, _c_int, ctypes.POINTER(_c_int),
+                                    ctypes.POINTER(_c_int), ctypes.POINTER(_c_int), ctypes.POINTER(_c_dbl)]
+    L.orc_analytic_u.restype = _c_dbl
+    L.orc_analytic_u.argtypes = [_c_dbl, _c_dbl, _c_dbl, _c_int]
+    return L
 
 
 def _opt(a, dtype):
@@ -224,16 +236,17 @@ def bcrs13_spmv(A, fmt, x):
     return y
 
 
-def cg(A, b=None, x0=None, tol=1e-8, max_iter=200, history=False):
+def cg(A, b=None, x0=None, tol=1e-8, max_iter=200, history=False, library=None):
     """Unpreconditioned CG (Sec. 1 CG module).  Returns a dict with x,
     status, iterations, recurrence and true relative residuals and, when
-    asked, the residual history ||r_k||/||b||, k = 0..iterations."""
+    asked, the residual history ||r_k||/||b||, k = 0..iterations.  library:
+    a timing build (load_timing_build) instead of the oracle's own."""
     b = A.b if b is None else np.ascontiguousarray(b, np.float64)
     x = np.zeros(A.m) if x0 is None else np.array(x0, np.float64, copy=True)
     its, rr, rt = _c_int(0), _c_dbl(0), _c_dbl(0)
     hist = np.zeros(max_iter + 1) if history else None
     hp = hist.ctypes.data_as(ctypes.c_void_p) if history else None
-    st = lib().orc_cg(A.m, A.ptr, A.col, A.val, b, x, tol, max_iter,
+    st = (library or lib()).orc_cg(A.m, A.ptr, A.col, A.val, b, x, tol, max_iter,
                       ctypes.byref(its), ctypes.byref(rr), ctypes.byref(rt), hp)
     out = dict(x=x, status=st, iterations=its.value, rel_res_rec=rr.value, rel_res_true=rt.value)
     if history:

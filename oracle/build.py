@@ -16,6 +16,23 @@ LIB = os.path.join(HERE, "liboracle.so")
 CFLAGS = ["-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-Wextra"]
 
 
+def build_timing(out_dir, openmp=False, verbose=False):
+    """A timing build of the same source for the CPU baseline, compiled on the
+    host that runs it: -O3 -march=native (still -ffp-contract=off), and with
+    openmp the annotated loops over all cores.  Returns the library path."""
+    name = "liboracle_native_omp.so" if openmp else "liboracle_native.so"
+    out = os.path.join(out_dir, name)
+    flags = ["-O3", "-march=native", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared"]
+    if openmp:
+        flags.append("-fopenmp")
+    cmd = ["gcc"] + flags + [SRC, "-o", out + ".tmp", "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.run(cmd, check=True)
+    os.replace(out + ".tmp", out)
+    return out
+
+
 def build(verbose=False):
     cmd = ["gcc"] + CFLAGS + [SRC, "-o", LIB + ".tmp", "-lm"]
     if verbose:

@@ -61,6 +61,7 @@ SIGNATURES = {
     "mfe_dot": (c_int, [c_vp, c_i64, c_vp, c_vp, ctypes.POINTER(c_dbl)]),
     "mfe_cg_mixed_warm": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_cg_mixed_ex": (c_int, [c_vp, c_int, c_vp, c_dbl, c_dbl, c_int, c_int, c_int, ctypes.POINTER(mfe_cg_stats)]),
+    "mfe_prolong_trilinear": (c_int, [c_vp, c_int, c_int, c_int, c_vp, c_int, c_vp, c_vp]),
     "mfe_stream_probe": (c_int, [c_vp, c_int, c_i64, c_vp, c_vp, c_vp, c_vp]),
     "mfe_cg": (c_int, [c_vp, c_int, c_vp, c_dbl, c_int, c_vp, ctypes.POINTER(mfe_cg_stats)]),
     "mfe_spmv_dot_f32": (c_int, [c_vp, c_int, c_vp, c_vp, c_vp, c_vp, c_vp]),

@@ -129,7 +129,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 11; }
+int mfe_version(void) { return 12; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {

@@ -112,7 +112,7 @@ def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0, energy=None):
     return history
 
 
-def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_direction=False):
+def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_direction=False, errors=True):
     """Per held-out seed: plain FP64 CG from x0 = 0 against CG from the
     network's guess (inference included in its time; the solver falls back to
     the zero start when the guess's residual is not below ||b||), and, with
@@ -121,11 +121,16 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
     Problem.cg_mixed).  All solves stop at the same
     tolerance on ||b - A x|| / ||b||.  Every variant runs once on the first
     seed before timing (graph capture).  Times are host wall clock,
-    GPU-synchronised."""
+    GPU-synchronised.  With errors, every solution's ||x - x_ref|| / ||x_ref||
+    against FP64 CG to tol / 100 (outside the timed regions)."""
     V = (n + 1) ** 3
     P = Problem.mesh(ctx, n, n, n, formats=("bcrs13",), precisions=("f64", "f32") if mixed else ("f64",))
     x = torch.zeros(V, dtype=torch.float64, device=ctx.device)
     x0 = torch.zeros(V, dtype=torch.float64, device=ctx.device)
+    xr = torch.zeros(V, dtype=torch.float64, device=ctx.device)
+
+    def err(v):
+        return float(torch.linalg.norm(v - xr) / torch.linalg.norm(xr))
 
     def timed(fn):
         torch.cuda.synchronize()
@@ -139,23 +144,34 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
         P.set_bc(node_g=g)
         r = dict(seed=int(s))
         x.zero_()
+        if errors:
+            xr.zero_()
+            P.cg(xr, tol=tol / 100, max_iter=20000)
         r["t_plain"], st0 = timed(lambda: P.cg(x, tol=tol, max_iter=20000)[1])
+        if errors:
+            r["err_plain"] = err(x)
 
         def learned_fp64():
             net.predict_x0(g, x0)
             return P.cg(x0, tol=tol, max_iter=20000, warm=True)[1]
         r["t_learned"], st1 = timed(learned_fp64)
+        if errors:
+            r["err_learned"] = err(x0)
         r.update(its_plain=st0["iterations"], its_learned=st1["iterations"], used=not st1["guess_rejected"],
                  res_plain=st0["rel_res_true"], res_learned=st1["rel_res_true"])
         if mixed:
             x.zero_()
             r["t_mixed"], st2 = timed(lambda: P.cg_mixed(x, tol=tol, inner_tol=inner_tol,
                                                          keep_direction=keep_direction)[1])
+            if errors:
+                r["err_mixed"] = err(x)
 
             def learned_mixed():
                 net.predict_x0(g, x0)
                 return P.cg_mixed(x0, tol=tol, inner_tol=inner_tol, warm=True, keep_direction=keep_direction)[1]
             r["t_learned_mixed"], st3 = timed(learned_mixed)
+            if errors:
+                r["err_learned_mixed"] = err(x0)
             r.update(its_mixed=st2["iterations"], its_learned_mixed=st3["iterations"],
                      res_mixed=st2["rel_res_true"], res_learned_mixed=st3["rel_res_true"],
                      used_mixed=not st3["guess_rejected"])
@@ -181,6 +197,13 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
                    guesses_used_mixed=int(sum(r["used_mixed"] for r in rows)),
                    speedup_time_mixed=a("t_plain") / a("t_mixed"),
                    speedup_time_learned_mixed=a("t_plain") / a("t_learned_mixed"))
+    if errors:
+        out["error_vs_fp64_ref"] = {
+            "reference": f"FP64 CG to {tol / 100:g}",
+            **{f"{k}_mean": a(f"err_{k}") for k in (("plain", "learned", "mixed", "learned_mixed") if mixed
+                                                     else ("plain", "learned"))},
+            **{f"{k}_max": max(r[f"err_{k}"] for r in rows) for k in (("plain", "learned", "mixed", "learned_mixed")
+                                                                       if mixed else ("plain", "learned"))}}
     out["rows"] = rows
     return out
 

@@ -130,6 +130,22 @@ class Context:
                                             _ptr(dst, torch.float64, None, "dst"), ev[0], ev[1]),
                   "mfe_stream_probe")
 
+    def prolong(self, xc, coarse, factor, bnd=None, xf=None):
+        """Trilinear prolongation of nodal values xc of the coarse (Nx, Ny, Nz)
+        element mesh to the mesh refined factor times (mfe_prolong_trilinear);
+        bnd: values for the fine boundary nodes (e.g. the fine problem's b)."""
+        Nx, Ny, Nz = coarse
+        mc = (Nx + 1) * (Ny + 1) * (Nz + 1)
+        mf = (Nx * factor + 1) * (Ny * factor + 1) * (Nz * factor + 1)
+        if xf is None:
+            with _on(self):
+                xf = torch.empty(mf, dtype=torch.float64, device=self.device)
+        with _on(self):
+            check(self.lib.mfe_prolong_trilinear(self.handle, Nx, Ny, Nz, _ptr(xc, torch.float64, mc, "xc"), factor,
+                                                 _ptr(bnd, torch.float64, mf, "bnd"), _ptr(xf, torch.float64, mf, "xf")),
+                  "mfe_prolong_trilinear")
+        return xf
+
     def close(self):
         if self.handle:
             for p in list(self.problems):

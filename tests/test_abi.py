@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_string():
     lib = _lib.load()
-    assert lib.mfe_version() == 11
+    assert lib.mfe_version() == 12
     assert isinstance(lib.mfe_last_error(), bytes)
 
 
@@ -68,6 +68,7 @@ def test_argument_checks_before_any_device_call():
     assert lib.mfe_batch_cg_mixed_ex(None, 1, None, 1e-8, 1e-4, 10, 10, 0, None) == _lib.MFE_EINVAL
     assert lib.mfe_net_set_grad(None, None) == _lib.MFE_EINVAL
     assert lib.mfe_rhs(None, None) == _lib.MFE_EINVAL
+    assert lib.mfe_prolong_trilinear(None, 4, 4, 4, None, 2, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_problem_from_csr_host(None, 4, None, None, None, None, 1, 1, ctypes.byref(out)) == _lib.MFE_EINVAL
     assert lib.mfe_problem_export_csr_host(None, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_batch_from_problems(None, 1, None, 1, 1, ctypes.byref(out)) == _lib.MFE_EINVAL

@@ -184,3 +184,31 @@ def test_batch_from_crs_problems_rejects_set_bc_and_foreign_problems(ctx):
     other.close()
     P.close()
     M.close()
+
+
+@pytest.mark.parametrize("coarse,factor", [((4, 3, 5), 2), ((8, 8, 8), 4), ((3, 2, 2), 3), ((5, 5, 5), 1)])
+def test_prolong_trilinear(ctx, coarse, factor):
+    """mfe_prolong_trilinear against scipy's linear interpolation on the
+    regular coarse grid (x fastest), exact on an affine field, and with the
+    fine boundary values taken from bnd."""
+    from scipy.interpolate import RegularGridInterpolator
+    Nx, Ny, Nz = coarse
+    rng = np.random.default_rng(sum(coarse) + factor)
+    xc = rng.uniform(-1, 1, (Nz + 1, Ny + 1, Nx + 1))
+    fine = [N * factor for N in coarse]
+    zf, yf, xf = np.meshgrid(*[np.arange(n + 1) / n for n in fine[::-1]], indexing="ij")
+    interp = RegularGridInterpolator([np.arange(n + 1) / n for n in coarse[::-1]], xc)
+    ref = interp(np.stack([zf, yf, xf], axis=-1).reshape(-1, 3))
+    got = np_(ctx.prolong(torch.tensor(xc.ravel(), device=ctx.device), coarse, factor))
+    assert np.allclose(got, ref, rtol=0, atol=1e-14)
+    # affine fields are reproduced exactly (to rounding)
+    zc, yc, xcg = np.meshgrid(*[np.arange(n + 1) / n for n in coarse[::-1]], indexing="ij")
+    aff = lambda x, y, z: 0.3 + 1.5 * x - 0.7 * y + 2.0 * z
+    got = np_(ctx.prolong(torch.tensor(aff(xcg, yc, zc).ravel(), device=ctx.device), coarse, factor))
+    assert np.allclose(got, aff(xf, yf, zf).ravel(), rtol=0, atol=1e-14)
+    # boundary nodes from bnd
+    bnd = rng.uniform(5, 6, xf.size)
+    got = np_(ctx.prolong(torch.tensor(xc.ravel(), device=ctx.device), coarse, factor,
+                          bnd=torch.tensor(bnd, device=ctx.device)))
+    on = ((xf == 0) | (xf == 1) | (yf == 0) | (yf == 1) | (zf == 0) | (zf == 1)).ravel()
+    assert np.array_equal(got[on], bnd[on]) and np.allclose(got[~on], ref[~on], rtol=0, atol=1e-14)
