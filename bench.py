@@ -47,7 +47,9 @@ def log(*a):
 def spmv_bytes(fmt, m, nnz, nb, fp=8, layout=None):
     """Algorithmic bytes of one SpMV: matrix streamed once, x read once, y
     written once, int32 indices; for the fused dot p_i is the x entry already
-    read.  CRS (layout: the problem's csr_layout): fp nnz values, 4 bytes of
+    read.  CRS (layout: the problem's csr_layout): with a group walk, fp nnz
+    values, 8 bytes per work item, 4 per group, 12 per other row and 4 per
+    entry of the other rows; else fp nnz values, 4 bytes of
     column index per entry outside the descriptor tiles, 112 per descriptor
     tile, 4 (tiles + 1) of tile bounds plus 4 per row of the other tiles,
     2 fp m.  1x3 BCRS (layout: b13_layout): 3 fp nb values, 4 bytes of column
@@ -57,6 +59,13 @@ def spmv_bytes(fmt, m, nnz, nb, fp=8, layout=None):
     if fmt == "csr":
         if layout is None:
             return (fp + 4) * nnz + 4 * (m + 1) + 2 * fp * m
+        if layout.get("items", 0) > 0:
+            # group walk: every value; per item an 8-byte record; per group its
+            # first row pointer; the other rows' list entry, two row pointers
+            # and column indices
+            other_nnz = nnz - 27 * layout["group_rows"]
+            return (fp * nnz + 8 * layout["items"] + 4 * layout["groups"] + 12 * layout["other_rows"]
+                    + 4 * other_nnz + 2 * fp * m)
         R, tiles, ct = layout["tile_rows"], layout["tiles"], layout["compressed_tiles"]
         return fp * nnz + 4 * (nnz - 27 * R * ct) + 112 * ct + 4 * (tiles + 1) + 4 * (m - R * ct) + 2 * fp * m
     slices = (m + 63) // 64

@@ -146,6 +146,17 @@ int mfe_problem_info(const mfe_problem *p, int64_t *m, int64_t *nnz, int64_t *nb
  * stay stored.  Any output pointer may be NULL. */
 int mfe_problem_csr_layout(const mfe_problem *p, int64_t *tile_rows, int64_t *tiles, int64_t *compressed_tiles);
 
+/* The CRS product's walk of a mesh problem (all zero when it walks the
+ * wavefront tiles of mfe_problem_csr_layout instead): *items work items in
+ * row order, *groups of them runs of up to 64 consecutive rows that hold 27
+ * entries each with the mesh's 27 neighbour columns (*group_rows rows in
+ * all, their values staged with 16-byte loads and their columns formed from
+ * the 27 offsets, whose indices stay stored), the other *other_rows rows
+ * taken 16 per item from a row list with their column indices read.  Any
+ * output pointer may be NULL. */
+int mfe_problem_csr_groups(const mfe_problem *p, int64_t *items, int64_t *groups, int64_t *group_rows,
+                           int64_t *other_rows);
+
 /* Storage of the 1x3 BCRS (all zero when it was not built): 64-row slices;
  * slot rows (slice s stores 64 x its slot count blocks, padding included);
  * slices whose column indices the SpMV forms from a 48-byte per-slice

@@ -49,6 +49,7 @@ SIGNATURES = {
     "mfe_problem_set_bc": (c_int, [c_vp, c_vp, c_vp]),
     "mfe_problem_info": (c_int, [c_vp, ctypes.POINTER(c_i64), ctypes.POINTER(c_i64), ctypes.POINTER(c_i64)]),
     "mfe_problem_csr_layout": (c_int, [c_vp] + [ctypes.POINTER(c_i64)] * 3),
+    "mfe_problem_csr_groups": (c_int, [c_vp] + [ctypes.POINTER(c_i64)] * 4),
     "mfe_problem_bcrs13_layout": (c_int, [c_vp] + [ctypes.POINTER(c_i64)] * 4),
     "mfe_batch_bcrs13_layout": (c_int, [c_vp] + [ctypes.POINTER(c_i64)] * 4),
     "mfe_problem_export_csr": (c_int, [c_vp, c_vp, c_vp, c_vp, c_vp]),

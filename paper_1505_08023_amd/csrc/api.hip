@@ -93,7 +93,8 @@ void free_problem_storage(mfe_problem *P) {
     mfe_ctx *ctx = P->ctx;
     release_graphs(P);
     Buffer *bufs[] = {&P->ptr, &P->col, &P->val64, &P->val32, &P->b, &P->slot_base, &P->jas, &P->bval64,
-                      &P->bval32, &P->rowblocks, &P->bdesc, &P->cdesc, &P->r, &P->p, &P->q, &P->state, &P->partials,
+                      &P->bval32, &P->rowblocks, &P->bdesc, &P->cdesc, &P->citems, &P->crows, &P->r, &P->p, &P->q,
+                      &P->state, &P->partials,
                       &P->r32, &P->p32, &P->q32, &P->d32, &P->ax, &P->s, &P->dinv};
     for (Buffer *b : bufs) dev_free(ctx, b);
 }
@@ -101,6 +102,7 @@ void free_problem_storage(mfe_problem *P) {
 // Derived formats and precisions after the FP64 CRS exists.
 int finish_problem(mfe_problem *P) {
     MFE_TRY(build_csr_tiles(P));
+    MFE_TRY(build_csr_groups(P));
     if (P->formats & MFE_BCRS13) MFE_TRY(build_bcrs13(P));
     if (P->precisions & MFE_F32) MFE_TRY(cast_values_f32(P));
     MFE_HIP_TRY(hipStreamSynchronize(P->ctx->stream));
@@ -129,7 +131,7 @@ extern "C" {
 
 const char *mfe_last_error(void) { return g_error.c_str(); }
 
-int mfe_version(void) { return 12; }
+int mfe_version(void) { return 13; }
 
 int mfe_ctx_create(int device, void *stream, mfe_alloc_fn alloc, mfe_free_fn free_fn, void *alloc_user,
                    mfe_ctx **out) {
@@ -393,6 +395,20 @@ int mfe_problem_csr_layout(const mfe_problem *p, int64_t *tile_rows, int64_t *ti
     if (tile_rows) *tile_rows = kCsrsRows;
     if (tiles) *tiles = (p->m + kCsrsRows - 1) / kCsrsRows;
     if (compressed_tiles) *compressed_tiles = p->csr_ctiles;
+    return MFE_OK;
+}
+
+int mfe_problem_csr_groups(const mfe_problem *p, int64_t *items, int64_t *groups, int64_t *group_rows,
+                           int64_t *other_rows) {
+    clear_error();
+    if (!p) {
+        set_error("problem is NULL");
+        return MFE_EINVAL;
+    }
+    if (items) *items = p->ncitems;
+    if (groups) *groups = p->ncgroups;
+    if (group_rows) *group_rows = p->ncgroup_rows;
+    if (other_rows) *other_rows = p->ncitems > 0 ? p->ncrows : 0;
     return MFE_OK;
 }
 

@@ -117,6 +117,22 @@ struct CsrDesc {
 };
 static_assert(sizeof(CsrDesc) == 112, "CsrDesc is 112 bytes");
 
+// CRS row groups of a mesh problem (MFE_CSR_GROUPS): a row is "full" when it
+// holds 27 entries with column row + o_k, o_k the 27 neighbour offsets of the
+// mesh numbering (ascending, in 9 runs of three consecutive columns).  Full
+// rows come in runs (the interior of each x-line); the CRS product takes up
+// to 64 consecutive full rows per wavefront (one lane per row, the group's
+// contiguous values staged in LDS with 16-byte loads) and the other rows 16
+// at a time from a row list.  Work items in row order:
+//   {r0, n},       n in 1..64:  full rows r0 .. r0 + n - 1
+//   {start, -n},   n in 1..16:  rows list[start .. start + n - 1]
+#ifndef MFE_CSR_GROUPS
+#define MFE_CSR_GROUPS 1  // group walk of the CRS product for mesh problems (0: 16-row tiles everywhere)
+#endif
+struct CsrRuns {
+    int32_t r[9];  // first column offset of each run of three
+};
+
 // ------------------------------------------------------------------ context / problem
 
 struct Buffer {
@@ -190,6 +206,9 @@ struct mfe_problem {
     // CRS (always FP64; FP32 values when MFE_F32)
     mfe::Buffer ptr, col, val64, val32, b;
     mfe::Buffer cdesc;  // CsrDesc per CRS wavefront tile
+    mfe::Buffer citems, crows;  // CRS group walk: work items (int2) and the list of the other rows
+    int64_t ncitems = 0, ncrows = 0, ncgroups = 0, ncgroup_rows = 0;
+    mfe::CsrRuns cruns{};
     // 1x3 BCRS
     mfe::Buffer slot_base, jas, bval64, bval32, rowblocks;
     mfe::Buffer bdesc;  // B13Desc per slice
@@ -214,6 +233,7 @@ int launch_assemble_into(hipStream_t s, int Nx, int Ny, int Nz, const double *fa
 
 // formats (formats.hip)
 int build_csr_tiles(mfe_problem *P);
+int build_csr_groups(mfe_problem *P);
 int build_bcrs13(mfe_problem *P);
 int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const int32_t *col);
 int cast_values_f32(mfe_problem *P);

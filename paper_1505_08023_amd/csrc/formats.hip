@@ -9,6 +9,9 @@
 // of 64 (one wavefront); inside a slice the k-th block of every row is stored
 // contiguously, so each block load of a wavefront is one coalesced access
 // (layout in b13_layout.hpp).
+#include <algorithm>
+#include <vector>
+
 #include "b13_layout.hpp"
 #include "common.hpp"
 #include "device_util.hpp"
@@ -370,6 +373,38 @@ __global__ __launch_bounds__(kBlock) void k_validate_csr(int64_t m, int64_t nnz,
     if (!ok) atomicOr(bad, 1);
 }
 
+// flag[i] = 1 when row i holds 27 entries with column i + off[k] (k-th entry).
+struct CsrOffsets {
+    int32_t off[27];
+};
+__global__ __launch_bounds__(kBlock) void k_csr_fullflag(int64_t m, const int32_t *__restrict__ ptr,
+                                                         const int32_t *__restrict__ col, CsrOffsets O,
+                                                         int32_t *__restrict__ flag) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= m) return;
+    const int32_t lo = ptr[i];
+    bool ok = ptr[i + 1] - lo == 27;
+    for (int k = 0; ok && k < 27; ++k) ok = (int64_t)col[lo + k] - i == (int64_t)O.off[k];
+    flag[i] = ok ? 1 : 0;
+}
+
+// chg[i] = 1 where the flag changes between rows i - 1 and i (i = 0..m, with
+// the flag taken as 0 outside the matrix): run starts and run ends alternate.
+__global__ __launch_bounds__(kBlock) void k_flag_changes(int64_t m, const int32_t *__restrict__ flag,
+                                                         int32_t *__restrict__ chg) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i > m) return;
+    const int32_t cur = i < m ? flag[i] : 0, prev = i > 0 ? flag[i - 1] : 0;
+    chg[i] = cur != prev ? 1 : 0;
+}
+
+// out[pos[i]] = i for every i with chg[i] set.
+__global__ __launch_bounds__(kBlock) void k_compact_rows(int64_t n, const int32_t *__restrict__ chg,
+                                                         const int32_t *__restrict__ pos, int32_t *__restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < n && chg[i]) out[pos[i]] = (int32_t)i;
+}
+
 }  // namespace
 
 int validate_csr(mfe_ctx *ctx, int64_t m, int64_t nnz, const int32_t *ptr, const int32_t *col) {
@@ -432,6 +467,91 @@ int build_csr_tiles(mfe_problem *P) {
     MFE_HIP_TRY(hipMemcpyAsync(&n, total.ptr(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
     MFE_HIP_TRY(hipStreamSynchronize(s));
     P->csr_ctiles = n;
+    return MFE_OK;
+}
+
+// Work items of the CRS group walk of a mesh problem (see CsrRuns): full
+// rows are flagged on the device, the run boundaries compacted and copied
+// to the host, and the items built there in row order: each run of full rows
+// cut into groups of at most 64, the rows between runs gathered into tiles
+// of at most 16, a tile emitted when full (or at the end).
+int build_csr_groups(mfe_problem *P) {
+    P->ncitems = P->ncrows = P->ncgroups = P->ncgroup_rows = 0;
+    if (!MFE_CSR_GROUPS || !P->is_mesh || P->Nx < 2 || P->Ny < 2 || P->Nz < 2) return MFE_OK;
+    mfe_ctx *ctx = P->ctx;
+    hipStream_t s = ctx->stream;
+    const int64_t m = P->m, nx = P->Nx + 1, nxy = nx * (P->Ny + 1);
+    CsrOffsets O{};
+    int k = 0;
+    for (int dz = -1; dz <= 1; ++dz)
+        for (int dy = -1; dy <= 1; ++dy)
+            for (int dx = -1; dx <= 1; ++dx) O.off[k++] = (int32_t)(dx + nx * dy + nxy * dz);
+    for (int i = 0; i < 9; ++i) P->cruns.r[i] = O.off[3 * i];
+    TempBuffer flag(ctx), chg(ctx), pos(ctx), total(ctx), edges(ctx);
+    MFE_TRY(flag.alloc((size_t)m * sizeof(int32_t)));
+    MFE_TRY(chg.alloc((size_t)(m + 1) * sizeof(int32_t)));
+    MFE_TRY(pos.alloc((size_t)(m + 2) * sizeof(int32_t)));
+    MFE_TRY(total.alloc(sizeof(int64_t)));
+    const unsigned g1 = (unsigned)((m + 1 + kBlock - 1) / kBlock);
+    hipLaunchKernelGGL(k_csr_fullflag, dim3(g1), dim3(kBlock), 0, s, m, (const int32_t *)P->ptr.ptr,
+                       (const int32_t *)P->col.ptr, O, (int32_t *)flag.ptr());
+    hipLaunchKernelGGL(k_flag_changes, dim3(g1), dim3(kBlock), 0, s, m, (const int32_t *)flag.ptr(),
+                       (int32_t *)chg.ptr());
+    MFE_HIP_TRY(hipGetLastError());
+    MFE_TRY(scan_counts(ctx, m + 1, (const int32_t *)chg.ptr(), (int32_t *)pos.ptr(), (int64_t *)total.ptr()));
+    int64_t nchg = 0;
+    MFE_HIP_TRY(hipMemcpyAsync(&nchg, total.ptr(), sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    if (nchg == 0) return MFE_OK;  // no full rows
+    MFE_TRY(edges.alloc((size_t)nchg * sizeof(int32_t)));
+    hipLaunchKernelGGL(k_compact_rows, dim3(g1), dim3(kBlock), 0, s, m + 1, (const int32_t *)chg.ptr(),
+                       (const int32_t *)pos.ptr(), (int32_t *)edges.ptr());
+    MFE_HIP_TRY(hipGetLastError());
+    std::vector<int32_t> e((size_t)nchg);
+    MFE_HIP_TRY(hipMemcpyAsync(e.data(), edges.ptr(), nchg * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    if (nchg % 2 != 0) {
+        set_error("internal: unpaired run boundaries of the CRS row groups");
+        return MFE_EINVAL;
+    }
+    std::vector<int32_t> items, rows;  // items as (a, b) pairs
+    std::vector<int32_t> pending;
+    auto flush = [&](bool all) {
+        size_t at = 0;
+        while (pending.size() - at >= 16 || (all && at < pending.size())) {
+            const int n = (int)std::min<size_t>(16, pending.size() - at);
+            items.push_back((int32_t)rows.size());
+            items.push_back(-n);
+            rows.insert(rows.end(), pending.begin() + (long)at, pending.begin() + (long)at + n);
+            at += (size_t)n;
+        }
+        pending.erase(pending.begin(), pending.begin() + (long)at);
+    };
+    int64_t prev_end = 0, ngroups = 0, grows = 0;
+    for (int64_t j = 0; j < nchg; j += 2) {
+        const int64_t rs = e[(size_t)j], re = e[(size_t)j + 1];
+        for (int64_t r = prev_end; r < rs; ++r) pending.push_back((int32_t)r);
+        flush(false);
+        for (int64_t r = rs; r < re; r += 64) {
+            items.push_back((int32_t)r);
+            items.push_back((int32_t)std::min<int64_t>(64, re - r));
+            ++ngroups;
+        }
+        grows += re - rs;
+        prev_end = re;
+    }
+    for (int64_t r = prev_end; r < m; ++r) pending.push_back((int32_t)r);
+    flush(true);
+    MFE_TRY(dev_alloc(ctx, &P->citems, items.size() * sizeof(int32_t)));
+    MFE_TRY(dev_alloc(ctx, &P->crows, std::max<size_t>(rows.size(), 1) * sizeof(int32_t)));
+    MFE_HIP_TRY(hipMemcpyAsync(P->citems.ptr, items.data(), items.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    if (!rows.empty())
+        MFE_HIP_TRY(hipMemcpyAsync(P->crows.ptr, rows.data(), rows.size() * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    P->ncitems = (int64_t)items.size() / 2;
+    P->ncrows = (int64_t)rows.size();
+    P->ncgroups = ngroups;
+    P->ncgroup_rows = grows;
     return MFE_OK;
 }
 

@@ -232,6 +232,82 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
     store_partials<MODE>(d1, d2, partials);
 }
 
+// CRS by row groups (mesh problems, see CsrRuns in common.hpp).  A group of
+// up to 64 consecutive full rows owns a contiguous run of 27 n values: the
+// wavefront stages it in LDS with 16-byte loads, all issued before the first
+// LDS store (the run is read from the 16-byte boundary at or before its
+// start; its end never reaches the matrix's end, whose last row is a corner
+// row outside every group), then lane l sums row r0 + l in ascending column
+// order, nine runs of three consecutive x entries, reading its 27 values from
+// LDS at stride 27 (the lanes' accesses fall into distinct banks).  The other
+// rows (mesh boundary rows) come 16 per wavefront from the row list and are
+// summed by 4 lanes each from global memory.
+constexpr int kCsrgVec = 16;  // bytes per staging load
+
+template <typename T>
+struct CsrgStage {
+    static constexpr int V = kCsrgVec / (int)sizeof(T);        // values per staging load
+    static constexpr int Q = (27 * 64 + V - 1 + 64 * V - 1) / (64 * V);  // staging loads per lane
+    static constexpr int N = Q * 64 * V;                         // LDS values per wavefront
+};
+
+template <typename T, int MODE, bool MNT>
+__global__ __launch_bounds__(kBlock) void k_spmv_csrg(const int32_t *__restrict__ ptr, const int32_t *__restrict__ col,
+                                                      const T *__restrict__ val, const int2 *__restrict__ items,
+                                                      long nitems, const int32_t *__restrict__ rows, CsrRuns R,
+                                                      Epi<T> E, CgState *st, double *partials) {
+    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
+    using S = CsrgStage<T>;
+    typedef T vec_t __attribute__((ext_vector_type(S::V)));
+    __shared__ vec_t sval[kBlock / 64][S::N / S::V];
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    vec_t *sv = sval[wave];
+    const T *svs = (const T *)sv;
+    const long ntiles = (nitems + kBlock / 64 - 1) / (kBlock / 64);
+    double d1 = 0.0, d2 = 0.0;
+    for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
+        const long it = tr.t * (kBlock / 64) + wave;
+        if (it >= nitems) continue;  // wavefront-uniform
+        const int2 item = items[it];
+        if (item.y > 0) {
+            const int64_t r0 = item.x;
+            const int n = item.y;
+            const int32_t lo = ptr[r0];
+            const int pad = lo % S::V;
+            const int nv = (pad + 27 * n + S::V - 1) / S::V;
+            const vec_t *src = (const vec_t *)(val + (lo - pad));
+            vec_t v[S::Q];
+#pragma unroll
+            for (int q = 0; q < S::Q; ++q)
+                if (lane + 64 * q < nv) v[q] = matrix_load<MNT>(src + lane + 64 * q);
+#pragma unroll
+            for (int q = 0; q < S::Q; ++q)
+                if (lane + 64 * q < nv) sv[lane + 64 * q] = v[q];
+            wave_sync();
+            if (lane < n) {
+                const int64_t row = r0 + lane;
+                const T *a = svs + pad + 27 * lane;
+                T sum = 0;
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const T *xp = E.x + row + R.r[i];
+                    sum += a[3 * i] * xp[0];
+                    sum += a[3 * i + 1] * xp[1];
+                    sum += a[3 * i + 2] * xp[2];
+                }
+                finish_row<T, MODE>(E, row, sum, d1, d2);
+            }
+            wave_sync();
+        } else {
+            const int rl = lane >> 2, sub = lane & 3;
+            const int64_t row = rl < -item.y ? rows[item.x + rl] : -1;
+            const T sum = csr_row<T, 4, MNT>(ptr, col, val, row, sub, E.x);
+            if (sub == 0 && row >= 0) finish_row<T, MODE>(E, row, sum, d1, d2);
+        }
+    }
+    store_partials<MODE>(d1, d2, partials);
+}
+
 // ---------------------------------------------------------------- 1x3 BCRS
 
 // One slice per wavefront per tile: slice bounds, column indices, values,
@@ -333,6 +409,18 @@ template <typename T, int MODE, bool MNT>
 int launch_csr_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *partials, hipStream_t s,
                   int *grid_out, int cap) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->val64.ptr : (const T *)P->val32.ptr;
+    if (P->ncitems > 0) {
+        auto kern = k_spmv_csrg<T, MODE, MNT>;
+        const long ntiles = (P->ncitems + kBlock / 64 - 1) / (kBlock / 64);
+        const int grid = grid_for(kern, ntiles, P->ctx->num_cu);
+        MFE_TRY(check_cap(grid, cap));
+        hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, (const int32_t *)P->ptr.ptr,
+                           (const int32_t *)P->col.ptr, val, (const int2 *)P->citems.ptr, (long)P->ncitems,
+                           (const int32_t *)P->crows.ptr, P->cruns, E, st, partials);
+        MFE_HIP_TRY(hipGetLastError());
+        if (grid_out) *grid_out = grid;
+        return MFE_OK;
+    }
 #if MFE_CSR_STREAM
     auto kern = k_spmv_csrs<T, MODE, MNT>;
     const long ntiles = (P->m + (kBlock / 64) * kCsrsRows - 1) / ((kBlock / 64) * kCsrsRows);

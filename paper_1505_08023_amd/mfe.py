@@ -182,6 +182,10 @@ class Problem:
         check(ctx.lib.mfe_problem_csr_layout(handle, *[ctypes.byref(t) for t in v]), "mfe_problem_csr_layout")
         # CRS wavefront tiles: rows per tile, tiles, tiles with descriptor-formed column indices
         self.csr_layout = dict(zip(("tile_rows", "tiles", "compressed_tiles"), (t.value for t in v)))
+        v = [ctypes.c_int64() for _ in range(4)]
+        check(ctx.lib.mfe_problem_csr_groups(handle, *[ctypes.byref(t) for t in v]), "mfe_problem_csr_groups")
+        # CRS group walk of a mesh problem (zeros: the tiles above are walked)
+        self.csr_layout.update(zip(("items", "groups", "group_rows", "other_rows"), (t.value for t in v)))
         ctx.problems.add(self)
         _LIVE.add(self)
 

@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_version_and_error_string():
     lib = _lib.load()
-    assert lib.mfe_version() == 12
+    assert lib.mfe_version() == 13
     assert isinstance(lib.mfe_last_error(), bytes)
 
 
@@ -61,6 +61,7 @@ def test_argument_checks_before_any_device_call():
     assert lib.mfe_problem_info(None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_problem_bcrs13_layout(None, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_problem_csr_layout(None, None, None, None) == _lib.MFE_EINVAL
+    assert lib.mfe_problem_csr_groups(None, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_batch_bcrs13_layout(None, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_problem_export_csr(None, None, None, None, None) == _lib.MFE_EINVAL
     assert lib.mfe_net_loss_grad_energy(None, None, 1, 1, None, None, None, None) == _lib.MFE_EINVAL
