@@ -101,8 +101,10 @@ void free_problem_storage(mfe_problem *P) {
 
 // Derived formats and precisions after the FP64 CRS exists.
 int finish_problem(mfe_problem *P) {
-    MFE_TRY(build_csr_tiles(P));
+    // the wavefront tiles and their descriptors serve the CRS product only
+    // where it does not walk row groups
     MFE_TRY(build_csr_groups(P));
+    if (P->ncitems == 0) MFE_TRY(build_csr_tiles(P));
     if (P->formats & MFE_BCRS13) MFE_TRY(build_bcrs13(P));
     if (P->precisions & MFE_F32) MFE_TRY(cast_values_f32(P));
     MFE_HIP_TRY(hipStreamSynchronize(P->ctx->stream));

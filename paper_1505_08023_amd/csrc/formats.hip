@@ -374,17 +374,29 @@ __global__ __launch_bounds__(kBlock) void k_validate_csr(int64_t m, int64_t nnz,
 }
 
 // flag[i] = 1 when row i holds 27 entries with column i + off[k] (k-th entry).
+// One 64-thread workgroup per 64 rows: their column run is staged in LDS
+// with coalesced loads (a run longer than 27 per row is read in place).
 struct CsrOffsets {
     int32_t off[27];
 };
-__global__ __launch_bounds__(kBlock) void k_csr_fullflag(int64_t m, const int32_t *__restrict__ ptr,
-                                                         const int32_t *__restrict__ col, CsrOffsets O,
-                                                         int32_t *__restrict__ flag) {
-    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(64) void k_csr_fullflag(int64_t m, const int32_t *__restrict__ ptr,
+                                                     const int32_t *__restrict__ col, CsrOffsets O,
+                                                     int32_t *__restrict__ flag) {
+    __shared__ int32_t sc[64 * 27];
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int lane = (int)threadIdx.x;
+    const int64_t r1 = r0 + 64 < m ? r0 + 64 : m;
+    const int32_t lo = ptr[r0], hi = ptr[r1];
+    const bool staged = hi - lo <= 64 * 27;
+    if (staged)
+        for (int32_t j = lane; j < hi - lo; j += 64) sc[j] = col[lo + j];
+    __syncthreads();
+    const int64_t i = r0 + lane;
     if (i >= m) return;
-    const int32_t lo = ptr[i];
-    bool ok = ptr[i + 1] - lo == 27;
-    for (int k = 0; ok && k < 27; ++k) ok = (int64_t)col[lo + k] - i == (int64_t)O.off[k];
+    const int32_t a = ptr[i] - lo;
+    bool ok = ptr[i + 1] - lo - a == 27;
+    for (int k = 0; ok && k < 27; ++k)
+        ok = (int64_t)(staged ? sc[a + k] : col[lo + a + k]) - i == (int64_t)O.off[k];
     flag[i] = ok ? 1 : 0;
 }
 
@@ -493,8 +505,8 @@ int build_csr_groups(mfe_problem *P) {
     MFE_TRY(pos.alloc((size_t)(m + 2) * sizeof(int32_t)));
     MFE_TRY(total.alloc(sizeof(int64_t)));
     const unsigned g1 = (unsigned)((m + 1 + kBlock - 1) / kBlock);
-    hipLaunchKernelGGL(k_csr_fullflag, dim3(g1), dim3(kBlock), 0, s, m, (const int32_t *)P->ptr.ptr,
-                       (const int32_t *)P->col.ptr, O, (int32_t *)flag.ptr());
+    hipLaunchKernelGGL(k_csr_fullflag, dim3((unsigned)((m + 63) / 64)), dim3(64), 0, s, m,
+                       (const int32_t *)P->ptr.ptr, (const int32_t *)P->col.ptr, O, (int32_t *)flag.ptr());
     hipLaunchKernelGGL(k_flag_changes, dim3(g1), dim3(kBlock), 0, s, m, (const int32_t *)flag.ptr(),
                        (int32_t *)chg.ptr());
     MFE_HIP_TRY(hipGetLastError());

@@ -265,24 +265,32 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrg(const int32_t *__restrict_
     const T *svs = (const T *)sv;
     const long ntiles = (nitems + kBlock / 64 - 1) / (kBlock / 64);
     double d1 = 0.0, d2 = 0.0;
-    for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
-        const long it = tr.t * (kBlock / 64) + wave;
-        if (it >= nitems) continue;  // wavefront-uniform
-        const int2 item = items[it];
-        if (item.y > 0) {
-            const int64_t r0 = item.x;
-            const int n = item.y;
-            const int32_t lo = ptr[r0];
-            const int pad = lo % S::V;
+    // one work item: its record and, for a group, its staged values in registers
+    struct Cur {
+        int2 item;
+        int32_t lo;
+        vec_t v[S::Q];
+    };
+    auto fetch = [&](long it, Cur &c) {
+        c.item = items[it];
+        if (c.item.y <= 0) return;
+        c.lo = ptr[c.item.x];
+        const int pad = c.lo % S::V;
+        const int nv = (pad + 27 * c.item.y + S::V - 1) / S::V;
+        const vec_t *src = (const vec_t *)(val + (c.lo - pad));
+#pragma unroll
+        for (int q = 0; q < S::Q; ++q)
+            if (lane + 64 * q < nv) c.v[q] = matrix_load<MNT>(src + lane + 64 * q);
+    };
+    auto process = [&](Cur &c) {
+        if (c.item.y > 0) {
+            const int64_t r0 = c.item.x;
+            const int n = c.item.y;
+            const int pad = c.lo % S::V;
             const int nv = (pad + 27 * n + S::V - 1) / S::V;
-            const vec_t *src = (const vec_t *)(val + (lo - pad));
-            vec_t v[S::Q];
 #pragma unroll
             for (int q = 0; q < S::Q; ++q)
-                if (lane + 64 * q < nv) v[q] = matrix_load<MNT>(src + lane + 64 * q);
-#pragma unroll
-            for (int q = 0; q < S::Q; ++q)
-                if (lane + 64 * q < nv) sv[lane + 64 * q] = v[q];
+                if (lane + 64 * q < nv) sv[lane + 64 * q] = c.v[q];
             wave_sync();
             if (lane < n) {
                 const int64_t row = r0 + lane;
@@ -300,10 +308,19 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrg(const int32_t *__restrict_
             wave_sync();
         } else {
             const int rl = lane >> 2, sub = lane & 3;
-            const int64_t row = rl < -item.y ? rows[item.x + rl] : -1;
+            const int64_t row = rl < -c.item.y ? rows[c.item.x + rl] : -1;
             const T sum = csr_row<T, 4, MNT>(ptr, col, val, row, sub, E.x);
             if (sub == 0 && row >= 0) finish_row<T, MODE>(E, row, sum, d1, d2);
         }
+    };
+    // (issuing the next item's staging loads before the current item's sums,
+    // from a second register set, measured no faster: 0.916 against 0.912 ms)
+    for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
+        const long it = tr.t * (kBlock / 64) + wave;
+        if (it >= nitems) continue;  // wavefront-uniform
+        Cur c;
+        fetch(it, c);
+        process(c);
     }
     store_partials<MODE>(d1, d2, partials);
 }

@@ -79,3 +79,49 @@ def csr_descriptor_tiles_closed_form(Nx, Ny, Nz, R=16):
             hi = lo + Nx - 1
             count += max(0, hi // R - (lo + R - 1) // R)
     return count
+
+
+def csr_groups(ptr, col, m, N):
+    """The CRS product's group walk of a mesh problem, modelled on the
+    oracle's CRS: full rows (27 entries, column - row = the mesh's 27
+    neighbour offsets in ascending order) in runs of consecutive rows, each
+    run cut into groups of at most 64; the other rows packed 16 to an item in
+    row order, an item closed when 16 rows are pending before the next run
+    (or at the end).  Returns (items, groups, group_rows, other_rows), all 0
+    when no row is full."""
+    Nx, Ny, Nz = N
+    nx, nxy = Nx + 1, (Nx + 1) * (Ny + 1)
+    off = np.array([dx + nx * dy + nxy * dz for dz in (-1, 0, 1) for dy in (-1, 0, 1) for dx in (-1, 0, 1)])
+    full = np.zeros(m, bool)
+    cnt = np.diff(ptr)
+    for i in np.nonzero(cnt == 27)[0]:
+        full[i] = np.array_equal(col[ptr[i]:ptr[i] + 27].astype(np.int64) - i, off)
+    items = groups = grows = pending = 0
+    i = 0
+    while i < m:
+        if full[i]:
+            j = i
+            while j < m and full[j]:
+                j += 1
+            items += pending // 16
+            pending %= 16
+            g = (j - i + 63) // 64
+            items += g
+            groups += g
+            grows += j - i
+            i = j
+        else:
+            pending += 1
+            i += 1
+    items += (pending + 15) // 16
+    if grows == 0:
+        return 0, 0, 0, 0  # no full rows: the product walks wavefront tiles instead
+    return items, groups, grows, m - grows
+
+
+def csr_groups_closed_form(Nx, Ny, Nz):
+    """Box mesh: one run of Nx - 1 full rows per interior x-line, so
+    ceil((Nx - 1) / 64) groups each and (Nx-1)(Ny-1)(Nz-1) group rows."""
+    if min(Nx, Ny, Nz) < 2:
+        return 0, 0
+    return (Ny - 1) * (Nz - 1) * ((Nx - 1 + 63) // 64), (Nx - 1) * (Ny - 1) * (Nz - 1)

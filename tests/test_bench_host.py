@@ -80,3 +80,34 @@ def test_multi_gpu_request_is_refused(monkeypatch, capsys):
         bench.main()
     assert e.value.code == 2
     assert "one GPU" in capsys.readouterr().err
+
+
+def test_algorithmic_bytes_at_256_cubed():
+    """The roofline's bytes: every index read, row pointers counted as for
+    CRS (12 nnz + 4 (m+1) + 16 m for CRS FP64; 28 nb + 4 (m+1) + 16 m for the
+    1x3 BCRS FP64; values at 4 bytes for FP32)."""
+    m, nnz, nb = 257 ** 3, 769 ** 3, 257 * 769 ** 2
+    assert bench.algorithmic_bytes("bcrs13", m, nnz, nb) == 28 * nb + 4 * (m + 1) + 16 * m == 4_594_925_620
+    assert bench.algorithmic_bytes("csr", m, nnz, nb) == 5_796_571_172
+    assert bench.algorithmic_bytes("csr", m, nnz, nb, fp=4) == 8 * nnz + 4 * (m + 1) + 8 * m
+    assert bench.algorithmic_bytes("bcrs13", m, nnz, nb, fp=4) == 16 * nb + 4 * (m + 1) + 8 * m
+
+
+def test_csr_group_walk_bytes_and_closed_form():
+    """The CRS group walk's moved bytes at 256^3 (every value, 8 bytes per
+    work item, 4 per group, 12 per other row and 4 per entry of the other
+    rows, x and y once), with the group counts of the closed form checked
+    against the model over the oracle's CRS on small meshes."""
+    for N in ((20, 20, 20), (33, 33, 33), (40, 9, 6), (70, 3, 4), (65, 5, 5)):
+        A = oracle.assemble(*N)
+        items, groups, grows, other = b13_model.csr_groups(A.ptr, A.col, A.m, N)
+        assert (groups, grows) == b13_model.csr_groups_closed_form(*N), N
+        assert grows + other == A.m
+    m, nnz = 257 ** 3, 769 ** 3
+    groups, grows = b13_model.csr_groups_closed_form(256, 256, 256)
+    assert (groups, grows) == (255 * 255 * 4, 255 ** 3)
+    other = m - grows
+    lay = dict(items=groups + (other + 15) // 16, groups=groups, group_rows=grows, other_rows=other)
+    by = bench.spmv_bytes("csr", m, nnz, 0, layout=lay)
+    assert by == 8 * nnz + 8 * lay["items"] + 4 * groups + 12 * other + 4 * (nnz - 27 * grows) + 16 * m
+    assert by < bench.spmv_bytes("csr", m, nnz, 0)

@@ -116,10 +116,12 @@ def test_bcrs13_descriptor_slices(ctx, N):
     assert (lay["compressed_slices"], lay["compressed_blocks"]) == want, (lay, want)
     if min(N) >= 20:
         assert lay["compressed_slices"] >= 0.5 * lay["slices"]
-    # CRS wavefront tiles with descriptors
+    # the CRS group walk (index work: bit-exact counts against the host model
+    # and, for the groups, the closed form)
     cl = P.csr_layout
-    assert cl["tiles"] == (A.m + cl["tile_rows"] - 1) // cl["tile_rows"]
-    assert cl["compressed_tiles"] == b13_model.csr_descriptor_tiles(A.ptr, A.col, A.m, cl["tile_rows"])
+    want = b13_model.csr_groups(A.ptr, A.col, A.m, N)
+    assert (cl["items"], cl["groups"], cl["group_rows"], cl["other_rows"]) == want, (cl, want)
+    assert (cl["groups"], cl["group_rows"]) == b13_model.csr_groups_closed_form(*N)
     x = inputs.spmv_vector(A.m, seed=3)
     for fmt in ("bcrs13", "csr"):
         check_spmv(np_(P.spmv(torch.tensor(x, device=ctx.device), fmt=fmt)), A, x, oracle.csr_spmv(A, x))
@@ -230,8 +232,9 @@ def test_spmv_full_size_sampled_rows(ctx, fmt):
         assert P.b13_layout["compressed_slices"] == b13_model.descriptor_slices_closed_form(*N)
         assert P.b13_layout["compressed_blocks"] == 576 * P.b13_layout["compressed_slices"]
     else:
-        R = P.csr_layout["tile_rows"]
-        assert P.csr_layout["compressed_tiles"] == b13_model.csr_descriptor_tiles_closed_form(*N, R=R)
+        cl = P.csr_layout
+        assert (cl["groups"], cl["group_rows"]) == b13_model.csr_groups_closed_form(*N)
+        assert cl["other_rows"] == m - cl["group_rows"] and cl["compressed_tiles"] == 0
     x = inputs.spmv_vector(m, seed=0)
     y = np_(P.spmv(torch.tensor(x, device=ctx.device), fmt=fmt))
     rng = np.random.default_rng(7)
