@@ -447,9 +447,25 @@ def extras(args, ctx, P, x, line, torch):
     # batched uneven solves: 64 meshes, Nx, Ny, Nz ~ U{16..96}, seed 0, to 1e-8 each
     sizes, faces = inputs.batched_meshes(nsys=64, lo=16, hi=96, seed=0)
     B = Batch(ctx, sizes, faces, precisions=("f64", "f32"))
-    lanes, factor = B.autotune(args.fmt)
-    bat = {"systems": 64, "rows": B.m, "nnz": B.nnz, "autotune": {"lanes_per_row": lanes, "grid_factor": factor}}
     xb = torch.zeros(B.m, dtype=torch.float64, device=ctx.device)
+
+    def batch_fp64_seconds():
+        for _ in range(2):  # warm-up (graph capture), then timed
+            with torch.cuda.stream(ctx.stream):
+                xb.zero_()
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            B.cg(xb, tol=1e-8, fmt=args.fmt)
+            torch.cuda.synchronize()
+        return time.perf_counter() - t
+    t_default = batch_fp64_seconds()
+    lanes, factor = B.autotune(args.fmt)
+    shape = ({"slices_per_wavefront": lanes, "rows_per_wavefront": 64 * lanes} if args.fmt == "bcrs13"
+             else {"lanes_per_row": lanes, "rows_per_wavefront": 64 // lanes})
+    bat = {"systems": 64, "rows": B.m, "nnz": B.nnz,
+           "autotune": {**shape, "grid_factor": factor, "fp64_seconds_untuned": t_default,
+                        "untuned_shape": "1 slice per wavefront, grid 1 x resident" if args.fmt == "bcrs13"
+                        else "32 lanes per row, grid 1 x resident"}}
     xbr = torch.zeros_like(xb)
     B.cg(xbr, tol=1e-10, fmt=args.fmt)
     offs = B.row_offsets.tolist()
@@ -488,6 +504,7 @@ def extras(args, ctx, P, x, line, torch):
             bat[name]["algorithmic_bytes"] = tot
             bat[name]["effective_GBps"] = tot / dt / 1e9
         log(f"[bench] batched {name}: {bat[name]}")
+    bat["autotune"]["gain_fp64"] = t_default / bat["fp64"]["seconds"]
     line["batched_64_meshes_1e-8"] = bat
     B.close()
 

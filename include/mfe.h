@@ -395,10 +395,13 @@ int mfe_batch_bcrs13_layout(const mfe_batch *b, int64_t *slices, int64_t *slots,
                             int64_t *compressed_blocks);
 /* FP64 CRS of the block-diagonal matrix and b (device buffers, as mfe_problem_export_csr). */
 int mfe_batch_export_csr(const mfe_batch *b, int32_t *ptr_dev, int32_t *col_dev, double *val_dev, double *b_dev);
-/* Times the batched SpMV for each candidate launch shape (CRS lanes per row
- * 8/16/32, i.e. rows per wavefront 8/4/2, and grid = 1, 2 or 4 times the
- * resident workgroups) on this batch and keeps the fastest for later solves
- * in `format`.  *lanes_out / *factor_out (may be NULL) receive the choice. */
+/* Times the batched SpMV for each candidate launch shape (CRS: lanes per row
+ * 8/16/32, i.e. rows per wavefront 8/4/2; 1x3 BCRS: one lane per row and
+ * 1 or 2 64-row slices per wavefront and pass, i.e. rows per wavefront
+ * 64/128; both with grid = 1, 2 or 4 times the resident workgroups) on this
+ * batch and keeps the fastest for later solves in `format`.  *lanes_out
+ * (CRS lanes per row, or 1x3 BCRS slices per wavefront) and *factor_out (may
+ * be NULL) receive the choice. */
 int mfe_batch_autotune(mfe_batch *b, int format, int *lanes_out, int *factor_out);
 /* FP64 CG on every system from x_dev (length m_total): per system stop at
  * ||r||/||b|| <= tol or max_iter iterations.  stats: host array of nsys.

@@ -80,31 +80,41 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
     };
     if (FMT == MFE_BCRS13) {
         // the 64-row slices overlapping [lo, hi) (system offsets are not
-        // slice aligned), one per wavefront per pass; rows outside [lo, hi)
-        // belong to the neighbouring workgroup.  The next pass's column
-        // indices are requested before this pass's values and gathers.
+        // slice aligned), L per wavefront per pass (wavefront w takes slices
+        // sb + w, sb + w + 4, ...: rows per wavefront 64 L); rows outside
+        // [lo, hi) belong to the neighbouring workgroup.  The next pass's
+        // column indices are requested before this pass's values and gathers.
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
         const int64_t s_lo = lo >> 6, s_hi = (hi + 63) >> 6;
-        constexpr int SP = kBlock / 64;  // slices per pass
-        B13Idx cur, nxt;
-        auto fetch = [&](int64_t sb, B13Idx &r) {
-            const int64_t sl = sb + wave, row = sl * 64 + lane;
-            r.sl.S = 0;
-            if (sl >= s_hi) return;
-            r.sl = b13_slice(slot_base[sl], slot_base[sl + 1]);
-            if (row >= lo && row < hi) b13_cols(jas, desc, sl, lane, r);
+        constexpr int W = kBlock / 64;
+        constexpr int SP = W * L;  // slices per pass
+        B13Idx cur[L], nxt[L];
+        auto fetch = [&](int64_t sb, B13Idx *r) {
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                const int64_t sl = sb + j * W + wave, row = sl * 64 + lane;
+                r[j].sl.S = 0;
+                if (sl >= s_hi) continue;
+                r[j].sl = b13_slice(slot_base[sl], slot_base[sl + 1]);
+                if (row >= lo && row < hi) b13_cols(jas, desc, sl, lane, r[j]);
+            }
         };
         if (s_lo < s_hi) fetch(s_lo, cur);
         for (int64_t sb = s_lo; sb < s_hi; sb += SP) {
-            nxt.sl.S = 0;
+#pragma unroll
+            for (int j = 0; j < L; ++j) nxt[j].sl.S = 0;
             if (sb + SP < s_hi) fetch(sb + SP, nxt);
-            const int64_t row = (sb + wave) * 64 + lane;
-            if (sb + wave < s_hi && row >= lo && row < hi) {
-                const T sum = cur.sl.S == 9 ? b13_row9_idx(cur.c, bval, cur.sl, lane, x)
-                                            : b13_row_generic(jas, bval, cur.sl, lane, x);
-                emit(row, sum);
+#pragma unroll
+            for (int j = 0; j < L; ++j) {
+                const int64_t sl = sb + j * W + wave, row = sl * 64 + lane;
+                if (sl < s_hi && row >= lo && row < hi) {
+                    const T sum = cur[j].sl.S == 9 ? b13_row9_idx(cur[j].c, bval, cur[j].sl, lane, x)
+                                                   : b13_row_generic(jas, bval, cur[j].sl, lane, x);
+                    emit(row, sum);
+                }
             }
-            cur = nxt;
+#pragma unroll
+            for (int j = 0; j < L; ++j) cur[j] = nxt[j];
         }
     } else {
         constexpr int R = kBlock / L;  // rows per pass
@@ -316,7 +326,8 @@ const void *bspmv_kernel() {
 }
 
 int resident_for(int format, int lanes) {
-    const void *k = format == MFE_BCRS13 ? bspmv_kernel<double, MFE_BCRS13, 1, kSpmvDot>()
+    const void *k = format == MFE_BCRS13 ? (lanes == 2 ? bspmv_kernel<double, MFE_BCRS13, 2, kSpmvDot>()
+                                                       : bspmv_kernel<double, MFE_BCRS13, 1, kSpmvDot>())
                     : lanes == 8        ? bspmv_kernel<double, MFE_CSR, 8, kSpmvDot>()
                     : lanes == 16       ? bspmv_kernel<double, MFE_CSR, 16, kSpmvDot>()
                                         : bspmv_kernel<double, MFE_CSR, 32, kSpmvDot>();
@@ -394,7 +405,8 @@ int bspmv(const mfe_batch *B, int format, const Tuning &t, const void *x, void *
           CgState *st, double *part, hipStream_t s) {
     const T *xx = (const T *)x;
     T *yy = (T *)y, *pp = (T *)pout;
-    if (format == MFE_BCRS13) launch_b<T, MFE_BCRS13, 1, MODE>(B, xx, yy, pp, b, st, part, s);
+    if (format == MFE_BCRS13 && t.lanes == 2) launch_b<T, MFE_BCRS13, 2, MODE>(B, xx, yy, pp, b, st, part, s);
+    else if (format == MFE_BCRS13) launch_b<T, MFE_BCRS13, 1, MODE>(B, xx, yy, pp, b, st, part, s);
     else if (t.lanes == 8) launch_b<T, MFE_CSR, 8, MODE>(B, xx, yy, pp, b, st, part, s);
     else if (t.lanes == 16) launch_b<T, MFE_CSR, 16, MODE>(B, xx, yy, pp, b, st, part, s);
     else launch_b<T, MFE_CSR, 32, MODE>(B, xx, yy, pp, b, st, part, s);
@@ -873,15 +885,19 @@ int mfe_batch_autotune(mfe_batch *B, int format, int *lanes_out, int *factor_out
         return MFE_EINVAL;
     }
     if (hipSetDevice(B->ctx->device) != hipSuccess) return MFE_EHIP;
+    // CRS: lanes per row 8 / 16 / 32 (rows per wavefront 8 / 4 / 2);
+    // 1x3 BCRS: one lane per row, slices per wavefront and pass 1 / 2 (rows
+    // per wavefront 64 / 128); both with grids of 1, 2, 4 x resident
     static const int lanes_c[3] = {8, 16, 32};
+    static const int slices_b[2] = {1, 2};
     static const int factors[3] = {1, 2, 4};
     Tuning best{};
     double best_ms = 1e300;
-    for (int li = 0; li < 3; ++li) {
-        if (format == MFE_BCRS13 && li > 0) break;  // one lane per row
+    const int nl = format == MFE_BCRS13 ? 2 : 3;
+    for (int li = 0; li < nl; ++li) {
         for (int fi = 0; fi < 3; ++fi) {
             Tuning t;
-            t.lanes = format == MFE_BCRS13 ? 1 : lanes_c[li];
+            t.lanes = format == MFE_BCRS13 ? slices_b[li] : lanes_c[li];
             t.factor = factors[fi];
             double ms = 0;
             MFE_TRY(time_spmv(B, format, t, &ms));

@@ -94,7 +94,7 @@ def test_batch_autotune_and_resolve(ctx, fmt):
     B = Batch(ctx, sizes, faces)
     lanes, factor = B.autotune(fmt)
     assert factor in (1, 2, 4)
-    assert lanes in ((8, 16, 32) if fmt == "csr" else (1,))
+    assert lanes in ((8, 16, 32) if fmt == "csr" else (1, 2))
     x, stats = B.cg(tol=1e-8, max_iter=2000, fmt=fmt)
     x = x.cpu().numpy()
     for j, (N, fv) in enumerate(zip(sizes, faces)):
