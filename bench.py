@@ -656,10 +656,26 @@ def guess_at_scale(args, ctx, P, x, net, torch):
         ctx.prolong(x64, (64, 64, 64), f, bnd=b, xf=x)
         return P.cg(x, tol=1e-8, max_iter=args.max_iter, fmt=args.fmt, warm=True)[1]
 
+    # the same guesses followed by the FP32-inner / FP64-refinement solve that
+    # keeps its inner direction (the learned + mixed-precision form)
+    def learned_mixed():
+        net.predict_x0(g64, x64)
+        ctx.prolong(x64, (64, 64, 64), f, bnd=b, xf=x)
+        return P.cg_mixed(x, tol=1e-8, inner_tol=KEEP_INNER_TOL, fmt=args.fmt, warm=True, keep_direction=True)[1]
+
+    def coarse_mixed():
+        with torch.cuda.stream(ctx.stream):
+            x64.zero_()
+        P64.cg(x64, tol=1e-8, max_iter=args.max_iter, fmt=args.fmt)
+        ctx.prolong(x64, (64, 64, 64), f, bnd=b, xf=x)
+        return P.cg_mixed(x, tol=1e-8, inner_tol=KEEP_INNER_TOL, fmt=args.fmt, warm=True, keep_direction=True)[1]
+
     out = {"mesh": [n, n, n], "boundary_data": "paper (u = 1 on x = 1, 0 elsewhere)",
            "error_reference": "FP64 CG to 1e-10"}
     for name, fn in (("zero_start", zero), ("learned_64cubed_guess_prolonged", learned),
-                     ("cg_64cubed_solution_prolonged", coarse)):
+                     ("cg_64cubed_solution_prolonged", coarse),
+                     ("learned_64cubed_guess_prolonged_mixed_keep_direction", learned_mixed),
+                     ("cg_64cubed_solution_prolonged_mixed_keep_direction", coarse_mixed)):
         fn()  # warm-up (graph capture)
         torch.cuda.synchronize()
         t = time.perf_counter()
@@ -670,7 +686,7 @@ def guess_at_scale(args, ctx, P, x, net, torch):
                          guess_rejected=st["guess_rejected"], error_vs_fp64=float(torch.linalg.norm(x - xr)) / nr)
         if name != "zero_start":
             # the guess's own residual, untimed
-            if name == "learned_64cubed_guess_prolonged":
+            if name.startswith("learned"):
                 net.predict_x0(g64, x64)
             else:
                 with torch.cuda.stream(ctx.stream):
