@@ -35,6 +35,7 @@ MEASURED_TRAFFIC = {("bcrs13", 256): (4.007e9, "profiles/spmv_b13_fp64_256cubed_
 PAPER_CONTEXT = ("Wu et al. report no absolute times; BCRS over CRS on their CPU server: SpMV +10.42 %, CG "
                  "+10.56 %, whole program +8.31 % on average (best +16.30 %, worst +1.50 %)")
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
+CG_ITERS_256 = 399  # FP64 CG iterations to 1e-8 of the 256^3 paper problem (measured on the GPU)
 # inner tolerance of the mixed-precision refinement that keeps the inner CG
 # direction (the fastest of 1e-1 ... 1e-4 at 256^3, to 1e-10 and to 1e-8)
 KEEP_INNER_TOL = 1e-2
@@ -180,6 +181,22 @@ def cpu_baseline(N, its=(2, 42), its_omp=(4, 204)):
                                           sample=f"{its_omp[1] - its_omp[0]} iterations, the same loops with "
                                                  f"OpenMP over {threads} threads, gcc -O3 -march=native -fopenmp")
         log(f"[bench] oracle -O3 -march=native, {threads} threads: {1.0 / sm:.3f} it/s")
+        # the CRS product alone (median of 10, x ~ U[-1, 1) as on the GPU) and
+        # the time to 1e-8 extrapolated from the iteration rate
+        from paper_1505_08023_amd import inputs
+        xv = inputs.spmv_vector(A.m, seed=0)
+        for lib, key in ((native, "native_O3_one_core"), (omp, "native_O3_all_cores")):
+            ts = []
+            for _ in range(10):
+                t = time.perf_counter()
+                oracle.csr_spmv(A, xv, library=lib)
+                ts.append(time.perf_counter() - t)
+            ms = sorted(ts)[5] * 1e3
+            out[key]["spmv_ms"] = ms
+            out[key]["spmv_GBps"] = algorithmic_bytes("csr", A.m, A.nnz, 0) / (ms * 1e-3) / 1e9
+        out["native_O3_all_cores"]["time_to_1e-8_s_extrapolated"] = CG_ITERS_256 * sm
+        out["native_O3_all_cores"]["extrapolation"] = (f"{CG_ITERS_256} iterations (the GPU solve's count) x the "
+                                                       "measured seconds per iteration")
     except (OSError, subprocess.CalledProcessError) as e:
         out["native_builds_error"] = str(e)
     return out

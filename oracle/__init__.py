@@ -185,11 +185,12 @@ def assemble_rows(Nx, Ny, Nz, rows, face_vals=None, node_g=None):
     return out, b
 
 
-def csr_spmv(A, x):
-    """y = A x over CRS, summed in ascending column order (Fig 3.1)."""
+def csr_spmv(A, x, library=None):
+    """y = A x over CRS, summed in ascending column order (Fig 3.1).
+    library: a timing build (load_timing_build) instead of the oracle's own."""
     x = np.ascontiguousarray(x, np.float64)
     y = np.empty(A.m)
-    lib().orc_csr_spmv(A.m, A.ptr, A.col, A.val, x, y)
+    (library or lib()).orc_csr_spmv(A.m, A.ptr, A.col, A.val, x, y)
     return y
 
 
