@@ -339,29 +339,110 @@ void release_batch_graphs(mfe_batch *B) {
     B->graphs.clear();
 }
 
-// Workgroup -> (system, row chunk) map for a grid of about `target` groups.
-int build_map(mfe_batch *B, int format, const Tuning &t) {
-    if (B->nwg > 0 && B->map_format == format && B->map_tuning.lanes == t.lanes && B->map_tuning.factor == t.factor)
-        return MFE_OK;
-    mfe_ctx *ctx = B->ctx;
-    const int64_t mt = B->row0[B->nsys];
-    const long target = (long)ctx->num_cu * resident_for(format, t.lanes) * t.factor;
-    std::vector<int32_t> wsys, swg(B->nsys + 1);
+struct MapPlan {
+    std::vector<int32_t> wsys, swg;
     std::vector<int64_t> wlo, whi;
+};
+
+// Workgroup -> (system, row chunk) map of every system for a grid of about
+// `target` groups, in proportion to rows (chunks of whole 64-row slices).
+MapPlan plan_full(const mfe_batch *B, long target) {
+    MapPlan m;
+    m.swg.resize(B->nsys + 1);
+    const int64_t mt = B->row0[B->nsys];
     for (int j = 0; j < B->nsys; ++j) {
         const int64_t mj = B->row0[j + 1] - B->row0[j];
         int64_t gj = (int64_t)std::llround((double)target * (double)mj / (double)mt);
         if (gj < 1) gj = 1;
         int64_t chunk = (mj + gj - 1) / gj;
         chunk = (chunk + 63) / 64 * 64;
-        swg[j] = (int32_t)wsys.size();
+        m.swg[j] = (int32_t)m.wsys.size();
         for (int64_t a = 0; a < mj; a += chunk) {
-            wsys.push_back(j);
-            wlo.push_back(B->row0[j] + a);
-            whi.push_back(B->row0[j] + std::min(mj, a + chunk));
+            m.wsys.push_back(j);
+            m.wlo.push_back(B->row0[j] + a);
+            m.whi.push_back(B->row0[j] + std::min(mj, a + chunk));
         }
     }
-    swg[B->nsys] = (int32_t)wsys.size();
+    m.swg[B->nsys] = (int32_t)m.wsys.size();
+    return m;
+}
+
+// The same grid of exactly nwg workgroups spread over the systems with
+// on[j] set only, in proportion to their rows (at least one each; a
+// workgroup may get an empty chunk); the other systems get none, so the
+// iteration kernels leave them untouched.  Needs nwg >= the number of
+// systems on.
+MapPlan plan_active(const mfe_batch *B, int nwg, const std::vector<char> &on) {
+    const int ns = B->nsys;
+    std::vector<int64_t> g(ns, 0);
+    int64_t ma = 0;
+    for (int j = 0; j < ns; ++j)
+        if (on[j]) ma += B->row0[j + 1] - B->row0[j];
+    int64_t used = 0;
+    for (int j = 0; j < ns; ++j)
+        if (on[j]) {
+            g[j] = std::max<int64_t>(1, (int64_t)((double)nwg * (double)(B->row0[j + 1] - B->row0[j]) / (double)ma));
+            used += g[j];
+        }
+    // the rounding left over goes to (or comes from) the systems in order of size
+    std::vector<int> order;
+    for (int j = 0; j < ns; ++j)
+        if (on[j]) order.push_back(j);
+    std::sort(order.begin(), order.end(), [&](int a, int b) {
+        return B->row0[a + 1] - B->row0[a] > B->row0[b + 1] - B->row0[b];
+    });
+    for (size_t i = 0; used < nwg; i = (i + 1) % order.size(), ++used) ++g[order[i]];
+    for (size_t i = 0; used > nwg; i = (i + 1) % order.size())
+        if (g[order[i]] > 1) {
+            --g[order[i]];
+            --used;
+        }
+    MapPlan m;
+    m.swg.resize(ns + 1);
+    for (int j = 0; j < ns; ++j) {
+        m.swg[j] = (int32_t)m.wsys.size();
+        const int64_t mj = B->row0[j + 1] - B->row0[j];
+        if (g[j] == 0) continue;
+        int64_t chunk = (mj + g[j] - 1) / g[j];
+        chunk = (chunk + 63) / 64 * 64;
+        for (int64_t i = 0; i < g[j]; ++i) {
+            m.wsys.push_back(j);
+            m.wlo.push_back(B->row0[j] + std::min(mj, i * chunk));
+            m.whi.push_back(B->row0[j] + std::min(mj, (i + 1) * chunk));
+        }
+    }
+    m.swg[ns] = (int32_t)m.wsys.size();
+    return m;
+}
+
+// Upload a plan of B->nwg workgroups into the map buffers (graphs keep their grid).
+int upload_map(mfe_batch *B, const MapPlan &m) {
+    const int nwg = (int)m.wsys.size();
+    if (nwg != B->nwg) {
+        set_error("internal: a workgroup map of another grid size");
+        return MFE_EINVAL;
+    }
+    hipStream_t s = B->ctx->stream;
+    MFE_HIP_TRY(hipMemcpyAsync(B->wg_sys.ptr, m.wsys.data(), nwg * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipMemcpyAsync(B->wg_lo.ptr, m.wlo.data(), nwg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipMemcpyAsync(B->wg_hi.ptr, m.whi.data(), nwg * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipMemcpyAsync(B->sys_wg.ptr, m.swg.data(), (B->nsys + 1) * sizeof(int32_t), hipMemcpyHostToDevice, s));
+    MFE_HIP_TRY(hipStreamSynchronize(s));
+    return MFE_OK;
+}
+
+long map_target(const mfe_batch *B, int format, const Tuning &t) {
+    return (long)B->ctx->num_cu * resident_for(format, t.lanes) * t.factor;
+}
+
+// Workgroup -> (system, row chunk) map for a grid of about `target` groups.
+int build_map(mfe_batch *B, int format, const Tuning &t) {
+    if (B->nwg > 0 && B->map_format == format && B->map_tuning.lanes == t.lanes && B->map_tuning.factor == t.factor)
+        return MFE_OK;
+    mfe_ctx *ctx = B->ctx;
+    const MapPlan plan = plan_full(B, map_target(B, format, t));
+    const std::vector<int32_t> &wsys = plan.wsys, &swg = plan.swg;
+    const std::vector<int64_t> &wlo = plan.wlo, &whi = plan.whi;
     const int nwg = (int)wsys.size();
     if (nwg > B->nwg || !B->wg_sys.ptr) {
         dev_free(ctx, &B->wg_sys);
@@ -524,19 +605,56 @@ bool any_running(const std::vector<CgState> &v) {
     return false;
 }
 
-// Replay the iteration graph until no system runs.
+#ifndef MFE_BATCH_REMAP
+#define MFE_BATCH_REMAP 1  // spread the grid over the running systems only once their rows fall below 60 %
+#endif
+
+// Replay the iteration graph until no system runs.  Once the running
+// systems hold at most 60 % of the rows the grid is spread over, the same
+// grid is spread over them alone (the graphs keep their launch shape and read
+// the map at replay), so the systems that remain take the whole GPU; the
+// full map is restored at the end.
 int run_batch(mfe_batch *B, hipGraphExec_t exec, const CgState *st, int k, int max_iter, std::vector<CgState> &fin) {
     hipStream_t s = B->ctx->stream;
     const long limit = (long)max_iter / k + 2;
+    int64_t spread = B->row0[B->nsys];  // rows the current map spreads the grid over
+    bool partial = false;
+    int rc = MFE_OK;
     for (long launched = 0;; ++launched) {
         if (launched > limit) {
             set_error("batched CG still running after the iteration cap");
-            return MFE_EHIP;
+            rc = MFE_EHIP;
+            break;
         }
-        MFE_HIP_TRY(hipGraphLaunch(exec, s));
-        MFE_TRY(read_states(B, st, fin));
-        if (!any_running(fin)) return MFE_OK;
+        if (hipGraphLaunch(exec, s) != hipSuccess) {
+            set_error("hipGraphLaunch failed");
+            rc = MFE_EHIP;
+            break;
+        }
+        rc = read_states(B, st, fin);
+        if (rc != MFE_OK || !any_running(fin)) break;
+        if (MFE_BATCH_REMAP) {
+            std::vector<char> on(B->nsys, 0);
+            int64_t active = 0, nact = 0;
+            for (int j = 0; j < B->nsys; ++j)
+                if (fin[j].status == kRunning) {
+                    on[j] = 1;
+                    active += B->row0[j + 1] - B->row0[j];
+                    ++nact;
+                }
+            if (active * 10 <= spread * 6 && nact <= B->nwg) {
+                rc = upload_map(B, plan_active(B, B->nwg, on));
+                if (rc != MFE_OK) break;
+                spread = active;
+                partial = true;
+            }
+        }
     }
+    if (partial) {
+        const int r2 = upload_map(B, plan_full(B, map_target(B, B->map_format, B->map_tuning)));
+        if (rc == MFE_OK) rc = r2;
+    }
+    return rc;
 }
 
 // FP64 batched CG on all systems from x.  out_states: final states.
