@@ -28,14 +28,13 @@ HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 # and WRITE_SIZE (x 1.0) counter runs, scaled by streaming kernels of known
 # size; taken from the profile named beside each, not in this run.  Reset to
 # None whenever the kernel changes.
-MEASURED_TRAFFIC = {("bcrs13", 256): (4.007e9, "profiles/spmv_b13_fp64_256cubed_hbm_counters.md"),
-                    ("csr", 256): (4.252e9, "profiles/spmv_b13_fp64_256cubed_hbm_counters.md")}
+MEASURED_TRAFFIC = {("bcrs13", 256): (4.318e9, "profiles/spmv_b13_fp64_256cubed_hbm_counters.md"),
+                    ("csr", 256): (4.293e9, "profiles/spmv_b13_fp64_256cubed_hbm_counters.md")}
 # The paper's own gains of the BCRS format over CRS on its CPU server (it
 # prints no absolute numbers): context, not a target.
 PAPER_CONTEXT = ("Wu et al. report no absolute times; BCRS over CRS on their CPU server: SpMV +10.42 %, CG "
                  "+10.56 %, whole program +8.31 % on average (best +16.30 %, worst +1.50 %)")
 METRIC = "SpMV GB/s & %HBM peak, CG iter/s at 256³; time-to-1e-8 learned vs plain"
-CG_ITERS_256 = 399  # FP64 CG iterations to 1e-8 of the 256^3 paper problem (measured on the GPU)
 # inner tolerance of the mixed-precision refinement that keeps the inner CG
 # direction (the fastest of 1e-1 ... 1e-4 at 256^3, to 1e-10 and to 1e-8)
 KEEP_INNER_TOL = 1e-2
@@ -149,11 +148,12 @@ def time_oracle_cg(A, its, library=None):
     return (times[1] - times[0]) / (its[1] - its[0])
 
 
-def cpu_baseline(N, its=(2, 42), its_omp=(4, 204)):
+def cpu_baseline(N, gpu_iters, its=(2, 42), its_omp=(4, 204)):
     """The oracle's CG on the host (assembly untimed): as it stands (the
     plain single-threaded build), and for context the same source built on
     this host with -O3 -march=native, single-threaded and with its loops over
-    all the cores OpenMP is given."""
+    all the cores OpenMP is given.  gpu_iters: the iterations of the GPU
+    solve, from which the time to the tolerance is extrapolated."""
     import tempfile
 
     import oracle
@@ -194,8 +194,8 @@ def cpu_baseline(N, its=(2, 42), its_omp=(4, 204)):
             ms = sorted(ts)[5] * 1e3
             out[key]["spmv_ms"] = ms
             out[key]["spmv_GBps"] = algorithmic_bytes("csr", A.m, A.nnz, 0) / (ms * 1e-3) / 1e9
-        out["native_O3_all_cores"]["time_to_1e-8_s_extrapolated"] = CG_ITERS_256 * sm
-        out["native_O3_all_cores"]["extrapolation"] = (f"{CG_ITERS_256} iterations (the GPU solve's count) x the "
+        out["native_O3_all_cores"]["time_to_1e-8_s_extrapolated"] = gpu_iters * sm
+        out["native_O3_all_cores"]["extrapolation"] = (f"{gpu_iters} iterations (the GPU solve's count) x the "
                                                        "measured seconds per iteration")
     except (OSError, subprocess.CalledProcessError) as e:
         out["native_builds_error"] = str(e)
@@ -294,7 +294,7 @@ def main():
                      "frac": dom["GBps"] / HBM_PEAK_GBS,
                      "traffic": (MEASURED_TRAFFIC.get((args.fmt, N)) or (None, None))[0],
                      "traffic_source": (MEASURED_TRAFFIC.get((args.fmt, N)) or (None, None))[1],
-                     "kernel": "k_spmv_b13p<double, dot>" if args.fmt == "bcrs13" else "k_spmv_csrs<double, dot>",
+                     "kernel": "k_spmv_b13s<double, dot>" if args.fmt == "bcrs13" else "k_spmv_csrg<double, dot>",
                      "timing": "HIP events around each launch on the library stream, 1 GiB of other memory "
                                "written before each, as between two products of a CG iteration",
                      "bytes_per_launch": dom["bytes"],
@@ -326,7 +326,7 @@ def main():
         extras(args, ctx, P, x, line, torch)
     if not args.no_cpu_baseline:
         log("[bench] CPU oracle baseline (bounded sample) ...")
-        line["cpu_baseline"] = cpu_baseline(N)
+        line["cpu_baseline"] = cpu_baseline(N, stats[-1]["iterations"])
         log(f"[bench] oracle {line['cpu_baseline']['value']:.3f} it/s")
     print(json.dumps(line), flush=True)
 

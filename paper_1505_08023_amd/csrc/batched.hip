@@ -63,18 +63,21 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
     }
     const int64_t lo = M.wg_lo[w], hi = M.wg_hi[w];
     double d1 = 0.0, d2 = 0.0;
-    auto emit = [&](int64_t row, T sum) {
+    // the row's epilogue operand (x[row] or b[row]) is loaded before its
+    // gathers, not after the y store (which would add a memory round trip)
+    auto operand = [&](int64_t row) -> double { return MODE == kSpmvDot ? (double)x[row] : b[row]; };
+    auto emit = [&](int64_t row, T sum, double opnd) {
         if (MODE == kSpmvDot) {
             y[row] = sum;
-            d1 += (double)x[row] * (double)sum;
+            d1 += opnd * (double)sum;
         } else if (MODE == kSpmvResid) {
-            const double bi = b[row], r = bi - (double)sum;
+            const double bi = opnd, r = bi - (double)sum;
             y[row] = (T)r;
             pout[row] = (T)r;
             d1 += r * r;
             d2 += bi * bi;
         } else {  // kSpmvTrue
-            const double r = b[row] - (double)sum;
+            const double r = opnd - (double)sum;
             d1 += r * r;
         }
     };
@@ -108,9 +111,10 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
             for (int j = 0; j < L; ++j) {
                 const int64_t sl = sb + j * W + wave, row = sl * 64 + lane;
                 if (sl < s_hi && row >= lo && row < hi) {
+                    const double opnd = operand(row);
                     const T sum = cur[j].sl.S == 9 ? b13_row9_idx(cur[j].c, bval, cur[j].sl, lane, x)
                                                    : b13_row_generic(jas, bval, cur[j].sl, lane, x);
-                    emit(row, sum);
+                    emit(row, sum, opnd);
                 }
             }
 #pragma unroll
@@ -121,9 +125,10 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
         const int g = threadIdx.x / L, sub = threadIdx.x % L;
         for (int64_t base = lo; base < hi; base += R) {
             const int64_t row = base + g;
+            const double opnd = sub == 0 && row < hi ? operand(row) : 0.0;
             const T sum = csr_row<T, L>(ptr, col, cval, row < hi ? row : -1, sub, x);
             if (sub != 0 || row >= hi) continue;
-            emit(row, sum);
+            emit(row, sum, opnd);
         }
     }
     d1 = block_sum(d1);

@@ -43,7 +43,10 @@ constexpr int64_t kMallBytes = 256ll << 20;  // memory-side (Infinity) cache of 
 
 // Stream CG vectors non-temporally when the five FP64 vectors an iteration
 // touches exceed the memory-side cache.
-inline bool vectors_stream_nt(int64_t m) { return 40 * m > kMallBytes; }
+#ifndef MFE_VECTORS_NT
+#define MFE_VECTORS_NT 1  // 0: never stream the CG vectors non-temporally
+#endif
+inline bool vectors_stream_nt(int64_t m) { return MFE_VECTORS_NT != 0 && 40 * m > kMallBytes; }
 
 // Load a stored matrix (values and indices, `bytes` in all) non-temporally
 // when it is larger than MFE_MATRIX_NT_MIN_BYTES; a smaller one is loaded

@@ -7,7 +7,7 @@
 #include "common.hpp"
 
 #ifndef MFE_XCD_REMAP
-#define MFE_XCD_REMAP 1  // XCD-contiguous tile ranges (see tile_range)
+#define MFE_XCD_REMAP 1  // XCD-contiguous tile ranges for the CRS products (see tile_range)
 #endif
 
 namespace mfe {
@@ -54,29 +54,55 @@ __device__ __forceinline__ double sum_partials(const double *__restrict__ p, int
     return total;
 }
 
-// Tile range of this workgroup.  Workgroups are dispatched to the 8 XCDs
-// round-robin (workgroup w runs on XCD w % 8), so XCD k takes the k-th
-// contiguous eighth of the tiles and its workgroups stride through it
-// together: each XCD's L2 then holds only the x entries near its own rows.
-// gridDim.x must be a multiple of kNumXcd.
+// Tile range of this workgroup.  With XCD = true: workgroups are dispatched
+// to the 8 XCDs round-robin (workgroup w runs on XCD w % 8), so XCD k takes
+// the k-th contiguous eighth of the tiles and its workgroups stride through
+// it together: each XCD's L2 then holds only the x entries near its own
+// rows (gridDim.x must be a multiple of kNumXcd).  With XCD = false the
+// whole grid strides through the tiles together, so that the chip reads
+// one compact window of the matrix at a time.
 struct TileRange {
     long t, end, step;
 };
+template <bool XCD = (MFE_XCD_REMAP != 0)>
 __device__ __forceinline__ TileRange tile_range(long ntiles) {
     TileRange r;
-#if MFE_XCD_REMAP
-    const int xcd = blockIdx.x % kNumXcd;
-    const int lid = blockIdx.x / kNumXcd;
-    const int per = gridDim.x / kNumXcd;
-    r.t = ntiles * xcd / kNumXcd + lid;
-    r.end = ntiles * (xcd + 1) / kNumXcd;
-    r.step = per;
-#else
-    r.t = blockIdx.x;
-    r.end = ntiles;
-    r.step = gridDim.x;
-#endif
+    if (XCD) {
+        const int xcd = blockIdx.x % kNumXcd;
+        const int lid = blockIdx.x / kNumXcd;
+        const int per = gridDim.x / kNumXcd;
+        r.t = ntiles * xcd / kNumXcd + lid;
+        r.end = ntiles * (xcd + 1) / kNumXcd;
+        r.step = per;
+    } else {
+        r.t = blockIdx.x;
+        r.end = ntiles;
+        r.step = gridDim.x;
+    }
     return r;
+}
+
+// Tile order of the 1x3 BCRS walks: the grid moves through the tiles in
+// super-tiles of 8 S tiles, and inside each the XCD k takes the k-th run of S
+// consecutive tiles, its workgroups striding through the XCD's runs in turn.
+// S = 1 is the grid-wide order, S >= ntiles / 8 the XCD-contiguous one;
+// between them each XCD's L2 keeps the x entries of its runs while the chip
+// still reads one region of the matrix at a time.  gridDim.x must be a
+// multiple of kNumXcd.
+struct TileSeq {
+    long i, step, S, ntiles;
+    int xcd;
+    __device__ __forceinline__ long tile(long j) const { return (j / S) * (kNumXcd * S) + xcd * S + j % S; }
+    __device__ __forceinline__ bool valid(long j) const { return tile(j) < ntiles; }
+};
+__device__ __forceinline__ TileSeq tile_seq(long ntiles, long S) {
+    TileSeq q;
+    q.xcd = blockIdx.x % kNumXcd;
+    q.i = blockIdx.x / kNumXcd;
+    q.step = gridDim.x / kNumXcd;
+    q.S = S;
+    q.ntiles = ntiles;
+    return q;
 }
 
 // Vector streams whose next use is more than one kernel away (or never).

@@ -13,10 +13,15 @@
 //   entry (CsrDesc, B13Desc) form them from a small descriptor instead of
 //   loading them; the sums are the same.
 //
-// Both kernels run a workgroup grid sized to stay resident and walk row tiles
-// in XCD-contiguous ranges, so each XCD's L2 holds the x entries of the mesh
-// planes its rows touch while the matrix streams past (non-temporally when it
-// is larger than the memory-side cache can usefully keep, matrix_stream_nt).
+// Both kernels run a workgroup grid sized to stay resident.  The CRS kernels
+// walk row tiles in XCD-contiguous ranges, so each XCD's L2 holds the x
+// entries of the mesh planes its rows touch.  The 1x3 BCRS kernels walk
+// super-tiles of 8 x 16 tiles with the whole grid in step, each XCD taking 16
+// consecutive tiles of each (tile_seq): the chip reads one region of the
+// matrix at a time, which measured faster for them, and each XCD's L2 still
+// serves most of its x gathers.  The matrix streams past non-temporally when
+// it is larger than the memory-side cache can usefully keep
+// (matrix_stream_nt).
 #include <type_traits>
 
 #include "b13_layout.hpp"
@@ -36,6 +41,12 @@
 #endif
 #ifndef MFE_B13_PIPE_TILES
 #define MFE_B13_PIPE_TILES 8  // tiles per workgroup from which the pipelined 1x3 BCRS walk is used
+#endif
+#ifndef MFE_B13_WALK
+#define MFE_B13_WALK 2  // pipelined 1x3 BCRS walk: 0 column indices read ahead, 1 scalars read ahead, 2 by precision
+#endif
+#ifndef MFE_B13_SUPER
+#define MFE_B13_SUPER 16      // 1x3 BCRS products: consecutive tiles per XCD in each super-tile (tile_seq)
 #endif
 #ifndef MFE_SPMV_WG_PER_CU
 #define MFE_SPMV_WG_PER_CU 0  // resident workgroups per CU (0: as many as fit)
@@ -61,36 +72,62 @@ struct Epi {
     bool nt;  // store y non-temporally (dot mode: y is read once, by the r update)
 };
 
-// Per-row epilogue; accumulates the reduction terms in FP64.
+// The epilogue's own operand of a row: x[row] for the dot modes, b[row] for
+// the residual modes.  The kernels load it before the row's gathers: read
+// after the y store (finish_row's order of use) it would cost every tile a
+// second memory round trip, since the vector memory counter that the wait
+// for it uses also counts the store.
 template <typename T, int MODE>
-__device__ __forceinline__ void finish_row(const Epi<T> &E, int64_t row, T sum, double &d1, double &d2) {
-    if (MODE == kSpmvPlain) {
-        E.y[row] = sum;
-    } else if (MODE == kSpmvDot) {
-#if MFE_SPMV_Q_NT == 1
-        stream_store(sum, E.y + row, true);
-#elif MFE_SPMV_Q_NT == 2
-        E.y[row] = sum;
-#else
-        stream_store(sum, E.y + row, E.nt);
-#endif
-        d1 += (double)E.x[row] * (double)sum;
+__device__ __forceinline__ double row_operand(const Epi<T> &E, int64_t row) {
+    if (MODE == kSpmvDot || MODE == kSpmvDot2) return (double)E.x[row];
+    if (MODE == kSpmvResid || MODE == kSpmvTrue) return E.b[row];
+    return 0.0;
+}
+
+// The value a row's y entry receives, with the row's reduction terms
+// accumulated in FP64 (`opnd` from row_operand).
+template <typename T, int MODE>
+__device__ __forceinline__ T row_result(T sum, double opnd, double &d1, double &d2) {
+    if (MODE == kSpmvDot) {
+        d1 += opnd * (double)sum;
     } else if (MODE == kSpmvDot2) {
-        E.y[row] = sum;
-        const double ri = (double)E.x[row];
-        d1 += ri * (double)sum;
-        d2 += ri * ri;
+        d1 += opnd * (double)sum;
+        d2 += opnd * opnd;
     } else if (MODE == kSpmvResid) {
-        const double bi = E.b[row];
-        const double r = bi - (double)sum;
-        E.y[row] = (T)r;
-        if (E.pout) E.pout[row] = (T)r;
+        const double r = opnd - (double)sum;
         d1 += r * r;
-        d2 += bi * bi;
-    } else {  // kSpmvTrue
-        const double r = E.b[row] - (double)sum;
+        d2 += opnd * opnd;
+        return (T)r;
+    } else if (MODE == kSpmvTrue) {
+        const double r = opnd - (double)sum;
         d1 += r * r;
     }
+    return sum;
+}
+
+// The row's stores (none for kSpmvTrue; y and p for kSpmvResid).
+template <typename T, int MODE>
+__device__ __forceinline__ void row_store(const Epi<T> &E, int64_t row, T v) {
+    if (MODE == kSpmvTrue) return;
+    if (MODE == kSpmvDot) {
+#if MFE_SPMV_Q_NT == 1
+        stream_store(v, E.y + row, true);
+#elif MFE_SPMV_Q_NT == 2
+        E.y[row] = v;
+#else
+        stream_store(v, E.y + row, E.nt);
+#endif
+    } else {
+        E.y[row] = v;
+    }
+    if (MODE == kSpmvResid && E.pout) E.pout[row] = v;
+}
+
+// Per-row epilogue: the row's result, stored at once.
+template <typename T, int MODE>
+__device__ __forceinline__ void finish_row(const Epi<T> &E, int64_t row, T sum, double opnd, double &d1,
+                                           double &d2) {
+    row_store<T, MODE>(E, row, row_result<T, MODE>(sum, opnd, d1, d2));
 }
 
 // Workgroup partial(s) of the fused reductions; the consumer (the next
@@ -133,8 +170,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csr(int64_t m, const int32_t *_
     double d1 = 0.0, d2 = 0.0;
     for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
         const int64_t row = tr.t * R + g;
+        const double opnd = sub == 0 && row < m ? row_operand<T, MODE>(E, row) : 0.0;
         const T sum = csr_row<T, L, MNT>(ptr, col, val, row < m ? row : -1, sub, E.x);
-        if (sub == 0 && row < m) finish_row<T, MODE>(E, row, sum, d1, d2);
+        if (sub == 0 && row < m) finish_row<T, MODE>(E, row, sum, opnd, d1, d2);
     }
     store_partials<MODE>(d1, d2, partials);
 }
@@ -181,6 +219,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
         const int32_t lo = ptr[r0], hi = ptr[r1];
         const int64_t row = r0 + rl;
         const CsrDesc &D = cdesc[tr.t * (kBlock / 64) + wave];  // this wavefront's tile
+        const double opnd = sub == 0 && row < r1 ? row_operand<T, MODE>(E, row) : 0.0;
         T sum = 0;
         if (D.uniform == 2) {
             // 27 entries per row in 9 runs of three consecutive columns: stage
@@ -227,7 +266,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrs(int64_t m, const int32_t *
         }
 #pragma unroll
         for (int off = LPR / 2; off > 0; off >>= 1) sum += __shfl_xor(sum, off, 64);
-        if (sub == 0 && row < r1) finish_row<T, MODE>(E, row, sum, d1, d2);
+        if (sub == 0 && row < r1) finish_row<T, MODE>(E, row, sum, opnd, d1, d2);
     }
     store_partials<MODE>(d1, d2, partials);
 }
@@ -294,6 +333,7 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrg(const int32_t *__restrict_
             wave_sync();
             if (lane < n) {
                 const int64_t row = r0 + lane;
+                const double opnd = row_operand<T, MODE>(E, row);
                 const T *a = svs + pad + 27 * lane;
                 T sum = 0;
 #pragma unroll
@@ -303,14 +343,15 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrg(const int32_t *__restrict_
                     sum += a[3 * i + 1] * xp[1];
                     sum += a[3 * i + 2] * xp[2];
                 }
-                finish_row<T, MODE>(E, row, sum, d1, d2);
+                finish_row<T, MODE>(E, row, sum, opnd, d1, d2);
             }
             wave_sync();
         } else {
             const int rl = lane >> 2, sub = lane & 3;
             const int64_t row = rl < -c.item.y ? rows[c.item.x + rl] : -1;
+            const double opnd = sub == 0 && row >= 0 ? row_operand<T, MODE>(E, row) : 0.0;
             const T sum = csr_row<T, 4, MNT>(ptr, col, val, row, sub, E.x);
-            if (sub == 0 && row >= 0) finish_row<T, MODE>(E, row, sum, d1, d2);
+            if (sub == 0 && row >= 0) finish_row<T, MODE>(E, row, sum, opnd, d1, d2);
         }
     };
     // (issuing the next item's staging loads before the current item's sums,
@@ -339,12 +380,14 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13(int64_t m
     const long ntiles = (m + kBlock - 1) / kBlock;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double d1 = 0.0, d2 = 0.0;
-    for (TileRange tr = tile_range(ntiles); tr.t < tr.end; tr.t += tr.step) {
-        const int64_t s = (int64_t)tr.t * (kBlock / 64) + wave;
+    const TileSeq q = tile_seq(ntiles, MFE_B13_SUPER);
+    for (long j = q.i; q.valid(j); j += q.step) {
+        const int64_t s = (int64_t)q.tile(j) * (kBlock / 64) + wave;
         const int64_t row = s * 64 + lane;
         if (row >= m) continue;
+        const double opnd = row_operand<T, MODE>(E, row);
         const T sum = b13_row<T, MNT>(slot_base, jas, desc, val, s, lane, E.x);
-        finish_row<T, MODE>(E, row, sum, d1, d2);
+        finish_row<T, MODE>(E, row, sum, opnd, d1, d2);
     }
     store_partials<MODE>(d1, d2, partials);
 }
@@ -366,7 +409,7 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t 
     const long ntiles = (m + kBlock - 1) / kBlock;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double d1 = 0.0, d2 = 0.0;
-    TileRange tr = tile_range(ntiles);
+    const TileSeq q = tile_seq(ntiles, MFE_B13_SUPER);
     B13Idx cur, nxt;
     auto fetch = [&](long t, B13Idx &r) {
         const int64_t s = (int64_t)t * (kBlock / 64) + wave;
@@ -376,16 +419,84 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t 
         r.sl = b13_slice(slot_base[s], slot_base[s + 1]);
         if (row < m) b13_cols<MNT>(jas, desc, s, lane, r);
     };
-    if (tr.t < tr.end) fetch(tr.t, cur);
-    for (; tr.t < tr.end; tr.t += tr.step) {
-        const long tn = tr.t + tr.step;
+    if (q.valid(q.i)) fetch(q.tile(q.i), cur);
+    for (long j = q.i; q.valid(j); j += q.step) {
         nxt.sl.S = 0;
-        if (tn < tr.end) fetch(tn, nxt);
-        const int64_t row = tr.t * kBlock + threadIdx.x;
+        if (q.valid(j + q.step)) fetch(q.tile(j + q.step), nxt);
+        const int64_t row = q.tile(j) * kBlock + threadIdx.x;
         if (row < m) {
+            const double opnd = row_operand<T, MODE>(E, row);
             const T sum = cur.sl.S == 9 ? b13_row9_idx<T, MNT>(cur.c, val, cur.sl, lane, E.x)
                                         : b13_row_generic<T, MNT>(jas, val, cur.sl, lane, E.x);
-            finish_row<T, MODE>(E, row, sum, d1, d2);
+            finish_row<T, MODE>(E, row, sum, opnd, d1, d2);
+        }
+        cur = nxt;
+    }
+    store_partials<MODE>(d1, d2, partials);
+}
+
+// Scalar-prefetch walk: a wavefront owns slice 4t + w of tile t.  Only
+// wavefront-uniform data is read ahead: the next tile's slice bounds and
+// descriptor come from scalar loads issued before the current tile's vector
+// loads, and nothing that a vector load wrote is carried into the next tile.
+// A tile's row result is complete before its y store, so no wait on the
+// vector memory counter (which also counts stores) falls between that store
+// and the next tile's loads: the store's latency overlaps them.  Descriptor
+// slices form their column indices from the carried scalars; the few others
+// load theirs in place.  Arithmetic and summation order are those of
+// k_spmv_b13.
+struct B13Ahead {
+    int32_t k0, k1;  // slot_base[s], slot_base[s + 1]
+    B13Desc D;
+};
+
+template <typename T, int MODE, bool MNT>
+__global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13s(int64_t m, const int32_t *__restrict__ slot_base,
+                                                      const int32_t *__restrict__ jas,
+                                                      const B13Desc *__restrict__ desc,
+                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
+                                                      double *partials) {
+    if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
+    const long ntiles = (m + kBlock - 1) / kBlock;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    double d1 = 0.0, d2 = 0.0;
+    const TileSeq q = tile_seq(ntiles, MFE_B13_SUPER);
+    const int64_t nslices = (m + 63) / 64;
+    auto ahead = [&](long j, B13Ahead &a) {
+        a.k0 = a.k1 = 0;
+        if (!q.valid(j)) return;
+        const int64_t s = (int64_t)q.tile(j) * (kBlock / 64) + wave;
+        if (s >= nslices) return;
+        a.k0 = slot_base[s];
+        a.k1 = slot_base[s + 1];
+        a.D = desc[s];
+    };
+    B13Ahead cur, nxt;
+    ahead(q.i, cur);
+    for (long j = q.i; q.valid(j); j += q.step) {
+        ahead(j + q.step, nxt);
+        const int64_t s = (int64_t)q.tile(j) * (kBlock / 64) + wave;
+        const int64_t row = s * 64 + lane;
+        if (row < m) {
+            const double opnd = row_operand<T, MODE>(E, row);
+            B13Idx r;
+            r.sl = b13_slice(cur.k0, cur.k1);
+            T sum;
+            if (r.sl.S == 9) {
+                if (cur.D.uniform) {
+                    const uint32_t bits = lane < 32 ? cur.D.e_lo : cur.D.e_hi;
+                    const int32_t base = (int32_t)row + (int32_t)((bits >> (lane & 31)) & 1u);
+#pragma unroll
+                    for (int k = 0; k < 9; ++k) r.c[k] = base + cur.D.d[k];
+                } else {
+                    b13_load_idx<MNT>(jas, lane, r);
+                }
+                sum = b13_row9_idx<T, MNT>(r.c, val, r.sl, lane, E.x);
+            } else {
+                sum = b13_row_generic<T, MNT>(jas, val, r.sl, lane, E.x);
+            }
+            const T v = row_result<T, MODE>(sum, opnd, d1, d2);
+            row_store<T, MODE>(E, row, v);
         }
         cur = nxt;
     }
@@ -474,8 +585,11 @@ int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
                   int *grid_out, int cap) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
     const long ntiles = (P->m + kBlock - 1) / kBlock;
-    // the pipelined walk pays off once each workgroup takes several tiles
-    auto kern = k_spmv_b13p<T, MODE, MNT>;
+    // a pipelined walk pays off once each workgroup takes several tiles; the
+    // scalar read-ahead measured faster in FP64, the index read-ahead in FP32
+    // (256^3: 0.794 against 0.803 ms, and 0.404 against 0.414 ms)
+    constexpr bool scalar_walk = MFE_B13_WALK == 1 || (MFE_B13_WALK == 2 && std::is_same<T, double>::value);
+    auto kern = scalar_walk ? k_spmv_b13s<T, MODE, MNT> : k_spmv_b13p<T, MODE, MNT>;
     int grid = grid_for(kern, ntiles, P->ctx->num_cu);
     if (ntiles < (long)MFE_B13_PIPE_TILES * grid) {
         kern = k_spmv_b13<T, MODE, MNT>;

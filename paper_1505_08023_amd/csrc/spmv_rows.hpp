@@ -70,7 +70,11 @@ __device__ __forceinline__ void b13_cols(const int32_t *__restrict__ jas, const 
     if (r.sl.S != 9) return;
     const B13Desc &D = desc[s];
     if (D.uniform) {
-        const uint32_t bits = lane < 32 ? D.e_lo : D.e_hi;
+        // both shift words as scalars, then a per-lane select (selecting the
+        // address instead would turn the read into a vector load that the
+        // tile's gathers wait for)
+        const uint32_t e_lo = __builtin_amdgcn_readfirstlane(D.e_lo), e_hi = __builtin_amdgcn_readfirstlane(D.e_hi);
+        const uint32_t bits = lane < 32 ? e_lo : e_hi;
         const int32_t base = (int32_t)(s * 64 + lane) + (int32_t)((bits >> (lane & 31)) & 1u);
 #pragma unroll
         for (int k = 0; k < 9; ++k) r.c[k] = base + D.d[k];
