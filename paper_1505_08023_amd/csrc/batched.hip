@@ -315,6 +315,9 @@ struct mfe_batch {
         hipGraphExec_t exec;
     };
     std::vector<GraphEntry> graphs;
+    // per system: mean d log(residual) / d iteration of its last FP64 solve
+    // and of its last FP32 inner solve (the forecast priors; 0: none yet)
+    std::vector<double> rate64, rate32;
 };
 
 namespace mfe {
@@ -546,7 +549,7 @@ int capture_iterations(mfe_batch *B, int format, const Tuning &t, T *x, T *r, T 
     return MFE_OK;
 }
 
-constexpr int kMaxBatchGraphs = 16;
+constexpr int kMaxBatchGraphs = 32;
 
 template <typename T>
 int graph_for_batch(mfe_batch *B, int format, const Tuning &t, bool f32, T *x, T *r, T *p, T *q, CgState *st, int k,
@@ -573,6 +576,27 @@ int graph_for_batch(mfe_batch *B, int format, const Tuning &t, bool f32, T *x, T
     }
     B->graphs.push_back({format, t.lanes, t.factor, k, f32, x, st, ex});
     *out = ex;
+    return MFE_OK;
+}
+
+// The iteration graphs of a batched solve: k iterations, and kt for the end
+// of the solve (tail = nullptr when k <= kTailIters).
+struct BatchGraphs {
+    hipGraphExec_t exec = nullptr, tail = nullptr;
+    int k = 0, kt = 0;
+};
+
+template <typename T>
+int batch_graphs(mfe_batch *B, int format, const Tuning &t, bool f32, T *x, T *r, T *p, T *q, CgState *st,
+                 int max_iter, BatchGraphs *G) {
+    G->k = std::min(kGraphIters, max_iter);
+    MFE_TRY(graph_for_batch<T>(B, format, t, f32, x, r, p, q, st, G->k, &G->exec));
+    G->tail = nullptr;
+    G->kt = 0;
+    if (G->k > kTailIters) {
+        G->kt = kTailIters;
+        MFE_TRY(graph_for_batch<T>(B, format, t, f32, x, r, p, q, st, G->kt, &G->tail));
+    }
     return MFE_OK;
 }
 
@@ -614,30 +638,51 @@ bool any_running(const std::vector<CgState> &v) {
 #define MFE_BATCH_REMAP 1  // spread the grid over the running systems only once their rows fall below 60 %
 #endif
 
-// Replay the iteration graph until no system runs.  Once the running
-// systems hold at most 60 % of the rows the grid is spread over, the same
-// grid is spread over them alone (the graphs keep their launch shape and read
-// the map at replay), so the systems that remain take the whole GPU; the
-// full map is restored at the end.
-int run_batch(mfe_batch *B, hipGraphExec_t exec, const CgState *st, int k, int max_iter, std::vector<CgState> &fin) {
+// Replay the iteration graphs until no system runs.  fin holds the start
+// states on entry and the final ones on return.  Each system's residual is
+// forecast as in the single-system driver (prior: rates, updated here); the
+// tail graph is launched once every running system is forecast to stop
+// within one long graph, so that few frozen iterations follow the last
+// system's end.  Once the running systems hold at most 60 % of the rows the
+// grid is spread over, the same grid is spread over them alone (the graphs
+// keep their launch shape and read the map at replay), so the systems that
+// remain take the whole GPU; the full map is restored at the end.
+int run_batch(mfe_batch *B, const BatchGraphs &G, const CgState *st, int max_iter, std::vector<double> &rates,
+              std::vector<CgState> &fin) {
     hipStream_t s = B->ctx->stream;
-    const long limit = (long)max_iter / k + 2;
+    const int ns = B->nsys;
+    if ((int)rates.size() != ns) rates.assign(ns, 0.0);
+    std::vector<Forecast> fc(ns);
+    std::vector<double> res0(ns, 0.0);
+    double rem = 0.0;  // the largest forecast over the running systems
+    for (int j = 0; j < ns; ++j) {
+        fc[j].slope = rates[j];
+        res0[j] = stop_residual(fin[j], 0);
+        if (fin[j].status == kRunning) rem = std::max(rem, fc[j].observe(0, res0[j], fin[j].tol));
+    }
+    const long limit = (long)max_iter + 2L * G.k;  // iterations; the device cap ends the loop first
     int64_t spread = B->row0[B->nsys];  // rows the current map spreads the grid over
     bool partial = false;
     int rc = MFE_OK;
-    for (long launched = 0;; ++launched) {
+    for (long launched = 0;;) {
         if (launched > limit) {
             set_error("batched CG still running after the iteration cap");
             rc = MFE_EHIP;
             break;
         }
-        if (hipGraphLaunch(exec, s) != hipSuccess) {
+        const bool tail = G.tail && std::min(rem, (double)(max_iter - launched)) <= (double)G.k;
+        if (hipGraphLaunch(tail ? G.tail : G.exec, s) != hipSuccess) {
             set_error("hipGraphLaunch failed");
             rc = MFE_EHIP;
             break;
         }
+        launched += tail ? G.kt : G.k;
         rc = read_states(B, st, fin);
         if (rc != MFE_OK || !any_running(fin)) break;
+        rem = 0.0;
+        for (int j = 0; j < ns; ++j)
+            if (fin[j].status == kRunning)
+                rem = std::max(rem, fc[j].observe(fin[j].iters, stop_residual(fin[j], 0), fin[j].tol));
         if (MFE_BATCH_REMAP) {
             std::vector<char> on(B->nsys, 0);
             int64_t active = 0, nact = 0;
@@ -659,6 +704,14 @@ int run_batch(mfe_batch *B, hipGraphExec_t exec, const CgState *st, int k, int m
         const int r2 = upload_map(B, plan_full(B, map_target(B, B->map_format, B->map_tuning)));
         if (rc == MFE_OK) rc = r2;
     }
+    if (rc == MFE_OK)
+        for (int j = 0; j < ns; ++j) {
+            const double res = stop_residual(fin[j], 0);
+            if (fin[j].iters > 0 && res0[j] > 0.0 && res > 0.0 && std::isfinite(res) && std::isfinite(res0[j])) {
+                const double r = (std::log(res) - std::log(res0[j])) / fin[j].iters;
+                if (r < 0.0) rates[j] = r;
+            }
+        }
     return rc;
 }
 
@@ -676,11 +729,10 @@ int batch_cg_fp64(mfe_batch *B, int format, const Tuning &t, double *x, double t
     MFE_HIP_TRY(hipGetLastError());
     MFE_TRY(read_states(B, st, fin));
     if (any_running(fin)) {
-        const int k = std::min(kGraphIters, max_iter);
-        hipGraphExec_t exec = nullptr;
-        MFE_TRY(graph_for_batch<double>(B, format, t, false, x, (double *)P->r.ptr, (double *)P->p.ptr,
-                                        (double *)P->q.ptr, st, k, &exec));
-        MFE_TRY(run_batch(B, exec, st, k, max_iter, fin));
+        BatchGraphs G;
+        MFE_TRY(batch_graphs<double>(B, format, t, false, x, (double *)P->r.ptr, (double *)P->p.ptr,
+                                     (double *)P->q.ptr, st, max_iter, &G));
+        MFE_TRY(run_batch(B, G, st, max_iter, B->rate64, fin));
     }
     MFE_TRY(bspmv<double, kSpmvTrue>(B, format, t, x, nullptr, nullptr, (const double *)P->b.ptr, st, pa, s));
     MFE_TRY(bfinalize(B, kFinTrue, pa, st, nullptr, s));
@@ -1138,11 +1190,11 @@ int mfe_batch_cg_mixed_ex(mfe_batch *B, int format, double *x_dev, double tol, d
                            (float *)B->p32.ptr, (float *)B->d32.ptr, pa, B->nwg);
         MFE_HIP_TRY(hipGetLastError());
         MFE_TRY(bfinalize(B, kFinStart, pa, inner, outer, s));
-        const int k = std::min(kGraphIters, max_inner);
-        hipGraphExec_t exec = nullptr;
-        MFE_TRY(graph_for_batch<float>(B, format, t, true, (float *)B->d32.ptr, (float *)B->r32.ptr,
-                                       (float *)B->p32.ptr, (float *)B->q32.ptr, inner, k, &exec));
-        MFE_TRY(run_batch(B, exec, inner, k, max_inner, in));
+        BatchGraphs G;
+        MFE_TRY(batch_graphs<float>(B, format, t, true, (float *)B->d32.ptr, (float *)B->r32.ptr,
+                                    (float *)B->p32.ptr, (float *)B->q32.ptr, inner, max_inner, &G));
+        MFE_TRY(read_states(B, inner, in));  // the start states seed the forecast
+        if (any_running(in)) MFE_TRY(run_batch(B, G, inner, max_inner, B->rate32, in));
         bool breakdown = false;
         for (int j = 0; j < ns; ++j) {
             // the next step keeps the direction of an inner solve that met its tolerance (scale = its s)

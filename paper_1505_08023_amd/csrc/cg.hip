@@ -10,7 +10,12 @@
 // K iterations are captured once into a HIP graph and replayed.  The host
 // keeps one graph ahead and polls a pinned copy of the solver state after
 // each; once the state leaves "running" every kernel returns at entry, so
-// the speculative graph changes nothing.
+// a speculative graph changes nothing.  It still costs its launches (a
+// kernel that returns at entry takes several microseconds to dispatch), so
+// once the residual history forecasts the end of the solve the host switches
+// to graphs of kTailIters iterations, and launches none ahead when the end is
+// forecast within the graphs already in flight.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <vector>
@@ -19,7 +24,7 @@
 
 // Iteration graphs kept per problem, keyed by solver kind, format, precision,
 // solution buffer, graph length and state slot.
-constexpr int kMaxGraphs = 16;
+constexpr int kMaxGraphs = 32;
 
 struct mfe_graph_cache {
     struct Entry {
@@ -146,39 +151,91 @@ void release_graphs(mfe_problem *P) {
     P->graphs = nullptr;
 }
 
-// Replay the iteration graph until the device state stops running.  On
-// return *fin holds the final state.
-int run_iterations(mfe_problem *P, hipGraphExec_t exec, const CgState *st, int k, int max_iter, CgState *fin) {
+double Forecast::observe(int i, double res, double tol) {
+    if (!(res > 0.0) || !std::isfinite(res)) return 0.0;
+    const double l = std::log(res);
+    if (it >= 0 && i > it) {
+        const double d = (l - lr) / (i - it);
+        if (d < 0.0 && std::isfinite(d)) slope = d;  // a stall keeps the previous rate
+    }
+    it = i;
+    lr = l;
+    if (res <= tol) return 0.0;
+    if (!(slope < 0.0)) return 1e30;
+    return (std::log(tol) - l) / slope;
+}
+
+double stop_residual(const CgState &s, int kind) {
+    const double v = kind == 2 ? s.rr : s.rho;
+    return s.bnorm > 0.0 && v >= 0.0 ? std::sqrt(v) / s.bnorm : 0.0;
+}
+
+void record_rate(mfe_problem *P, int slot, double res0, const CgState &fin, int kind) {
+    const double res = stop_residual(fin, kind);
+    if (fin.iters > 0 && res0 > 0.0 && res > 0.0 && std::isfinite(res0) && std::isfinite(res)) {
+        const double r = (std::log(res) - std::log(res0)) / fin.iters;
+        if (r < 0.0) P->rate[slot] = r;
+    }
+}
+
+int iteration_graphs(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st,
+                     int max_iter, int kind, IterGraphs *G) {
+    G->k = kGraphIters < max_iter ? kGraphIters : max_iter;
+    MFE_TRY(graph_for(P, format, f32, x, r, p, q, st, G->k, &G->exec, kind));
+    G->tail = nullptr;
+    G->kt = 0;
+    if (G->k > kTailIters) {
+        G->kt = kTailIters;
+        MFE_TRY(graph_for(P, format, f32, x, r, p, q, st, G->kt, &G->tail, kind));
+    }
+    return MFE_OK;
+}
+
+// Replay the iteration graphs until the device state stops running.  Up to
+// two graphs are in flight, each followed by a copy of the state to its
+// pinned slot (0 or 1) and an event.  Before waiting for the older one the
+// host launches the next, unless the forecast puts the end of the solve
+// within the iterations already launched; it launches the tail graph when
+// the end is forecast within one more long graph.  rem: the forecast at the
+// start (1e30 if unknown).  On return *fin holds the final state.
+int run_iterations(mfe_problem *P, const IterGraphs &G, const CgState *st, int max_iter, int kind, Forecast &fc,
+                   double rem, CgState *fin) {
     mfe_ctx *ctx = P->ctx;
     hipStream_t s = ctx->stream;
     CgState *pin = (CgState *)ctx->pinned;
-    const long limit = (long)max_iter / k + 3;  // the device cap ends the loop well before this
-    long launched = 0;
-    int slot = 0;
-    MFE_HIP_TRY(hipGraphLaunch(exec, s));
-    MFE_HIP_TRY(hipMemcpyAsync(&pin[0], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-    MFE_HIP_TRY(hipEventRecord(ctx->ev[0], s));
-    launched = 1;
+    const long limit = (long)max_iter + 2L * G.k;  // iterations launched at most; the device cap ends the loop first
+    long launched = 0, polled = 0;                 // iterations launched, and done at the last poll
+    int head = 0, count = 0;                       // in-flight graphs occupy slots head, head ^ 1
     for (;;) {
-        const int nxt = slot ^ 1;
-        const bool more = launched < limit;
-        if (more) {
-            MFE_HIP_TRY(hipGraphLaunch(exec, s));
-            MFE_HIP_TRY(hipMemcpyAsync(&pin[nxt], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
-            MFE_HIP_TRY(hipEventRecord(ctx->ev[nxt], s));
-            ++launched;
+        while (count < 2 && launched < limit) {
+            const long ahead = launched - polled;
+            // the device stops at max_iter in any case
+            const double r = std::min(rem, (double)(max_iter - polled));
+            if (count > 0 && r <= (double)ahead) break;  // the end is forecast within the graphs in flight
+            const bool tail = G.tail && r <= (double)(ahead + G.k);
+            const int slot = (head + count) & 1;
+            MFE_HIP_TRY(hipGraphLaunch(tail ? G.tail : G.exec, s));
+            MFE_HIP_TRY(hipMemcpyAsync(&pin[slot], st, sizeof(CgState), hipMemcpyDeviceToHost, s));
+            MFE_HIP_TRY(hipEventRecord(ctx->ev[slot], s));
+            launched += tail ? G.kt : G.k;
+            ++count;
         }
-        MFE_HIP_TRY(hipEventSynchronize(ctx->ev[slot]));
-        if (pin[slot].status != kRunning) {
-            if (more) MFE_HIP_TRY(hipEventSynchronize(ctx->ev[nxt]));
-            *fin = pin[slot];
-            return MFE_OK;
-        }
-        if (!more) {
+        if (count == 0) {
             set_error("CG state still running after the iteration cap");
             return MFE_EHIP;
         }
-        slot = nxt;
+        const int slot = head;
+        MFE_HIP_TRY(hipEventSynchronize(ctx->ev[slot]));
+        head ^= 1;
+        --count;
+        const CgState cur = pin[slot];
+        if (cur.status != kRunning) {
+            if (count > 0) MFE_HIP_TRY(hipEventSynchronize(ctx->ev[head]));
+            *fin = cur;
+            return MFE_OK;
+        }
+        polled = cur.iters;
+        rem = fc.observe(cur.iters, stop_residual(cur, kind), cur.tol);
     }
 }
 
@@ -213,10 +270,13 @@ int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, do
     CgState fin = pin[0];
     int spmvs = 1;
     if (fin.status == kRunning) {
-        const int k = kGraphIters < max_iter ? kGraphIters : max_iter;
-        hipGraphExec_t exec = nullptr;
-        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, k, &exec));
-        MFE_TRY(run_iterations(P, exec, st, k, max_iter, &fin));
+        IterGraphs G;
+        MFE_TRY(iteration_graphs(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, max_iter, 0, &G));
+        Forecast fc;
+        fc.slope = P->rate[0];
+        const double res0 = stop_residual(fin, 0);
+        MFE_TRY(run_iterations(P, G, st, max_iter, 0, fc, fc.observe(0, res0, tol), &fin));
+        record_rate(P, 0, res0, fin, 0);
         spmvs += fin.iters + (fin.status == kBreakdown ? 1 : 0);
     }
     // true residual ||b - A x|| in FP64
@@ -277,10 +337,13 @@ int cg_sr_solve(mfe_problem *P, int format, double *x, double tol, int max_iter,
     CgState fin = pin[0];
     int spmvs = 1;
     if (fin.status == kRunning) {
-        const int k = kGraphIters < max_iter + 1 ? kGraphIters : max_iter + 1;
-        hipGraphExec_t exec = nullptr;
-        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, k, &exec, 1));
-        MFE_TRY(run_iterations(P, exec, st, k, max_iter + 1, &fin));
+        IterGraphs G;
+        MFE_TRY(iteration_graphs(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, max_iter + 1, 1, &G));
+        Forecast fc;
+        fc.slope = P->rate[1];
+        const double res0 = stop_residual(fin, 1);
+        MFE_TRY(run_iterations(P, G, st, max_iter + 1, 1, fc, fc.observe(0, res0, tol), &fin));
+        record_rate(P, 1, res0, fin, 1);
         spmvs += fin.iters + 1;
     }
     SpmvArgs a1{x, nullptr, nullptr, (const double *)P->b.ptr, st, partials};
@@ -342,10 +405,13 @@ int cg_jacobi_solve(mfe_problem *P, int format, double *x, double tol, int max_i
     CgState fin = pin[0];
     int spmvs = 1;
     if (fin.status == kRunning) {
-        const int k = kGraphIters < max_iter ? kGraphIters : max_iter;
-        hipGraphExec_t exec = nullptr;
-        MFE_TRY(graph_for(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, k, &exec, 2));
-        MFE_TRY(run_iterations(P, exec, st, k, max_iter, &fin));
+        IterGraphs G;
+        MFE_TRY(iteration_graphs(P, format, false, x, P->r.ptr, P->p.ptr, P->q.ptr, st, max_iter, 2, &G));
+        Forecast fc;
+        fc.slope = P->rate[2];
+        const double res0 = stop_residual(fin, 2);
+        MFE_TRY(run_iterations(P, G, st, max_iter, 2, fc, fc.observe(0, res0, tol), &fin));
+        record_rate(P, 2, res0, fin, 2);
         spmvs += fin.iters + (fin.status == kBreakdown ? 1 : 0);
     }
     SpmvArgs a1{x, nullptr, nullptr, (const double *)P->b.ptr, st, partials};

@@ -221,6 +221,10 @@ struct mfe_problem {
     mfe::Buffer s;                       // single-reduction CG: s = A p
     mfe::Buffer dinv;                    // Jacobi-preconditioned CG: 1 / diag(A)
     mfe_graph_cache *graphs = nullptr;
+    // mean d log(residual) / d iteration of the last solve of each kind (CG,
+    // single-reduction CG, Jacobi CG, FP32 inner CG): the prior of the next
+    // solve's forecast (0: none yet)
+    double rate[4] = {0.0, 0.0, 0.0, 0.0};
 };
 
 namespace mfe {
@@ -277,10 +281,39 @@ int finish_problem(mfe_problem *P);
 
 // CG driver (cg.hip)
 constexpr int kGraphIters = 16;  // CG iterations per captured graph
+constexpr int kTailIters = 4;    // iterations per graph once the end of a solve is forecast
 int ensure_workspace(mfe_problem *P);
 int graph_for(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st, int k,
               hipGraphExec_t *out, int kind = 0);
-int run_iterations(mfe_problem *P, hipGraphExec_t exec, const CgState *st, int k, int max_iter, CgState *fin);
+
+// Host-side forecast of the iterations a solve still needs: a geometric fit
+// of its stop-test residual between two polls of the device state, seeded
+// with a prior rate (the last solve of the same kind on the same problem).
+// Only the length of the graphs the host launches depends on it.
+struct Forecast {
+    double slope = 0.0;  // d log(residual) / d iteration; < 0 once known
+    int it = -1;         // iterations at the last observation
+    double lr = 0.0;     // log(residual) there
+    // observation: residual res after i iterations; returns the iterations
+    // forecast to reach tol (1e30 while no decreasing rate is known)
+    double observe(int i, double res, double tol);
+};
+
+// The iteration graphs of one solve: k iterations, and kt < k for the end of
+// the solve (tail = nullptr when k <= kTailIters).
+struct IterGraphs {
+    hipGraphExec_t exec = nullptr, tail = nullptr;
+    int k = 0, kt = 0;
+};
+int iteration_graphs(mfe_problem *P, int format, bool f32, void *x, void *r, void *p, void *q, CgState *st,
+                     int max_iter, int kind, IterGraphs *G);
+// the stop-test residual ||r|| / ||b|| of a polled state (kind 2: the
+// unpreconditioned r.r of the Jacobi CG)
+double stop_residual(const CgState &s, int kind);
+int run_iterations(mfe_problem *P, const IterGraphs &G, const CgState *st, int max_iter, int kind, Forecast &fc,
+                   double rem, CgState *fin);
+// records the mean rate of a finished solve as the prior of the next one
+void record_rate(mfe_problem *P, int slot, double res0, const CgState &fin, int kind);
 int cg_solve(mfe_problem *P, int format, double *x, double tol, int max_iter, double *hist, mfe_cg_stats *st,
              bool warm = false);
 // Jacobi-preconditioned CG (FP64)

@@ -189,10 +189,14 @@ int cg_mixed_solve(mfe_problem *P, int format, double *x, double tol, double inn
         MFE_HIP_TRY(hipGetLastError());
         MFE_TRY(launch_finalize(kFinStart, partials, g, inner, s));
         CgState in{};
-        const int k = kGraphIters < max_inner ? kGraphIters : max_inner;
-        hipGraphExec_t exec = nullptr;
-        MFE_TRY(graph_for(P, format, true, d32, r32, p32, q32, inner, k, &exec));
-        MFE_TRY(run_iterations(P, exec, inner, k, max_inner, &in));
+        IterGraphs G;
+        MFE_TRY(iteration_graphs(P, format, true, d32, r32, p32, q32, inner, max_inner, 0, &G));
+        // the inner solve starts at relative residual 1 (its right-hand side is
+        // its starting residual)
+        Forecast fc;
+        fc.slope = P->rate[3];
+        MFE_TRY(run_iterations(P, G, inner, max_inner, 0, fc, fc.observe(0, 1.0, eff), &in));
+        record_rate(P, 3, 1.0, in, 0);
         inner_its += in.iters;
         spmvs += in.iters;
         ++nouter;
