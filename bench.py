@@ -167,8 +167,9 @@ def cpu_baseline(N, gpu_iters, its=(2, 42), its_omp=(4, 204)):
                sample=f"{N}^3 FP64 CRS oracle CG, {n} iterations timed as cg(max_iter={its[1]}) minus "
                       f"cg(max_iter={its[0]}) on one host core (gcc -O2, generic x86-64); assembly untimed",
                host=host_cpu(), paper_context=PAPER_CONTEXT)
+    tmp = tempfile.TemporaryDirectory(prefix="oracle_timing_")  # removed below; loaded builds stay mapped
     try:
-        d = tempfile.mkdtemp(prefix="oracle_timing_")
+        d = tmp.name
         native = oracle.load_timing_build(obuild.build_timing(d))
         s1 = time_oracle_cg(A, its, native)
         out["native_O3_one_core"] = dict(value=1.0 / s1, unit="CG iter/s", cores=1,
@@ -199,6 +200,8 @@ def cpu_baseline(N, gpu_iters, its=(2, 42), its_omp=(4, 204)):
                                                        "measured seconds per iteration")
     except (OSError, subprocess.CalledProcessError) as e:
         out["native_builds_error"] = str(e)
+    finally:
+        tmp.cleanup()
     return out
 
 
