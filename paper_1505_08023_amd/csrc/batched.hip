@@ -24,6 +24,10 @@
 #include "device_util.hpp"
 #include "spmv_rows.hpp"
 
+#ifndef MFE_BATCH_SCALAR_WALK
+#define MFE_BATCH_SCALAR_WALK 1  // FP64 1x3 BCRS, one slice per wavefront: the scalar read-ahead walk
+#endif
+
 namespace mfe {
 namespace {
 
@@ -90,6 +94,22 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
         const int64_t s_lo = lo >> 6, s_hi = (hi + 63) >> 6;
         constexpr int W = kBlock / 64;
+        if constexpr (L == 1 && std::is_same<T, double>::value && MFE_BATCH_SCALAR_WALK) {
+            // FP64, one slice per wavefront: the scalar read-ahead walk of the
+            // single-system product (only the next slice's bounds and
+            // descriptor are read ahead, with scalar loads)
+            B13Ahead cur, nxt;
+            b13_ahead(slot_base, desc, s_lo + wave < s_hi ? s_lo + wave : -1, cur);
+            for (int64_t sl = s_lo + wave; sl < s_hi; sl += W) {
+                b13_ahead(slot_base, desc, sl + W < s_hi ? sl + W : -1, nxt);
+                const int64_t row = sl * 64 + lane;
+                if (row >= lo && row < hi) {
+                    const double opnd = operand(row);
+                    emit(row, b13_row_ahead<T>(cur, jas, bval, sl, lane, x), opnd);
+                }
+                cur = nxt;
+            }
+        } else {
         constexpr int SP = W * L;  // slices per pass
         B13Idx cur[L], nxt[L];
         auto fetch = [&](int64_t sb, B13Idx *r) {
@@ -119,6 +139,7 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
             }
 #pragma unroll
             for (int j = 0; j < L; ++j) cur[j] = nxt[j];
+        }
         }
     } else {
         constexpr int R = kBlock / L;  // rows per pass

@@ -443,13 +443,8 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t 
 // vector memory counter (which also counts stores) falls between that store
 // and the next tile's loads: the store's latency overlaps them.  Descriptor
 // slices form their column indices from the carried scalars; the few others
-// load theirs in place.  Arithmetic and summation order are those of
-// k_spmv_b13.
-struct B13Ahead {
-    int32_t k0, k1;  // slot_base[s], slot_base[s + 1]
-    B13Desc D;
-};
-
+// load theirs in place (b13_ahead, b13_row_ahead).  Arithmetic and
+// summation order are those of k_spmv_b13.
 template <typename T, int MODE, bool MNT>
 __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13s(int64_t m, const int32_t *__restrict__ slot_base,
                                                       const int32_t *__restrict__ jas,
@@ -462,39 +457,20 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13s(int64_t 
     double d1 = 0.0, d2 = 0.0;
     const TileSeq q = tile_seq(ntiles, MFE_B13_SUPER);
     const int64_t nslices = (m + 63) / 64;
-    auto ahead = [&](long j, B13Ahead &a) {
-        a.k0 = a.k1 = 0;
-        if (!q.valid(j)) return;
+    auto slice = [&](long j) -> int64_t {  // this wavefront's slice of the j-th tile, or -1
+        if (!q.valid(j)) return -1;
         const int64_t s = (int64_t)q.tile(j) * (kBlock / 64) + wave;
-        if (s >= nslices) return;
-        a.k0 = slot_base[s];
-        a.k1 = slot_base[s + 1];
-        a.D = desc[s];
+        return s < nslices ? s : -1;
     };
     B13Ahead cur, nxt;
-    ahead(q.i, cur);
+    b13_ahead(slot_base, desc, slice(q.i), cur);
     for (long j = q.i; q.valid(j); j += q.step) {
-        ahead(j + q.step, nxt);
+        b13_ahead(slot_base, desc, slice(j + q.step), nxt);
         const int64_t s = (int64_t)q.tile(j) * (kBlock / 64) + wave;
         const int64_t row = s * 64 + lane;
         if (row < m) {
             const double opnd = row_operand<T, MODE>(E, row);
-            B13Idx r;
-            r.sl = b13_slice(cur.k0, cur.k1);
-            T sum;
-            if (r.sl.S == 9) {
-                if (cur.D.uniform) {
-                    const uint32_t bits = lane < 32 ? cur.D.e_lo : cur.D.e_hi;
-                    const int32_t base = (int32_t)row + (int32_t)((bits >> (lane & 31)) & 1u);
-#pragma unroll
-                    for (int k = 0; k < 9; ++k) r.c[k] = base + cur.D.d[k];
-                } else {
-                    b13_load_idx<MNT>(jas, lane, r);
-                }
-                sum = b13_row9_idx<T, MNT>(r.c, val, r.sl, lane, E.x);
-            } else {
-                sum = b13_row_generic<T, MNT>(jas, val, r.sl, lane, E.x);
-            }
+            const T sum = b13_row_ahead<T, MNT>(cur, jas, val, s, lane, E.x);
             const T v = row_result<T, MODE>(sum, opnd, d1, d2);
             row_store<T, MODE>(E, row, v);
         }

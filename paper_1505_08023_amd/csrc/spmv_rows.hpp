@@ -129,6 +129,42 @@ __device__ __forceinline__ T b13_row9_idx(const int32_t *c, const T *val, const 
     return sum;
 }
 
+// Wavefront-uniform data of a slice, read one slice ahead with scalar loads
+// (the scalar read-ahead walks): its slot range and descriptor.
+struct B13Ahead {
+    int32_t k0, k1;  // slot_base[s], slot_base[s + 1]
+    B13Desc D;
+};
+
+// s wavefront-uniform; s < 0 (no slice) leaves an empty slot range.
+__device__ __forceinline__ void b13_ahead(const int32_t *__restrict__ slot_base, const B13Desc *__restrict__ desc,
+                                          int64_t s, B13Ahead &a) {
+    a.k0 = a.k1 = 0;
+    if (s < 0) return;
+    a.k0 = slot_base[s];
+    a.k1 = slot_base[s + 1];
+    a.D = desc[s];
+}
+
+// Row 64 s + lane of slice s from its read-ahead data: descriptor slices form
+// their column indices from it, the others load theirs here.
+template <typename T, bool NT = (MFE_MATRIX_NT != 0)>
+__device__ __forceinline__ T b13_row_ahead(const B13Ahead &a, const int32_t *__restrict__ jas,
+                                           const T *__restrict__ val, int64_t s, int lane, const T *__restrict__ x) {
+    B13Idx r;
+    r.sl = b13_slice(a.k0, a.k1);
+    if (r.sl.S != 9) return b13_row_generic<T, NT>(jas, val, r.sl, lane, x);
+    if (a.D.uniform) {
+        const uint32_t bits = lane < 32 ? a.D.e_lo : a.D.e_hi;
+        const int32_t base = (int32_t)(s * 64 + lane) + (int32_t)((bits >> (lane & 31)) & 1u);
+#pragma unroll
+        for (int k = 0; k < 9; ++k) r.c[k] = base + a.D.d[k];
+    } else {
+        b13_load_idx<NT>(jas, lane, r);
+    }
+    return b13_row9_idx<T, NT>(r.c, val, r.sl, lane, x);
+}
+
 // 1x3 BCRS row 64 s + lane (one lane per row; s wavefront-uniform).
 template <typename T, bool NT = (MFE_MATRIX_NT != 0)>
 __device__ __forceinline__ T b13_row(const int32_t *__restrict__ slot_base, const int32_t *__restrict__ jas,
