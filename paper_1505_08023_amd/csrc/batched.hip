@@ -24,8 +24,11 @@
 #include "device_util.hpp"
 #include "spmv_rows.hpp"
 
+#ifndef MFE_CG_TAIL
+#define MFE_CG_TAIL 1  // short graphs at the forecast end of a solve (0: fixed length)
+#endif
 #ifndef MFE_BATCH_SCALAR_WALK
-#define MFE_BATCH_SCALAR_WALK 1  // FP64 1x3 BCRS, one slice per wavefront: the scalar read-ahead walk
+#define MFE_BATCH_SCALAR_WALK 1  // 1x3 BCRS, one slice per wavefront: the scalar read-ahead walk
 #endif
 
 namespace mfe {
@@ -94,9 +97,9 @@ __global__ __launch_bounds__(kBlock) void k_bspmv(const int32_t *__restrict__ pt
         const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
         const int64_t s_lo = lo >> 6, s_hi = (hi + 63) >> 6;
         constexpr int W = kBlock / 64;
-        if constexpr (L == 1 && std::is_same<T, double>::value && MFE_BATCH_SCALAR_WALK) {
-            // FP64, one slice per wavefront: the scalar read-ahead walk of the
-            // single-system product (only the next slice's bounds and
+        if constexpr (L == 1 && MFE_BATCH_SCALAR_WALK) {
+            // one slice per wavefront: the scalar read-ahead walk of the
+            // single-system FP64 product (only the next slice's bounds and
             // descriptor are read ahead, with scalar loads)
             B13Ahead cur, nxt;
             b13_ahead(slot_base, desc, s_lo + wave < s_hi ? s_lo + wave : -1, cur);
@@ -614,7 +617,7 @@ int batch_graphs(mfe_batch *B, int format, const Tuning &t, bool f32, T *x, T *r
     MFE_TRY(graph_for_batch<T>(B, format, t, f32, x, r, p, q, st, G->k, &G->exec));
     G->tail = nullptr;
     G->kt = 0;
-    if (G->k > kTailIters) {
+    if (MFE_CG_TAIL && G->k > kTailIters) {
         G->kt = kTailIters;
         MFE_TRY(graph_for_batch<T>(B, format, t, f32, x, r, p, q, st, G->kt, &G->tail));
     }

@@ -22,6 +22,10 @@
 
 #include "common.hpp"
 
+#ifndef MFE_CG_TAIL
+#define MFE_CG_TAIL 1  // short graphs at the forecast end of a solve, none launched ahead past it (0: fixed length)
+#endif
+
 // Iteration graphs kept per problem, keyed by solver kind, format, precision,
 // solution buffer, graph length and state slot.
 constexpr int kMaxGraphs = 32;
@@ -184,7 +188,7 @@ int iteration_graphs(mfe_problem *P, int format, bool f32, void *x, void *r, voi
     MFE_TRY(graph_for(P, format, f32, x, r, p, q, st, G->k, &G->exec, kind));
     G->tail = nullptr;
     G->kt = 0;
-    if (G->k > kTailIters) {
+    if (MFE_CG_TAIL && G->k > kTailIters) {
         G->kt = kTailIters;
         MFE_TRY(graph_for(P, format, f32, x, r, p, q, st, G->kt, &G->tail, kind));
     }
@@ -211,7 +215,7 @@ int run_iterations(mfe_problem *P, const IterGraphs &G, const CgState *st, int m
             const long ahead = launched - polled;
             // the device stops at max_iter in any case
             const double r = std::min(rem, (double)(max_iter - polled));
-            if (count > 0 && r <= (double)ahead) break;  // the end is forecast within the graphs in flight
+            if (MFE_CG_TAIL && count > 0 && r <= (double)ahead) break;  // the end is forecast within the graphs in flight
             const bool tail = G.tail && r <= (double)(ahead + G.k);
             const int slot = (head + count) & 1;
             MFE_HIP_TRY(hipGraphLaunch(tail ? G.tail : G.exec, s));
