@@ -670,7 +670,8 @@ bool any_running(const std::vector<CgState> &v) {
 // system's end.  Once the running systems hold at most 60 % of the rows the
 // grid is spread over, the same grid is spread over them alone (the graphs
 // keep their launch shape and read the map at replay), so the systems that
-// remain take the whole GPU; the full map is restored at the end.
+// remain take the whole GPU; this is decided at multiples of kGraphIters
+// iterations only, and the full map is restored at the end.
 int run_batch(mfe_batch *B, const BatchGraphs &G, const CgState *st, int max_iter, std::vector<double> &rates,
               std::vector<CgState> &fin) {
     hipStream_t s = B->ctx->stream;
@@ -707,7 +708,10 @@ int run_batch(mfe_batch *B, const BatchGraphs &G, const CgState *st, int max_ite
         for (int j = 0; j < ns; ++j)
             if (fin[j].status == kRunning)
                 rem = std::max(rem, fc[j].observe(fin[j].iters, stop_residual(fin[j], 0), fin[j].tol));
-        if (MFE_BATCH_REMAP) {
+        // the map decides each system's reduction order: it changes only at
+        // multiples of kGraphIters iterations, so that results do not depend
+        // on the graph lengths the forecast picks
+        if (MFE_BATCH_REMAP && launched % kGraphIters == 0) {
             std::vector<char> on(B->nsys, 0);
             int64_t active = 0, nact = 0;
             for (int j = 0; j < B->nsys; ++j)

@@ -79,13 +79,18 @@ def test_repeated_mixed_solves_agree_bitwise(ctx, keep):
     P.close()
 
 
-def test_repeated_batched_solves_agree_bitwise(ctx):
+@pytest.mark.parametrize("mixed", [False, True])
+def test_repeated_batched_solves_agree_bitwise(ctx, mixed):
+    """Uneven meshes, so that the small systems stop early and the grid is
+    spread over the remaining ones (the batched driver does that at
+    multiples of the long graph length only, whatever graphs it launches)."""
     from paper_1505_08023_amd.mfe import Batch
-    print("batched repeat", flush=True)
-    sizes, faces = inputs.batched_meshes(nsys=7, lo=3, hi=20, seed=11)
-    B = Batch(ctx, sizes, faces)
-    runs = [B.cg(tol=1e-9) for _ in range(3)]
+    print("batched repeat", mixed, flush=True)
+    sizes, faces = inputs.batched_meshes(nsys=9, lo=3, hi=36, seed=11)
+    B = Batch(ctx, sizes, faces, precisions=("f64", "f32") if mixed else ("f64",))
+    runs = [(B.cg_mixed(tol=1e-9) if mixed else B.cg(tol=1e-9)) for _ in range(3)]
     x0, s0 = runs[0]
+    assert all(s["status"] == 0 for s in s0)
     for x, st in runs[1:]:
         assert [s["iterations"] for s in st] == [s["iterations"] for s in s0]
         assert same(x, x0)
