@@ -182,19 +182,31 @@ def cpu_baseline(N, gpu_iters, its=(2, 42), its_omp=(4, 204)):
                                           sample=f"{its_omp[1] - its_omp[0]} iterations, the same loops with "
                                                  f"OpenMP over {threads} threads, gcc -O3 -march=native -fopenmp")
         log(f"[bench] oracle -O3 -march=native, {threads} threads: {1.0 / sm:.3f} it/s")
-        # the CRS product alone (median of 10, x ~ U[-1, 1) as on the GPU) and
-        # the time to 1e-8 extrapolated from the iteration rate
+        # the CRS and the 1x3 BCRS products alone (median of 10, x ~ U[-1, 1)
+        # as on the GPU; the paper's own comparison, on this host) and the
+        # time to 1e-8 extrapolated from the iteration rate
         from paper_1505_08023_amd import inputs
         xv = inputs.spmv_vector(A.m, seed=0)
-        for lib, key in ((native, "native_O3_one_core"), (omp, "native_O3_all_cores")):
+        b13 = oracle.bcrs13(A)
+        nb = len(b13[1])
+
+        def median_ms(fn):
             ts = []
             for _ in range(10):
                 t = time.perf_counter()
-                oracle.csr_spmv(A, xv, library=lib)
+                fn()
                 ts.append(time.perf_counter() - t)
-            ms = sorted(ts)[5] * 1e3
+            return sorted(ts)[5] * 1e3
+        for lib, key in ((native, "native_O3_one_core"), (omp, "native_O3_all_cores")):
+            ms = median_ms(lambda: oracle.csr_spmv(A, xv, library=lib))
             out[key]["spmv_ms"] = ms
             out[key]["spmv_GBps"] = algorithmic_bytes("csr", A.m, A.nnz, 0) / (ms * 1e-3) / 1e9
+            mb = median_ms(lambda: oracle.bcrs13_spmv(A, b13, xv, library=lib))
+            out[key]["bcrs13_spmv_ms"] = mb
+            out[key]["bcrs13_spmv_GBps"] = algorithmic_bytes("bcrs13", A.m, A.nnz, nb) / (mb * 1e-3) / 1e9
+            out[key]["bcrs13_over_csr_spmv"] = ms / mb
+            log(f"[bench] oracle products, {key}: CRS {ms:.1f} ms, 1x3 BCRS {mb:.1f} ms")
+        del b13
         out["native_O3_all_cores"]["time_to_1e-8_s_extrapolated"] = gpu_iters * sm
         out["native_O3_all_cores"]["extrapolation"] = (f"{gpu_iters} iterations (the GPU solve's count) x the "
                                                        "measured seconds per iteration")

@@ -229,11 +229,14 @@ def bcrs13(A):
     return bptr, bcol, bval
 
 
-def bcrs13_spmv(A, fmt, x):
+def bcrs13_spmv(A, fmt, x, library=None):
+    """y = A x over the 1x3 blocks of bcrs13(A), each block's three products
+    in column order (Figs 3.2/3.3 with n = 3).  library: a timing build
+    (load_timing_build) instead of the oracle's own."""
     bptr, bcol, bval = fmt
     x = np.ascontiguousarray(x, np.float64)
     y = np.empty(A.m)
-    lib().orc_bcrs13_spmv(A.m, bptr, bcol, bval, x, y)
+    (library or lib()).orc_bcrs13_spmv(A.m, bptr, bcol, bval, x, y)
     return y
 
 

@@ -47,8 +47,8 @@
 #include <string.h>
 
 /* The benchmark's CPU baseline also times this file built with -fopenmp:
- * the row loop of the CRS product and the vector loops and dot products of
- * orc_cg then run over the host's cores (the dots' partial sums combined in
+ * the row loops of the CRS and 1x3 BCRS products and the vector loops and
+ * dot products of orc_cg then run over the host's cores (the dots' partial sums combined in
  * OpenMP's reduction order).  The plain build, the oracle, ignores these
  * annotations: single-threaded, every sum in the order stated. */
 #define ORC_PRAGMA(x) _Pragma(#x)
@@ -463,6 +463,7 @@ int64_t orc_bcrs13_build(int64_t m, const int64_t *ptr, const int32_t *col, cons
 void orc_bcrs13_spmv(int64_t m, const int64_t *bptr, const int32_t *bcol, const double *bval,
                      const double *x, double *y)
 {
+    ORC_PARALLEL_FOR
     for (int64_t i = 0; i < m; ++i) {
         double s = 0.0;
         for (int64_t j = bptr[i]; j < bptr[i + 1]; ++j) {
