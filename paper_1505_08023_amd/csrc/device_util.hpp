@@ -85,9 +85,9 @@ __device__ __forceinline__ TileRange tile_range(long ntiles) {
 // Tile order of the 1x3 BCRS walks: the grid moves through the tiles in
 // super-tiles of 8 S tiles, and inside each the XCD k takes the k-th run of S
 // consecutive tiles, its workgroups striding through the XCD's runs in turn.
-// S = 1 is the grid-wide order, S >= ntiles / 8 the XCD-contiguous one;
-// between them each XCD's L2 keeps the x entries of its runs while the chip
-// still reads one region of the matrix at a time.  gridDim.x must be a
+// S = 1 is the grid-wide order, and S near ntiles / 8 comes close to the
+// XCD-contiguous one; between them each XCD's L2 keeps the x entries of its
+// runs while the chip still reads one region of the matrix at a time.  gridDim.x must be a
 // multiple of kNumXcd.
 struct TileSeq {
     long i, step, S, ntiles;
