@@ -1,5 +1,7 @@
 """Host-side logic of the benchmark: the algorithmic byte counts against the
 structure the oracle builds (nnz, 1x3 blocks) and the closed forms."""
+import os
+
 import numpy as np
 import pytest
 
@@ -111,3 +113,26 @@ def test_csr_group_walk_bytes_and_closed_form():
     by = bench.spmv_bytes("csr", m, nnz, 0, layout=lay)
     assert by == 8 * nnz + 8 * lay["items"] + 4 * groups + 12 * other + 4 * (nnz - 27 * grows) + 16 * m
     assert by < bench.spmv_bytes("csr", m, nnz, 0)
+
+
+def test_cpu_baseline_fields_at_a_small_mesh():
+    """The CPU baseline as the bench computes it, on a 12^3 mesh: the
+    oracle's own build, the two native builds, both products' times and the
+    extrapolation from the GPU solve's iteration count."""
+    import glob
+    import tempfile
+
+    import bench
+    before = set(glob.glob(os.path.join(tempfile.gettempdir(), "oracle_timing_*")))
+    out = bench.cpu_baseline(12, 57, its=(1, 4), its_omp=(1, 4))
+    assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] == 1
+    assert out.get("native_builds_error") is None, out.get("native_builds_error")
+    for key in ("native_O3_one_core", "native_O3_all_cores"):
+        o = out[key]
+        assert o["value"] > 0 and o["spmv_ms"] > 0 and o["bcrs13_spmv_ms"] > 0
+        assert abs(o["bcrs13_over_csr_spmv"] - o["spmv_ms"] / o["bcrs13_spmv_ms"]) < 1e-12
+    allc = out["native_O3_all_cores"]
+    assert abs(allc["time_to_1e-8_s_extrapolated"] - 57 / allc["value"]) < 1e-9
+    assert allc["extrapolation"].startswith("57 iterations")
+    # the timing builds' temporary directory is removed
+    assert set(glob.glob(os.path.join(tempfile.gettempdir(), "oracle_timing_*"))) <= before
