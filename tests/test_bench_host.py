@@ -116,15 +116,17 @@ def test_csr_group_walk_bytes_and_closed_form():
 
 
 def test_cpu_baseline_fields_at_a_small_mesh():
-    """The CPU baseline as the bench computes it, on a 12^3 mesh: the
-    oracle's own build, the two native builds, both products' times and the
-    extrapolation from the GPU solve's iteration count."""
+    """The CPU baseline as the bench computes it, on a 28^3 mesh (whose CG
+    needs more than the 30 iterations timed, so the timed difference of two
+    capped solves is 28 iterations): the oracle's own build, the two native
+    builds, both products' times and the extrapolation from the GPU solve's
+    iteration count."""
     import glob
     import tempfile
 
     import bench
     before = set(glob.glob(os.path.join(tempfile.gettempdir(), "oracle_timing_*")))
-    out = bench.cpu_baseline(12, 57, its=(1, 4), its_omp=(1, 4))
+    out = bench.cpu_baseline(28, 57, its=(2, 30), its_omp=(2, 30))
     assert out["kind"] == "oracle" and out["value"] > 0 and out["cores"] == 1
     assert out.get("native_builds_error") is None, out.get("native_builds_error")
     for key in ("native_O3_one_core", "native_O3_all_cores"):
