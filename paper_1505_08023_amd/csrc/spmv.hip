@@ -2,9 +2,11 @@
 // epilogues (the DOT that follows MATVEC in CG, Sec. 3.1 discussion of
 // Fig 3.5, and the residual at CG start/exit).
 //
-//   CRS (Fig 3.1):  16-row wavefront tiles staged in LDS, 4 lanes per row
-//                   over the row's (val, col) pairs, gathers of x, an xor
-//                   butterfly per row.
+//   CRS (Fig 3.1):  mesh problems by row groups (up to 64 consecutive
+//                   full rows per wavefront, their values staged in LDS,
+//                   one lane per row); other matrices by 16-row wavefront
+//                   tiles staged in LDS, 4 lanes per row over the row's
+//                   (val, col) pairs, an xor butterfly per row.
 //   1x3 BCRS:       one lane per row; per block one column index and three
 //                   values, all coalesced across the wavefront's 64 rows,
 //                   and three consecutive x entries (the implicit column
@@ -368,8 +370,9 @@ __global__ __launch_bounds__(kBlock) void k_spmv_csrg(const int32_t *__restrict_
 
 // ---------------------------------------------------------------- 1x3 BCRS
 
-// One slice per wavefront per tile: slice bounds, column indices, values,
-// gathers, in that dependent order.
+// Plain walk (the FP32 product on small grids): one slice per wavefront per
+// tile; slice bounds, column indices, values, gathers, in that dependent
+// order.
 template <typename T, int MODE, bool MNT>
 __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13(int64_t m, const int32_t *__restrict__ slot_base,
                                                      const int32_t *__restrict__ jas,
