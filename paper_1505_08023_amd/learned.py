@@ -118,7 +118,8 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
     the zero start when the guess's residual is not below ||b||), and, with
     mixed, the FP32-inner / FP64-refinement solve from zero and from the guess
     (the learned + mixed-precision form; inner_tol and keep_direction as in
-    Problem.cg_mixed).  All solves stop at the same
+    Problem.cg_mixed), and, for context, plain FP64 CG from the trivial guess
+    that holds g on the boundary and 0 inside.  All solves stop at the same
     tolerance on ||b - A x|| / ||b||.  Every variant runs once on the first
     seed before timing (graph capture).  Times are host wall clock,
     GPU-synchronised.  With errors, every solution's ||x - x_ref|| / ||x_ref||
@@ -128,6 +129,12 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
     x = torch.zeros(V, dtype=torch.float64, device=ctx.device)
     x0 = torch.zeros(V, dtype=torch.float64, device=ctx.device)
     xr = torch.zeros(V, dtype=torch.float64, device=ctx.device)
+    # boundary nodes of the (n+1)^3 grid, x fastest: the trivial guess keeps
+    # g there and 0 inside (r = 0 on the Dirichlet rows, as the network's
+    # guess, whose boundary values are exact, also has)
+    ids = np.arange(V)
+    gx, gy, gz = ids % (n + 1), (ids // (n + 1)) % (n + 1), ids // ((n + 1) ** 2)
+    on_b = torch.tensor((gx == 0) | (gx == n) | (gy == 0) | (gy == n) | (gz == 0) | (gz == n), device=ctx.device)
 
     def err(v):
         return float(torch.linalg.norm(v - xr) / torch.linalg.norm(xr))
@@ -157,8 +164,13 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
         r["t_learned"], st1 = timed(learned_fp64)
         if errors:
             r["err_learned"] = err(x0)
+
+        def boundary_fp64():
+            torch.where(on_b, g, torch.zeros_like(g), out=x)
+            return P.cg(x, tol=tol, max_iter=20000)[1]
+        r["t_boundary"], stb = timed(boundary_fp64)
         r.update(its_plain=st0["iterations"], its_learned=st1["iterations"], used=not st1["guess_rejected"],
-                 res_plain=st0["rel_res_true"], res_learned=st1["rel_res_true"])
+                 res_plain=st0["rel_res_true"], res_learned=st1["rel_res_true"], its_boundary=stb["iterations"])
         if mixed:
             x.zero_()
             r["t_mixed"], st2 = timed(lambda: P.cg_mixed(x, tol=tol, inner_tol=inner_tol,
@@ -189,7 +201,10 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
                mean_time_plain_s=a("t_plain"), mean_time_learned_s=a("t_learned"),
                mean_guess_rel_res=a("guess_rel_res"), guesses_used=int(sum(r["used"] for r in rows)),
                worst_res_learned=max(r["res_learned"] for r in rows),
-               speedup_time=a("t_plain") / a("t_learned"))
+               speedup_time=a("t_plain") / a("t_learned"),
+               # context: the trivial guess (g on the boundary, 0 inside)
+               mean_its_boundary_start=a("its_boundary"), mean_time_boundary_start_s=a("t_boundary"),
+               speedup_time_vs_boundary_start=a("t_boundary") / a("t_learned"))
     if mixed:
         out.update(mean_its_mixed=a("its_mixed"), mean_its_learned_mixed=a("its_learned_mixed"),
                    mean_time_mixed_s=a("t_mixed"), mean_time_learned_mixed_s=a("t_learned_mixed"),

@@ -393,5 +393,7 @@ def test_trained_network_reduces_cg_iterations(ctx):
     assert ev["worst_res_learned"] <= 1e-8 and ev["worst_res_learned_mixed"] <= 1e-8
     assert ev["mean_its_learned"] <= 0.85 * ev["mean_its_plain"]
     assert ev["mean_its_learned_mixed"] < ev["mean_its_mixed"]
+    # and than from the trivial guess that is exact on the boundary only
+    assert ev["mean_its_learned"] < ev["mean_its_boundary_start"] <= ev["mean_its_plain"]
     assert ev["mean_guess_rel_res"] < 1e-2
     net.close()
