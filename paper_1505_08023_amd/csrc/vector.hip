@@ -29,21 +29,6 @@ template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ r, const T *__restrict__ q,
                                                      CgState *st, const double *__restrict__ pq_part, int n_pq,
                                                      double *__restrict__ rr_part) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    // 16 bytes per vector access (the pointers need only element alignment),
-    // then the < W trailing elements (69.1 -> 64.9 us at 256^3)
-    using V = Vec16<T>;
-    constexpr int W = V::W;
-    const int64_t mv = m / W;
-    // The thread's first r and q are loaded before the entry test and the
-    // p.q sum, so that the three waits overlap (on a small mesh this is the
-    // thread's whole share); a stopped solve discards them.
-    typename V::t r0 = {}, q0 = {};
-    if (gid < mv) {
-        r0 = ((const typename V::t *)r)[gid];
-        q0 = stream_load((const typename V::t *)q + gid, NT);
-    }
     if (st->status != kRunning) return;
     const double pq = sum_partials(pq_part, n_pq);
     const double rho = st->rho;
@@ -63,7 +48,16 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ 
     }
     const T a = (T)alpha;
     double d = 0.0;
-    auto update = [&](int64_t i, typename V::t rv, const typename V::t &qv) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    // 16 bytes per vector access (the pointers need only element alignment),
+    // then the < W trailing elements (69.1 -> 64.9 us at 256^3)
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t mv = m / W;
+    for (int64_t i = gid; i < mv; i += stride) {
+        typename V::t rv = ((const typename V::t *)r)[i];
+        const typename V::t qv = stream_load((const typename V::t *)q + i, NT);
 #pragma unroll
         for (int j = 0; j < W; ++j) {
             const T ri = rv[j] - a * qv[j];
@@ -71,10 +65,7 @@ __global__ __launch_bounds__(kBlock) void k_update_r(int64_t m, T *__restrict__ 
             d += (double)ri * (double)ri;
         }
         ((typename V::t *)r)[i] = rv;
-    };
-    if (gid < mv) update(gid, r0, q0);
-    for (int64_t i = gid + stride; i < mv; i += stride)
-        update(i, ((const typename V::t *)r)[i], stream_load((const typename V::t *)q + i, NT));
+    }
     for (int64_t i = mv * W + gid; i < m; i += stride) {
         const T ri = r[i] - a * stream_load(q + i, NT);
         r[i] = ri;
@@ -88,16 +79,6 @@ template <typename T, bool NT>
 __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__ x, T *__restrict__ p,
                                                       const T *__restrict__ r, CgState *st,
                                                       const double *__restrict__ rr_part, int n_rr) {
-    const int64_t stride = (int64_t)gridDim.x * kBlock;
-    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    // the thread's first x, p and r before the entry test and the r.r sum,
-    // as in k_update_r
-    T x0 = 0, p0 = 0, r0 = 0;
-    if (gid < m) {
-        p0 = p[gid];
-        x0 = stream_load(x + gid, NT);
-        r0 = stream_load(r + gid, NT);
-    }
     if (!st->active) return;
     const double rho_new = sum_partials(rr_part, n_rr);
     const double alpha = st->alpha, rho_old = st->rho_old;
@@ -117,11 +98,8 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__
     // (16-byte vector accesses were measured no faster here: 114.7 against
     // 113.4 us at 256^3)
     const T a = (T)alpha, be = (T)beta;
-    if (gid < m) {
-        stream_store(x0 + a * p0, x + gid, NT);
-        p[gid] = r0 + be * p0;
-    }
-    for (int64_t i = gid + stride; i < m; i += stride) {
+    const int64_t stride = (int64_t)gridDim.x * kBlock;
+    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
         const T pi = p[i];
         stream_store(stream_load(x + i, NT) + a * pi, x + i, NT);
         p[i] = stream_load(r + i, NT) + be * pi;
