@@ -97,7 +97,11 @@ __global__ __launch_bounds__(256) void k_conv(const bf16 *__restrict__ in, int G
     const int s0 = blockIdx.z * steps_per_split;
     const int s1 = min(s0 + steps_per_split, Kpad >> 5);
     const int row = lane & 15, kg = lane >> 4;
-    const int64_t Vo = (int64_t)Go * Go * Go, Vi = (int64_t)Gi * Gi * Gi;
+    const int64_t Vi = (int64_t)Gi * Gi * Gi;
+    // Voxel coordinates by 32-bit division (the launchers keep total below
+    // 2^31): 64-bit division has no hardware path and cost more issue time
+    // than the products at batch 1.
+    const uint32_t uGo = (uint32_t)Go, uVo = uGo * uGo * uGo;
     int pz[MT], py[MT], px[MT];
     int64_t nb[MT];
     bool rv[MT];
@@ -105,12 +109,12 @@ __global__ __launch_bounds__(256) void k_conv(const bf16 *__restrict__ in, int G
     for (int mt = 0; mt < MT; ++mt) {
         const int64_t v = base + mt * 16 + row;
         rv[mt] = v < total;
-        const int64_t vv = rv[mt] ? v : 0;
-        const int64_t n = vv / Vo, p = vv % Vo;
-        px[mt] = (int)(p % Go);
-        py[mt] = (int)((p / Go) % Go);
-        pz[mt] = (int)(p / ((int64_t)Go * Go));
-        nb[mt] = n * Vi;
+        const uint32_t vv = rv[mt] ? (uint32_t)v : 0u;
+        const uint32_t n = vv / uVo, p = vv - n * uVo, q = p / uGo, z = q / uGo;
+        px[mt] = (int)(p - q * uGo);
+        py[mt] = (int)(q - z * uGo);
+        pz[mt] = (int)z;
+        nb[mt] = (int64_t)n * Vi;
     }
     f32x4 acc[MT][NT];
 #pragma unroll
@@ -180,7 +184,7 @@ __global__ __launch_bounds__(256) void k_conv_reduce(const float *__restrict__ p
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += stride) {
         float val = 0.0f;
         for (int z = 0; z < nsplit; ++z) val += part[(int64_t)z * n + i];
-        if (bias) val += bias[i % Cout];
+        if (bias) val += bias[i & (Cout - 1)];  // Cout is a power of two
         if (add) val += (float)add[i];
         if (relu) val = fmaxf(val, 0.0f);
         out[i] = (bf16)val;
@@ -393,24 +397,31 @@ __global__ __launch_bounds__(256) void k_conv_t2(const bf16 *__restrict__ in, in
     const int64_t cvox = (int64_t)ex * ey * ez, count = (int64_t)batch * cvox;
     const int64_t base = (wave - T.tile0[c]) * 16 * MT;
     const int Go = 2 * Gi - 1;
-    const int64_t Vi = (int64_t)Gi * Gi * Gi, Vo = (int64_t)Go * Go * Go;
+    const int64_t Vi = (int64_t)Gi * Gi * Gi;
     const int o0 = blockIdx.y * 16 * NT;
     const int row = lane & 15, kg = lane >> 4;
     const int Kc = t2_ntaps(c) << cin_log2, Kcpad = L.kcpad[c];
     const int cmask = (1 << cin_log2) - 1;
-    int jx[MT], jy[MT], jz[MT];
+    // Class coordinates by 32-bit division (the launcher keeps the output
+    // voxel count below 2^31), and the flat output voxel of row `row` of each
+    // tile, which the epilogue fetches from that row's lane instead of
+    // dividing again.
+    const uint32_t uex = (uint32_t)ex, uey = (uint32_t)ey, ucv = (uint32_t)cvox;
+    const uint32_t uGo = (uint32_t)Go, uVo = uGo * uGo * uGo;
+    int jx[MT], jy[MT], jz[MT], ovr[MT];
     int64_t nb[MT];
     bool rv[MT];
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt) {
         const int64_t v = base + mt * 16 + row;
         rv[mt] = v < count;
-        const int64_t vv = rv[mt] ? v : 0;
-        const int64_t n = vv / cvox, r = vv % cvox;
-        jx[mt] = (int)(r % ex);
-        jy[mt] = (int)((r / ex) % ey);
-        jz[mt] = (int)(r / ((int64_t)ex * ey));
-        nb[mt] = n * Vi;
+        const uint32_t vv = rv[mt] ? (uint32_t)v : 0u;
+        const uint32_t n = vv / ucv, r = vv - n * ucv, q = r / uex, z = q / uey;
+        jx[mt] = (int)(r - q * uex);
+        jy[mt] = (int)(q - z * uey);
+        jz[mt] = (int)z;
+        nb[mt] = (int64_t)n * Vi;
+        ovr[mt] = (int)(n * uVo + ((2 * z + qz) * uGo + 2 * (uint32_t)jy[mt] + qy) * uGo + 2 * (uint32_t)jx[mt] + qx);
     }
     f32x4 acc[MT][NT];
 #pragma unroll
@@ -451,16 +462,19 @@ __global__ __launch_bounds__(256) void k_conv_t2(const bf16 *__restrict__ in, in
             for (int nt = 0; nt < NT; ++nt) b0[nt] = b1[nt];
         }
     }
+    // accumulator element j of lane (row, kg) is tile row 4 kg + j
+    int ovs[MT][4];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) ovs[mt][j] = __shfl(ovr[mt], 4 * kg + j, 64);
 #pragma unroll
     for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int64_t v = base + mt * 16 + 4 * kg + j;
             if (v >= count) continue;
-            const int64_t n = v / cvox, r = v % cvox;
-            const int px = 2 * (int)(r % ex) + qx, py = 2 * (int)((r / ex) % ey) + qy,
-                      pz = 2 * (int)(r / ((int64_t)ex * ey)) + qz;
-            const int64_t ov = n * Vo + ((int64_t)pz * Go + py) * Go + px;
+            const int64_t ov = ovs[mt][j];
 #pragma unroll
             for (int nt = 0; nt < NT; ++nt) {
                 const int o = o0 + nt * 16 + row;
@@ -493,7 +507,9 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ gy, int 
     const int64_t v_lo = (int64_t)split * per_split;
     const int64_t v_hi = v_lo + per_split < total ? v_lo + per_split : total;
     const int t = threadIdx.x, lane = t & 63, wave = t >> 6, row = lane & 15, kg = lane >> 4;
-    const int64_t Vo = (int64_t)Go * Go * Go, Vi = (int64_t)Gi * Gi * Gi;
+    const int64_t Vi = (int64_t)Gi * Gi * Gi;
+    // voxel coordinates by 32-bit division, as in k_conv (total < 2^31)
+    const uint32_t uGo = (uint32_t)Go, uVo = uGo * uGo * uGo;
     const int cmask = (1 << cin_log2) - 1;
     f32x4 acc[NT];
 #pragma unroll
@@ -514,10 +530,10 @@ __global__ __launch_bounds__(256) void k_wgrad(const bf16 *__restrict__ gy, int 
             const int k = kb * 64 + grp * 8;
             bf16x8 val = zero8();
             if (v < v_hi && k < Kreal) {
-                const int64_t n = v / Vo, p = v % Vo;
-                const int px = (int)(p % Go), py = (int)((p / Go) % Go), pz = (int)(p / ((int64_t)Go * Go));
+                const uint32_t uv = (uint32_t)v, n = uv / uVo, p = uv - n * uVo, q = p / uGo, z = q / uGo;
+                const int px = (int)(p - q * uGo), py = (int)(q - z * uGo), pz = (int)z;
                 const int64_t s = src_voxel<MODE>(pz, py, px, k >> cin_log2, Gi);
-                if (s >= 0) val = load8(X + ((n * Vi + s) << cin_log2) + (k & cmask));
+                if (s >= 0) val = load8(X + (((int64_t)n * Vi + s) << cin_log2) + (k & cmask));
             }
 #pragma unroll
             for (int j = 0; j < 8; ++j) xT[grp * 8 + j][vv] = val[j];
@@ -765,6 +781,10 @@ int conv_mode(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *W, int
         set_error("conv3d: output channels must be 8, 16, 32, 64 or 128");
         return MFE_EUNSUPPORTED;
     }
+    if (total >= ((int64_t)1 << 31)) {
+        set_error("conv3d: 2^31 or more output voxels in one call");
+        return MFE_EUNSUPPORTED;
+    }
     const int cl = ilog2(Cin), Kreal = 27 * Cin;
     const ConvPlan pl = conv_plan(total, Cout, Kpad, ws ? ws_floats : 0);
     float *part = pl.nsplit > 1 ? ws : nullptr;
@@ -804,6 +824,10 @@ int conv_t2(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *WC, int 
     }
     const T2Layout L = t2_layout(Cin, nt * 16);
     const int64_t total = (int64_t)batch * (2 * Gi - 1) * (2 * Gi - 1) * (2 * Gi - 1);
+    if (total >= ((int64_t)1 << 31)) {
+        set_error("conv3d: 2^31 or more output voxels in one call");
+        return MFE_EUNSUPPORTED;
+    }
     const ConvPlan pl = conv_plan(total, Cout, 64, 0);  // tile shape only
     T2Tiles T;
     T.tile0[0] = 0;
@@ -900,6 +924,10 @@ template <int MODE>
 int wgrad_mode(hipStream_t s, const bf16 *gy, int Go, int Cout, const bf16 *X, int Gi, int Cin, int Kpad, int batch,
                float *part, int nsplit) {
     const int64_t total = (int64_t)batch * Go * Go * Go;
+    if (total >= ((int64_t)1 << 31)) {
+        set_error("conv3d weight gradient: 2^31 or more output voxels in one call");
+        return MFE_EUNSUPPORTED;
+    }
     const int64_t per = ((total + nsplit - 1) / nsplit + 31) / 32 * 32;
     const int nt = (Cout + 15) / 16, cl = ilog2(Cin);
     const dim3 grid(Kpad / 64, nsplit);
