@@ -460,6 +460,24 @@ def test_cg_edge_cases(ctx):
     check_solution_gap(np_(x), ref, st, N, A)
 
 
+def test_mesh_size_limit(ctx):
+    """The structural count nnz = (3 Nx + 1)(3 Ny + 1)(3 Nz + 1) must stay below
+    2^31 for the 32-bit row pointers: 429^3 elements is the largest cube
+    (1288^3 entries) and one more per axis is refused with EUNSUPPORTED before
+    anything is allocated, as is a flat mesh whose rows would fit but whose
+    entries would not; the context stays usable."""
+    from paper_1505_08023_amd._lib import MfeError
+    assert (3 * 429 + 1) ** 3 < 2 ** 31 - 1 < (3 * 430 + 1) ** 3
+    for N in [(430, 430, 430), (2000, 2000, 60)]:
+        print("refused", N, flush=True)
+        with pytest.raises(MfeError, match="EUNSUPPORTED"):
+            mesh_problem(ctx, N)
+    P = mesh_problem(ctx, (4, 4, 4))
+    _, st = P.cg(tol=1e-10, max_iter=200)
+    assert st["status"] == 0
+    P.close()
+
+
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
 def test_cg_warm_start(ctx, fmt):
     """mfe_cg_warm keeps a guess closer than x0 = 0 and otherwise solves from
