@@ -83,24 +83,26 @@ __device__ __forceinline__ TileRange tile_range(long ntiles) {
 }
 
 // Tile order of the 1x3 BCRS walks: the grid moves through the tiles in
-// super-tiles of 8 S tiles, and inside each the XCD k takes the k-th run of S
-// consecutive tiles, its workgroups striding through the XCD's runs in turn.
-// S = 1 is the grid-wide order, and S near ntiles / 8 comes close to the
-// XCD-contiguous one; between them each XCD's L2 keeps the x entries of its
-// runs while the chip still reads one region of the matrix at a time.  gridDim.x must be a
-// multiple of kNumXcd.
+// super-tiles of 8 S tiles (S = 2^sl), and inside each the XCD k takes the
+// k-th run of S consecutive tiles, its workgroups striding through the XCD's
+// runs in turn.  S = 1 is the grid-wide order, and S near ntiles / 8 comes
+// close to the XCD-contiguous one; between them each XCD's L2 keeps the x
+// entries of its runs while the chip still reads one region of the matrix at
+// a time.  gridDim.x must be a multiple of kNumXcd.
 struct TileSeq {
-    long i, step, S, ntiles;
-    int xcd;
-    __device__ __forceinline__ long tile(long j) const { return (j / S) * (kNumXcd * S) + xcd * S + j % S; }
+    long i, step, ntiles;
+    int xcd, sl;
+    __device__ __forceinline__ long tile(long j) const {
+        return ((j >> sl) * kNumXcd + xcd) * (1L << sl) + (j & ((1L << sl) - 1));
+    }
     __device__ __forceinline__ bool valid(long j) const { return tile(j) < ntiles; }
 };
-__device__ __forceinline__ TileSeq tile_seq(long ntiles, long S) {
+__device__ __forceinline__ TileSeq tile_seq(long ntiles, int sl) {
     TileSeq q;
     q.xcd = blockIdx.x % kNumXcd;
     q.i = blockIdx.x / kNumXcd;
     q.step = gridDim.x / kNumXcd;
-    q.S = S;
+    q.sl = sl;
     q.ntiles = ntiles;
     return q;
 }

@@ -19,9 +19,10 @@
 // walk row tiles in XCD-contiguous ranges, so each XCD's L2 holds the x
 // entries of the mesh planes its rows touch.  The 1x3 BCRS kernels walk
 // super-tiles of 8 x 16 tiles with the whole grid in step, each XCD taking 16
-// consecutive tiles of each (tile_seq): the chip reads one region of the
-// matrix at a time, which measured faster for them, and each XCD's L2 still
-// serves most of its x gathers.  The matrix streams past non-temporally when
+// consecutive tiles of each (tile_seq; fewer on a matrix with fewer than 16
+// tiles per workgroup): the chip reads one region of the matrix at a time,
+// which measured faster for them, and each XCD's L2 still serves most of its
+// x gathers.  The matrix streams past non-temporally when
 // it is larger than the memory-side cache can usefully keep
 // (matrix_stream_nt).
 #include <type_traits>
@@ -48,7 +49,7 @@
 #define MFE_B13_WALK 2  // pipelined 1x3 BCRS walk: 0 column indices read ahead, 1 scalars read ahead, 2 by precision
 #endif
 #ifndef MFE_B13_SUPER
-#define MFE_B13_SUPER 16      // 1x3 BCRS products: consecutive tiles per XCD in each super-tile (tile_seq)
+#define MFE_B13_SUPER 16      // 1x3 BCRS products: most consecutive tiles per XCD in a super-tile, a power of two (tile_seq)
 #endif
 #ifndef MFE_SPMV_WG_PER_CU
 #define MFE_SPMV_WG_PER_CU 0  // resident workgroups per CU (0: as many as fit)
@@ -378,12 +379,12 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13(int64_t m
                                                      const int32_t *__restrict__ jas,
                                                      const B13Desc *__restrict__ desc,
                                                      const T *__restrict__ val, Epi<T> E, CgState *st,
-                                                     double *partials) {
+                                                     double *partials, int super_log2) {
     if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double d1 = 0.0, d2 = 0.0;
-    const TileSeq q = tile_seq(ntiles, MFE_B13_SUPER);
+    const TileSeq q = tile_seq(ntiles, super_log2);
     for (long j = q.i; q.valid(j); j += q.step) {
         const int64_t s = (int64_t)q.tile(j) * (kBlock / 64) + wave;
         const int64_t row = s * 64 + lane;
@@ -407,12 +408,12 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13p(int64_t 
                                                       const int32_t *__restrict__ jas,
                                                       const B13Desc *__restrict__ desc,
                                                       const T *__restrict__ val, Epi<T> E, CgState *st,
-                                                      double *partials) {
+                                                      double *partials, int super_log2) {
     if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double d1 = 0.0, d2 = 0.0;
-    const TileSeq q = tile_seq(ntiles, MFE_B13_SUPER);
+    const TileSeq q = tile_seq(ntiles, super_log2);
     B13Idx cur, nxt;
     auto fetch = [&](long t, B13Idx &r) {
         const int64_t s = (int64_t)t * (kBlock / 64) + wave;
@@ -453,12 +454,12 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13s(int64_t 
                                                       const int32_t *__restrict__ jas,
                                                       const B13Desc *__restrict__ desc,
                                                       const T *__restrict__ val, Epi<T> E, CgState *st,
-                                                      double *partials) {
+                                                      double *partials, int super_log2) {
     if ((MODE == kSpmvDot || MODE == kSpmvDot2) && st && !cg_gate(st)) return;
     const long ntiles = (m + kBlock - 1) / kBlock;
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     double d1 = 0.0, d2 = 0.0;
-    const TileSeq q = tile_seq(ntiles, MFE_B13_SUPER);
+    const TileSeq q = tile_seq(ntiles, super_log2);
     const int64_t nslices = (m + 63) / 64;
     auto slice = [&](long j) -> int64_t {  // this wavefront's slice of the j-th tile, or -1
         if (!q.valid(j)) return -1;
@@ -483,6 +484,26 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13s(int64_t 
 }
 
 // ---------------------------------------------------------------- launch
+
+// Super-tile length (log2) of the 1x3 BCRS walks: the longest run, up to
+// MFE_B13_SUPER tiles, that leaves no workgroup more tiles to walk than
+// single tiles dealt round the XCDs would.  XCD 0 holds the most tiles, the
+// full super-tiles' runs plus the first run of the ragged last one; on a
+// matrix of few super-tiles long runs would load the first XCDs only (16^3:
+// 20 tiles, with runs of 16 on 2 of the 8 XCDs, 6 tiles for some
+// workgroups).  From 64^3 up the runs stay at 16.
+int b13_super_log2(long ntiles, int grid) {
+    const long per_xcd = grid >= kNumXcd ? grid / kNumXcd : 1;
+    auto worst = [&](long S) {
+        const long F = ntiles / (kNumXcd * S), R = ntiles % (kNumXcd * S);
+        return (F * S + (R < S ? R : S) + per_xcd - 1) / per_xcd;
+    };
+    const long best = worst(1);
+    int sl = 0;
+    for (int l = 1; (1L << l) <= MFE_B13_SUPER; ++l)
+        if (worst(1L << l) == best) sl = l;
+    return sl;
+}
 
 template <typename K>
 int grid_for(K kernel, long ntiles, int num_cu) {
@@ -578,7 +599,8 @@ int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
     }
     MFE_TRY(check_cap(grid, cap));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
-                       (const int32_t *)P->jas.ptr, (const B13Desc *)P->bdesc.ptr, val, E, st, partials);
+                       (const int32_t *)P->jas.ptr, (const B13Desc *)P->bdesc.ptr, val, E, st, partials,
+                       b13_super_log2(ntiles, grid));
     MFE_HIP_TRY(hipGetLastError());
     if (grid_out) *grid_out = grid;
     return MFE_OK;
