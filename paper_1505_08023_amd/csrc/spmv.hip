@@ -597,6 +597,19 @@ int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
         kern = k_spmv_b13<T, MODE, MNT>;
         grid = grid_for(kern, ntiles, P->ctx->num_cu);
     }
+    // Where the scalar walk's resident grid would leave some workgroups a
+    // second tile and the plain walk's larger one (fewer registers, more
+    // resident workgroups) takes every tile in one pass, there is no next
+    // tile to read ahead and the plain walk is faster (64^3 FP64 CG: 37.7
+    // against 36.5 k it/s; from 48^3 down and from 96^3 up it is 1-3 %
+    // slower).
+    if (scalar_walk && ntiles > grid) {
+        const int gp = grid_for(k_spmv_b13<T, MODE, MNT>, ntiles, P->ctx->num_cu);
+        if (ntiles <= gp) {
+            kern = k_spmv_b13<T, MODE, MNT>;
+            grid = gp;
+        }
+    }
     MFE_TRY(check_cap(grid, cap));
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kBlock), 0, s, P->m, (const int32_t *)P->slot_base.ptr,
                        (const int32_t *)P->jas.ptr, (const B13Desc *)P->bdesc.ptr, val, E, st, partials,
