@@ -771,13 +771,17 @@ ConvPlan conv_plan(int64_t total, int Cout, int Kpad, int64_t ws_floats) {
     return p;
 }
 
+// Channel counts the convolution kernels take (powers of two: the tiles are
+// 16 channels wide, 8 for the last layer).
+bool conv_channels_ok(int c) { return c == 8 || c == 16 || c == 32 || c == 64 || c == 128; }
+
 template <int MODE>
 int conv_mode(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *W, int Kpad, int Cout, int Go,
               int batch, const float *bias, const bf16 *add, int relu, bf16 *out, float *out32, float *ws,
               int64_t ws_floats) {
     const int64_t total = (int64_t)batch * Go * Go * Go;
     const int nt = (Cout + 15) / 16;
-    if (nt != 1 && nt != 2 && nt != 4 && nt != 8) {
+    if (!conv_channels_ok(Cout)) {  // k_conv_reduce takes the bias channel as i & (Cout - 1)
         set_error("conv3d: output channels must be 8, 16, 32, 64 or 128");
         return MFE_EUNSUPPORTED;
     }
@@ -818,7 +822,7 @@ int conv_mode(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *W, int
 int conv_t2(hipStream_t s, const bf16 *in, int Gi, int Cin, const bf16 *WC, int Cout, int batch,
             const float *bias, const bf16 *add, int relu, bf16 *out, float *out32) {
     const int nt = (Cout + 15) / 16;
-    if (nt != 1 && nt != 2 && nt != 4 && nt != 8) {
+    if (!conv_channels_ok(Cout)) {
         set_error("conv3d: output channels must be 8, 16, 32, 64 or 128");
         return MFE_EUNSUPPORTED;
     }
