@@ -401,7 +401,12 @@ int launch_stream_probe(mfe_ctx *ctx, int kind, int64_t n, const double *src, do
 template <typename T, bool NT>
 int update_r_as(const mfe_problem *P, void *r, const void *q, CgState *st, const double *pq_partials, int n_pq,
                 double *rr_partials, hipStream_t s, int *grid) {
-    const int g = vec_grid((const void *)k_update_r<T, NT>, P->m, P->ctx->num_cu);
+    // one thread per 16-byte chunk: a grid sized by elements would leave the
+    // workgroups past m / W without rows (half of them in FP64, three
+    // quarters in FP32) and their zero partials to the next kernel's sum;
+    // the other workgroups keep their rows, so the sums are unchanged
+    const int g = vec_grid((const void *)k_update_r<T, NT>, (P->m + Vec16<T>::W - 1) / Vec16<T>::W,
+                           P->ctx->num_cu);
     hipLaunchKernelGGL((k_update_r<T, NT>), dim3(g), dim3(kBlock), 0, s, P->m, (T *)r, (const T *)q, st, pq_partials,
                        n_pq, rr_partials);
     MFE_HIP_TRY(hipGetLastError());
