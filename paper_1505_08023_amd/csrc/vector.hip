@@ -14,6 +14,7 @@
 #include "common.hpp"
 #include "device_util.hpp"
 
+
 namespace mfe {
 namespace {
 
@@ -94,12 +95,28 @@ __global__ __launch_bounds__(kBlock) void k_update_xp(int64_t m, T *__restrict__
         else if (it >= st->max_iter) st->status = kCapped;
     }
     // p is updated even on the last iteration: the update is not needed then,
-    // but deciding it would need the stopping test in every workgroup
-    // (16-byte vector accesses were measured no faster here: 114.7 against
-    // 113.4 us at 256^3)
+    // but deciding it would need the stopping test in every workgroup.
+    // 16-byte accesses, then the < W trailing elements (at 256^3 on par with
+    // 8-byte ones, which need twice the workgroups; 128^3 CG +2 %, 48^3 +5 %)
     const T a = (T)alpha, be = (T)beta;
     const int64_t stride = (int64_t)gridDim.x * kBlock;
-    for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < m; i += stride) {
+    const int64_t gid = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    using V = Vec16<T>;
+    constexpr int W = V::W;
+    const int64_t mv = m / W;
+    for (int64_t i = gid; i < mv; i += stride) {
+        const typename V::t pv = ((const typename V::t *)p)[i];
+        typename V::t xv = stream_load((const typename V::t *)x + i, NT);
+        typename V::t rv = stream_load((const typename V::t *)r + i, NT);
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            xv[j] = xv[j] + a * pv[j];
+            rv[j] = rv[j] + be * pv[j];
+        }
+        stream_store(xv, (typename V::t *)x + i, NT);
+        ((typename V::t *)p)[i] = rv;
+    }
+    for (int64_t i = mv * W + gid; i < m; i += stride) {
         const T pi = p[i];
         stream_store(stream_load(x + i, NT) + a * pi, x + i, NT);
         p[i] = stream_load(r + i, NT) + be * pi;
@@ -417,7 +434,9 @@ int update_r_as(const mfe_problem *P, void *r, const void *q, CgState *st, const
 template <typename T, bool NT>
 int update_xp_as(const mfe_problem *P, void *x, void *p, const void *r, CgState *st, const double *rr_partials,
                  int n_rr, hipStream_t s) {
-    const int g = vec_grid((const void *)k_update_xp<T, NT>, P->m, P->ctx->num_cu);
+    // one thread per 16-byte chunk, as the r update
+    const int g = vec_grid((const void *)k_update_xp<T, NT>, (P->m + Vec16<T>::W - 1) / Vec16<T>::W,
+                           P->ctx->num_cu);
     hipLaunchKernelGGL((k_update_xp<T, NT>), dim3(g), dim3(kBlock), 0, s, P->m, (T *)x, (T *)p, (const T *)r, st,
                        rr_partials, n_rr);
     MFE_HIP_TRY(hipGetLastError());
