@@ -670,13 +670,11 @@ def guess_at_scale(args, ctx, P, x, net, torch):
     b = P.rhs()
     P.cg(xr, tol=1e-10, max_iter=args.max_iter, fmt=args.fmt)
     nr = float(torch.linalg.norm(xr))
-    # interior nodes of the (n+1)^3 grid: the trivial guess keeps b (= g, the
-    # boundary rows being identity rows) on the boundary and 0 inside
+    # the trivial guess keeps b (= g, the boundary rows being identity rows)
+    # on the boundary nodes and 0 on the interior ones
+    from paper_1505_08023_amd.learned import boundary_mask
     with torch.cuda.stream(ctx.stream):
-        ids = torch.arange((n + 1) ** 3, device=ctx.device)
-        inner = ((2 * (ids % (n + 1)) - n).abs() < n) & ((2 * ((ids // (n + 1)) % (n + 1)) - n).abs() < n) \
-            & ((2 * (ids // (n + 1) ** 2) - n).abs() < n)
-        del ids
+        inner = ~torch.tensor(boundary_mask(n), device=ctx.device)
 
     def set_boundary_start():
         with torch.cuda.stream(ctx.stream):

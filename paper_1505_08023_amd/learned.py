@@ -112,6 +112,15 @@ def train(net, g, u, epochs, batch, lr, seed=0, log_every=60.0, energy=None):
     return history
 
 
+def boundary_mask(n):
+    """Boolean mask over the (n+1)^3 nodes of an n^3 mesh (node id
+    ix + (n+1)(iy + (n+1) iz), x fastest) of the nodes on the six faces,
+    where the Dirichlet values sit (Sec. 1)."""
+    i = np.arange(n + 1)
+    face = (i == 0) | (i == n)
+    return (face[None, None, :] | face[None, :, None] | face[:, None, None]).reshape(-1)
+
+
 def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_direction=False, errors=True):
     """Per held-out seed: plain FP64 CG from x0 = 0 against CG from the
     network's guess (inference included in its time; the solver falls back to
@@ -129,12 +138,10 @@ def evaluate(ctx, net, n, seeds, tol=1e-8, mixed=True, inner_tol=1e-4, keep_dire
     x = torch.zeros(V, dtype=torch.float64, device=ctx.device)
     x0 = torch.zeros(V, dtype=torch.float64, device=ctx.device)
     xr = torch.zeros(V, dtype=torch.float64, device=ctx.device)
-    # boundary nodes of the (n+1)^3 grid, x fastest: the trivial guess keeps
-    # g there and 0 inside (r = 0 on the Dirichlet rows, as the network's
-    # guess, whose boundary values are exact, also has)
-    ids = np.arange(V)
-    gx, gy, gz = ids % (n + 1), (ids // (n + 1)) % (n + 1), ids // ((n + 1) ** 2)
-    on_b = torch.tensor((gx == 0) | (gx == n) | (gy == 0) | (gy == n) | (gz == 0) | (gz == n), device=ctx.device)
+    # the trivial guess keeps g on the boundary nodes and 0 inside (r = 0 on
+    # the Dirichlet rows, as the network's guess, whose boundary values are
+    # exact, also has)
+    on_b = torch.tensor(boundary_mask(n), device=ctx.device)
 
     def err(v):
         return float(torch.linalg.norm(v - xr) / torch.linalg.norm(xr))

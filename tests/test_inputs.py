@@ -46,3 +46,17 @@ def test_generators_are_seeded():
     s2, f2 = inputs.batched_meshes(seed=5)
     assert np.array_equal(s1, s2) and np.array_equal(f1, f2)
     assert s1.shape == (64, 3) and s1.min() >= 16 and s1.max() <= 96
+
+
+def test_boundary_mask_marks_the_six_faces():
+    """The boundary-node mask of the learned evaluation and the benchmark's
+    boundary-only start: against a direct loop over (ix, iy, iz), and the
+    count (n+1)^3 - (n-1)^3."""
+    from paper_1505_08023_amd.learned import boundary_mask
+    for n in (1, 2, 3, 6):
+        G = n + 1
+        m = boundary_mask(n)
+        assert m.shape == (G ** 3,) and m.dtype == bool
+        want = [ix in (0, n) or iy in (0, n) or iz in (0, n) for iz in range(G) for iy in range(G) for ix in range(G)]
+        assert m.tolist() == want
+        assert int(m.sum()) == G ** 3 - max(n - 1, 0) ** 3
