@@ -585,11 +585,11 @@ int launch_b13_as(const mfe_problem *P, const Epi<T> &E, CgState *st, double *pa
                   int *grid_out, int cap) {
     const T *val = std::is_same<T, double>::value ? (const T *)P->bval64.ptr : (const T *)P->bval32.ptr;
     const long ntiles = (P->m + kBlock - 1) / kBlock;
-    // the scalar read-ahead walk measured faster in FP64 at every size (256^3:
-    // 0.794 against 0.803 ms for the index read-ahead; 64^3: 18.7 against
-    // 21.2 us for the plain walk), the index read-ahead in FP32 once each
-    // workgroup takes several tiles (256^3: 0.404 against 0.414 ms), and the
-    // plain walk in FP32 below that
+    // the scalar read-ahead walk measured faster in FP64 (256^3: 0.794 against
+    // 0.803 ms for the index read-ahead; 64^3 with runs of 16 tiles: 18.7
+    // against 21.2 us for the plain walk; one exception below), the index
+    // read-ahead in FP32 once each workgroup takes several tiles (256^3:
+    // 0.404 against 0.414 ms), and the plain walk in FP32 below that
     constexpr bool scalar_walk = MFE_B13_WALK == 1 || (MFE_B13_WALK == 2 && std::is_same<T, double>::value);
     auto kern = scalar_walk ? k_spmv_b13s<T, MODE, MNT> : k_spmv_b13p<T, MODE, MNT>;
     int grid = grid_for(kern, ntiles, P->ctx->num_cu);
