@@ -491,7 +491,7 @@ __global__ __launch_bounds__(kBlock) MFE_B13_OCCUPANCY void k_spmv_b13s(int64_t 
 // full super-tiles' runs plus the first run of the ragged last one; on a
 // matrix of few super-tiles long runs would load the first XCDs only (16^3:
 // 20 tiles, with runs of 16 on 2 of the 8 XCDs, 6 tiles for some
-// workgroups).  From 96^3 up the runs stay at 16.
+// workgroups).  From 77^3 up the runs stay at 16.
 int b13_super_log2(long ntiles, int grid) {
     const long per_xcd = grid >= kNumXcd ? grid / kNumXcd : 1;
     auto worst = [&](long S) {

@@ -205,7 +205,12 @@ def check_spmv(y_gpu, A, x, y_ref):
 
 # 64^3: matrices loaded through the caches; 112^3: non-temporal loads with the
 # plain 1x3 BCRS walk; 128^3: non-temporal loads with the pipelined walk
-@pytest.mark.parametrize("N", MESHES + [(64, 64, 64), (112, 112, 112), (128, 128, 128)])
+# Besides the small meshes, sizes that take each 1x3 BCRS walk and tile order:
+# 24^3 runs of 8 tiles per XCD, 48^3 runs of 2, 64^3 and 76^3 the plain walk
+# (its grid takes every tile in one pass, the read-ahead walk's would not),
+# 77^3 and up the read-ahead walk with runs of 16.
+@pytest.mark.parametrize("N", MESHES + [(24, 24, 24), (48, 48, 48), (64, 64, 64), (76, 76, 76), (77, 77, 77),
+                                        (112, 112, 112), (128, 128, 128)])
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
 def test_spmv_matches_oracle(ctx, N, fmt):
     print("spmv", N, fmt, flush=True)
