@@ -58,7 +58,7 @@ def check_history(h, hr, first=20):
 
 @pytest.mark.parametrize("variant", list(VARIANTS))
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
-@pytest.mark.parametrize("N", [(20, 20, 20), (17, 9, 23), (64, 64, 64)])
+@pytest.mark.parametrize("N", [(20, 20, 20), (17, 9, 23), (24, 24, 24), (64, 64, 64)])
 def test_cg_from_boundary_start_matches_oracle(ctx, N, fmt, variant):
     print("boundary start", variant, N, fmt, flush=True)
     tol, cap = 1e-8, 1000

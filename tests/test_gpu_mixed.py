@@ -47,7 +47,7 @@ def lam_min(N):
 
 
 @pytest.mark.parametrize("fmt", ["csr", "bcrs13"])
-@pytest.mark.parametrize("N", [(2, 3, 4), (20, 20, 20), (33, 17, 9), (64, 64, 64)])
+@pytest.mark.parametrize("N", [(2, 3, 4), (20, 20, 20), (24, 24, 24), (33, 17, 9), (48, 48, 48), (64, 64, 64)])
 def test_spmv_f32(ctx, N, fmt):
     from paper_1505_08023_amd.mfe import Problem
     A = oracle.assemble(*N)
