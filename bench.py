@@ -231,12 +231,18 @@ def main():
     ap.add_argument("--learned-samples", type=int, default=1000, help="held-out seeds in the learned section")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the mixed-precision and batched sections (for profiler runs)")
+    ap.add_argument("--size-sweep", action="store_true",
+                    help="instead of the benchmark: FP64 CG iterations/s for exactly 200 iterations at meshes "
+                         "16^3 to 320^3 in both formats, one JSON line per mesh")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); "
               "this build has no multi-GPU path", file=sys.stderr)
         sys.exit(2)
+    if args.size_sweep:
+        size_sweep()
+        return
 
     import torch
     from paper_1505_08023_amd.mfe import Context, Problem
@@ -344,6 +350,43 @@ def main():
         line["cpu_baseline"] = cpu_baseline(N, stats[-1]["iterations"])
         log(f"[bench] oracle {line['cpu_baseline']['value']:.3f} it/s")
     print(json.dumps(line), flush=True)
+
+
+def size_sweep(sizes=(16, 24, 32, 48, 64, 96, 128, 160, 192, 224, 256, 288, 320), its=200):
+    """CG iterations per second against mesh size: FP64 CG for exactly `its`
+    iterations (tol 0) from x0 = 0 on the paper's problem, fastest of 3 timed
+    solves after one untimed, in both formats; `TBps` divides the format's
+    algorithmic SpMV bytes plus the 64 m vector bytes of an iteration by the
+    iteration time."""
+    import torch
+    from paper_1505_08023_amd.mfe import Context, Problem
+    ctx = Context(0)
+    for n in sizes:
+        P = Problem.mesh(ctx, n, n, n, formats=("csr", "bcrs13"))
+        x = torch.zeros(P.m, dtype=torch.float64, device=ctx.device)
+        row = {"mesh": [n, n, n], "rows": P.m, "nnz": P.nnz, "blocks_1x3": P.nblocks, "iterations": its}
+        for fmt in ("bcrs13", "csr"):
+            def solve():
+                with torch.cuda.stream(ctx.stream):
+                    x.zero_()
+                return P.cg(x, tol=0.0, max_iter=its, fmt=fmt, raise_on_breakdown=False)[1]
+            solve()
+            times = []
+            for _ in range(3):
+                torch.cuda.synchronize()
+                t = time.perf_counter()
+                st = solve()
+                torch.cuda.synchronize()
+                times.append(time.perf_counter() - t)
+            assert st["iterations"] == its
+            rate = its / min(times)
+            by = algorithmic_bytes(fmt, P.m, P.nnz, P.nblocks) + 64 * P.m
+            row[fmt] = {"it_per_s": rate, "TBps": by * rate / 1e12}
+        print(json.dumps(row), flush=True)
+        P.close()
+        del x
+        torch.cuda.empty_cache()
+    ctx.close()
 
 
 def assembly_and_conversion(ctx, n, torch, reps=3):
